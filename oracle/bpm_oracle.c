@@ -1,0 +1,323 @@
+/*
+ * bpm_oracle.c — TEST INFRASTRUCTURE (see bpm_oracle.h).
+ *
+ * A plain FP64 transcription of the two-beam FFT BPM march, step by step in the
+ * paper's order: propagate each envelope in Fourier space with its shifted
+ * propagator, return to real space, then couple the two envelopes through the
+ * n = 0, +/-1 harmonics of the susceptibility phase (Sec. 2, Eq. (4), (8)-(12)).
+ * No blocking, fusion or reordering beyond what those equations state.
+ * Built with -O2 -ffp-contract=off so every product is rounded on its own.
+ */
+#include "bpm_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+static int is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+/* ---------------------------------------------------------------- DFTs ---- */
+
+/* Twiddle table w[m] = exp(sign*2*pi*i*m/n), m < n/2, straight from cos/sin (no
+ * recurrence). */
+static double complex *twiddles(int n, int sign)
+{
+    double complex *w = malloc(sizeof(double complex) * (size_t)(n / 2 > 0 ? n / 2 : 1));
+    if (!w) return NULL;
+    for (int m = 0; m < n / 2; m++) {
+        double ang = sign * 2.0 * M_PI * (double)m / (double)n;
+        w[m] = cos(ang) + I * sin(ang);
+    }
+    return w;
+}
+
+/* Iterative radix-2 Cooley-Tukey: bit-reversal permutation, then log2(n) stages of
+ * butterflies using the table above. */
+static void fft_with(double complex *a, int n, const double complex *w)
+{
+    for (int i = 1, j = 0; i < n; i++) {
+        int bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) { double complex t = a[i]; a[i] = a[j]; a[j] = t; }
+    }
+    for (int len = 2; len <= n; len <<= 1) {
+        int half = len / 2, wstep = n / len;
+        for (int i = 0; i < n; i += len)
+            for (int k = 0; k < half; k++) {
+                double complex u = a[i + k];
+                double complex v = a[i + k + half] * w[k * wstep];
+                a[i + k] = u + v;
+                a[i + k + half] = u - v;
+            }
+    }
+}
+
+int oracle_fft(double complex *a, int n, int sign)
+{
+    if (!is_pow2(n)) return -1;
+    double complex *w = twiddles(n, sign);
+    if (!w) return -2;
+    fft_with(a, n, w);
+    free(w);
+    return 0;
+}
+
+void oracle_dft(const double complex *in, double complex *out, int n, int sign)
+{
+    for (int f = 0; f < n; f++) {
+        double complex acc = 0;
+        for (int j = 0; j < n; j++) {
+            /* reduce j*f mod n exactly before forming the angle */
+            long long m = ((long long)j * f) % n;
+            double ang = sign * 2.0 * M_PI * (double)m / (double)n;
+            acc += in[j] * (cos(ang) + I * sin(ang));
+        }
+        out[f] = acc;
+    }
+}
+
+/* ------------------------------------------------------------- scalars ---- */
+
+/* Jacobi-Anger for delta_eps = chi0 + chih e^{+i k_d x} + chihb e^{-i k_d x}
+ * (Eq. (8)-(10), generalised to chih != chihb): with A = dzh/(2c) and
+ * y = -A^2 chih chihb,
+ *   harmonic 0 : J0 = sum_m y^m/(m!)^2
+ *   harmonic +1: i A chih  * G,   G = sum_m y^m/(m!(m+1)!)   (= 2 J1(w)/w)
+ * Both series are even in w = 2A sqrt(chih chihb), so no square root is taken. */
+void oracle_bessel_series(double complex y, double complex *j0, double complex *g)
+{
+    double complex t0 = 1.0, s0 = 1.0; /* y^m/(m!)^2 */
+    double complex t1 = 1.0, s1 = 1.0; /* y^m/(m!(m+1)!) */
+    for (int m = 1; m < 200; m++) {
+        t0 = t0 * y / ((double)m * (double)m);
+        t1 = t1 * y / ((double)m * (double)(m + 1));
+        s0 += t0;
+        s1 += t1;
+        if (cabs(t0) <= 1e-18 * cabs(s0) && cabs(t1) <= 1e-18 * cabs(s1)) break;
+    }
+    *j0 = s0;
+    *g = s1;
+}
+
+static int desc_valid(const oracle_desc *d)
+{
+    if (!d || !is_pow2(d->nx) || d->nz < 0) return 0;
+    if (!(d->dx_um > 0) || !(d->dz_um > 0) || !(d->lambda_um > 0) || !(d->d_um > 0)) return 0;
+    if (!(d->lambda_um < 2.0 * d->d_um)) return 0;
+    if (d->nseg < 0 || (d->nseg > 0 && d->nz > 0 && !d->seg)) return 0;
+    if (d->strain_kind == ORACLE_STRAIN_TABLE && !d->u_table && d->nz > 0) return 0;
+    return 1;
+}
+
+int oracle_scalars_get(const oracle_desc *d, oracle_scalars *o)
+{
+    if (!desc_valid(d)) return -1;
+    o->k = 2.0 * M_PI / d->lambda_um;
+    o->h = 2.0 * M_PI / d->d_um;
+    o->s = o->h / (2.0 * o->k);
+    o->c = sqrt(1.0 - o->s * o->s);
+    o->dzh = o->k * d->dz_um;
+    double complex chi0 = d->chi0_re + I * d->chi0_im;
+    double complex chih = d->chih_re + I * d->chih_im;
+    double complex chihb = d->chihb_re + I * d->chihb_im;
+    double A = o->dzh / (2.0 * o->c);
+    double complex E = cexp(I * A * chi0);
+    double complex y = -A * A * chih * chihb;
+    double complex j0, g;
+    oracle_bessel_series(y, &j0, &g);
+    o->a0 = j0 * E;
+    o->ap = I * A * chih * g * E;
+    o->am = I * A * chihb * g * E;
+    return 0;
+}
+
+/* p+- = exp(i dzh (S(q +/- s) - c)) / nx on the numpy frequency grid.  The
+ * difference S - c is formed without cancellation as
+ * -(q^2 +/- 2 s q) / (S + c); dropping the constant -c relative to Eq. (4) only
+ * multiplies both envelopes by the same global phase per step. */
+int oracle_propagator(const oracle_desc *d, double complex *pp, double complex *pm)
+{
+    oracle_scalars sc;
+    if (oracle_scalars_get(d, &sc)) return -1;
+    int n = d->nx;
+    for (int f = 0; f < n; f++) {
+        int ff = f < n / 2 ? f : f - n;
+        double q = 2.0 * M_PI * (double)ff / ((double)n * d->dx_um * sc.k);
+        for (int b = 0; b < 2; b++) {
+            double sg = b == 0 ? 1.0 : -1.0;
+            double p = q + sg * sc.s;
+            double complex P;
+            if (fabs(p) <= 1.0) {
+                double S = sqrt(1.0 - p * p);
+                double th = -sc.dzh * (q * q + 2.0 * sg * sc.s * q) / (S + sc.c);
+                P = cexp(I * th);
+            } else {
+                P = exp(-sc.dzh * sqrt(p * p - 1.0)) * cexp(-I * sc.dzh * sc.c);
+            }
+            P /= (double)n;
+            if (b == 0) pp[f] = P; else pm[f] = P;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------- strain ----- */
+
+double oracle_strain_phase(const oracle_desc *d, int j, int n)
+{
+    double h = 2.0 * M_PI / d->d_um;
+    double x = d->x0_um + j * d->dx_um;
+    double z = n * d->dz_um;
+    double X = x - d->x_ref_um, Z = z - d->z_ref_um;
+    double u = 0.0;
+    switch (d->strain_kind) {
+    case ORACLE_STRAIN_POLY2: {
+        const double *c = d->strain_c;
+        u = c[0] + c[1] * X + c[2] * Z + c[3] * X * X + c[4] * X * Z + c[5] * Z * Z;
+        break;
+    }
+    case ORACLE_STRAIN_EDGE_DISL: {
+        /* Eq. (15) for a line along y and b along h: only the arctangent and the
+         * y0 z0 / (2(1-nu) r^2) terms have a component along h. */
+        double r2 = X * X + Z * Z;
+        double t = atan2(Z, X);
+        if (r2 > 0) t += X * Z / (2.0 * (1.0 - d->disl_nu) * r2);
+        u = d->disl_b_um / (2.0 * M_PI) * t;
+        break;
+    }
+    case ORACLE_STRAIN_TABLE:
+        u = d->u_table[(size_t)n * d->nx + j];
+        break;
+    default:
+        u = 0.0;
+    }
+    return h * u;
+}
+
+/* ------------------------------------------------------------- march ------ */
+
+static int inside_mask(const oracle_desc *d, int j, int n)
+{
+    for (int k = 0; k < d->nseg; k++) {
+        const int *iv = d->seg + ((size_t)n * d->nseg + k) * 2;
+        if (j >= iv[0] && j < iv[1]) return 1;
+    }
+    return 0;
+}
+
+/* Compensated (Kahan) sum of |a_j|^2 over [lo, hi). */
+static double power_sum(const double complex *a, int lo, int hi)
+{
+    double s = 0.0, comp = 0.0;
+    for (int j = lo; j < hi; j++) {
+        double v = creal(a[j]) * creal(a[j]) + cimag(a[j]) * cimag(a[j]);
+        double yv = v - comp;
+        double t = s + yv;
+        comp = (t - s) - yv;
+        s = t;
+    }
+    return s;
+}
+
+int oracle_propagate(const oracle_desc *d, double complex *psi_p, double complex *psi_m,
+                     double *R, double *T)
+{
+    if (!desc_valid(d)) return -1;
+    int n = d->nx;
+    oracle_scalars sc;
+    oracle_scalars_get(d, &sc);
+    double complex *pp = malloc(sizeof(double complex) * (size_t)n);
+    double complex *pm = malloc(sizeof(double complex) * (size_t)n);
+    double complex *wf = twiddles(n, -1), *wi = twiddles(n, +1);
+    if (!pp || !pm || !wf || !wi) { free(pp); free(pm); free(wf); free(wi); return -2; }
+    oracle_propagator(d, pp, pm);
+    double pin = power_sum(psi_p, 0, n);
+
+    for (int step = 0; step < d->nz; step++) {
+        /* Fourier-space propagation of each envelope about its own carrier */
+        fft_with(psi_p, n, wf);
+        fft_with(psi_m, n, wf);
+        for (int f = 0; f < n; f++) { psi_p[f] *= pp[f]; psi_m[f] *= pm[f]; }
+        fft_with(psi_p, n, wi);
+        fft_with(psi_m, n, wi);
+        /* real-space coupling at z_step */
+        for (int j = 0; j < n; j++) {
+            if (!inside_mask(d, j, step)) continue;
+            double complex e = 1.0;
+            if (d->strain_kind != ORACLE_STRAIN_NONE) {
+                double phi = oracle_strain_phase(d, j, step);
+                e = cos(phi) + I * sin(phi);
+            }
+            double complex p = psi_p[j], m = psi_m[j];
+            psi_p[j] = sc.a0 * p + sc.ap * e * m;
+            psi_m[j] = sc.a0 * m + sc.am * conj(e) * p;
+        }
+    }
+    int lo = d->det_lo < 0 ? 0 : d->det_lo;
+    int hi = d->det_hi > n ? n : d->det_hi;
+    if (hi < lo) hi = lo;
+    double r = 0.0, t = 0.0;
+    if (pin > 0) {
+        r = power_sum(psi_m, lo, hi) / pin;
+        t = power_sum(psi_p, lo, hi) / pin;
+    }
+    if (R) *R = r;
+    if (T) *T = t;
+    free(pp);
+    free(pm);
+    free(wf);
+    free(wi);
+    return 0;
+}
+
+/* ------------------------------------------------------------- batch ------ */
+
+typedef struct {
+    const oracle_desc *descs;
+    int n;
+    double complex **psi;
+    double *R, *T;
+    int next;
+    int status;
+    pthread_mutex_t mu;
+} batch_ctx;
+
+static void *batch_worker(void *arg)
+{
+    batch_ctx *b = arg;
+    for (;;) {
+        pthread_mutex_lock(&b->mu);
+        int i = b->next++;
+        pthread_mutex_unlock(&b->mu);
+        if (i >= b->n) break;
+        int nx = b->descs[i].nx;
+        int rc = oracle_propagate(&b->descs[i], b->psi[i], b->psi[i] + nx,
+                                  b->R ? b->R + i : NULL, b->T ? b->T + i : NULL);
+        if (rc) {
+            pthread_mutex_lock(&b->mu);
+            b->status = rc;
+            pthread_mutex_unlock(&b->mu);
+        }
+    }
+    return NULL;
+}
+
+int oracle_propagate_batch(const oracle_desc *descs, int n, double complex **psi,
+                           double *R, double *T, int nthreads)
+{
+    if (n < 0 || nthreads < 1) return -1;
+    batch_ctx b = {descs, n, psi, R, T, 0, 0, PTHREAD_MUTEX_INITIALIZER};
+    if (nthreads > n) nthreads = n > 0 ? n : 1;
+    pthread_t *th = malloc(sizeof(pthread_t) * (size_t)nthreads);
+    if (!th) return -2;
+    int started = 0;
+    for (int i = 0; i < nthreads; i++)
+        if (pthread_create(&th[i], NULL, batch_worker, &b) == 0) started++;
+        else break;
+    if (started == 0) batch_worker(&b);
+    for (int i = 0; i < started; i++) pthread_join(th[i], NULL);
+    free(th);
+    return b.status;
+}

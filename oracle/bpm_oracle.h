@@ -1,0 +1,91 @@
+/*
+ * bpm_oracle.h — TEST INFRASTRUCTURE.
+ *
+ * Plain, slow, FP64 CPU reference for the two-beam FFT beam-propagation march
+ * (the split-step method of Eq. (4) in its two-envelope form, Eq. (12)).
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load, call or link this code.  The product library never does
+ * and shares no code, header or table with it.
+ *
+ * Conventions (the paper is silent on them; the readings are listed with the
+ * tests that pin them):
+ *   x_j = x0 + j*dx, j = 0..nx-1, periodic window;  z_n = n*dz, n = 0..nz-1.
+ *   Forward DFT  X_f = sum_j x_j exp(-2*pi*i*j*f/nx), inverse with +i and 1/nx.
+ *   Frequency of bin f: f for f < nx/2, f - nx otherwise (Nyquist negative).
+ *   k = 2*pi/lambda, h = 2*pi/d, s = h/(2k) = sin(theta_B), c = sqrt(1-s^2),
+ *   dzh = k*dz (the normalised step of Eq. (4)).
+ *
+ * One step n -> n+1:
+ *   psi_pm <- IDFT( DFT(psi_pm) * exp(i*dzh*(S(q +/- s) - c)) ),   S(p) = sqrt(1-p^2)
+ *   inside the crystal mask at (x_j, z_n):
+ *      psi_p <- a0*psi_p + ap*exp(+i*phi)*psi_m
+ *      psi_m <- a0*psi_m + am*exp(-i*phi)*psi_p        (old values on the right)
+ *   with phi = h*u(x_j, z_n) and a0, ap, am the n = 0, +1, -1 harmonics of
+ *   exp(i*dzh*delta_eps/(2c)) (Eq. (8)-(11)).
+ */
+#ifndef BPM_ORACLE_H
+#define BPM_ORACLE_H
+
+#include <complex.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ORACLE_STRAIN_NONE = 0,
+    ORACLE_STRAIN_POLY2 = 1,       /* u = c0 + c1 X + c2 Z + c3 X^2 + c4 X Z + c5 Z^2 */
+    ORACLE_STRAIN_EDGE_DISL = 2,   /* straight edge dislocation, line along y, b along h */
+    ORACLE_STRAIN_TABLE = 3        /* u given at every (x_j, z_n) */
+};
+
+typedef struct oracle_desc {
+    int nx, nz;
+    double dx_um, dz_um, x0_um;
+    double lambda_um, d_um;
+    double chi0_re, chi0_im, chih_re, chih_im, chihb_re, chihb_im;
+    int nseg;              /* mask intervals per step */
+    const int *seg;        /* [nz][nseg][2] half-open [lo, hi) grid-index intervals */
+    int strain_kind;
+    double x_ref_um, z_ref_um;   /* X = x - x_ref, Z = z - z_ref */
+    double strain_c[6];          /* POLY2 coefficients (um, um^-1, um^-1 ...) */
+    double disl_b_um, disl_nu;   /* EDGE_DISL Burgers vector length and Poisson ratio */
+    const double *u_table;       /* TABLE: [nz][nx] displacement along h (um) */
+    int det_lo, det_hi;          /* detector interval for R and T */
+} oracle_desc;
+
+/* Plan-level scalars, exposed so that the tests can pin them. */
+typedef struct oracle_scalars {
+    double k, h, s, c, dzh;
+    double complex a0, ap, am;
+} oracle_scalars;
+
+/* Iterative radix-2 DFT in place; sign = -1 forward, +1 inverse (unnormalised). */
+int oracle_fft(double complex *a, int n, int sign);
+/* Direct O(n^2) DFT, out of place. */
+void oracle_dft(const double complex *in, double complex *out, int n, int sign);
+
+/* Series for J0(w) and 2*J1(w)/w written in y = -w^2/4 (branch-free, complex y). */
+void oracle_bessel_series(double complex y, double complex *j0, double complex *g);
+
+int oracle_scalars_get(const oracle_desc *d, oracle_scalars *out);
+/* Propagator tables P+[f], P-[f] including the 1/nx of the inverse transform. */
+int oracle_propagator(const oracle_desc *d, double complex *pp, double complex *pm);
+/* Strain phase phi = h*u at grid point (j, n). */
+double oracle_strain_phase(const oracle_desc *d, int j, int n);
+
+/* Full march.  psi_p/psi_m hold the entrance envelopes and receive the exit ones.
+ * R and T may be NULL.  Returns 0 or a negative error code. */
+int oracle_propagate(const oracle_desc *d, double complex *psi_p, double complex *psi_m,
+                     double *R, double *T);
+
+/* Many independent solves on a pool of nthreads POSIX threads (one solve per thread
+ * at a time).  psi arrays are [n][2][nx] in the caller's packing: psi[i] points at
+ * solve i's psi_p, followed by its psi_m. */
+int oracle_propagate_batch(const oracle_desc *descs, int n, double complex **psi,
+                           double *R, double *T, int nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
