@@ -1,0 +1,211 @@
+/*
+ * bpm.h — C ABI of the MI355X two-beam FFT beam-propagation library
+ * (libbpm_hip.so, gfx950).
+ *
+ * The library marches the slowly varying envelopes psi+ (transmitted) and psi-
+ * (reflected) of an X-ray field through a deformed crystal with the two-beam
+ * split-step FFT BPM: each z-step propagates both envelopes in Fourier space
+ * with their shifted propagators and then couples them in real space through
+ * the susceptibility harmonics, the crystal-shape mask and the strain phase
+ * (paper Sec. 2, Eq. (4), Eq. (6)-(12); bent crystals Eq. (14); dislocations
+ * Eq. (15)).
+ *
+ * Conventions shared by every call
+ *   x_j = x0_um + j*dx_um (j = 0..nx-1), periodic window; z_n = n*dz_um.
+ *   Step n couples with the mask and strain sampled at (x_j, z_n), after the
+ *   propagation of that step (Eq. (12): propagate, then multiply by the
+ *   harmonics).
+ *   Envelope storage: interleaved complex (re, im).  A solve's device state is
+ *   psi+[nx] followed by psi-[nx], in the plan's precision (complex128 for
+ *   BPM_F64, complex64 for BPM_F32).  Host-side buffers are always complex128.
+ *   R = sum_{j in [det_lo, det_hi)} |psi-_j(nz)|^2 / sum_j |psi+_j(0)|^2 and
+ *   T likewise for psi+ (both accumulated in FP64; 0 if the incident power is 0).
+ *
+ * Errors: every call returns a bpm_status; no exception crosses the ABI.  On
+ * failure bpm_last_error() returns a thread-local message.  A plan or batch is
+ * used by one thread at a time; the server API is thread-safe.
+ */
+#ifndef BPM_H
+#define BPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bpm_status {
+    BPM_OK = 0,
+    BPM_E_INVALID = 1,     /* bad argument, descriptor or NULL pointer */
+    BPM_E_NOMEM = 2,       /* host or device allocation failed */
+    BPM_E_DEVICE = 3,      /* HIP runtime error, or no gfx950 device */
+    BPM_E_BUDGET = 4,      /* request can never fit the server's device-memory budget */
+    BPM_E_PENDING = 5,     /* ticket not finished yet */
+    BPM_E_CANCELLED = 6,   /* ticket was cancelled before it finished */
+    BPM_E_NOTFOUND = 7,    /* unknown ticket */
+    BPM_E_UNSUPPORTED = 8, /* valid request outside what this build runs */
+    BPM_E_NUMERIC = 9      /* non-finite input or result */
+} bpm_status;
+
+typedef struct bpm_complex {
+    double re, im;
+} bpm_complex;
+
+typedef enum bpm_precision {
+    BPM_F64 = 0, /* complex128 envelopes and arithmetic */
+    BPM_F32 = 1  /* complex64 envelopes and arithmetic; FP64 for plan setup,
+                    strain-phase arguments and R/T accumulation */
+} bpm_precision;
+
+typedef enum bpm_strain_kind {
+    BPM_STRAIN_NONE = 0,
+    /* u = c0 + c1 X + c2 Z + c3 X^2 + c4 X Z + c5 Z^2 with X = x - x_ref, Z = z - z_ref
+     * (covers Eq. (14) bending, u = xz/R plate bending, uniform strain, offsets) */
+    BPM_STRAIN_POLY2 = 1,
+    /* straight edge dislocation, line along y, Burgers vector b along h (Eq. (15)):
+     * u = b/(2 pi) * (atan2(Z, X) + X Z / (2 (1 - nu) (X^2 + Z^2))), core at (x_ref, z_ref) */
+    BPM_STRAIN_EDGE_DISLOCATION = 2,
+    /* u given at every grid point: u_table[n*nx + j] (um), copied at plan creation */
+    BPM_STRAIN_TABLE = 3
+} bpm_strain_kind;
+
+typedef struct bpm_strain {
+    int32_t kind;            /* bpm_strain_kind */
+    double x_ref_um, z_ref_um;
+    double c[6];             /* POLY2 coefficients (um, dimensionless, um^-1) */
+    double b_um, nu;         /* EDGE_DISLOCATION Burgers vector length, Poisson ratio */
+    const double *u_table;   /* TABLE: [nz][nx] displacement along h (um) */
+} bpm_strain;
+
+/* One solve.  Geometry and asymmetry enter through the crystal mask: the caller
+ * rasterises the crystal shape (slab, asymmetric trapezoid, any polygon) into
+ * per-step index intervals, so every consumer sees the same binary Pi(x, z). */
+typedef struct bpm_plan_desc {
+    int32_t nx;              /* power of two, 64 <= nx <= 65536 */
+    int32_t nz;              /* number of z-steps, >= 0 */
+    double dx_um, dz_um;     /* > 0 */
+    double x0_um;            /* x of sample 0 */
+    double lambda_um;        /* vacuum wavelength, 0 < lambda < 2 d */
+    double d_um;             /* spacing of the reflecting planes; h = 2 pi / d */
+    bpm_complex chi0, chih, chihbar;  /* susceptibility harmonics 0, +h, -h (Eq. (8)) */
+    int32_t nseg;            /* mask intervals per step, >= 1 */
+    const int32_t *seg;      /* [nz][nseg][2] half-open [lo, hi) index intervals; lo >= hi
+                                is empty; 0 <= lo, hi <= nx.  Copied at creation. */
+    bpm_strain strain;
+    int32_t det_lo, det_hi;  /* detector interval for R and T, 0 <= det_lo <= det_hi <= nx */
+    int32_t precision;       /* bpm_precision */
+} bpm_plan_desc;
+
+typedef struct bpm_plan bpm_plan;
+typedef struct bpm_batch bpm_batch;
+typedef struct bpm_server bpm_server;
+
+typedef struct bpm_plan_info {
+    int32_t nx, nz, precision;
+    int32_t threads_per_solve;   /* workgroup size of the march kernel */
+    size_t state_bytes;          /* device bytes of one solve's envelope pair */
+    size_t device_bytes;         /* device bytes held by the plan (tables, mask) */
+    double cell_steps;           /* nx * nz * 2 */
+} bpm_plan_info;
+
+/* --- plans ------------------------------------------------------------------
+ * bpm_plan_create validates the descriptor, copies every array it points to,
+ * and builds the plan's device tables (propagators, coupling scalars) with FP64
+ * setup kernels on the current device (plan setup of Eq. (12)'s p+-, Eq. (9)-(10)).
+ * Errors: BPM_E_INVALID (nx not a power of two in [64, 65536], nz < 0, a spacing
+ * or wavelength <= 0, lambda >= 2d, non-finite values, bad intervals, unknown
+ * kinds), BPM_E_UNSUPPORTED (nx too large for this build at this precision),
+ * BPM_E_NOMEM, BPM_E_DEVICE.  *out is NULL on failure. */
+bpm_status bpm_plan_create(const bpm_plan_desc *desc, bpm_plan **out);
+void bpm_plan_destroy(bpm_plan *plan);
+bpm_status bpm_plan_info_get(const bpm_plan *plan, bpm_plan_info *info);
+
+/* Blocking march from host buffers (each nx complex128).  psi_m0 may be NULL
+ * (zero reflected envelope).  Outputs psi_p_out, psi_m_out, R, T may each be
+ * NULL.  Output buffers may alias the inputs.  Eq. (12) applied nz times. */
+bpm_status bpm_propagate(bpm_plan *plan, const bpm_complex *psi_p0, const bpm_complex *psi_m0,
+                         bpm_complex *psi_p_out, bpm_complex *psi_m_out, double *R, double *T);
+
+/* Asynchronous march on device buffers owned by the caller, enqueued on
+ * `stream` (a hipStream_t; NULL = default stream).  d_in and d_out each hold
+ * one solve's state (psi+ then psi-, plan precision); they may be equal.
+ * d_RT receives R, T (2 doubles) or may be NULL. */
+bpm_status bpm_propagate_device(bpm_plan *plan, void *stream, const void *d_in, void *d_out,
+                                double *d_RT);
+
+/* --- batches (many solves in one launch) ------------------------------------
+ * A batch groups plans (any mix of nx, nz, wavelength, crystal, strain) into
+ * one kernel launch per precision; solves are ordered longest first so the
+ * hardware dispatcher balances uneven work.  The plans must outlive the batch.
+ * bpm_batch_layout returns each solve's byte offset in the packed device
+ * state buffer (offsets[n]) and the buffer's total size.  bpm_batch_run marches
+ * every solve: state in d_in (packed), results to d_out (may equal d_in), R/T
+ * of solve i to d_RT[2i], d_RT[2i+1] (may be NULL). */
+bpm_status bpm_batch_create(bpm_plan *const *plans, int32_t n, bpm_batch **out);
+bpm_status bpm_batch_layout(const bpm_batch *batch, size_t *offsets, size_t *total_bytes);
+bpm_status bpm_batch_run(bpm_batch *batch, void *stream, const void *d_in, void *d_out,
+                         double *d_RT);
+void bpm_batch_destroy(bpm_batch *batch);
+
+/* --- serving (continuous batching) ------------------------------------------
+ * A server owns a device-memory budget and a pool of solve slots.  A worker
+ * thread advances all admitted solves together, `chunk_steps` z-steps per
+ * launch; between launches it retires finished solves and admits waiting
+ * requests whose state and tables fit the budget, so requests that arrive while
+ * others run join the next launch.  Per-solve arithmetic does not depend on what
+ * else is in the launch, so a result is the same alone and in the mix. */
+typedef struct bpm_server_desc {
+    size_t hbm_budget_bytes;   /* device bytes the server may hold for admitted solves */
+    int32_t max_slots;         /* max solves in flight */
+    int32_t chunk_steps;       /* z-steps per launch (>= 1) */
+} bpm_server_desc;
+
+typedef struct bpm_request {
+    const bpm_plan_desc *plan;      /* copied at submit */
+    const bpm_complex *psi_p0;      /* nx complex128, copied at submit */
+    const bpm_complex *psi_m0;      /* may be NULL */
+    bpm_complex *psi_p_out;         /* may be NULL; written before the ticket completes */
+    bpm_complex *psi_m_out;         /* may be NULL */
+} bpm_request;
+
+typedef struct bpm_result {
+    int32_t status;                 /* bpm_status of the solve */
+    double R, T;
+    double t_submit, t_admit, t_done;   /* seconds on the server's monotonic clock */
+} bpm_result;
+
+typedef struct bpm_server_stats {
+    int64_t submitted, admitted, completed, cancelled, failed;
+    int64_t launches;
+    double cell_steps_done;
+    size_t bytes_in_use, peak_bytes;
+} bpm_server_stats;
+
+bpm_status bpm_server_create(const bpm_server_desc *desc, bpm_server **out);
+/* Copies n requests and returns one ticket each.  BPM_E_BUDGET if a request can
+ * never fit the budget (its ticket is still issued and completes with that
+ * status); BPM_E_INVALID for a bad descriptor (no ticket issued for it). */
+bpm_status bpm_batch_submit(bpm_server *server, const bpm_request *reqs, int32_t n,
+                            uint64_t *tickets);
+/* BPM_E_PENDING until done; then fills *out and returns BPM_OK (the solve's own
+ * status is out->status).  A completed ticket can be polled repeatedly. */
+bpm_status bpm_poll(bpm_server *server, uint64_t ticket, bpm_result *out);
+/* Cancels a waiting or running ticket (it completes with BPM_E_CANCELLED). */
+bpm_status bpm_cancel(bpm_server *server, uint64_t ticket);
+bpm_status bpm_server_stats_get(bpm_server *server, bpm_server_stats *out);
+/* Blocks until every submitted ticket has completed (or timeout_s elapses:
+ * BPM_E_PENDING). */
+bpm_status bpm_server_drain(bpm_server *server, double timeout_s);
+void bpm_server_destroy(bpm_server *server);
+
+/* --- misc -------------------------------------------------------------------- */
+const char *bpm_status_str(bpm_status s);
+const char *bpm_last_error(void);
+/* Largest nx this build marches at a precision (LDS/register-resident lane). */
+int32_t bpm_max_nx(int32_t precision);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

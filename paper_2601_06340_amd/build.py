@@ -1,0 +1,101 @@
+"""Build libbpm_hip.so (gfx950) from csrc/ with hipcc.
+
+Every (precision, nx) march kernel is instantiated in its own translation unit
+(generated under ``_build/gen``) so the units compile in parallel; the host
+library (C ABI, server) and the setup kernels are separate units.  The link
+produces ``paper_2601_06340_amd/libbpm_hip.so``.
+
+Usage: python -m paper_2601_06340_amd.build [-j N]
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+import time
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INC = os.path.join(ROOT, "include")
+BUILD = os.path.join(ROOT, "_build")
+GEN = os.path.join(BUILD, "gen")
+LIB = os.path.join(PKG, "libbpm_hip.so")
+
+ARCH = "gfx950"
+# -packed-fp32-ops: no v_pk_{add,mul,fma}_f32 anywhere in the library.
+HIPFLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-I", INC, "-I", CSRC]
+
+# keep in sync with Limits<> in csrc/bpm_march.hpp
+UNIFORM = {"float": range(6, 15), "double": range(6, 14)}
+MIXED = ("float", "double")
+
+
+def _gen_units() -> list[str]:
+    os.makedirs(GEN, exist_ok=True)
+    units = []
+
+    def write(name, body):
+        path = os.path.join(GEN, name)
+        old = open(path).read() if os.path.exists(path) else None
+        if old != body:
+            with open(path, "w") as f:
+                f.write(body)
+        units.append(path)
+
+    for t, rng in UNIFORM.items():
+        for l2 in rng:
+            write("march_%s_%d.hip" % (t, l2),
+                  '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
+                  "template hipError_t launch_uniform<%s, %d>(const SolveDesc *, int, const char *, "
+                  "char *, double *, hipStream_t);\n}\n" % (t, l2))
+    for t in MIXED:
+        write("march_mixed_%s.hip" % t,
+              '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
+              "template hipError_t launch_mixed<%s>(const SolveDesc *, int, const char *, char *, "
+              "double *, hipStream_t);\n}\n" % t)
+    return units
+
+
+def _compile(src: str) -> str:
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    cmd = ["hipcc"] + HIPFLAGS + ["-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    errs = [l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip()]
+    if r.returncode != 0:
+        raise RuntimeError("compile failed: %s\n%s" % (src, "\n".join(errs)))
+    return obj
+
+
+def build(jobs: int | None = None, verbose: bool = True) -> str:
+    t0 = time.time()
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = [os.path.join(CSRC, f) for f in ("bpm_setup.hip", "bpm_api.cpp", "bpm_server.cpp")]
+    srcs += _gen_units()
+    # largest units first
+    srcs.sort(key=lambda s: ("mixed" not in s, not s.endswith(("_13.hip", "_14.hip", "_12.hip"))))
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(_compile, srcs))
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    subprocess.run(cmd, check=True, capture_output=True)
+    os.replace(tmp, LIB)
+    if verbose:
+        print("built %s in %.0f s (%d units, -j%d)" % (LIB, time.time() - t0, len(srcs), jobs))
+    return LIB
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("-j", type=int, default=None)
+    a = ap.parse_args()
+    try:
+        build(a.j)
+    except RuntimeError as e:
+        print(e, file=sys.stderr)
+        sys.exit(1)

@@ -1,0 +1,593 @@
+// bpm_api.cpp — the C ABI of libbpm_hip.so (plans, batches, errors).
+// The serving loop lives in bpm_server.cpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "bpm.h"
+#include "bpm_api_internal.hpp"
+#include "bpm_internal.hpp"
+
+using namespace bpm;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+bpm_status bpm::fail(bpm_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = std::string(bpm_status_str(s)) + ": " + buf;
+    return s;
+}
+
+extern "C" const char *bpm_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *bpm_status_str(bpm_status s)
+{
+    switch (s) {
+    case BPM_OK: return "BPM_OK";
+    case BPM_E_INVALID: return "BPM_E_INVALID";
+    case BPM_E_NOMEM: return "BPM_E_NOMEM";
+    case BPM_E_DEVICE: return "BPM_E_DEVICE";
+    case BPM_E_BUDGET: return "BPM_E_BUDGET";
+    case BPM_E_PENDING: return "BPM_E_PENDING";
+    case BPM_E_CANCELLED: return "BPM_E_CANCELLED";
+    case BPM_E_NOTFOUND: return "BPM_E_NOTFOUND";
+    case BPM_E_UNSUPPORTED: return "BPM_E_UNSUPPORTED";
+    case BPM_E_NUMERIC: return "BPM_E_NUMERIC";
+    }
+    return "BPM_E_UNKNOWN";
+}
+
+bpm_status bpm::hip_fail(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory) return fail(BPM_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(BPM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ device check
+bpm_status bpm::ensure_device()
+{
+    static std::once_flag once;
+    static bpm_status st = BPM_OK;
+    static std::string msg;
+    std::call_once(once, [] {
+        int dev = 0, count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+            st = BPM_E_DEVICE;
+            msg = "no HIP device";
+            return;
+        }
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+            st = BPM_E_DEVICE;
+            msg = "hipGetDeviceProperties failed";
+            return;
+        }
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            st = BPM_E_DEVICE;
+            msg = std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950";
+        }
+    });
+    if (st != BPM_OK) return fail(st, "%s", msg.c_str());
+    return BPM_OK;
+}
+
+// ------------------------------------------------------------------ twiddle cache
+// One table per (precision, nx, elements per thread), shared by every plan.
+static std::mutex g_tw_mu;
+static std::map<std::tuple<int, int, int>, void *> g_tw;
+
+bpm_status bpm::twiddle_table(int prec, int log2n, int log2e, const void **out)
+{
+    std::lock_guard<std::mutex> lk(g_tw_mu);
+    auto key = std::make_tuple(prec, log2n, log2e);
+    auto it = g_tw.find(key);
+    if (it != g_tw.end()) {
+        *out = it->second;
+        return BPM_OK;
+    }
+    const size_t bytes = std::max<size_t>(twiddle_bytes(prec, log2n, log2e), 16);
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return hip_fail(e, "twiddle table");
+    e = launch_twiddles(p, prec, log2n, log2e, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        return hip_fail(e, "twiddle setup kernel");
+    }
+    g_tw[key] = p;
+    *out = p;
+    return BPM_OK;
+}
+
+// ------------------------------------------------------------------ plans
+static bool is_finite(double v) { return std::isfinite(v); }
+static bool is_finite(bpm_complex c) { return std::isfinite(c.re) && std::isfinite(c.im); }
+
+bpm_status bpm::validate_desc(const bpm_plan_desc *d)
+{
+    if (!d) return fail(BPM_E_INVALID, "NULL descriptor");
+    if (d->nx < 64 || d->nx > 65536 || (d->nx & (d->nx - 1)))
+        return fail(BPM_E_INVALID, "nx = %d is not a power of two in [64, 65536]", d->nx);
+    if (d->nz < 0) return fail(BPM_E_INVALID, "nz = %d < 0", d->nz);
+    if (!is_finite(d->dx_um) || d->dx_um <= 0 || !is_finite(d->dz_um) || d->dz_um <= 0)
+        return fail(BPM_E_INVALID, "dx and dz must be finite and > 0");
+    if (!is_finite(d->x0_um)) return fail(BPM_E_INVALID, "x0 is not finite");
+    if (!is_finite(d->lambda_um) || d->lambda_um <= 0 || !is_finite(d->d_um) || d->d_um <= 0)
+        return fail(BPM_E_INVALID, "lambda and d must be finite and > 0");
+    if (!(d->lambda_um < 2.0 * d->d_um)) return fail(BPM_E_INVALID, "lambda >= 2d: no Bragg angle");
+    if (!is_finite(d->chi0) || !is_finite(d->chih) || !is_finite(d->chihbar))
+        return fail(BPM_E_INVALID, "susceptibilities must be finite");
+    if (d->nseg < 1) return fail(BPM_E_INVALID, "nseg = %d < 1", d->nseg);
+    if (d->nz > 0 && !d->seg) return fail(BPM_E_INVALID, "seg is NULL");
+    for (long long i = 0; i < (long long)d->nz * d->nseg; ++i) {
+        const int lo = d->seg[2 * i], hi = d->seg[2 * i + 1];
+        if (lo < 0 || hi < 0 || lo > d->nx || hi > d->nx)
+            return fail(BPM_E_INVALID, "mask interval %lld = [%d, %d) outside [0, %d]", i, lo, hi, d->nx);
+    }
+    const bpm_strain &st = d->strain;
+    switch (st.kind) {
+    case BPM_STRAIN_NONE: break;
+    case BPM_STRAIN_POLY2:
+        for (double c : st.c)
+            if (!is_finite(c)) return fail(BPM_E_INVALID, "POLY2 coefficient not finite");
+        if (!is_finite(st.x_ref_um) || !is_finite(st.z_ref_um)) return fail(BPM_E_INVALID, "strain origin not finite");
+        break;
+    case BPM_STRAIN_EDGE_DISLOCATION:
+        if (!is_finite(st.b_um) || !is_finite(st.nu) || st.nu >= 1.0 || !is_finite(st.x_ref_um) || !is_finite(st.z_ref_um))
+            return fail(BPM_E_INVALID, "dislocation parameters invalid (need finite b, nu < 1, core)");
+        break;
+    case BPM_STRAIN_TABLE:
+        if (d->nz > 0 && !st.u_table) return fail(BPM_E_INVALID, "u_table is NULL");
+        for (long long i = 0; i < (long long)d->nz * d->nx; ++i)
+            if (!is_finite(st.u_table[i])) return fail(BPM_E_INVALID, "u_table[%lld] not finite", i);
+        break;
+    default: return fail(BPM_E_INVALID, "unknown strain kind %d", st.kind);
+    }
+    if (d->det_lo < 0 || d->det_hi > d->nx || d->det_lo > d->det_hi)
+        return fail(BPM_E_INVALID, "detector [%d, %d) outside [0, %d]", d->det_lo, d->det_hi, d->nx);
+    if (d->precision != BPM_F64 && d->precision != BPM_F32)
+        return fail(BPM_E_INVALID, "unknown precision %d", d->precision);
+    int log2n = 0;
+    while ((1 << log2n) < d->nx) ++log2n;
+    if (log2n > max_log2n(d->precision))
+        return fail(BPM_E_UNSUPPORTED, "nx = %d above the largest size this build marches at %s (%d)", d->nx,
+                    d->precision == BPM_F32 ? "FP32" : "FP64", 1 << max_log2n(d->precision));
+    return BPM_OK;
+}
+
+static size_t elem_bytes(int prec) { return prec == BPM_F32 ? 8 : 16; }
+
+void bpm_plan::release()
+{
+    (void)hipFree(d_sc);
+    (void)hipFree(d_params);
+    (void)hipFree(d_prop);
+    (void)hipFree(d_seg);
+    (void)hipFree(d_utab);
+    (void)hipFree(d_pin);
+    (void)hipFree(d_desc1);
+    (void)hipFree(d_state);
+    (void)hipFree(d_rt);
+    d_sc = nullptr;
+    d_params = nullptr;
+    d_prop = d_utab = d_state = nullptr;
+    d_seg = nullptr;
+    d_pin = d_rt = nullptr;
+    d_desc1 = nullptr;
+}
+
+size_t bpm_plan::state_bytes() const { return 2 * (size_t)desc.nx * elem_bytes(desc.precision); }
+
+void bpm_plan::fill(SolveDesc &s, int log2e, const void *tw, int flags, int step0, int nsteps, uint64_t in_off,
+                    uint64_t out_off, int rt_index) const
+{
+    std::memset(&s, 0, sizeof s);
+    s.log2n = log2n;
+    s.nz = desc.nz;
+    s.nseg = desc.nseg;
+    s.strain_kind = desc.strain.kind;
+    s.det_lo = desc.det_lo;
+    s.det_hi = desc.det_hi;
+    s.step0 = step0;
+    s.nsteps = nsteps;
+    s.flags = flags;
+    s.opaque_zero = 0;
+    s.rt_index = rt_index;
+    s.sc = d_sc;
+    s.prop = d_prop;
+    s.tw = tw;
+    s.seg = d_seg;
+    s.utab = d_utab;
+    s.pin = d_pin;
+    s.x0 = desc.x0_um;
+    s.dx = desc.dx_um;
+    s.dz = desc.dz_um;
+    s.inv_d = 1.0 / desc.d_um;
+    s.x_ref = desc.strain.x_ref_um;
+    s.z_ref = desc.strain.z_ref_um;
+    for (int i = 0; i < 6; ++i) s.c[i] = desc.strain.c[i];
+    s.disl_k = desc.strain.b_um / (2.0 * M_PI * desc.d_um);
+    s.disl_q = 1.0 / (2.0 * (1.0 - desc.strain.nu));
+    s.in_off = in_off;
+    s.out_off = out_off;
+    (void)log2e;
+}
+
+template <typename F>
+static bpm_status dev_alloc(F **p, size_t bytes, const char *what)
+{
+    hipError_t e = hipMalloc((void **)p, std::max<size_t>(bytes, 16));
+    if (e != hipSuccess) return hip_fail(e, what);
+    return BPM_OK;
+}
+
+extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
+{
+    if (!out) return fail(BPM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    bpm_status st = validate_desc(d);
+    if (st != BPM_OK) return st;
+    if ((st = ensure_device()) != BPM_OK) return st;
+
+    bpm_plan *p = new (std::nothrow) bpm_plan();
+    if (!p) return fail(BPM_E_NOMEM, "host allocation");
+    p->desc = *d;
+    p->desc.seg = nullptr;
+    p->desc.strain.u_table = nullptr;
+    p->log2n = 0;
+    while ((1 << p->log2n) < d->nx) ++p->log2n;
+    const int prec = d->precision;
+    const size_t nx = d->nx, nz = d->nz;
+
+    auto bail = [&](bpm_status s) {
+        p->release();
+        delete p;
+        return s;
+    };
+    if ((st = dev_alloc(&p->d_sc, sizeof(PlanScalars), "plan scalars")) != BPM_OK) return bail(st);
+    if ((st = dev_alloc(&p->d_params, sizeof(PlanParams), "plan params")) != BPM_OK) return bail(st);
+    if ((st = dev_alloc(&p->d_prop, 2 * nx * elem_bytes(prec), "propagator table")) != BPM_OK) return bail(st);
+    if ((st = dev_alloc(&p->d_seg, std::max<size_t>(nz, 1) * d->nseg * 2 * sizeof(int32_t), "mask")) != BPM_OK)
+        return bail(st);
+    if ((st = dev_alloc(&p->d_pin, sizeof(double), "incident power")) != BPM_OK) return bail(st);
+    if ((st = dev_alloc(&p->d_rt, 2 * sizeof(double), "R/T")) != BPM_OK) return bail(st);
+    p->device_bytes = sizeof(PlanScalars) + sizeof(PlanParams) + 2 * nx * elem_bytes(prec) +
+                      std::max<size_t>(nz, 1) * d->nseg * 2 * sizeof(int32_t) + 3 * sizeof(double);
+
+    PlanParams pp;
+    std::memset(&pp, 0, sizeof pp);
+    pp.nx = d->nx;
+    pp.dx = d->dx_um;
+    pp.dz = d->dz_um;
+    pp.lambda = d->lambda_um;
+    pp.d = d->d_um;
+    pp.chi0x = d->chi0.re;
+    pp.chi0y = d->chi0.im;
+    pp.chihx = d->chih.re;
+    pp.chihy = d->chih.im;
+    pp.chihbx = d->chihbar.re;
+    pp.chihby = d->chihbar.im;
+    hipError_t e = hipMemcpy(p->d_params, &pp, sizeof pp, hipMemcpyHostToDevice);
+    if (e == hipSuccess && nz > 0)
+        e = hipMemcpy(p->d_seg, d->seg, nz * d->nseg * 2 * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(hip_fail(e, "plan upload"));
+    e = launch_plan_setup(p->d_params, p->d_sc, p->d_prop, prec, d->nx, nullptr);
+    if (e != hipSuccess) return bail(hip_fail(e, "plan setup kernel"));
+
+    if (d->strain.kind == BPM_STRAIN_TABLE && nz > 0) {
+        double *d_u = nullptr;
+        if ((st = dev_alloc(&d_u, nz * nx * sizeof(double), "strain staging")) != BPM_OK) return bail(st);
+        if ((st = dev_alloc(&p->d_utab, nz * nx * (prec == BPM_F32 ? 4 : 8), "strain table")) != BPM_OK) {
+            (void)hipFree(d_u);
+            return bail(st);
+        }
+        e = hipMemcpy(d_u, d->strain.u_table, nz * nx * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_utab(d_u, p->d_utab, prec, nz * nx, 1.0 / d->d_um, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        (void)hipFree(d_u);
+        if (e != hipSuccess) return bail(hip_fail(e, "strain table"));
+        p->device_bytes += nz * nx * (prec == BPM_F32 ? 4 : 8);
+    }
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return bail(hip_fail(e, "plan setup"));
+
+    const int log2e = uniform_log2e(p->log2n);
+    if ((st = twiddle_table(prec, p->log2n, log2e, &p->tw_uniform)) != BPM_OK) return bail(st);
+    march_shape(prec, p->log2n, &p->threads, &p->lds_bytes);
+
+    // single-solve launch descriptor (state at offset 0, R/T at index 0)
+    SolveDesc s;
+    p->fill(s, log2e, p->tw_uniform, SF_FIRST | SF_LAST, 0, d->nz, 0, 0, 0);
+    if ((st = dev_alloc(&p->d_desc1, sizeof s, "launch descriptor")) != BPM_OK) return bail(st);
+    e = hipMemcpy(p->d_desc1, &s, sizeof s, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(hip_fail(e, "descriptor upload"));
+    *out = p;
+    return BPM_OK;
+}
+
+extern "C" void bpm_plan_destroy(bpm_plan *p)
+{
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    p->release();
+    delete p;
+}
+
+extern "C" bpm_status bpm_plan_info_get(const bpm_plan *p, bpm_plan_info *info)
+{
+    if (!p || !info) return fail(BPM_E_INVALID, "NULL argument");
+    info->nx = p->desc.nx;
+    info->nz = p->desc.nz;
+    info->precision = p->desc.precision;
+    info->threads_per_solve = p->threads;
+    info->state_bytes = p->state_bytes();
+    info->device_bytes = p->device_bytes;
+    info->cell_steps = 2.0 * p->desc.nx * (double)p->desc.nz;
+    return BPM_OK;
+}
+
+extern "C" int32_t bpm_max_nx(int32_t precision)
+{
+    if (precision != BPM_F32 && precision != BPM_F64) return 0;
+    return 1 << max_log2n(precision);
+}
+
+extern "C" bpm_status bpm_propagate_device(bpm_plan *p, void *stream, const void *d_in, void *d_out, double *d_RT)
+{
+    if (!p || !d_in || !d_out) return fail(BPM_E_INVALID, "NULL argument");
+    hipError_t e = launch_march(p->d_desc1, 1, p->desc.precision, p->log2n, (const char *)d_in, (char *)d_out,
+                                d_RT ? d_RT : p->d_rt, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "march launch");
+    return BPM_OK;
+}
+
+// host complex128 <-> device state in plan precision
+static void pack_state(const bpm_plan *p, const bpm_complex *a, const bpm_complex *b, std::vector<char> &buf)
+{
+    const size_t nx = p->desc.nx;
+    buf.resize(p->state_bytes());
+    if (p->desc.precision == BPM_F64) {
+        double *o = (double *)buf.data();
+        for (size_t j = 0; j < nx; ++j) {
+            o[2 * j] = a[j].re;
+            o[2 * j + 1] = a[j].im;
+            o[2 * (nx + j)] = b ? b[j].re : 0.0;
+            o[2 * (nx + j) + 1] = b ? b[j].im : 0.0;
+        }
+    } else {
+        float *o = (float *)buf.data();
+        for (size_t j = 0; j < nx; ++j) {
+            o[2 * j] = (float)a[j].re;
+            o[2 * j + 1] = (float)a[j].im;
+            o[2 * (nx + j)] = b ? (float)b[j].re : 0.0f;
+            o[2 * (nx + j) + 1] = b ? (float)b[j].im : 0.0f;
+        }
+    }
+}
+
+static void unpack_state(const bpm_plan *p, const std::vector<char> &buf, bpm_complex *a, bpm_complex *b)
+{
+    const size_t nx = p->desc.nx;
+    for (size_t j = 0; j < nx; ++j) {
+        double v[4];
+        if (p->desc.precision == BPM_F64) {
+            const double *o = (const double *)buf.data();
+            v[0] = o[2 * j], v[1] = o[2 * j + 1], v[2] = o[2 * (nx + j)], v[3] = o[2 * (nx + j) + 1];
+        } else {
+            const float *o = (const float *)buf.data();
+            v[0] = o[2 * j], v[1] = o[2 * j + 1], v[2] = o[2 * (nx + j)], v[3] = o[2 * (nx + j) + 1];
+        }
+        if (a) a[j] = {v[0], v[1]};
+        if (b) b[j] = {v[2], v[3]};
+    }
+}
+
+bpm_status bpm::check_input(const bpm_plan_desc &d, const bpm_complex *a, const bpm_complex *b)
+{
+    if (!a) return fail(BPM_E_INVALID, "psi_p0 is NULL");
+    for (int j = 0; j < d.nx; ++j) {
+        if (!is_finite(a[j]) || (b && !is_finite(b[j])))
+            return fail(BPM_E_NUMERIC, "non-finite entrance envelope at j = %d", j);
+    }
+    return BPM_OK;
+}
+
+extern "C" bpm_status bpm_propagate(bpm_plan *p, const bpm_complex *psi_p0, const bpm_complex *psi_m0,
+                                    bpm_complex *psi_p_out, bpm_complex *psi_m_out, double *R, double *T)
+{
+    if (!p) return fail(BPM_E_INVALID, "plan is NULL");
+    bpm_status st = check_input(p->desc, psi_p0, psi_m0);
+    if (st != BPM_OK) return st;
+    if (!p->d_state && (st = dev_alloc(&p->d_state, p->state_bytes(), "state buffer")) != BPM_OK) return st;
+    std::vector<char> buf;
+    pack_state(p, psi_p0, psi_m0, buf);
+    hipError_t e = hipMemcpy(p->d_state, buf.data(), buf.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload");
+    if ((st = bpm_propagate_device(p, nullptr, p->d_state, p->d_state, p->d_rt)) != BPM_OK) return st;
+    double rt[2];
+    e = hipMemcpy(buf.data(), p->d_state, buf.size(), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(rt, p->d_rt, sizeof rt, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "march / download");
+    unpack_state(p, buf, psi_p_out, psi_m_out);
+    if (R) *R = rt[0];
+    if (T) *T = rt[1];
+    if (!std::isfinite(rt[0]) || !std::isfinite(rt[1])) return fail(BPM_E_NUMERIC, "non-finite R or T");
+    return BPM_OK;
+}
+
+// ------------------------------------------------------------------ batches
+bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<int> &rt_index,
+                               const std::vector<uint64_t> &in_off, const std::vector<uint64_t> &out_off,
+                               const std::vector<int> &step0, const std::vector<int> &nsteps,
+                               const std::vector<int> &flags, std::vector<Launch> &launches)
+{
+    launches.clear();
+    for (int prec : {BPM_F32, BPM_F64}) {
+        std::vector<int> idx;
+        for (int i = 0; i < n; ++i)
+            if (plans[i]->desc.precision == prec) idx.push_back(i);
+        if (idx.empty()) continue;
+        // longest first: the hardware dispatcher then balances uneven solves
+        auto cost = [&](int i) { return (double)nsteps[i] * plans[i]->desc.nx * (plans[i]->log2n + 4); };
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost(a) > cost(b); });
+        int lo = 99, hi = -1;
+        for (int i : idx) {
+            lo = std::min(lo, plans[i]->log2n);
+            hi = std::max(hi, plans[i]->log2n);
+        }
+        std::vector<std::vector<int>> groups;
+        std::vector<int> group_log2n;
+        if (lo == hi) {
+            groups.push_back(idx);
+            group_log2n.push_back(lo);
+        } else if (lo >= mixed_min_log2n(prec) && hi <= mixed_max_log2n(prec)) {
+            groups.push_back(idx);
+            group_log2n.push_back(-1);
+        } else {
+            for (int l = lo; l <= hi; ++l) {
+                std::vector<int> g;
+                for (int i : idx)
+                    if (plans[i]->log2n == l) g.push_back(i);
+                if (!g.empty()) {
+                    groups.push_back(g);
+                    group_log2n.push_back(l);
+                }
+            }
+        }
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            Launch L;
+            L.prec = prec;
+            L.uniform_log2n = group_log2n[gi];
+            std::vector<SolveDesc> descs(groups[gi].size());
+            for (size_t k = 0; k < groups[gi].size(); ++k) {
+                const int i = groups[gi][k];
+                const bpm_plan *p = plans[i];
+                const void *tw = p->tw_uniform;
+                int log2e = uniform_log2e(p->log2n);
+                if (L.uniform_log2n < 0) {
+                    log2e = mixed_log2e(prec, p->log2n);
+                    bpm_status st = twiddle_table(prec, p->log2n, log2e, &tw);
+                    if (st != BPM_OK) return st;
+                }
+                p->fill(descs[k], log2e, tw, flags[i], step0[i], nsteps[i], in_off[i], out_off[i], rt_index[i]);
+            }
+            L.n = (int)descs.size();
+            L.host = descs;
+            launches.push_back(std::move(L));
+        }
+    }
+    return BPM_OK;
+}
+
+bpm_status bpm::upload_launches(std::vector<Launch> &launches)
+{
+    for (auto &L : launches) {
+        if (!L.d_descs) {
+            L.d_cap = L.host.size();
+            hipError_t e = hipMalloc((void **)&L.d_descs, std::max<size_t>(L.d_cap, 1) * sizeof(SolveDesc));
+            if (e != hipSuccess) return hip_fail(e, "descriptor buffer");
+        }
+        hipError_t e = hipMemcpy(L.d_descs, L.host.data(), L.host.size() * sizeof(SolveDesc), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    }
+    return BPM_OK;
+}
+
+bpm_status bpm::run_launches(const std::vector<Launch> &launches, hipStream_t s, const char *in, char *out,
+                             double *rt)
+{
+    for (const auto &L : launches) {
+        hipError_t e = launch_march(L.d_descs, L.n, L.prec, L.uniform_log2n, in, out, rt, s);
+        if (e != hipSuccess) return hip_fail(e, "march launch");
+    }
+    return BPM_OK;
+}
+
+void bpm::free_launches(std::vector<Launch> &launches)
+{
+    for (auto &L : launches) (void)hipFree(L.d_descs);
+    launches.clear();
+}
+
+struct bpm_batch {
+    std::vector<bpm_plan *> plans;
+    std::vector<size_t> offsets;
+    size_t total = 0;
+    std::vector<Launch> launches;
+    double *d_rt_scratch = nullptr;
+};
+
+extern "C" bpm_status bpm_batch_create(bpm_plan *const *plans, int32_t n, bpm_batch **out)
+{
+    if (!out) return fail(BPM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n < 0 || (n > 0 && !plans)) return fail(BPM_E_INVALID, "bad plan array");
+    for (int i = 0; i < n; ++i)
+        if (!plans[i]) return fail(BPM_E_INVALID, "plan %d is NULL", i);
+    bpm_batch *b = new (std::nothrow) bpm_batch();
+    if (!b) return fail(BPM_E_NOMEM, "host allocation");
+    b->plans.assign(plans, plans + n);
+    std::vector<int> rt(n), s0(n, 0), ns(n), fl(n, SF_FIRST | SF_LAST);
+    std::vector<uint64_t> off(n);
+    for (int i = 0; i < n; ++i) {
+        b->offsets.push_back(b->total);
+        off[i] = b->total;
+        b->total += (plans[i]->state_bytes() + 255) / 256 * 256;
+        rt[i] = i;
+        ns[i] = plans[i]->desc.nz;
+    }
+    bpm_status st = build_launches(plans, n, rt, off, off, s0, ns, fl, b->launches);
+    if (st == BPM_OK) st = upload_launches(b->launches);
+    if (st == BPM_OK) {
+        hipError_t e = hipMalloc((void **)&b->d_rt_scratch, std::max(2 * n, 2) * sizeof(double));
+        if (e != hipSuccess) st = hip_fail(e, "R/T scratch");
+    }
+    if (st != BPM_OK) {
+        free_launches(b->launches);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return BPM_OK;
+}
+
+extern "C" bpm_status bpm_batch_layout(const bpm_batch *b, size_t *offsets, size_t *total_bytes)
+{
+    if (!b) return fail(BPM_E_INVALID, "batch is NULL");
+    if (offsets) std::copy(b->offsets.begin(), b->offsets.end(), offsets);
+    if (total_bytes) *total_bytes = b->total;
+    return BPM_OK;
+}
+
+extern "C" bpm_status bpm_batch_run(bpm_batch *b, void *stream, const void *d_in, void *d_out, double *d_RT)
+{
+    if (!b || !d_in || !d_out) return fail(BPM_E_INVALID, "NULL argument");
+    return run_launches(b->launches, (hipStream_t)stream, (const char *)d_in, (char *)d_out,
+                        d_RT ? d_RT : b->d_rt_scratch);
+}
+
+extern "C" void bpm_batch_destroy(bpm_batch *b)
+{
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    free_launches(b->launches);
+    (void)hipFree(b->d_rt_scratch);
+    delete b;
+}

@@ -1,0 +1,63 @@
+// bpm_api_internal.hpp — host-side objects behind the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "bpm.h"
+#include "bpm_internal.hpp"
+
+struct bpm_plan {
+    bpm_plan_desc desc{};     // copy; its array pointers are cleared
+    int log2n = 0;
+    int threads = 0;
+    size_t lds_bytes = 0;
+    size_t device_bytes = 0;
+    bpm::PlanScalars *d_sc = nullptr;
+    bpm::PlanParams *d_params = nullptr;
+    void *d_prop = nullptr;      // [2][nx] (P - 1)/nx
+    int32_t *d_seg = nullptr;    // [nz][nseg][2]
+    void *d_utab = nullptr;      // strain table (TABLE kind)
+    double *d_pin = nullptr;     // incident power
+    bpm::SolveDesc *d_desc1 = nullptr;  // single-solve descriptor
+    const void *tw_uniform = nullptr;   // shared twiddle table
+    void *d_state = nullptr;     // staging for bpm_propagate
+    double *d_rt = nullptr;      // R/T scratch
+
+    void release();
+    size_t state_bytes() const;
+    void fill(bpm::SolveDesc &s, int log2e, const void *tw, int flags, int step0, int nsteps, uint64_t in_off,
+              uint64_t out_off, int rt_index) const;
+};
+
+namespace bpm {
+
+bpm_status fail(bpm_status s, const char *fmt, ...);
+bpm_status hip_fail(hipError_t e, const char *what);
+bpm_status ensure_device();
+bpm_status validate_desc(const bpm_plan_desc *d);
+bpm_status check_input(const bpm_plan_desc &d, const bpm_complex *a, const bpm_complex *b);
+bpm_status twiddle_table(int prec, int log2n, int log2e, const void **out);
+
+// One kernel launch over a group of solves.
+struct Launch {
+    int prec = 0;
+    int uniform_log2n = -1;
+    int n = 0;
+    std::vector<SolveDesc> host;
+    SolveDesc *d_descs = nullptr;
+    size_t d_cap = 0;
+};
+
+bpm_status build_launches(bpm_plan *const *plans, int n, const std::vector<int> &rt_index,
+                          const std::vector<uint64_t> &in_off, const std::vector<uint64_t> &out_off,
+                          const std::vector<int> &step0, const std::vector<int> &nsteps,
+                          const std::vector<int> &flags, std::vector<Launch> &launches);
+bpm_status upload_launches(std::vector<Launch> &launches);
+bpm_status run_launches(const std::vector<Launch> &launches, hipStream_t s, const char *in, char *out,
+                        double *rt);
+void free_launches(std::vector<Launch> &launches);
+
+}  // namespace bpm

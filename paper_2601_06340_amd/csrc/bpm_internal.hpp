@@ -1,0 +1,79 @@
+// bpm_internal.hpp — structures shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+namespace bpm {
+
+enum Prec : int32_t { PREC_F64 = 0, PREC_F32 = 1 };
+enum StrainKind : int32_t { STRAIN_NONE = 0, STRAIN_POLY2 = 1, STRAIN_EDGE = 2, STRAIN_TABLE = 3 };
+
+// Per-plan scalars, produced on the device by the FP64 setup kernel.
+struct PlanScalars {
+    double k, h, s, c, dzh;   // 2pi/lambda, 2pi/d, h/(2k), sqrt(1-s^2), k*dz
+    double d0x, d0y;          // a0 - 1     (harmonic 0 of exp(i dzh delta_eps / 2c), minus one)
+    double apx, apy;          // a+         (harmonic +1, pairs with chi_h)
+    double amx, amy;          // a-         (harmonic -1, pairs with chi_hbar)
+    double pad[5];
+};
+
+// Inputs of the setup kernel (host-filled).
+struct PlanParams {
+    int32_t nx, pad0;
+    double dx, dz, lambda, d;
+    double chi0x, chi0y, chihx, chihy, chihbx, chihby;
+};
+
+// Flags of one solve in one launch.
+enum SolveFlags : int32_t {
+    SF_FIRST = 1,   // launch starts at z-step 0: compute the incident power
+    SF_LAST = 2     // launch ends at z-step nz: write R and T
+};
+
+// One solve inside one launch.  Host-built, copied to the device once per batch.
+struct SolveDesc {
+    int32_t log2n, nz, nseg, strain_kind;
+    int32_t det_lo, det_hi, step0, nsteps;   // run z-steps [step0, step0 + nsteps)
+    int32_t flags;
+    int32_t opaque_zero;                     // always 0 (keeps per-step table reads in the loop)
+    int32_t rt_index, pad2;                  // R,T go to RT[2*rt_index], -1 = none
+    const PlanScalars *sc;
+    const void *prop;        // [2][nx] (P - 1)/nx in solve precision
+    const void *tw;          // twiddle table of the (nx, elements-per-thread, precision) schedule
+    const int32_t *seg;      // [nz][nseg][2]
+    const void *utab;        // STRAIN_TABLE: [nz][nx] u/d reduced to [-1/2, 1/2), solve precision
+    double *pin;             // incident power (written when SF_FIRST, read when SF_LAST)
+    double x0, dx, dz, inv_d;
+    double x_ref, z_ref;
+    double c[6];             // POLY2 coefficients
+    double disl_k, disl_q;   // EDGE: b/(2 pi d), 1/(2 (1 - nu))
+    uint64_t in_off, out_off;  // byte offsets of the state in the launch's in/out buffers
+};
+
+// Elements per thread (log2) used for a given nx by the uniform-size kernels.
+constexpr int uniform_log2e(int log2n) { return log2n >= 8 ? 4 : (log2n >= 7 ? 3 : 2); }
+
+// Launchers (bpm_kernels.hip).  All return hipSuccess or the launch error.
+hipError_t launch_plan_setup(const PlanParams *d_params, PlanScalars *d_sc, void *d_prop, int prec,
+                             int nx, hipStream_t s);
+hipError_t launch_twiddles(void *d_tw, int prec, int log2n, int log2e, hipStream_t s);
+size_t twiddle_bytes(int prec, int log2n, int log2e);
+hipError_t launch_utab(const double *d_u, void *d_tab, int prec, size_t count, double inv_d,
+                       hipStream_t s);
+// March every solve of a launch.  All descs share prec; if `uniform_log2n` >= 0
+// they also share nx and use the uniform kernel, otherwise the mixed-size kernel.
+hipError_t launch_march(const SolveDesc *d_descs, int n, int prec, int uniform_log2n,
+                        const char *in_base, char *out_base, double *rt, hipStream_t s);
+// Launch shape of the uniform kernel (threads per workgroup, dynamic LDS bytes).
+void march_shape(int prec, int log2n, int *threads, size_t *lds_bytes);
+// Mixed-size kernel: elements-per-thread (log2) it uses for log2n, and its shape.
+int mixed_log2e(int prec, int log2n);
+void mixed_shape(int prec, int *threads, size_t *lds_bytes);
+int max_log2n(int prec);
+int mixed_min_log2n(int prec);
+int mixed_max_log2n(int prec);
+
+}  // namespace bpm

@@ -1,0 +1,87 @@
+// bpm_march_kernels.hpp — march kernels and their launch logic, instantiated once
+// per precision (march_f32.hip, march_f64.hip).
+#pragma once
+
+#include "bpm_march.hpp"
+
+namespace bpm {
+
+// One solve per workgroup, every solve of the launch has the same nx.
+template <typename T, int LOG2N>
+__global__ __launch_bounds__(1 << (LOG2N - uniform_log2e(LOG2N))) void k_march_uniform(
+    const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
+{
+    constexpr int LOG2E = uniform_log2e(LOG2N);
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[16];
+    const SolveDesc &d = descs[blockIdx.x];
+    March<T, LOG2N, LOG2E>::run(d, in_base, out_base, rt, reinterpret_cast<Cx<T> *>(smem), red);
+}
+
+// Mixed sizes in one launch: 512 threads per workgroup, E = nx/512.
+template <typename T>
+__global__ __launch_bounds__(1 << kMixedLog2Th) void k_march_mixed(const SolveDesc *descs, int n,
+                                                                    const char *in_base, char *out_base,
+                                                                    double *rt)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[16];
+    const SolveDesc &d = descs[blockIdx.x];
+    Cx<T> *lds = reinterpret_cast<Cx<T> *>(smem);
+    static_for<Limits<T>::mix_lo, Limits<T>::mix_hi + 1>([&](auto l) {
+        constexpr int L2 = CV(l);
+        if (d.log2n == L2) March<T, L2, L2 - kMixedLog2Th>::run(d, in_base, out_base, rt, lds, red);
+    });
+}
+
+// Launch every solve of a launch whose solves all have nx = 2^LOG2N.
+template <typename T, int LOG2N>
+hipError_t launch_uniform(const SolveDesc *d_descs, int n, const char *in_base, char *out_base, double *rt,
+                          hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    constexpr int th = 1 << (LOG2N - uniform_log2e(LOG2N));
+    const size_t lds = LdsPlan<T, LOG2N, uniform_log2e(LOG2N)>::bytes;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_uniform<T, LOG2N>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_march_uniform<T, LOG2N>), dim3(n), dim3(th), lds, s, d_descs, n, in_base, out_base, rt);
+    return hipGetLastError();
+}
+
+template <typename T>
+size_t mixed_lds_bytes()
+{
+    size_t m = 0;
+    static_for<Limits<T>::mix_lo, Limits<T>::mix_hi + 1>([&](auto l) {
+        constexpr int L2 = CV(l);
+        const size_t b = LdsPlan<T, L2, L2 - kMixedLog2Th>::bytes;
+        if (b > m) m = b;
+    });
+    return m;
+}
+
+// Launch solves of different nx (all within the mixed range) in one grid.
+template <typename T>
+hipError_t launch_mixed(const SolveDesc *d_descs, int n, const char *in_base, char *out_base, double *rt,
+                        hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const size_t lds = mixed_lds_bytes<T>();
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_mixed<T>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_march_mixed<T>, dim3(n), dim3(1 << kMixedLog2Th), lds, s, d_descs, n, in_base, out_base,
+                       rt);
+    return hipGetLastError();
+}
+
+}  // namespace bpm

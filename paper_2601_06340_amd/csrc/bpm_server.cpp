@@ -1,0 +1,412 @@
+// bpm_server.cpp — continuous-batching server over the march kernels.
+//
+// A worker thread owns every device resource of admitted solves.  Each round it
+// launches all admitted solves for up to `chunk_steps` z-steps (one uniform-size
+// launch per nx class, each on its own stream so different sizes run side by
+// side), waits, retires the solves that reached nz, and admits waiting requests
+// in arrival order while the device-memory budget and slot count allow.  A
+// solve's arithmetic is the same kernel and schedule as bpm_propagate, and its
+// state crosses chunk boundaries through HBM unchanged, so results do not
+// depend on what else is running.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "bpm.h"
+#include "bpm_api_internal.hpp"
+#include "bpm_internal.hpp"
+
+using namespace bpm;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+struct Request {
+    uint64_t ticket = 0;
+    bpm_plan_desc desc{};
+    std::vector<int32_t> seg;
+    std::vector<double> utab;
+    std::vector<bpm_complex> psi_p0, psi_m0;
+    bpm_complex *out_p = nullptr, *out_m = nullptr;
+    size_t need = 0;          // budgeted device bytes
+    bool cancel = false;
+    // running state
+    bpm_plan *plan = nullptr;
+    void *d_state = nullptr;
+    int step = 0;
+    int slot = -1;
+    // result
+    bool done = false;
+    bpm_result res{};
+};
+
+size_t estimate_bytes(const bpm_plan_desc &d)
+{
+    const size_t eb = d.precision == BPM_F32 ? 8 : 16;
+    size_t b = 2 * (size_t)d.nx * eb * 2;                           // state + propagator table
+    b += (size_t)std::max(d.nz, 1) * d.nseg * 2 * sizeof(int32_t);  // mask
+    if (d.strain.kind == BPM_STRAIN_TABLE) b += (size_t)d.nz * d.nx * (d.precision == BPM_F32 ? 4 : 8);
+    b += 4096;                                                       // scalars, descriptors
+    return b;
+}
+
+}  // namespace
+
+struct bpm_server {
+    bpm_server_desc cfg{};
+    Clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Request>> waiting;
+    std::vector<std::shared_ptr<Request>> active;
+    std::map<uint64_t, std::shared_ptr<Request>> all;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    bpm_server_stats stats{};
+    std::thread worker;
+    // worker-owned device resources
+    std::map<int, hipStream_t> streams;  // one per (prec, log2n) class
+    double *d_rt = nullptr;
+    std::vector<Launch> launches;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+    void run();
+    void finish(const std::shared_ptr<Request> &r, int status);
+    hipStream_t stream_for(int key);
+};
+
+hipStream_t bpm_server::stream_for(int key)
+{
+    auto it = streams.find(key);
+    if (it != streams.end()) return it->second;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    streams[key] = s;
+    return s;
+}
+
+// caller holds mu
+void bpm_server::finish(const std::shared_ptr<Request> &r, int status)
+{
+    r->res.status = status;
+    r->res.t_done = now();
+    r->done = true;
+    if (status == BPM_OK) stats.completed++;
+    else if (status == BPM_E_CANCELLED) stats.cancelled++;
+    else stats.failed++;
+    r->psi_p0.clear();
+    r->psi_p0.shrink_to_fit();
+    r->psi_m0.clear();
+    r->psi_m0.shrink_to_fit();
+    r->seg.clear();
+    r->seg.shrink_to_fit();
+    r->utab.clear();
+    r->utab.shrink_to_fit();
+    cv_done.notify_all();
+}
+
+void bpm_server::run()
+{
+    std::vector<char> host;
+    for (;;) {
+        std::vector<std::shared_ptr<Request>> admit_now;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            for (;;) {
+                if (stop) return;
+                // drop cancelled waiting requests
+                for (auto it = waiting.begin(); it != waiting.end();) {
+                    if ((*it)->cancel) {
+                        finish(*it, BPM_E_CANCELLED);
+                        it = waiting.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+                // admit in arrival order while slots and budget allow
+                while (!waiting.empty() && (int)active.size() + (int)admit_now.size() < cfg.max_slots &&
+                       stats.bytes_in_use + waiting.front()->need <= cfg.hbm_budget_bytes) {
+                    auto r = waiting.front();
+                    waiting.pop_front();
+                    stats.bytes_in_use += r->need;
+                    stats.peak_bytes = std::max(stats.peak_bytes, stats.bytes_in_use);
+                    admit_now.push_back(r);
+                }
+                if (!active.empty() || !admit_now.empty()) break;
+                cv_work.wait(lk);
+            }
+        }
+        // device setup of newly admitted solves (outside the lock)
+        for (auto &r : admit_now) {
+            r->desc.seg = r->seg.data();
+            r->desc.strain.u_table = r->utab.empty() ? nullptr : r->utab.data();
+            bpm_status st = bpm_plan_create(&r->desc, &r->plan);
+            if (st == BPM_OK) {
+                const size_t sb = r->plan->state_bytes();
+                hipError_t e = hipMalloc(&r->d_state, sb);
+                if (e == hipSuccess) {
+                    const size_t nx = r->desc.nx;
+                    host.resize(sb);
+                    for (size_t j = 0; j < nx; ++j) {
+                        const bpm_complex a = r->psi_p0[j];
+                        const bpm_complex b = r->psi_m0.empty() ? bpm_complex{0, 0} : r->psi_m0[j];
+                        if (r->desc.precision == BPM_F64) {
+                            double *o = (double *)host.data();
+                            o[2 * j] = a.re, o[2 * j + 1] = a.im, o[2 * (nx + j)] = b.re, o[2 * (nx + j) + 1] = b.im;
+                        } else {
+                            float *o = (float *)host.data();
+                            o[2 * j] = (float)a.re, o[2 * j + 1] = (float)a.im;
+                            o[2 * (nx + j)] = (float)b.re, o[2 * (nx + j) + 1] = (float)b.im;
+                        }
+                    }
+                    e = hipMemcpy(r->d_state, host.data(), sb, hipMemcpyHostToDevice);
+                }
+                if (e != hipSuccess) st = hip_fail(e, "server state");
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            if (st != BPM_OK) {
+                if (r->plan) bpm_plan_destroy(r->plan);
+                r->plan = nullptr;
+                (void)hipFree(r->d_state);
+                r->d_state = nullptr;
+                stats.bytes_in_use -= r->need;
+                finish(r, st);
+                continue;
+            }
+            r->res.t_admit = now();
+            stats.admitted++;
+            active.push_back(r);
+        }
+        if (active.empty()) continue;
+
+        // one round: every active solve advances min(chunk, remaining) steps
+        for (size_t i = 0; i < active.size(); ++i) active[i]->slot = (int)i;
+        std::map<int, std::vector<size_t>> cls;  // (prec, log2n) -> active indices
+        for (size_t i = 0; i < active.size(); ++i)
+            cls[active[i]->desc.precision * 64 + active[i]->plan->log2n].push_back(i);
+        free_launches(launches);
+        bool ok = true;
+        std::vector<std::pair<hipStream_t, size_t>> issued;
+        for (auto &kv : cls) {
+            const auto &ids = kv.second;
+            const int n = (int)ids.size();
+            std::vector<bpm_plan *> plans(n);
+            std::vector<int> rt(n), s0(n), ns(n), fl(n);
+            std::vector<uint64_t> off(n);
+            for (int k = 0; k < n; ++k) {
+                auto &r = active[ids[k]];
+                plans[k] = r->plan;
+                rt[k] = r->slot;
+                s0[k] = r->step;
+                ns[k] = std::min(cfg.chunk_steps, r->desc.nz - r->step);
+                fl[k] = (r->step == 0 ? SF_FIRST : 0) | (r->step + ns[k] == r->desc.nz ? SF_LAST : 0);
+                off[k] = (uint64_t)(uintptr_t)r->d_state;
+            }
+            std::vector<Launch> ls;
+            bpm_status st = build_launches(plans.data(), n, rt, off, off, s0, ns, fl, ls);
+            if (st == BPM_OK) st = upload_launches(ls);
+            if (st == BPM_OK) st = run_launches(ls, stream_for(kv.first), nullptr, nullptr, d_rt);
+            for (auto &L : ls) launches.push_back(std::move(L));
+            if (st != BPM_OK) ok = false;
+            stats.launches++;
+        }
+        for (auto &kv : streams)
+            if (hipStreamSynchronize(kv.second) != hipSuccess) ok = false;
+
+        // retire
+        std::vector<double> rt(2 * active.size());
+        if (ok && hipMemcpy(rt.data(), d_rt, rt.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+            ok = false;
+        std::vector<std::shared_ptr<Request>> keep;
+        for (auto &r : active) {
+            const int adv = std::min(cfg.chunk_steps, r->desc.nz - r->step);
+            r->step += adv;
+            bool fin = !ok || r->step >= r->desc.nz || r->cancel;
+            int status = !ok ? BPM_E_DEVICE : (r->cancel && r->step < r->desc.nz ? BPM_E_CANCELLED : BPM_OK);
+            if (fin && status == BPM_OK) {
+                const size_t sb = r->plan->state_bytes(), nx = r->desc.nx;
+                host.resize(sb);
+                if (hipMemcpy(host.data(), r->d_state, sb, hipMemcpyDeviceToHost) != hipSuccess) {
+                    status = BPM_E_DEVICE;
+                } else {
+                    for (size_t j = 0; j < nx; ++j) {
+                        double v[4];
+                        if (r->desc.precision == BPM_F64) {
+                            const double *o = (const double *)host.data();
+                            v[0] = o[2 * j], v[1] = o[2 * j + 1], v[2] = o[2 * (nx + j)], v[3] = o[2 * (nx + j) + 1];
+                        } else {
+                            const float *o = (const float *)host.data();
+                            v[0] = o[2 * j], v[1] = o[2 * j + 1], v[2] = o[2 * (nx + j)], v[3] = o[2 * (nx + j) + 1];
+                        }
+                        if (r->out_p) r->out_p[j] = {v[0], v[1]};
+                        if (r->out_m) r->out_m[j] = {v[2], v[3]};
+                    }
+                    r->res.R = rt[2 * r->slot];
+                    r->res.T = rt[2 * r->slot + 1];
+                    if (!std::isfinite(r->res.R) || !std::isfinite(r->res.T)) status = BPM_E_NUMERIC;
+                }
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            stats.cell_steps_done += 2.0 * r->desc.nx * adv;
+            if (fin) {
+                bpm_plan_destroy(r->plan);
+                r->plan = nullptr;
+                (void)hipFree(r->d_state);
+                r->d_state = nullptr;
+                stats.bytes_in_use -= r->need;
+                finish(r, status);
+            } else {
+                keep.push_back(r);
+            }
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        active.swap(keep);
+    }
+}
+
+extern "C" bpm_status bpm_server_create(const bpm_server_desc *d, bpm_server **out)
+{
+    if (!out) return fail(BPM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!d || d->chunk_steps < 1 || d->max_slots < 1 || d->hbm_budget_bytes == 0)
+        return fail(BPM_E_INVALID, "server needs chunk_steps >= 1, max_slots >= 1, a nonzero budget");
+    bpm_status st = ensure_device();
+    if (st != BPM_OK) return st;
+    bpm_server *s = new (std::nothrow) bpm_server();
+    if (!s) return fail(BPM_E_NOMEM, "host allocation");
+    s->cfg = *d;
+    s->t0 = Clock::now();
+    hipError_t e = hipMalloc((void **)&s->d_rt, 2 * (size_t)d->max_slots * sizeof(double));
+    if (e != hipSuccess) {
+        delete s;
+        return hip_fail(e, "server R/T buffer");
+    }
+    s->worker = std::thread([s] { s->run(); });
+    *out = s;
+    return BPM_OK;
+}
+
+extern "C" bpm_status bpm_batch_submit(bpm_server *s, const bpm_request *reqs, int32_t n, uint64_t *tickets)
+{
+    if (!s || (n > 0 && (!reqs || !tickets)) || n < 0) return fail(BPM_E_INVALID, "bad arguments");
+    bpm_status ret = BPM_OK;
+    std::vector<std::shared_ptr<Request>> made;
+    for (int i = 0; i < n; ++i) {
+        tickets[i] = 0;
+        const bpm_plan_desc *d = reqs[i].plan;
+        bpm_status st = validate_desc(d);
+        if (st == BPM_OK) st = check_input(*d, reqs[i].psi_p0, reqs[i].psi_m0);
+        if (st != BPM_OK) {
+            if (ret == BPM_OK) ret = st;
+            continue;
+        }
+        auto r = std::make_shared<Request>();
+        r->desc = *d;
+        r->seg.assign(d->seg, d->seg + (size_t)d->nz * d->nseg * 2);
+        if (d->strain.kind == BPM_STRAIN_TABLE) r->utab.assign(d->strain.u_table, d->strain.u_table + (size_t)d->nz * d->nx);
+        r->psi_p0.assign(reqs[i].psi_p0, reqs[i].psi_p0 + d->nx);
+        if (reqs[i].psi_m0) r->psi_m0.assign(reqs[i].psi_m0, reqs[i].psi_m0 + d->nx);
+        r->out_p = reqs[i].psi_p_out;
+        r->out_m = reqs[i].psi_m_out;
+        r->need = estimate_bytes(*d);
+        made.push_back(r);
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    size_t k = 0;
+    for (int i = 0; i < n; ++i) {
+        if (validate_desc(reqs[i].plan) != BPM_OK || check_input(*reqs[i].plan, reqs[i].psi_p0, reqs[i].psi_m0) != BPM_OK)
+            continue;
+        auto r = made[k++];
+        r->ticket = s->next_ticket++;
+        tickets[i] = r->ticket;
+        r->res.t_submit = s->now();
+        s->all[r->ticket] = r;
+        s->stats.submitted++;
+        if (r->need > s->cfg.hbm_budget_bytes) {
+            s->finish(r, BPM_E_BUDGET);
+            if (ret == BPM_OK) ret = fail(BPM_E_BUDGET, "request needs %zu bytes, budget is %zu", r->need,
+                                          s->cfg.hbm_budget_bytes);
+            continue;
+        }
+        s->waiting.push_back(r);
+    }
+    s->cv_work.notify_all();
+    return ret;
+}
+
+extern "C" bpm_status bpm_poll(bpm_server *s, uint64_t ticket, bpm_result *out)
+{
+    if (!s) return fail(BPM_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(BPM_E_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    if (!it->second->done) return BPM_E_PENDING;
+    if (out) *out = it->second->res;
+    return BPM_OK;
+}
+
+extern "C" bpm_status bpm_cancel(bpm_server *s, uint64_t ticket)
+{
+    if (!s) return fail(BPM_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(BPM_E_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    it->second->cancel = true;
+    s->cv_work.notify_all();
+    return BPM_OK;
+}
+
+extern "C" bpm_status bpm_server_stats_get(bpm_server *s, bpm_server_stats *out)
+{
+    if (!s || !out) return fail(BPM_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    return BPM_OK;
+}
+
+extern "C" bpm_status bpm_server_drain(bpm_server *s, double timeout_s)
+{
+    if (!s) return fail(BPM_E_INVALID, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto pred = [s] {
+        for (auto &kv : s->all)
+            if (!kv.second->done) return false;
+        return true;
+    };
+    if (timeout_s < 0) {
+        s->cv_done.wait(lk, pred);
+        return BPM_OK;
+    }
+    if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) return BPM_E_PENDING;
+    return BPM_OK;
+}
+
+extern "C" void bpm_server_destroy(bpm_server *s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    for (auto &r : s->active) {
+        if (r->plan) bpm_plan_destroy(r->plan);
+        (void)hipFree(r->d_state);
+    }
+    free_launches(s->launches);
+    for (auto &kv : s->streams)
+        if (kv.second) (void)hipStreamDestroy(kv.second);
+    (void)hipFree(s->d_rt);
+    delete s;
+}

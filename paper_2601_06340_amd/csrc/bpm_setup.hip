@@ -1,0 +1,249 @@
+// bpm_setup.hip — FP64 plan-setup kernels (propagator tables, coupling harmonics, twiddles, strain tables).
+#include "bpm_march.hpp"
+
+namespace bpm {
+
+// ----------------------------------------------------------------- setup kernels
+// FP64 plan setup: coupling harmonics and propagator tables (one launch per plan).
+template <typename T>
+__global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, Cx<T> *prop)
+{
+    const PlanParams P = *pp;
+    const double k = 2.0 * M_PI / P.lambda;
+    const double h = 2.0 * M_PI / P.d;
+    const double s = h / (2.0 * k);
+    const double c = sqrt(1.0 - s * s);
+    const double dzh = k * P.dz;
+    const double A = dzh / (2.0 * c);
+    const int nx = P.nx;
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // E - 1 = expm1(i A chi0) without cancellation
+        const double gx = -A * P.chi0y, gy = A * P.chi0x;  // i A chi0
+        const double eg = exp(gx), sgy = sin(gy), shalf = sin(0.5 * gy);
+        const double em1x = expm1(gx) * cos(gy) - 2.0 * shalf * shalf;
+        const double em1y = eg * sgy;
+        const double Ex = 1.0 + em1x, Ey = em1y;
+        // y = -A^2 chih chihb; J0 - 1 = sum_{m>=1} y^m/(m!)^2, G = sum_m y^m/(m!(m+1)!)
+        const double qx = P.chihx * P.chihbx - P.chihy * P.chihby;
+        const double qy = P.chihx * P.chihby + P.chihy * P.chihbx;
+        const double yx = -A * A * qx, yy = -A * A * qy;
+        double t0x = 1.0, t0y = 0.0, t1x = 1.0, t1y = 0.0;
+        double j0mx = 0.0, j0my = 0.0, gxs = 1.0, gys = 0.0;
+        for (int m = 1; m < 60; ++m) {
+            double nx0 = (t0x * yx - t0y * yy) / ((double)m * m);
+            double ny0 = (t0x * yy + t0y * yx) / ((double)m * m);
+            double nx1 = (t1x * yx - t1y * yy) / ((double)m * (m + 1));
+            double ny1 = (t1x * yy + t1y * yx) / ((double)m * (m + 1));
+            t0x = nx0; t0y = ny0; t1x = nx1; t1y = ny1;
+            j0mx += t0x; j0my += t0y; gxs += t1x; gys += t1y;
+            if (fabs(t0x) + fabs(t0y) + fabs(t1x) + fabs(t1y) < 1e-20) break;
+        }
+        // a0 - 1 = (J0 - 1) E + (E - 1)
+        sc->k = k; sc->h = h; sc->s = s; sc->c = c; sc->dzh = dzh;
+        sc->d0x = (j0mx * Ex - j0my * Ey) + em1x;
+        sc->d0y = (j0mx * Ey + j0my * Ex) + em1y;
+        // a+ = i A chih G E, a- = i A chihb G E
+        const double gex = gxs * Ex - gys * Ey, gey = gxs * Ey + gys * Ex;
+        const double cpx = -A * P.chihy, cpy = A * P.chihx;    // i A chih
+        const double cmx = -A * P.chihby, cmy = A * P.chihbx;  // i A chihb
+        sc->apx = cpx * gex - cpy * gey;
+        sc->apy = cpx * gey + cpy * gex;
+        sc->amx = cmx * gex - cmy * gey;
+        sc->amy = cmx * gey + cmy * gex;
+    }
+    if (f < nx) {
+        const int ff = f < nx / 2 ? f : f - nx;
+        const double q = 2.0 * M_PI * (double)ff / ((double)nx * P.dx * k);
+        const double invn = 1.0 / (double)nx;
+        for (int beam = 0; beam < 2; ++beam) {
+            const double sg = beam == 0 ? 1.0 : -1.0;
+            const double pq = q + sg * s;
+            double kx, ky;  // P - 1
+            if (fabs(pq) <= 1.0) {
+                const double S = sqrt(1.0 - pq * pq);
+                const double th = -dzh * (q * q + 2.0 * sg * s * q) / (S + c);
+                const double sh = sin(0.5 * th);
+                kx = -2.0 * sh * sh;
+                ky = sin(th);
+            } else {
+                const double mag = exp(-dzh * sqrt(pq * pq - 1.0));
+                kx = mag * cos(dzh * c) - 1.0;
+                ky = -mag * sin(dzh * c);
+            }
+            prop[beam * nx + f] = {(T)(kx * invn), (T)(ky * invn)};
+        }
+    }
+}
+
+// Twiddle table of one (nx, E) schedule: pass p, entry (m-1)*L + j holds
+// exp(-2 pi i j m / (L r)), m = 1..r-1, j < L.  FP64 sincospi of an exactly
+// reduced integer ratio; FP32 tables store the hi+lo split.
+template <typename T>
+__global__ void k_twiddles(Tw<T> *tw, int log2n, int log2e)
+{
+    const int REM = log2n % log2e;
+    const int P = (REM ? 1 : 0) + log2n / log2e;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    int base = 0, ll = 0;
+    for (int p = 0; p < P; ++p) {
+        const int lr = (p == P - 1 && REM) ? REM : log2e;
+        const int L = 1 << ll, r = 1 << lr;
+        const int cnt = L * (r - 1);
+        if (idx >= base && idx < base + cnt) {
+            const int m = (idx - base) / L + 1, j = (idx - base) % L;
+            const long long M = (long long)L * r;
+            const long long jm = ((long long)j * m) % M;
+            double sn, cs;
+            sincospi(-2.0 * (double)jm / (double)M, &sn, &cs);
+            if constexpr (std::is_same<T, float>::value) {
+                const float hx = (float)cs, hy = (float)sn;
+                tw[idx] = {hx, hy, (float)(cs - (double)hx), (float)(sn - (double)hy)};
+            } else {
+                tw[idx] = {cs, sn};
+            }
+        }
+        base += cnt;
+        ll += lr;
+    }
+}
+
+template <typename T>
+__global__ void k_utab(const double *u, T *tab, size_t count, double inv_d)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        const double rev = u[i] * inv_d;
+        tab[i] = (T)(rev - rint(rev));
+    }
+}
+
+// ----------------------------------------------------------------- host side
+template <typename T>
+static int tw_count(int log2n, int log2e)
+{
+    const int REM = log2n % log2e;
+    const int P = (REM ? 1 : 0) + log2n / log2e;
+    int s = 0, ll = 0;
+    for (int p = 0; p < P; ++p) {
+        const int lr = (p == P - 1 && REM) ? REM : log2e;
+        s += (1 << ll) * ((1 << lr) - 1);
+        ll += lr;
+    }
+    return s;
+}
+
+size_t twiddle_bytes(int prec, int log2n, int log2e)
+{
+    return (size_t)tw_count<float>(log2n, log2e) * 16;
+}
+
+hipError_t launch_twiddles(void *d_tw, int prec, int log2n, int log2e, hipStream_t s)
+{
+    const int cnt = tw_count<float>(log2n, log2e);
+    if (cnt == 0) return hipSuccess;
+    const int bs = 256, gs = (cnt + bs - 1) / bs;
+    if (prec == PREC_F32)
+        hipLaunchKernelGGL(k_twiddles<float>, dim3(gs), dim3(bs), 0, s, (Tw<float> *)d_tw, log2n, log2e);
+    else
+        hipLaunchKernelGGL(k_twiddles<double>, dim3(gs), dim3(bs), 0, s, (Tw<double> *)d_tw, log2n, log2e);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_setup(const PlanParams *d_params, PlanScalars *d_sc, void *d_prop, int prec, int nx,
+                             hipStream_t s)
+{
+    const int bs = 256, gs = (nx + bs - 1) / bs;
+    if (prec == PREC_F32)
+        hipLaunchKernelGGL(k_plan_setup<float>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (Cx<float> *)d_prop);
+    else
+        hipLaunchKernelGGL(k_plan_setup<double>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (Cx<double> *)d_prop);
+    return hipGetLastError();
+}
+
+hipError_t launch_utab(const double *d_u, void *d_tab, int prec, size_t count, double inv_d, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    const int bs = 256;
+    const size_t gs = (count + bs - 1) / bs;
+    if (prec == PREC_F32)
+        hipLaunchKernelGGL(k_utab<float>, dim3((unsigned)gs), dim3(bs), 0, s, d_u, (float *)d_tab, count, inv_d);
+    else
+        hipLaunchKernelGGL(k_utab<double>, dim3((unsigned)gs), dim3(bs), 0, s, d_u, (double *)d_tab, count, inv_d);
+    return hipGetLastError();
+}
+
+}  // namespace bpm
+
+// ----------------------------------------------------------------- march dispatch
+// The kernels are instantiated one translation unit per (precision, nx) by the
+// build; here only their launchers are declared.
+namespace bpm {
+
+template <typename T, int LOG2N>
+hipError_t launch_uniform(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
+template <typename T>
+hipError_t launch_mixed(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
+
+
+template <typename T>
+static hipError_t dispatch(const SolveDesc *d_descs, int n, int uniform_log2n, const char *in_base, char *out_base,
+                           double *rt, hipStream_t s)
+{
+    if (uniform_log2n < 0) return launch_mixed<T>(d_descs, n, in_base, out_base, rt, s);
+    hipError_t err = hipErrorInvalidValue;
+    static_for<Limits<T>::uni_lo, Limits<T>::uni_hi + 1>([&](auto l) {
+        if (uniform_log2n == CV(l)) err = launch_uniform<T, CV(l)>(d_descs, n, in_base, out_base, rt, s);
+    });
+    return err;
+}
+
+hipError_t launch_march(const SolveDesc *d_descs, int n, int prec, int uniform_log2n, const char *in_base,
+                        char *out_base, double *rt, hipStream_t s)
+{
+    if (prec == PREC_F32) return dispatch<float>(d_descs, n, uniform_log2n, in_base, out_base, rt, s);
+    return dispatch<double>(d_descs, n, uniform_log2n, in_base, out_base, rt, s);
+}
+
+template <typename T>
+static void shape_T(int log2n, int *threads, size_t *lds)
+{
+    *threads = 0;
+    *lds = 0;
+    static_for<Limits<T>::uni_lo, Limits<T>::uni_hi + 1>([&](auto l) {
+        constexpr int L2 = CV(l);
+        if (log2n == L2) {
+            *threads = 1 << (L2 - uniform_log2e(L2));
+            *lds = LdsPlan<T, L2, uniform_log2e(L2)>::bytes;
+        }
+    });
+}
+
+template <typename T>
+static size_t mixed_lds_T()
+{
+    size_t m = 0;
+    static_for<Limits<T>::mix_lo, Limits<T>::mix_hi + 1>([&](auto l) {
+        constexpr int L2 = CV(l);
+        const size_t b = LdsPlan<T, L2, L2 - kMixedLog2Th>::bytes;
+        if (b > m) m = b;
+    });
+    return m;
+}
+
+void march_shape(int prec, int log2n, int *threads, size_t *lds_bytes)
+{
+    if (prec == PREC_F32) shape_T<float>(log2n, threads, lds_bytes);
+    else shape_T<double>(log2n, threads, lds_bytes);
+}
+void mixed_shape(int prec, int *threads, size_t *lds_bytes)
+{
+    *threads = 1 << kMixedLog2Th;
+    *lds_bytes = prec == PREC_F32 ? mixed_lds_T<float>() : mixed_lds_T<double>();
+}
+int max_log2n(int prec) { return prec == PREC_F32 ? Limits<float>::uni_hi : Limits<double>::uni_hi; }
+int mixed_min_log2n(int prec) { return prec == PREC_F32 ? Limits<float>::mix_lo : Limits<double>::mix_lo; }
+int mixed_max_log2n(int prec) { return prec == PREC_F32 ? Limits<float>::mix_hi : Limits<double>::mix_hi; }
+int mixed_log2e(int prec, int log2n) { return log2n - kMixedLog2Th; }
+
+}  // namespace bpm

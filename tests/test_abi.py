@@ -1,0 +1,63 @@
+"""Host-side checks of the C ABI: the built library loads and exports every
+entry point that include/bpm.h declares, and the binding declares the same set.
+No compute call is made (no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bpm.h")
+LIB = os.path.join(ROOT, "paper_2601_06340_amd", "libbpm_hip.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(bpm_[a-z0-9_]+)\s*\(", src))
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("bpm_plan_create", "bpm_propagate", "bpm_batch_submit", "bpm_poll"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in sorted(declared_functions()) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    from paper_2601_06340_amd import bpm
+    assert set(bpm.SIGNATURES) == declared_functions()
+
+
+def test_synth_module_holds_no_method_arithmetic():
+    """The shared input module must not compute propagators, couplings or FFTs."""
+    import io
+    import tokenize
+    path = os.path.join(ROOT, "paper_2601_06340_amd", "synth.py")
+    code = " ".join(t.string for t in tokenize.generate_tokens(io.StringIO(open(path).read()).readline)
+                    if t.type not in (tokenize.STRING, tokenize.COMMENT)).lower()
+    for banned in ("fft", "jv", "bessel", "propagat", "oracle"):
+        assert banned not in code, banned
+
+
+def test_oracle_and_product_share_no_code():
+    """The HIP sources never include or name the oracle, and vice versa."""
+    csrc = os.path.join(ROOT, "paper_2601_06340_amd", "csrc")
+    for f in os.listdir(csrc):
+        txt = open(os.path.join(csrc, f)).read()
+        assert "oracle" not in txt.lower(), f
+    for f in ("bpm.py", "synth.py", "__init__.py", "build.py"):
+        txt = open(os.path.join(ROOT, "paper_2601_06340_amd", f)).read()
+        assert "import oracle" not in txt and "from oracle" not in txt, f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".c", ".h", ".py")):
+            txt = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "paper_2601_06340_amd" not in txt.replace("paper_2601_06340_amd.synth", ""), f
