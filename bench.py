@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput of the two-beam FFT BPM march on one MI355X.
+
+One "step" = one pass of the whole hot path over one batch: every solve of the
+workload marched through all of its z-steps (plan tables already built, entrance
+envelopes already resident in HBM).  Default workload: the Laue bent-crystal
+case, Nx = 16384, Nz = 8000, dz = 0.025 um, bend radii R = 1, 0.1, 10 m, FP32,
+85 seeded Gaussian beams per radius (255 solves, one per compute unit).
+
+Prints one JSON line (metric, value, roofline, cpu_baseline, ...).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "BPM cell-steps/s (Nx·Nz·2 beams), FP32 batched vs FP64 plain; p50/p99 solve ms"
+# MI355X: 256 CUs x 4 SIMD x 16 lanes, one FMA (2 flop) per lane per clock at 2.4 GHz.
+# The library is built without packed-FP32 instructions, so FP32 and FP64 share
+# this vector peak (the 157.3 TFLOP/s FP32 figure needs packed FP32).
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2601_06340_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def workload(name: str, beams_per_radius: int, nz_override: int | None):
+    from paper_2601_06340_amd import synth
+    if name == "bent_laue":
+        kw = {} if nz_override is None else {"nz": nz_override}
+        cases = synth.bent_laue(radii_m=(1.0, 0.1, 10.0), beams_per_radius=beams_per_radius,
+                                precision="f32", **kw)
+        cfg = {"workload": "bent_laue", "nx": 16384, "nz": cases[0][0]["nz"], "dz_um": 0.025,
+               "radii_m": [1.0, 0.1, 10.0], "beams_per_radius": beams_per_radius,
+               "solves": len(cases), "precision": "f32"}
+    elif name == "flat_bragg":
+        kw = {} if nz_override is None else {"nz": nz_override}
+        cases = synth.flat_bragg_scan(n_angles=64, precision="f64", **kw)
+        cfg = {"workload": "flat_bragg", "nx": 4096, "nz": cases[0][0]["nz"], "angles": 64,
+               "solves": 64, "precision": "f64"}
+    elif name == "td_batch":
+        cases = synth.td_batch()
+        cfg = {"workload": "td_batch", "components": len(cases), "nx": "2048..16384",
+               "nz": "1000..8000", "solves": len(cases), "precision": "f32"}
+    else:
+        raise SystemExit("unknown workload " + name)
+    return cases, cfg
+
+
+def time_batch(bpm, torch, cases, steps, warmup):
+    plans = [bpm.Plan(p) for p, _ in cases]
+    batch = bpm.Batch(plans)
+    d_in = batch.pack([(psi, None) for _, psi in cases])
+    d_out = torch.empty_like(d_in)
+    rt = torch.zeros(2 * len(plans), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    sid = stream.cuda_stream
+    for _ in range(warmup):
+        batch.run(d_in.data_ptr(), d_out.data_ptr(), rt.data_ptr(), sid)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(steps):
+        batch.run(d_in.data_ptr(), d_out.data_ptr(), rt.data_ptr(), sid)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    total_ms = ev[0].elapsed_time(ev[steps])
+    Rs = rt.cpu().numpy()
+    batch.close()
+    for p in plans:
+        p.close()
+    return per, total_ms, wall, Rs
+
+
+def fp64_plain(bpm, torch, synth):
+    """One FP64 solve alone on the GPU (the flat Bragg case: Nx 4096, Nz 2000)."""
+    p, psi = synth.flat_bragg_scan(n_angles=1, precision="f64")[0]
+    per, total, _, _ = time_batch(bpm, torch, [(p, psi)], 3, 1)
+    cs = 2.0 * p["nx"] * p["nz"]
+    return {"value": cs / (sum(per) / len(per) / 1e3), "unit": "cell-steps/s",
+            "workload": "flat_bragg Nx 4096 Nz 2000, one FP64 solve", "ms": sum(per) / len(per)}
+
+
+def cpu_baseline(cases, target_s=12.0):
+    """The FP64 oracle on the host cores over a bounded sample of the workload."""
+    import oracle
+    cores = min(16, os.cpu_count() or 1)
+    nsolve = min(cores, len(cases))
+    # size the sample: time one short solve first
+    p0, psi0 = cases[0]
+    probe = dict(p0, nz=20, seg=p0["seg"][:20])
+    t = time.perf_counter()
+    oracle.propagate(probe, psi0)
+    per_step = (time.perf_counter() - t) / 20
+    nz = max(20, min(p0["nz"], int(target_s / per_step)))
+    sample = []
+    for p, psi in cases[:nsolve]:
+        q = dict(p, nz=nz, seg=p["seg"][:nz])
+        if isinstance(q.get("strain"), dict) and q["strain"].get("kind") == "table":
+            q["strain"] = dict(q["strain"], u_table=q["strain"]["u_table"][:nz])
+        sample.append((q, psi))
+    t = time.perf_counter()
+    oracle.propagate_batch([q for q, _ in sample], [(psi, None) for _, psi in sample], nthreads=cores)
+    wall = time.perf_counter() - t
+    cs = sum(2.0 * q["nx"] * q["nz"] for q, _ in sample)
+    return {"value": cs / wall, "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
+            "sample": "%d of the %d solves, first %d of %d z-steps each, one solve per thread (%.1f s wall)"
+                      % (nsolve, len(cases), nz, p0["nz"], wall)}
+
+
+def traffic_entry(kernel: str, launch_cell_steps: float):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get(kernel)
+        if not e or e.get("source_hash") != kernel_source_hash():
+            return None
+        return (e["fetch_bytes_per_cell_step"] + e["write_bytes_per_cell_step"]) * launch_cell_steps
+    except (ValueError, KeyError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="bent_laue", choices=["bent_laue", "flat_bragg", "td_batch"])
+    ap.add_argument("--beams-per-radius", type=int, default=85)
+    ap.add_argument("--nz", type=int, default=None, help="shorter march (profiling runs only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-plain", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; every solve is independent, so N GPUs would "
+              "each march their own share of the batch (see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2601_06340_amd import bpm, synth
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if not os.path.exists(bpm.LIB_PATH):
+        from paper_2601_06340_amd import build as b
+        b.build()
+
+    if args.copy_calibration_mb:
+        nb = args.copy_calibration_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copy calibration: %d bytes read + %d bytes written per copy" % (nb, nb), file=sys.stderr)
+    cases, cfg = workload(args.workload, args.beams_per_radius, args.nz)
+    print("workload %s: %d solves" % (cfg["workload"], len(cases)), file=sys.stderr, flush=True)
+    launch_cs = sum(2.0 * p["nx"] * p["nz"] for p, _ in cases)
+    per, total_ms, wall, Rs = time_batch(bpm, torch, cases, args.steps, args.warmup)
+    ms = total_ms / args.steps
+    value = launch_cs / (ms / 1e3)
+    per_sorted = sorted(per)
+
+    def pct(q):
+        k = min(len(per_sorted) - 1, max(0, int(math.ceil(q * len(per_sorted))) - 1))
+        return per_sorted[k]
+
+    nx = cases[0][0]["nx"]
+    uniform = all(p["nx"] == nx for p, _ in cases)
+    prec = cases[0][0]["precision"]
+    kernel = ("k_march_uniform<%s,%d>" % ("float" if prec == "f32" else "double", int(math.log2(nx)))
+              if uniform else "k_march_mixed<%s>" % ("float" if prec == "f32" else "double"))
+    flop_cs = (sum((10 * math.log2(p["nx"]) + 26) * 2 * p["nx"] * p["nz"] for p, _ in cases) / launch_cs)
+    achieved = flop_cs * launch_cs / (sum(per) / len(per) / 1e3) / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / ALU_PEAK_TFLOPS, "traffic": traffic_entry(kernel, launch_cs),
+            "kernel": kernel, "flop_per_cell_step": flop_cs}
+
+    out = {"metric": METRIC, "value": value, "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": prec, "data": "synthetic", "config": cfg,
+           "latency_ms": {"p50": pct(0.5), "p99": pct(0.99), "what": "batch completion per step"},
+           "roofline": roof, "wall_s": wall}
+    if not args.no_fp64_plain:
+        out["fp64_plain"] = fp64_plain(bpm, torch, synth)
+        out["fp32_batched_over_fp64_plain"] = value / out["fp64_plain"]["value"]
+    out["R_mean"] = float(np.mean(Rs[0::2]))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cases)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

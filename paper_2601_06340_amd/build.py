@@ -33,6 +33,7 @@ HIPFLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
 # keep in sync with Limits<> in csrc/bpm_march.hpp
 UNIFORM = {"float": range(6, 15), "double": range(6, 14)}
 MIXED = ("float", "double")
+STRAIN_CLASSES = (0, 1, 2)   # none, polynomial, dislocation/table
 
 
 def _gen_units() -> list[str]:
@@ -47,17 +48,18 @@ def _gen_units() -> list[str]:
                 f.write(body)
         units.append(path)
 
-    for t, rng in UNIFORM.items():
-        for l2 in rng:
-            write("march_%s_%d.hip" % (t, l2),
+    for sc in STRAIN_CLASSES:
+        for t, rng in UNIFORM.items():
+            for l2 in rng:
+                write("march_%s_%d_sc%d.hip" % (t, l2, sc),
+                      '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
+                      "template hipError_t launch_uniform<%s, %d, %d>(const SolveDesc *, int, const char *, "
+                      "char *, double *, hipStream_t);\n}\n" % (t, l2, sc))
+        for t in MIXED:
+            write("march_mixed_%s_sc%d.hip" % (t, sc),
                   '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
-                  "template hipError_t launch_uniform<%s, %d>(const SolveDesc *, int, const char *, "
-                  "char *, double *, hipStream_t);\n}\n" % (t, l2))
-    for t in MIXED:
-        write("march_mixed_%s.hip" % t,
-              '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
-              "template hipError_t launch_mixed<%s>(const SolveDesc *, int, const char *, char *, "
-              "double *, hipStream_t);\n}\n" % t)
+                  "template hipError_t launch_mixed<%s, %d>(const SolveDesc *, int, const char *, char *, "
+                  "double *, hipStream_t);\n}\n" % (t, sc))
     return units
 
 
@@ -77,7 +79,7 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
     srcs = [os.path.join(CSRC, f) for f in ("bpm_setup.hip", "bpm_api.cpp", "bpm_server.cpp")]
     srcs += _gen_units()
     # largest units first
-    srcs.sort(key=lambda s: ("mixed" not in s, not s.endswith(("_13.hip", "_14.hip", "_12.hip"))))
+    srcs.sort(key=lambda s: ("mixed" not in s, not any(("_%d_" % k) in s for k in (12, 13, 14))))
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))

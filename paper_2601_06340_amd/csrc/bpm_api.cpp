@@ -352,7 +352,8 @@ extern "C" int32_t bpm_max_nx(int32_t precision)
 extern "C" bpm_status bpm_propagate_device(bpm_plan *p, void *stream, const void *d_in, void *d_out, double *d_RT)
 {
     if (!p || !d_in || !d_out) return fail(BPM_E_INVALID, "NULL argument");
-    hipError_t e = launch_march(p->d_desc1, 1, p->desc.precision, p->log2n, (const char *)d_in, (char *)d_out,
+    hipError_t e = launch_march(p->d_desc1, 1, p->desc.precision, p->log2n, strain_class(p->desc.strain.kind),
+                                (const char *)d_in, (char *)d_out,
                                 d_RT ? d_RT : p->d_rt, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "march launch");
     return BPM_OK;
@@ -439,10 +440,11 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
                                const std::vector<int> &flags, std::vector<Launch> &launches)
 {
     launches.clear();
-    for (int prec : {BPM_F32, BPM_F64}) {
+    for (int prec : {BPM_F32, BPM_F64})
+    for (int sc : {0, 1, 2}) {
         std::vector<int> idx;
         for (int i = 0; i < n; ++i)
-            if (plans[i]->desc.precision == prec) idx.push_back(i);
+            if (plans[i]->desc.precision == prec && strain_class(plans[i]->desc.strain.kind) == sc) idx.push_back(i);
         if (idx.empty()) continue;
         // longest first: the hardware dispatcher then balances uneven solves
         auto cost = [&](int i) { return (double)nsteps[i] * plans[i]->desc.nx * (plans[i]->log2n + 4); };
@@ -474,6 +476,7 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             Launch L;
             L.prec = prec;
+            L.sc = sc;
             L.uniform_log2n = group_log2n[gi];
             std::vector<SolveDesc> descs(groups[gi].size());
             for (size_t k = 0; k < groups[gi].size(); ++k) {
@@ -514,7 +517,7 @@ bpm_status bpm::run_launches(const std::vector<Launch> &launches, hipStream_t s,
                              double *rt)
 {
     for (const auto &L : launches) {
-        hipError_t e = launch_march(L.d_descs, L.n, L.prec, L.uniform_log2n, in, out, rt, s);
+        hipError_t e = launch_march(L.d_descs, L.n, L.prec, L.uniform_log2n, L.sc, in, out, rt, s);
         if (e != hipSuccess) return hip_fail(e, "march launch");
     }
     return BPM_OK;

@@ -44,6 +44,7 @@ bpm_status twiddle_table(int prec, int log2n, int log2e, const void **out);
 // One kernel launch over a group of solves.
 struct Launch {
     int prec = 0;
+    int sc = 0;            // strain class of every solve in the launch
     int uniform_log2n = -1;
     int n = 0;
     std::vector<SolveDesc> host;

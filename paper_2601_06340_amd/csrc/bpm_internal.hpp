@@ -11,6 +11,13 @@ namespace bpm {
 enum Prec : int32_t { PREC_F64 = 0, PREC_F32 = 1 };
 enum StrainKind : int32_t { STRAIN_NONE = 0, STRAIN_POLY2 = 1, STRAIN_EDGE = 2, STRAIN_TABLE = 3 };
 
+// Strain classes compiled as separate kernels (one straight-line coupling each).
+enum StrainClass : int { SC_NONE = 0, SC_POLY2 = 1, SC_GENERAL = 2 };
+__host__ __device__ constexpr int strain_class(int kind)
+{
+    return kind == STRAIN_NONE ? SC_NONE : kind == STRAIN_POLY2 ? SC_POLY2 : SC_GENERAL;
+}
+
 // Per-plan scalars, produced on the device by the FP64 setup kernel.
 struct PlanScalars {
     double k, h, s, c, dzh;   // 2pi/lambda, 2pi/d, h/(2k), sqrt(1-s^2), k*dz
@@ -63,9 +70,10 @@ hipError_t launch_twiddles(void *d_tw, int prec, int log2n, int log2e, hipStream
 size_t twiddle_bytes(int prec, int log2n, int log2e);
 hipError_t launch_utab(const double *d_u, void *d_tab, int prec, size_t count, double inv_d,
                        hipStream_t s);
-// March every solve of a launch.  All descs share prec; if `uniform_log2n` >= 0
-// they also share nx and use the uniform kernel, otherwise the mixed-size kernel.
-hipError_t launch_march(const SolveDesc *d_descs, int n, int prec, int uniform_log2n,
+// March every solve of a launch.  All descs share prec and strain class `sc`
+// (0 none, 1 polynomial, 2 dislocation/table); if `uniform_log2n` >= 0 they also
+// share nx and use the uniform kernel, otherwise the mixed-size kernel.
+hipError_t launch_march(const SolveDesc *d_descs, int n, int prec, int uniform_log2n, int sc,
                         const char *in_base, char *out_base, double *rt, hipStream_t s);
 // Launch shape of the uniform kernel (threads per workgroup, dynamic LDS bytes).
 void march_shape(int prec, int log2n, int *threads, size_t *lds_bytes);

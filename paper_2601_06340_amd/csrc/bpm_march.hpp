@@ -45,6 +45,30 @@ struct Cx {
     T x, y;
 };
 
+// Pointers read out of a descriptor carry no address space; these views tell
+// the compiler they point to global memory (global_load with a scalar base and
+// a 32-bit lane offset instead of 64-bit flat addresses per lane).
+template <typename X>
+using gptr = const X __attribute__((address_space(1))) *;
+template <typename X>
+__device__ __forceinline__ gptr<X> to_global(const void *p)
+{
+    return (gptr<X>)(p);
+}
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ Cx<float> gload(gptr<Cx<float>> p, size_t i)
+{
+    const f2v v = ((gptr<f2v>)p)[i];
+    return {v.x, v.y};
+}
+__device__ __forceinline__ Cx<double> gload(gptr<Cx<double>> p, size_t i)
+{
+    const d2v v = ((gptr<d2v>)p)[i];
+    return {v.x, v.y};
+}
+
 template <typename T>
 __device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>
@@ -184,6 +208,16 @@ __device__ __forceinline__ Cx<double> mul_tw_conj(Cx<double> a, const Tw<double>
 {
     return {fmaT(a.x, w.x, a.y * w.y), fmaT(a.y, w.x, -a.x * w.y)};
 }
+__device__ __forceinline__ Tw<float> gload(gptr<Tw<float>> p, size_t i)
+{
+    const f4v v = ((gptr<f4v>)p)[i];
+    return {v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ Tw<double> gload(gptr<Tw<double>> p, size_t i)
+{
+    const d2v v = ((gptr<d2v>)p)[i];
+    return {v.x, v.y};
+}
 
 // ----------------------------------------------------------------- schedule
 // N = 2^LOG2N split into passes of radix E = 2^LOG2E (remainder radix last).
@@ -261,6 +295,17 @@ __device__ __noinline__ double edge_phase_rev(double X, double Z, double k, doub
 __device__ __forceinline__ void sincospi_T(float x, float *s, float *c) { sincospif(x, s, c); }
 __device__ __forceinline__ void sincospi_T(double x, double *s, double *c) { sincospi(x, s, c); }
 
+// exp(2 pi i v) for a phase v in revolutions: reduced to [-1/2, 1/2] in FP64,
+// then evaluated in T.
+template <typename T>
+__device__ __forceinline__ Cx<T> phasor(double v)
+{
+    const double fr = v - rint(v);
+    T sn, cs;
+    sincospi_T((T)(2.0 * fr), &sn, &cs);
+    return {cs, sn};
+}
+
 // psi+ <- psi+ + d0 psi+ + bp psi-,  psi- <- psi- + d0 psi- + bm psi+   (Eq. (12))
 template <typename T>
 __device__ __forceinline__ void couple(Cx<T> &vp, Cx<T> &vm, Cx<T> d0, Cx<T> bp, Cx<T> bm)
@@ -272,7 +317,7 @@ __device__ __forceinline__ void couple(Cx<T> &vp, Cx<T> &vm, Cx<T> d0, Cx<T> bp,
           fmaT(bm.x, a.y, fmaT(bm.y, a.x, fmaT(d0.x, b.y, fmaT(d0.y, b.x, b.y))))};
 }
 
-template <typename T, int LOG2N, int LOG2E>
+template <typename T, int LOG2N, int LOG2E, int SC>
 struct March {
     using S = Sched<LOG2N, LOG2E>;
     using LP = LdsPlan<T, LOG2N, LOG2E>;
@@ -281,7 +326,7 @@ struct March {
     // ---- forward pass p, in registers: twiddle, DFT_r; output s of butterfly
     // i lands in v[i + s*E/r].
     template <int p>
-    static __device__ __forceinline__ void fwd_compute(Cx<T> *vp, Cx<T> *vm, const Tw<T> *tw, int t)
+    static __device__ __forceinline__ void fwd_compute(Cx<T> *vp, Cx<T> *vm, gptr<Tw<T>> tw, int t)
     {
         constexpr int r = 1 << S::log2r(p), EPR = E / r, L = 1 << S::log2L(p);
         static_for<0, EPR>([&](auto i) {
@@ -293,7 +338,7 @@ struct March {
             if constexpr (p > 0) {
                 const int j = (t + i * TH) & (L - 1);
                 static_for<1, r>([&](auto m) {
-                    const Tw<T> w = tw[S::twbase(p) + (m - 1) * L + j];
+                    const Tw<T> w = gload(tw, S::twbase(p) + (m - 1) * L + j);
                     ap[m] = mul_tw(ap[m], w);
                     am[m] = mul_tw(am[m], w);
                 });
@@ -308,7 +353,7 @@ struct March {
     }
 
     template <int p>
-    static __device__ __forceinline__ void inv_compute(Cx<T> *vp, Cx<T> *vm, const Tw<T> *tw, int t)
+    static __device__ __forceinline__ void inv_compute(Cx<T> *vp, Cx<T> *vm, gptr<Tw<T>> tw, int t)
     {
         constexpr int r = 1 << S::log2r(p), EPR = E / r, L = 1 << S::log2L(p);
         static_for<0, EPR>([&](auto i) {
@@ -322,7 +367,7 @@ struct March {
             if constexpr (p > 0) {
                 const int j = (t + i * TH) & (L - 1);
                 static_for<1, r>([&](auto m) {
-                    const Tw<T> w = tw[S::twbase(p) + (m - 1) * L + j];
+                    const Tw<T> w = gload(tw, S::twbase(p) + (m - 1) * L + j);
                     ap[m] = mul_tw_conj(ap[m], w);
                     am[m] = mul_tw_conj(am[m], w);
                 });
@@ -334,38 +379,63 @@ struct March {
         });
     }
 
-    // scattered positions of pass p: butterfly b = t + i*TH, output s
+    // Scattered positions of pass p: butterfly b = t + i*TH (j = b mod L,
+    // k = b / L) puts output s at j + s*L + k*L*r.  With the pad of one slot per
+    // L*r elements the padded address is (j + k*(L*r + 1)) + s*L: one base per
+    // butterfly plus compile-time offsets.
+    template <int p>
+    static __device__ __forceinline__ int scatter_base(int b)
+    {
+        constexpr int lr = S::log2r(p), ll = S::log2L(p), L = 1 << ll;
+        const int j = b & (L - 1), k = b >> ll;
+        if constexpr (S::padsh(p) >= 0) return j + k * ((1 << (ll + lr)) + 1);
+        else return j + (k << (ll + lr));
+    }
     template <int p>
     static __device__ __forceinline__ void scatter_write(Cx<T> *L0, const Cx<T> *v, int t)
     {
-        constexpr int lr = S::log2r(p), r = 1 << lr, EPR = E / r, ll = S::log2L(p), L = 1 << ll;
+        constexpr int r = 1 << S::log2r(p), EPR = E / r, L = 1 << S::log2L(p);
         static_for<0, EPR>([&](auto i) {
-            const int b = t + i * TH;
-            const int j = b & (L - 1), k = b >> ll;
-            const int base = j + (k << (ll + lr));
-            static_for<0, r>([&](auto s) { L0[padpos<S, p>(base + s * L)] = v[i + s * EPR]; });
+            Cx<T> *base = L0 + scatter_base<p>(t + i * TH);
+            static_for<0, r>([&](auto s) { base[s * L] = v[i + s * EPR]; });
         });
     }
     template <int p>
     static __device__ __forceinline__ void scatter_read(const Cx<T> *L0, Cx<T> *v, int t)
     {
-        constexpr int lr = S::log2r(p), r = 1 << lr, EPR = E / r, ll = S::log2L(p), L = 1 << ll;
+        constexpr int r = 1 << S::log2r(p), EPR = E / r, L = 1 << S::log2L(p);
         static_for<0, EPR>([&](auto i) {
-            const int b = t + i * TH;
-            const int j = b & (L - 1), k = b >> ll;
-            const int base = j + (k << (ll + lr));
-            static_for<0, r>([&](auto s) { v[i + s * EPR] = L0[padpos<S, p>(base + s * L)]; });
+            const Cx<T> *base = L0 + scatter_base<p>(t + i * TH);
+            static_for<0, r>([&](auto s) { v[i + s * EPR] = base[s * L]; });
         });
     }
+    // Column positions t + e*TH; padded: (t + t>>sh) + e*(TH + TH>>sh) when
+    // TH is a multiple of the pad period.
     template <int p>
     static __device__ __forceinline__ void column_write(Cx<T> *L0, const Cx<T> *v, int t)
     {
-        static_for<0, E>([&](auto e) { L0[padpos<S, p>(t + e * TH)] = v[e]; });
+        constexpr int sh = S::padsh(p);
+        if constexpr (sh < 0) {
+            static_for<0, E>([&](auto e) { L0[t + e * TH] = v[e]; });
+        } else if constexpr ((TH >> sh) << sh == TH) {
+            Cx<T> *base = L0 + t + (t >> sh);
+            static_for<0, E>([&](auto e) { base[e * (TH + (TH >> sh))] = v[e]; });
+        } else {
+            static_for<0, E>([&](auto e) { L0[padpos<S, p>(t + e * TH)] = v[e]; });
+        }
     }
     template <int p>
     static __device__ __forceinline__ void column_read(const Cx<T> *L0, Cx<T> *v, int t)
     {
-        static_for<0, E>([&](auto e) { v[e] = L0[padpos<S, p>(t + e * TH)]; });
+        constexpr int sh = S::padsh(p);
+        if constexpr (sh < 0) {
+            static_for<0, E>([&](auto e) { v[e] = L0[t + e * TH]; });
+        } else if constexpr ((TH >> sh) << sh == TH) {
+            const Cx<T> *base = L0 + t + (t >> sh);
+            static_for<0, E>([&](auto e) { v[e] = base[e * (TH + (TH >> sh))]; });
+        } else {
+            static_for<0, E>([&](auto e) { v[e] = L0[padpos<S, p>(t + e * TH)]; });
+        }
     }
 
     // exchange after forward pass p (slot p) / before inverse pass p (slot 2P-3-p)
@@ -427,8 +497,10 @@ struct March {
         const int t = threadIdx.x;
         const Cx<T> *in = reinterpret_cast<const Cx<T> *>(in_base + d.in_off);
         Cx<T> *out = reinterpret_cast<Cx<T> *>(out_base + d.out_off);
-        const Tw<T> *tw = reinterpret_cast<const Tw<T> *>(d.tw);
-        const Cx<T> *prop = reinterpret_cast<const Cx<T> *>(d.prop);
+        const gptr<Tw<T>> tw = to_global<Tw<T>>(d.tw);
+        const gptr<Cx<T>> prop = to_global<Cx<T>>(d.prop);
+        const gptr<int> seg = to_global<int>(d.seg);
+        const gptr<T> utab = to_global<T>(d.utab);
 
         Cx<T> vp[E], vm[E];
         static_for<0, E>([&](auto e) {
@@ -462,8 +534,14 @@ struct March {
             // cannot see through makes it re-read them each step (from L1/L2)
             // instead of pinning ~2*E constants per thread in the register file.
             const int oz = n & d.opaque_zero;
-            const Tw<T> *twn = tw + oz;
-            const Cx<T> *propn = prop + oz;
+            const gptr<Tw<T>> twn = tw + oz;
+            // a second opaque zero: the inverse passes re-read the twiddles
+            // instead of keeping the forward passes' copies alive across the step
+            const gptr<Tw<T>> twi = tw + ((n ^ 1) & d.opaque_zero);
+            const gptr<Cx<T>> propn = prop + oz;
+            // per-step opaque thread index: per-lane LDS and table offsets are
+            // recomputed in the loop instead of being hoisted and spilled
+            const int t = threadIdx.x + oz;
             // ---- Fourier-space propagation of both envelopes (Eq. (12) p+-)
             static_for<0, P>([&](auto pc) {
                 constexpr int p = CV(pc);
@@ -472,7 +550,7 @@ struct March {
             });
             static_for<0, E>([&](auto e) {
                 const int f = t + e * TH;
-                const Cx<T> kp = propn[f], km = propn[N + f];
+                const Cx<T> kp = gload(propn, f), km = gload(propn, N + f);
                 const Cx<T> a = vp[e], b = vm[e];
                 vp[e] = {fmaT(kp.x, a.x, fmaT(-kp.y, a.y, a.x * invN)),
                          fmaT(kp.x, a.y, fmaT(kp.y, a.x, a.y * invN))};
@@ -482,47 +560,58 @@ struct March {
             static_for<0, P>([&](auto pp) {
                 constexpr int p = P - 1 - CV(pp);
                 if constexpr (p + 1 < P) exchange<p, true>(vp, vm, lds, t);
-                inv_compute<p>(vp, vm, twn, t);
+                inv_compute<p>(vp, vm, twi, t);
             });
 
             // ---- real-space coupling inside the crystal (Eq. (9)-(12))
-            const int *sg = d.seg + (size_t)n * nseg * 2;
+            const gptr<int> sg = seg + (size_t)n * nseg * 2;
             const int lo0 = sg[0], hi0 = sg[1];
-            // strain: phase (revolutions) = u/d, with u a polynomial in x for this z
+            const bool all_in = (nseg == 1) & (lo0 <= 0) & (hi0 >= N);
+            auto inside_at = [&](int j) {
+                bool in = all_in | ((j >= lo0) & (j < hi0));
+                for (int k = 1; k < nseg; ++k) in |= (j >= sg[2 * k]) & (j < sg[2 * k + 1]);
+                return in;
+            };
             const double Z = n * d.dz - d.z_ref;
-            double pa = 0.0, pb = 0.0, pc = 0.0;
-            if (kind == STRAIN_POLY2) {
-                pa = (d.c[0] + Z * (d.c[2] + Z * d.c[5])) * d.inv_d;
-                pb = (d.c[1] + Z * d.c[4]) * d.inv_d;
-                pc = d.c[3] * d.inv_d;
-            }
-            if (kind == STRAIN_NONE) {
+            if constexpr (SC == SC_NONE) {
                 static_for<0, E>([&](auto e) {
-                    const int j = t + e * TH;
-                    bool inside = (j >= lo0) & (j < hi0);
-                    for (int k = 1; k < nseg; ++k) inside |= (j >= sg[2 * k]) & (j < sg[2 * k + 1]);
-                    if (inside) couple(vp[e], vm[e], d0, ap, am);
+                    if (inside_at(t + e * TH)) couple(vp[e], vm[e], d0, ap, am);
+                });
+            } else if constexpr (SC == SC_POLY2) {
+                // phase (revolutions) u/d = pa + pb X + pc X^2 along this z; along a
+                // thread's samples X_e = X_t + e D it is quadratic in e, so the
+                // phasors follow P_{e+1} = P_e Q_e, Q_{e+1} = Q_e R with P_0, Q_0, R
+                // from FP64 arguments reduced to one revolution.
+                const double pa = (d.c[0] + Z * (d.c[2] + Z * d.c[5])) * d.inv_d;
+                const double pb = (d.c[1] + Z * d.c[4]) * d.inv_d;
+                const double pc = d.c[3] * d.inv_d;
+                const double D = (double)TH * d.dx;
+                const double Xt = __builtin_fma((double)t, d.dx, X0);
+                Cx<T> P = phasor<T>(__builtin_fma(__builtin_fma(pc, Xt, pb), Xt, pa));
+                Cx<T> Q = phasor<T>(__builtin_fma(pc, __builtin_fma(2.0 * Xt, D, D * D), pb * D));
+                const Cx<T> Rr = phasor<T>(2.0 * pc * D * D);
+                static_for<0, E>([&](auto e) {
+                    if (inside_at(t + e * TH)) {
+                        const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
+                        const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
+                        couple(vp[e], vm[e], d0, bp, bm);
+                    }
+                    if constexpr (CV(e) + 1 < E) {
+                        P = {fmaT(P.x, Q.x, -P.y * Q.y), fmaT(P.x, Q.y, P.y * Q.x)};
+                        Q = {fmaT(Q.x, Rr.x, -Q.y * Rr.y), fmaT(Q.x, Rr.y, Q.y * Rr.x)};
+                    }
                 });
             } else {
                 static_for<0, E>([&](auto e) {
                     const int j = t + e * TH;
-                    bool inside = (j >= lo0) & (j < hi0);
-                    for (int k = 1; k < nseg; ++k) inside |= (j >= sg[2 * k]) & (j < sg[2 * k + 1]);
-                    if (inside) {
-                        double rev;
-                        if (kind == STRAIN_POLY2) {
-                            const double X = __builtin_fma((double)j, d.dx, X0);
-                            rev = __builtin_fma(__builtin_fma(pc, X, pb), X, pa);
-                        } else if (kind == STRAIN_EDGE) {
-                            rev = edge_phase_rev(__builtin_fma((double)j, d.dx, X0), Z, d.disl_k, d.disl_q);
-                        } else {
-                            rev = (double)reinterpret_cast<const T *>(d.utab)[(size_t)n * N + j];
-                        }
-                        const double fr = rev - rint(rev);
-                        T sn, cs;
-                        sincospi_T((T)(2.0 * fr), &sn, &cs);
-                        const Cx<T> bp = {fmaT(ap.x, cs, -ap.y * sn), fmaT(ap.x, sn, ap.y * cs)};
-                        const Cx<T> bm = {fmaT(am.x, cs, am.y * sn), fmaT(am.y, cs, -am.x * sn)};
+                    if (inside_at(j)) {
+                        const double rev = kind == STRAIN_EDGE
+                                               ? edge_phase_rev(__builtin_fma((double)j, d.dx, X0), Z, d.disl_k,
+                                                                d.disl_q)
+                                               : (double)utab[(size_t)n * N + j];
+                        const Cx<T> P = phasor<T>(rev);
+                        const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
+                        const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
                         couple(vp[e], vm[e], d0, bp, bm);
                     }
                 });

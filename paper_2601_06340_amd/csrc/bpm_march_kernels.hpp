@@ -7,7 +7,7 @@
 namespace bpm {
 
 // One solve per workgroup, every solve of the launch has the same nx.
-template <typename T, int LOG2N>
+template <typename T, int LOG2N, int SC>
 __global__ __launch_bounds__(1 << (LOG2N - uniform_log2e(LOG2N))) void k_march_uniform(
     const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
 {
@@ -15,11 +15,11 @@ __global__ __launch_bounds__(1 << (LOG2N - uniform_log2e(LOG2N))) void k_march_u
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[16];
     const SolveDesc &d = descs[blockIdx.x];
-    March<T, LOG2N, LOG2E>::run(d, in_base, out_base, rt, reinterpret_cast<Cx<T> *>(smem), red);
+    March<T, LOG2N, LOG2E, SC>::run(d, in_base, out_base, rt, reinterpret_cast<Cx<T> *>(smem), red);
 }
 
 // Mixed sizes in one launch: 512 threads per workgroup, E = nx/512.
-template <typename T>
+template <typename T, int SC>
 __global__ __launch_bounds__(1 << kMixedLog2Th) void k_march_mixed(const SolveDesc *descs, int n,
                                                                     const char *in_base, char *out_base,
                                                                     double *rt)
@@ -30,12 +30,12 @@ __global__ __launch_bounds__(1 << kMixedLog2Th) void k_march_mixed(const SolveDe
     Cx<T> *lds = reinterpret_cast<Cx<T> *>(smem);
     static_for<Limits<T>::mix_lo, Limits<T>::mix_hi + 1>([&](auto l) {
         constexpr int L2 = CV(l);
-        if (d.log2n == L2) March<T, L2, L2 - kMixedLog2Th>::run(d, in_base, out_base, rt, lds, red);
+        if (d.log2n == L2) March<T, L2, L2 - kMixedLog2Th, SC>::run(d, in_base, out_base, rt, lds, red);
     });
 }
 
 // Launch every solve of a launch whose solves all have nx = 2^LOG2N.
-template <typename T, int LOG2N>
+template <typename T, int LOG2N, int SC>
 hipError_t launch_uniform(const SolveDesc *d_descs, int n, const char *in_base, char *out_base, double *rt,
                           hipStream_t s)
 {
@@ -44,12 +44,12 @@ hipError_t launch_uniform(const SolveDesc *d_descs, int n, const char *in_base, 
     const size_t lds = LdsPlan<T, LOG2N, uniform_log2e(LOG2N)>::bytes;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_uniform<T, LOG2N>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_uniform<T, LOG2N, SC>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_march_uniform<T, LOG2N>), dim3(n), dim3(th), lds, s, d_descs, n, in_base, out_base, rt);
+    hipLaunchKernelGGL((k_march_uniform<T, LOG2N, SC>), dim3(n), dim3(th), lds, s, d_descs, n, in_base, out_base, rt);
     return hipGetLastError();
 }
 
@@ -66,7 +66,7 @@ size_t mixed_lds_bytes()
 }
 
 // Launch solves of different nx (all within the mixed range) in one grid.
-template <typename T>
+template <typename T, int SC>
 hipError_t launch_mixed(const SolveDesc *d_descs, int n, const char *in_base, char *out_base, double *rt,
                         hipStream_t s)
 {
@@ -74,12 +74,12 @@ hipError_t launch_mixed(const SolveDesc *d_descs, int n, const char *in_base, ch
     const size_t lds = mixed_lds_bytes<T>();
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_mixed<T>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_mixed<T, SC>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_march_mixed<T>, dim3(n), dim3(1 << kMixedLog2Th), lds, s, d_descs, n, in_base, out_base,
+    hipLaunchKernelGGL((k_march_mixed<T, SC>), dim3(n), dim3(1 << kMixedLog2Th), lds, s, d_descs, n, in_base, out_base,
                        rt);
     return hipGetLastError();
 }

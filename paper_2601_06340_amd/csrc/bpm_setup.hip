@@ -180,29 +180,38 @@ hipError_t launch_utab(const double *d_u, void *d_tab, int prec, size_t count, d
 // build; here only their launchers are declared.
 namespace bpm {
 
-template <typename T, int LOG2N>
+template <typename T, int LOG2N, int SC>
 hipError_t launch_uniform(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
-template <typename T>
+template <typename T, int SC>
 hipError_t launch_mixed(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
 
 
-template <typename T>
+template <typename T, int SC>
 static hipError_t dispatch(const SolveDesc *d_descs, int n, int uniform_log2n, const char *in_base, char *out_base,
                            double *rt, hipStream_t s)
 {
-    if (uniform_log2n < 0) return launch_mixed<T>(d_descs, n, in_base, out_base, rt, s);
+    if (uniform_log2n < 0) return launch_mixed<T, SC>(d_descs, n, in_base, out_base, rt, s);
     hipError_t err = hipErrorInvalidValue;
     static_for<Limits<T>::uni_lo, Limits<T>::uni_hi + 1>([&](auto l) {
-        if (uniform_log2n == CV(l)) err = launch_uniform<T, CV(l)>(d_descs, n, in_base, out_base, rt, s);
+        if (uniform_log2n == CV(l)) err = launch_uniform<T, CV(l), SC>(d_descs, n, in_base, out_base, rt, s);
     });
     return err;
 }
 
-hipError_t launch_march(const SolveDesc *d_descs, int n, int prec, int uniform_log2n, const char *in_base,
+template <typename T>
+static hipError_t dispatch_sc(const SolveDesc *d_descs, int n, int uniform_log2n, int sc, const char *in_base,
+                              char *out_base, double *rt, hipStream_t s)
+{
+    if (sc == SC_NONE) return dispatch<T, SC_NONE>(d_descs, n, uniform_log2n, in_base, out_base, rt, s);
+    if (sc == SC_POLY2) return dispatch<T, SC_POLY2>(d_descs, n, uniform_log2n, in_base, out_base, rt, s);
+    return dispatch<T, SC_GENERAL>(d_descs, n, uniform_log2n, in_base, out_base, rt, s);
+}
+
+hipError_t launch_march(const SolveDesc *d_descs, int n, int prec, int uniform_log2n, int sc, const char *in_base,
                         char *out_base, double *rt, hipStream_t s)
 {
-    if (prec == PREC_F32) return dispatch<float>(d_descs, n, uniform_log2n, in_base, out_base, rt, s);
-    return dispatch<double>(d_descs, n, uniform_log2n, in_base, out_base, rt, s);
+    if (prec == PREC_F32) return dispatch_sc<float>(d_descs, n, uniform_log2n, sc, in_base, out_base, rt, s);
+    return dispatch_sc<double>(d_descs, n, uniform_log2n, sc, in_base, out_base, rt, s);
 }
 
 template <typename T>
