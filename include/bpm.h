@@ -89,7 +89,7 @@ typedef struct bpm_plan_desc {
     double lambda_um;        /* vacuum wavelength, 0 < lambda < 2 d */
     double d_um;             /* spacing of the reflecting planes; h = 2 pi / d */
     bpm_complex chi0, chih, chihbar;  /* susceptibility harmonics 0, +h, -h (Eq. (8)) */
-    int32_t nseg;            /* mask intervals per step, >= 1 */
+    int32_t nseg;            /* mask intervals per step, 1..4 */
     const int32_t *seg;      /* [nz][nseg][2] half-open [lo, hi) index intervals; lo >= hi
                                 is empty; 0 <= lo, hi <= nx.  Copied at creation. */
     bpm_strain strain;

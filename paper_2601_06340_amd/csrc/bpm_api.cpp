@@ -135,6 +135,7 @@ bpm_status bpm::validate_desc(const bpm_plan_desc *d)
     if (!is_finite(d->chi0) || !is_finite(d->chih) || !is_finite(d->chihbar))
         return fail(BPM_E_INVALID, "susceptibilities must be finite");
     if (d->nseg < 1) return fail(BPM_E_INVALID, "nseg = %d < 1", d->nseg);
+    if (d->nseg > 4) return fail(BPM_E_UNSUPPORTED, "nseg = %d: at most 4 mask intervals per step", d->nseg);
     if (d->nz > 0 && !d->seg) return fail(BPM_E_INVALID, "seg is NULL");
     for (long long i = 0; i < (long long)d->nz * d->nseg; ++i) {
         const int lo = d->seg[2 * i], hi = d->seg[2 * i + 1];

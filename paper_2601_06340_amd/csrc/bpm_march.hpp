@@ -94,28 +94,55 @@ __host__ __device__ constexpr double cos64(int q)
 }
 __host__ __device__ constexpr double sin64(int q) { return cos64(q - 16); }
 
-// a * (c + i s) for a compile-time constant (after inlining) given in FP64.
-__device__ __forceinline__ Cx<float> cmul_const(Cx<float> a, double c, double s)
+// tan(pi k / 64), k = 0..16
+__host__ __device__ constexpr double qtan(int k)
 {
-    const float ch = (float)c, cl = (float)(c - (double)ch);
-    const float sh = (float)s, sl = (float)(s - (double)sh);
-    return {fmaT(a.x, ch, fmaT(-a.y, sh, fmaT(a.x, cl, -a.y * sl))),
-            fmaT(a.x, sh, fmaT(a.y, ch, fmaT(a.x, sl, a.y * cl)))};
+    return k == 0 ? 0
+         : k == 1 ? 0.049126849769467254
+         : k == 2 ? 0.098491403357164248
+         : k == 3 ? 0.14833598753834742
+         : k == 4 ? 0.19891236737965801
+         : k == 5 ? 0.25048696019130545
+         : k == 6 ? 0.3033466836073424
+         : k == 7 ? 0.35780572131452409
+         : k == 8 ? 0.41421356237309503
+         : k == 9 ? 0.47296477589131991
+         : k == 10 ? 0.53451113595079158
+         : k == 11 ? 0.59937693368192368
+         : k == 12 ? 0.66817863791929888
+         : k == 13 ? 0.74165054627203542
+         : k == 14 ? 0.82067879082866024
+         : k == 15 ? 0.90634716901914703
+         : 1.0;
 }
-__device__ __forceinline__ Cx<double> cmul_const(Cx<double> a, double c, double s)
-{
-    return {fmaT(a.x, c, -a.y * s), fmaT(a.x, s, a.y * c)};
-}
-// sqrt(1/2) * (a.x*cx + ..) for the odd multiples of 45 degrees.
-__device__ __forceinline__ float scale_rs2(float v)
-{
-    constexpr double r = 0.70710678118654757;
-    constexpr float rh = (float)r, rl = (float)(r - (double)rh);
-    return fmaT(v, rh, v * rl);
-}
-__device__ __forceinline__ double scale_rs2(double v) { return v * 0.70710678118654757; }
 
-// a * W^q with W = exp(-2 pi i / 64), compile-time q.
+// ---- rotations
+// FP32 rotations by a fixed angle phi are three lifting steps
+//   x += p y;  y += u x;  x += p y      (p = -tan(phi/2), u = sin(phi)),
+// with |phi| <= pi/2 after taking out an exact sign s = -1 for larger angles.
+// The same steps with (-p, -u) undo them exactly, so every inverse transform is
+// the exact inverse (in exact arithmetic) of its forward transform and the
+// rounding of p and u cannot accumulate from step to step.
+__device__ __forceinline__ Cx<float> lift(Cx<float> a, float p, float u)
+{
+    const float x1 = fmaT(p, a.y, a.x);
+    const float y1 = fmaT(u, x1, a.y);
+    return {fmaT(p, y1, x1), y1};
+}
+
+// Compile-time rotation by W^q, W = exp(-2 pi i / 64) (angle -2 pi q / 64).
+template <int Q>
+struct Rot64 {
+    static constexpr int qq = (Q & 63) > 32 ? (Q & 63) - 64 : (Q & 63);          // (-32, 32]
+    static constexpr int neg = (qq > 16 || qq < -16) ? 1 : 0;                     // exact -1 taken out
+    static constexpr int qr = neg ? (qq > 0 ? qq - 32 : qq + 32) : qq;            // [-16, 16]
+    // angle phi = -2 pi qr / 64; p = -tan(phi/2) = tan(pi qr / 64); u = sin(phi) = -sin(2 pi qr / 64)
+    static_assert(qr >= -16 && qr <= 16, "folded angle outside the tan table");
+    static constexpr double p = qr >= 0 ? qtan(qr) : -qtan(-qr);
+    static constexpr double u = -sin64(qr);
+};
+
+// a * W^QE, forward constants
 template <typename T, int QE>
 __device__ __forceinline__ Cx<T> mul_w64(Cx<T> a)
 {
@@ -124,15 +151,57 @@ __device__ __forceinline__ Cx<T> mul_w64(Cx<T> a)
     else if constexpr (q == 16) return {a.y, -a.x};
     else if constexpr (q == 32) return {-a.x, -a.y};
     else if constexpr (q == 48) return {-a.y, a.x};
-    else if constexpr (q == 8) return {scale_rs2(a.x + a.y), scale_rs2(a.y - a.x)};
-    else if constexpr (q == 24) return {scale_rs2(a.y - a.x), scale_rs2(-a.x - a.y)};
-    else if constexpr (q == 40) return {scale_rs2(-a.x - a.y), scale_rs2(a.x - a.y)};
-    else if constexpr (q == 56) return {scale_rs2(a.x - a.y), scale_rs2(a.x + a.y)};
-    else return cmul_const(a, cos64(q), -sin64(q));
+    else if constexpr (std::is_same<T, double>::value) {
+        const double c = cos64(q), s = -sin64(q);
+        return {fmaT(a.x, c, -a.y * s), fmaT(a.x, s, a.y * c)};
+    } else {
+        using R = Rot64<q>;
+        const Cx<float> r = lift(a, (float)R::p, (float)R::u);
+        if constexpr (R::neg) return {-r.x, -r.y};
+        else return r;
+    }
 }
 
-// In-register DFT of size R (forward: exp(-2 pi i ms/R); INV: conjugate, no 1/R).
-// Input and output in natural order.
+// exact inverse of mul_w64<T, QE> (FP64: multiply by the conjugate)
+template <typename T, int QE>
+__device__ __forceinline__ Cx<T> mul_w64_inv(Cx<T> a)
+{
+    constexpr int q = QE & 63;
+    if constexpr (q == 0) return a;
+    else if constexpr (q == 16) return {-a.y, a.x};
+    else if constexpr (q == 32) return {-a.x, -a.y};
+    else if constexpr (q == 48) return {a.y, -a.x};
+    else if constexpr (std::is_same<T, double>::value) {
+        const double c = cos64(q), s = sin64(q);
+        return {fmaT(a.x, c, -a.y * s), fmaT(a.x, s, a.y * c)};
+    } else {
+        using R = Rot64<q>;
+        const Cx<float> b = R::neg ? Cx<float>{-a.x, -a.y} : a;
+        return lift(b, (float)-R::p, (float)-R::u);
+    }
+}
+
+// In-register DFTs of size R in natural order.  Forward: exp(-2 pi i ms / R)
+// as R = 4 Q (inner size-Q DFTs over m2, rotations W_R^{m1 s2}, outer DFT4s).
+// Inverse: the same three stages undone in reverse order (outer, rotations,
+// inner), i.e. R times the exact inverse of the forward; no 1/R.
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(Cx<T> *a)
+{
+    Cx<T> s0 = cadd(a[0], a[2]), d0 = csub(a[0], a[2]);
+    Cx<T> s1 = cadd(a[1], a[3]), d1 = csub(a[1], a[3]);
+    Cx<T> mid = {d1.y, -d1.x};  // -i * d1
+    a[0] = cadd(s0, s1);
+    a[2] = csub(s0, s1);
+    if constexpr (!INV) {
+        a[1] = cadd(d0, mid);
+        a[3] = csub(d0, mid);
+    } else {
+        a[1] = csub(d0, mid);
+        a[3] = cadd(d0, mid);
+    }
+}
+
 template <typename T, int R, bool INV>
 struct Dft {
     static __device__ __forceinline__ void run(Cx<T> *a)
@@ -143,36 +212,41 @@ struct Dft {
             a[0] = cadd(t, a[1]);
             a[1] = csub(t, a[1]);
         } else if constexpr (R == 4) {
-            Cx<T> s0 = cadd(a[0], a[2]), d0 = csub(a[0], a[2]);
-            Cx<T> s1 = cadd(a[1], a[3]), d1 = csub(a[1], a[3]);
-            Cx<T> mid = {d1.y, -d1.x};  // -i * d1
-            a[0] = cadd(s0, s1);
-            a[2] = csub(s0, s1);
-            if constexpr (!INV) {
-                a[1] = cadd(d0, mid);
-                a[3] = csub(d0, mid);
-            } else {
-                a[1] = csub(d0, mid);
-                a[3] = cadd(d0, mid);
-            }
-        } else {
-            // R = 4 * Q: m = m1 + 4 m2, s = s2 + Q s1
+            dft4<T, INV>(a);
+        } else if constexpr (!INV) {
+            // m = m1 + 4 m2, s = s2 + Q s1
             constexpr int Q = R / 4;
             Cx<T> y[4][Q];
             static_for<0, 4>([&](auto m1) {
                 static_for<0, Q>([&](auto m2) { y[m1][m2] = a[m1 + 4 * m2]; });
-                Dft<T, Q, INV>::run(y[m1]);
+                Dft<T, Q, false>::run(y[m1]);
             });
             static_for<1, 4>([&](auto m1) {
                 static_for<1, Q>([&](auto s2) {
-                    constexpr int e = (CV(m1) * CV(s2) * (64 / R)) & 63;
-                    y[m1][s2] = mul_w64<T, INV ? (64 - e) & 63 : e>(y[m1][s2]);
+                    y[m1][s2] = mul_w64<T, (CV(m1) * CV(s2) * (64 / R)) & 63>(y[m1][s2]);
                 });
             });
             static_for<0, Q>([&](auto s2) {
                 Cx<T> z[4] = {y[0][s2], y[1][s2], y[2][s2], y[3][s2]};
-                Dft<T, 4, INV>::run(z);
+                dft4<T, false>(z);
                 static_for<0, 4>([&](auto s1) { a[s2 + Q * s1] = z[s1]; });
+            });
+        } else {
+            constexpr int Q = R / 4;
+            Cx<T> y[4][Q];
+            static_for<0, Q>([&](auto s2) {
+                Cx<T> z[4] = {a[s2], a[s2 + Q], a[s2 + 2 * Q], a[s2 + 3 * Q]};
+                dft4<T, true>(z);
+                static_for<0, 4>([&](auto m1) { y[m1][s2] = z[m1]; });
+            });
+            static_for<1, 4>([&](auto m1) {
+                static_for<1, Q>([&](auto s2) {
+                    y[m1][s2] = mul_w64_inv<T, (CV(m1) * CV(s2) * (64 / R)) & 63>(y[m1][s2]);
+                });
+            });
+            static_for<0, 4>([&](auto m1) {
+                Dft<T, Q, true>::run(y[m1]);
+                static_for<0, Q>([&](auto m2) { a[m1 + 4 * m2] = y[m1][m2]; });
             });
         }
     }
@@ -181,10 +255,12 @@ struct Dft {
 // ----------------------------------------------------------------- twiddles
 template <typename T>
 struct Tw;
+// FP32: lifting constants of the reduced angle and the exact sign (+1 or -1)
 template <>
 struct alignas(16) Tw<float> {
-    float hx, hy, lx, ly;  // w = (hx + lx) + i (hy + ly)
+    float p, u, s, pad;
 };
+// FP64: the rotation as a complex number
 template <>
 struct alignas(16) Tw<double> {
     double x, y;
@@ -192,19 +268,19 @@ struct alignas(16) Tw<double> {
 
 __device__ __forceinline__ Cx<float> mul_tw(Cx<float> a, const Tw<float> &w)
 {
-    return {fmaT(a.x, w.hx, fmaT(-a.y, w.hy, fmaT(a.x, w.lx, -a.y * w.ly))),
-            fmaT(a.x, w.hy, fmaT(a.y, w.hx, fmaT(a.x, w.ly, a.y * w.lx)))};
+    const Cx<float> r = lift(a, w.p, w.u);
+    return {r.x * w.s, r.y * w.s};
 }
-__device__ __forceinline__ Cx<float> mul_tw_conj(Cx<float> a, const Tw<float> &w)
+// exact inverse of mul_tw
+__device__ __forceinline__ Cx<float> mul_tw_inv(Cx<float> a, const Tw<float> &w)
 {
-    return {fmaT(a.x, w.hx, fmaT(a.y, w.hy, fmaT(a.x, w.lx, a.y * w.ly))),
-            fmaT(a.y, w.hx, fmaT(-a.x, w.hy, fmaT(a.y, w.lx, -a.x * w.ly)))};
+    return lift({a.x * w.s, a.y * w.s}, -w.p, -w.u);
 }
 __device__ __forceinline__ Cx<double> mul_tw(Cx<double> a, const Tw<double> &w)
 {
     return {fmaT(a.x, w.x, -a.y * w.y), fmaT(a.x, w.y, a.y * w.x)};
 }
-__device__ __forceinline__ Cx<double> mul_tw_conj(Cx<double> a, const Tw<double> &w)
+__device__ __forceinline__ Cx<double> mul_tw_inv(Cx<double> a, const Tw<double> &w)
 {
     return {fmaT(a.x, w.x, a.y * w.y), fmaT(a.y, w.x, -a.x * w.y)};
 }
@@ -266,13 +342,43 @@ __device__ __forceinline__ int padpos(int pos)
 
 constexpr size_t kLdsMax = 160 * 1024;
 
-// LDS plan: NBUF buffers, BX beams per buffer.
+// Work split of one solve: TH threads in G groups of LANES threads, E samples
+// per thread and beam; thread (g, l) holds sample g + G*l + TH*e of each beam.
+// The FFT of N = G*M points is an M-point Stockham FFT inside every group (over
+// its decimated samples, exchanging through the group's own LDS region)
+// followed, when G > 1, by one radix-G pass across the groups (the last
+// Stockham pass: twiddles W_N^{b*g}, then DFT_G).  Groups are either single
+// waves (G = TH/64; their exchanges need no workgroup barrier, only the
+// cross-group pass does) or the whole workgroup (G = 1; every exchange is a
+// workgroup barrier, double-buffered when LDS allows).
+template <int LOG2N, int LOG2E, bool WAVE_GROUPS>
+struct Geom {
+    static constexpr int N = 1 << LOG2N, E = 1 << LOG2E;
+    static constexpr int LOG2TH = LOG2N - LOG2E, TH = 1 << LOG2TH;
+    static constexpr int LOG2G = (WAVE_GROUPS && LOG2TH > 6) ? LOG2TH - 6 : 0, G = 1 << LOG2G;
+    static constexpr int LOG2LANES = LOG2TH - LOG2G, LANES = 1 << LOG2LANES;
+    static constexpr int LOG2M = LOG2N - LOG2G, M = 1 << LOG2M;
+    static constexpr bool WAVE_LOCAL = LANES <= 64;  // group exchanges stay inside one wave
+    using SW = Sched<LOG2M, LOG2E>;  // group-local schedule (its TH is LANES)
+    static_assert(SW::TH == LANES, "group-local schedule");
+    static_assert(G <= E, "the cross-group pass needs radix G <= E");
+    static constexpr int BUFM = SW::bufsz();       // padded region of one group
+    static constexpr int TWFINAL = SW::twcount();  // table base of the cross-group pass
+};
+
+// Wave groups for the sizes whose workgroup spans 8 or more waves; below that
+// the whole-workgroup FFT needs fewer passes.
+__host__ __device__ constexpr bool use_wave_groups(int log2n, int log2e) { return log2n - log2e >= 9; }
+
+// LDS: NBUF buffer sets (2 = alternate per exchange, whole-workgroup groups
+// only), BX beams per set (2 = one buffer per beam, 1 = beams in turn).
 template <typename T, int LOG2N, int LOG2E>
 struct LdsPlan {
-    using S = Sched<LOG2N, LOG2E>;
-    static constexpr size_t beam_bytes = (size_t)S::bufsz() * sizeof(Cx<T>);
-    static constexpr int NBUF = 4 * beam_bytes <= kLdsMax ? 2 : 1;
-    static constexpr int BX = 2 * beam_bytes <= kLdsMax ? 2 : 1;
+    static constexpr bool WG = use_wave_groups(LOG2N, LOG2E);
+    using G = Geom<LOG2N, LOG2E, WG>;
+    static constexpr size_t beam_bytes = (size_t)G::G * G::BUFM * sizeof(Cx<T>);
+    static constexpr int NBUF = (!G::WAVE_LOCAL && 4 * beam_bytes <= kLdsMax) ? 2 : 1;
+    static constexpr int BX = 2 * NBUF * beam_bytes <= kLdsMax ? 2 : 1;
     static constexpr size_t bytes = (size_t)NBUF * BX * beam_bytes;
     static constexpr bool fits = beam_bytes <= kLdsMax;
 };
@@ -281,28 +387,37 @@ struct LdsPlan {
 template <typename T>
 __device__ __forceinline__ T to_T(double v) { return (T)v; }
 
+// most mask intervals per z-step the kernels handle
+constexpr int kMaxSeg = 4;
+
 // Strain phase (revolutions) of a straight edge dislocation, line along y and b
-// along h (Eq. (15)): (b/d)/(2 pi) * (atan2(Z, X) + X Z / (2 (1 - nu) r^2)).
-// Kept out of line: it runs only inside the crystal of dislocation solves.
-__device__ __noinline__ double edge_phase_rev(double X, double Z, double k, double q)
+// along h (Eq. (15)): (b/d)/(2 pi) * (atan2(Z, X) + X Z / (2 (1 - nu) r^2)),
+// with X = x - x_d, Z = z - z_d formed in FP64 by the caller.  The phase is a
+// few revolutions at most, so FP32 solves evaluate it in FP32; FP64 solves in FP64.
+__device__ __forceinline__ float edge_phase_rev(float X, float Z, float k, float q)
+{
+    const float r2 = fmaT(X, X, Z * Z);
+    const float a = atan2f(Z, X) + (r2 > 0.0f ? X * Z * q / r2 : 0.0f);
+    return k * a;
+}
+__device__ __forceinline__ double edge_phase_rev(double X, double Z, double k, double q)
 {
     const double r2 = __builtin_fma(X, X, Z * Z);
-    double a = atan2(Z, X);
-    if (r2 > 0.0) a += X * Z * q / r2;
+    const double a = atan2(Z, X) + (r2 > 0.0 ? X * Z * q / r2 : 0.0);
     return k * a;
 }
 
 __device__ __forceinline__ void sincospi_T(float x, float *s, float *c) { sincospif(x, s, c); }
 __device__ __forceinline__ void sincospi_T(double x, double *s, double *c) { sincospi(x, s, c); }
 
-// exp(2 pi i v) for a phase v in revolutions: reduced to [-1/2, 1/2] in FP64,
-// then evaluated in T.
-template <typename T>
-__device__ __forceinline__ Cx<T> phasor(double v)
+// exp(2 pi i v) for a phase v in revolutions: reduced to [-1/2, 1/2] in the
+// precision of v (FP64 for large arguments), then evaluated in T.
+template <typename T, typename V>
+__device__ __forceinline__ Cx<T> phasor(V v)
 {
-    const double fr = v - rint(v);
+    const V fr = v - rint(v);
     T sn, cs;
-    sincospi_T((T)(2.0 * fr), &sn, &cs);
+    sincospi_T((T)(fr + fr), &sn, &cs);
     return {cs, sn};
 }
 
@@ -317,59 +432,74 @@ __device__ __forceinline__ void couple(Cx<T> &vp, Cx<T> &vm, Cx<T> d0, Cx<T> bp,
           fmaT(bm.x, a.y, fmaT(bm.y, a.x, fmaT(d0.x, b.y, fmaT(d0.y, b.x, b.y))))};
 }
 
-template <typename T, int LOG2N, int LOG2E, int SC>
-struct March {
-    using S = Sched<LOG2N, LOG2E>;
-    using LP = LdsPlan<T, LOG2N, LOG2E>;
-    static constexpr int N = S::N, E = S::E, TH = S::TH, P = S::P, BUF = S::bufsz();
+// Orders this wave's LDS writes before its following LDS reads (LDS executes a
+// wave's instructions in order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-    // ---- forward pass p, in registers: twiddle, DFT_r; output s of butterfly
-    // i lands in v[i + s*E/r].
-    template <int p>
-    static __device__ __forceinline__ void fwd_compute(Cx<T> *vp, Cx<T> *vm, gptr<Tw<T>> tw, int t)
+// One solve marched by the first TH of BLOCK threads (the rest only take part
+// in the workgroup barriers).
+template <typename T, int LOG2N, int LOG2E, int SC, int BLOCK = (1 << (LOG2N - LOG2E))>
+struct March {
+    using LP = LdsPlan<T, LOG2N, LOG2E>;
+    using G = typename LP::G;
+    using SW = typename G::SW;
+    static constexpr int N = G::N, E = G::E, TH = G::TH, W = G::G, LANES = G::LANES, M = G::M;
+    static constexpr int PW = SW::P, BUFM = G::BUFM;
+    static constexpr int NB = LP::NBUF, BX = LP::BX;
+    static_assert(G::WAVE_LOCAL || W == 1, "whole-workgroup groups");
+    static_assert(BLOCK >= TH, "block");
+
+    // ---- one Stockham pass over a set of threads: radix 2^LR, sub-length 2^LL,
+    // EE samples per thread, THR threads (thread tid), twiddles at tw[twb + ...]
+    template <int LR, int LL, int THR>
+    static __device__ __forceinline__ void pass_fwd(Cx<T> *vp, Cx<T> *vm, gptr<Tw<T>> tw, int twb, int tid)
     {
-        constexpr int r = 1 << S::log2r(p), EPR = E / r, L = 1 << S::log2L(p);
+        constexpr int r = 1 << LR, EPR = E / r, L = 1 << LL;
         static_for<0, EPR>([&](auto i) {
             Cx<T> ap[r], am[r];
             static_for<0, r>([&](auto m) {
                 ap[m] = vp[i + m * EPR];
                 am[m] = vm[i + m * EPR];
             });
-            if constexpr (p > 0) {
-                const int j = (t + i * TH) & (L - 1);
+            if constexpr (L > 1) {
+                const int j = (tid + i * THR) & (L - 1);
                 static_for<1, r>([&](auto m) {
-                    const Tw<T> w = gload(tw, S::twbase(p) + (m - 1) * L + j);
+                    const Tw<T> w = gload(tw, twb + (m - 1) * L + j);
                     ap[m] = mul_tw(ap[m], w);
                     am[m] = mul_tw(am[m], w);
                 });
             }
             Dft<T, r, false>::run(ap);
             Dft<T, r, false>::run(am);
-            static_for<0, r>([&](auto s) {
-                vp[i + s * EPR] = ap[s];
-                vm[i + s * EPR] = am[s];
+            static_for<0, r>([&](auto q) {
+                vp[i + q * EPR] = ap[q];
+                vm[i + q * EPR] = am[q];
             });
         });
     }
-
-    template <int p>
-    static __device__ __forceinline__ void inv_compute(Cx<T> *vp, Cx<T> *vm, gptr<Tw<T>> tw, int t)
+    template <int LR, int LL, int THR>
+    static __device__ __forceinline__ void pass_inv(Cx<T> *vp, Cx<T> *vm, gptr<Tw<T>> tw, int twb, int tid)
     {
-        constexpr int r = 1 << S::log2r(p), EPR = E / r, L = 1 << S::log2L(p);
+        constexpr int r = 1 << LR, EPR = E / r, L = 1 << LL;
         static_for<0, EPR>([&](auto i) {
             Cx<T> ap[r], am[r];
-            static_for<0, r>([&](auto s) {
-                ap[s] = vp[i + s * EPR];
-                am[s] = vm[i + s * EPR];
+            static_for<0, r>([&](auto q) {
+                ap[q] = vp[i + q * EPR];
+                am[q] = vm[i + q * EPR];
             });
             Dft<T, r, true>::run(ap);
             Dft<T, r, true>::run(am);
-            if constexpr (p > 0) {
-                const int j = (t + i * TH) & (L - 1);
+            if constexpr (L > 1) {
+                const int j = (tid + i * THR) & (L - 1);
                 static_for<1, r>([&](auto m) {
-                    const Tw<T> w = gload(tw, S::twbase(p) + (m - 1) * L + j);
-                    ap[m] = mul_tw_conj(ap[m], w);
-                    am[m] = mul_tw_conj(am[m], w);
+                    const Tw<T> w = gload(tw, twb + (m - 1) * L + j);
+                    ap[m] = mul_tw_inv(ap[m], w);
+                    am[m] = mul_tw_inv(am[m], w);
                 });
             }
             static_for<0, r>([&](auto m) {
@@ -379,113 +509,163 @@ struct March {
         });
     }
 
-    // Scattered positions of pass p: butterfly b = t + i*TH (j = b mod L,
-    // k = b / L) puts output s at j + s*L + k*L*r.  With the pad of one slot per
-    // L*r elements the padded address is (j + k*(L*r + 1)) + s*L: one base per
-    // butterfly plus compile-time offsets.
+    // ---- wave-local exchanges (inside one wave's region; no workgroup barrier).
+    // Scattered positions of wave-local pass p: butterfly b = l + i*LANES puts
+    // output s at j + s*L + k*L*r (j = b mod L, k = b / L); with one pad slot per
+    // L*r elements that is (j + k*(L*r + 1)) + s*L.
     template <int p>
     static __device__ __forceinline__ int scatter_base(int b)
     {
-        constexpr int lr = S::log2r(p), ll = S::log2L(p), L = 1 << ll;
+        constexpr int lr = SW::log2r(p), ll = SW::log2L(p), L = 1 << ll;
         const int j = b & (L - 1), k = b >> ll;
-        if constexpr (S::padsh(p) >= 0) return j + k * ((1 << (ll + lr)) + 1);
+        if constexpr (SW::padsh(p) >= 0) return j + k * ((1 << (ll + lr)) + 1);
         else return j + (k << (ll + lr));
     }
     template <int p>
-    static __device__ __forceinline__ void scatter_write(Cx<T> *L0, const Cx<T> *v, int t)
+    static __device__ __forceinline__ void scatter_write(Cx<T> *R0, const Cx<T> *v, int l)
     {
-        constexpr int r = 1 << S::log2r(p), EPR = E / r, L = 1 << S::log2L(p);
+        constexpr int r = 1 << SW::log2r(p), EPR = E / r, L = 1 << SW::log2L(p);
         static_for<0, EPR>([&](auto i) {
-            Cx<T> *base = L0 + scatter_base<p>(t + i * TH);
-            static_for<0, r>([&](auto s) { base[s * L] = v[i + s * EPR]; });
+            Cx<T> *base = R0 + scatter_base<p>(l + i * LANES);
+            static_for<0, r>([&](auto q) { base[q * L] = v[i + q * EPR]; });
         });
     }
     template <int p>
-    static __device__ __forceinline__ void scatter_read(const Cx<T> *L0, Cx<T> *v, int t)
+    static __device__ __forceinline__ void scatter_read(const Cx<T> *R0, Cx<T> *v, int l)
     {
-        constexpr int r = 1 << S::log2r(p), EPR = E / r, L = 1 << S::log2L(p);
+        constexpr int r = 1 << SW::log2r(p), EPR = E / r, L = 1 << SW::log2L(p);
         static_for<0, EPR>([&](auto i) {
-            const Cx<T> *base = L0 + scatter_base<p>(t + i * TH);
-            static_for<0, r>([&](auto s) { v[i + s * EPR] = base[s * L]; });
+            const Cx<T> *base = R0 + scatter_base<p>(l + i * LANES);
+            static_for<0, r>([&](auto q) { v[i + q * EPR] = base[q * L]; });
         });
     }
-    // Column positions t + e*TH; padded: (t + t>>sh) + e*(TH + TH>>sh) when
-    // TH is a multiple of the pad period.
+    // column positions l + e*LANES, padded as (l + l>>sh) + e*(LANES + LANES>>sh)
     template <int p>
-    static __device__ __forceinline__ void column_write(Cx<T> *L0, const Cx<T> *v, int t)
+    static __device__ __forceinline__ void column_write(Cx<T> *R0, const Cx<T> *v, int l)
     {
-        constexpr int sh = S::padsh(p);
+        constexpr int sh = SW::padsh(p);
         if constexpr (sh < 0) {
-            static_for<0, E>([&](auto e) { L0[t + e * TH] = v[e]; });
-        } else if constexpr ((TH >> sh) << sh == TH) {
-            Cx<T> *base = L0 + t + (t >> sh);
-            static_for<0, E>([&](auto e) { base[e * (TH + (TH >> sh))] = v[e]; });
+            static_for<0, E>([&](auto e) { R0[l + e * LANES] = v[e]; });
+        } else if constexpr ((LANES >> sh) << sh == LANES) {
+            Cx<T> *base = R0 + l + (l >> sh);
+            static_for<0, E>([&](auto e) { base[e * (LANES + (LANES >> sh))] = v[e]; });
         } else {
-            static_for<0, E>([&](auto e) { L0[padpos<S, p>(t + e * TH)] = v[e]; });
+            static_for<0, E>([&](auto e) { R0[padpos<SW, p>(l + e * LANES)] = v[e]; });
         }
     }
     template <int p>
-    static __device__ __forceinline__ void column_read(const Cx<T> *L0, Cx<T> *v, int t)
+    static __device__ __forceinline__ void column_read(const Cx<T> *R0, Cx<T> *v, int l)
     {
-        constexpr int sh = S::padsh(p);
+        constexpr int sh = SW::padsh(p);
         if constexpr (sh < 0) {
-            static_for<0, E>([&](auto e) { v[e] = L0[t + e * TH]; });
-        } else if constexpr ((TH >> sh) << sh == TH) {
-            const Cx<T> *base = L0 + t + (t >> sh);
-            static_for<0, E>([&](auto e) { v[e] = base[e * (TH + (TH >> sh))]; });
+            static_for<0, E>([&](auto e) { v[e] = R0[l + e * LANES]; });
+        } else if constexpr ((LANES >> sh) << sh == LANES) {
+            const Cx<T> *base = R0 + l + (l >> sh);
+            static_for<0, E>([&](auto e) { v[e] = base[e * (LANES + (LANES >> sh))]; });
         } else {
-            static_for<0, E>([&](auto e) { v[e] = L0[padpos<S, p>(t + e * TH)]; });
+            static_for<0, E>([&](auto e) { v[e] = R0[padpos<SW, p>(l + e * LANES)]; });
         }
     }
 
-    // exchange after forward pass p (slot p) / before inverse pass p (slot 2P-3-p)
-    template <int p, bool INVDIR>
-    static __device__ __forceinline__ void exchange(Cx<T> *vp, Cx<T> *vm, Cx<T> *lds, int t)
+    // ---- cross-wave transposes: wave w's region holds its M sub-transform
+    // outputs at index k1 = l + LANES*e; the radix-W pass of butterfly
+    // b = t + i*TH reads index b of every region.
+    static __device__ __forceinline__ void write_own(Cx<T> *R0, const Cx<T> *v, int l)
     {
-        constexpr int slot = INVDIR ? 2 * P - 3 - p : p;
-        constexpr int q = slot % LP::NBUF;
-        if constexpr (LP::BX == 2) {
-            Cx<T> *Lp = lds + (q * 2 + 0) * BUF;
-            Cx<T> *Lm = lds + (q * 2 + 1) * BUF;
-            if constexpr (LP::NBUF == 1) __syncthreads();
-            if constexpr (!INVDIR) {
-                scatter_write<p>(Lp, vp, t);
-                scatter_write<p>(Lm, vm, t);
-                __syncthreads();
-                column_read<p>(Lp, vp, t);
-                column_read<p>(Lm, vm, t);
-            } else {
-                column_write<p>(Lp, vp, t);
-                column_write<p>(Lm, vm, t);
-                __syncthreads();
-                scatter_read<p>(Lp, vp, t);
-                scatter_read<p>(Lm, vm, t);
+        static_for<0, E>([&](auto e) { R0[l + e * LANES] = v[e]; });
+    }
+    static __device__ __forceinline__ void read_own(const Cx<T> *R0, Cx<T> *v, int l)
+    {
+        static_for<0, E>([&](auto e) { v[e] = R0[l + e * LANES]; });
+    }
+    static __device__ __forceinline__ void read_all(const Cx<T> *B0, Cx<T> *v, int t)
+    {
+        constexpr int EPR = E / W;
+        static_for<0, EPR>([&](auto i) {
+            static_for<0, W>([&](auto m) { v[i + m * EPR] = B0[m * BUFM + t + i * TH]; });
+        });
+    }
+    static __device__ __forceinline__ void write_all(Cx<T> *B0, const Cx<T> *v, int t)
+    {
+        constexpr int EPR = E / W;
+        static_for<0, EPR>([&](auto i) {
+            static_for<0, W>([&](auto m) { B0[m * BUFM + t + i * TH] = v[i + m * EPR]; });
+        });
+    }
+
+    // Group-local exchange after forward pass p (slot p) or before inverse pass
+    // p (slot 2*PW - 3 - p): forward writes scattered and reads columns, the
+    // inverse the other way round.  Wave groups order their own LDS accesses;
+    // whole-workgroup groups synchronise with barriers (one per exchange when
+    // two buffer sets alternate, else one before the writes as well).
+    template <int p, bool INVDIR>
+    static __device__ __forceinline__ void gx(Cx<T> *vp, Cx<T> *vm, Cx<T> *Rp0, Cx<T> *Rm0, int l, bool active)
+    {
+        constexpr int slot = INVDIR ? 2 * PW - 3 - p : p;
+        constexpr int off = (slot % NB) * BX * W * BUFM;
+        Cx<T> *Rp = Rp0 + off;
+        Cx<T> *Rm = Rm0 + off;
+        auto put = [&](Cx<T> *R, const Cx<T> *v) {
+            if constexpr (!INVDIR) scatter_write<p>(R, v, l);
+            else column_write<p>(R, v, l);
+        };
+        auto get = [&](const Cx<T> *R, Cx<T> *v) {
+            if constexpr (!INVDIR) column_read<p>(R, v, l);
+            else scatter_read<p>(R, v, l);
+        };
+        if constexpr (G::WAVE_LOCAL) {
+            if (active) {
+                if constexpr (BX == 2) {
+                    put(Rp, vp);
+                    put(Rm, vm);
+                    wave_lds_sync();
+                    get(Rp, vp);
+                    get(Rm, vm);
+                } else {
+                    put(Rp, vp);
+                    wave_lds_sync();
+                    get(Rp, vp);
+                    wave_lds_sync();
+                    put(Rp, vm);
+                    wave_lds_sync();
+                    get(Rp, vm);
+                    wave_lds_sync();
+                }
+            }
+        } else if constexpr (BX == 2) {
+            if constexpr (NB == 1) __syncthreads();
+            if (active) {
+                put(Rp, vp);
+                put(Rm, vm);
+            }
+            __syncthreads();
+            if (active) {
+                get(Rp, vp);
+                get(Rm, vm);
             }
         } else {
-            Cx<T> *L0 = lds;
-            static_for<0, 2>([&](auto beam) {
-                Cx<T> *v = beam == 0 ? vp : vm;
-                __syncthreads();
-                if constexpr (!INVDIR) scatter_write<p>(L0, v, t);
-                else column_write<p>(L0, v, t);
-                __syncthreads();
-                if constexpr (!INVDIR) column_read<p>(L0, v, t);
-                else scatter_read<p>(L0, v, t);
-            });
+            __syncthreads();
+            if (active) put(Rp, vp);
+            __syncthreads();
+            if (active) get(Rp, vp);
+            __syncthreads();
+            if (active) put(Rp, vm);
+            __syncthreads();
+            if (active) get(Rp, vm);
         }
     }
 
-    // |a|^2 sums over a thread's samples, FP64
+    // |a|^2 sums over the block, FP64, fixed order
     static __device__ __forceinline__ double block_sum(double v, double *red, int t)
     {
-        constexpr int W = TH < 64 ? TH : 64;
-        for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
-        if constexpr (TH > 64) {
+        constexpr int WB = BLOCK < 64 ? BLOCK : 64;
+        for (int off = WB / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WB);
+        if constexpr (BLOCK > 64) {
             __syncthreads();
             if ((t & 63) == 0) red[t >> 6] = v;
             __syncthreads();
             double s = 0.0;
-            for (int w = 0; w < TH / 64; ++w) s += red[w];
+            for (int w = 0; w < BLOCK / 64; ++w) s += red[w];
             v = s;
         }
         return v;
@@ -494,19 +674,29 @@ struct March {
     static __device__ void run(const SolveDesc &d, const char *in_base, char *out_base, double *rt,
                                Cx<T> *lds, double *red)
     {
-        const int t = threadIdx.x;
+        const int t0 = threadIdx.x;
+        const bool active = (BLOCK == TH) || (t0 < TH);
         const Cx<T> *in = reinterpret_cast<const Cx<T> *>(in_base + d.in_off);
         Cx<T> *out = reinterpret_cast<Cx<T> *>(out_base + d.out_off);
         const gptr<Tw<T>> tw = to_global<Tw<T>>(d.tw);
         const gptr<Cx<T>> prop = to_global<Cx<T>>(d.prop);
         const gptr<int> seg = to_global<int>(d.seg);
         const gptr<T> utab = to_global<T>(d.utab);
+        // sample index of element e of this thread: j0 + TH*e
+        const int w0 = t0 >> G::LOG2LANES, l0 = t0 & (LANES - 1);
+        const int j00 = w0 + W * l0;
+        Cx<T> *bufp = lds;
+        Cx<T> *bufm = lds + (BX == 2 ? W * BUFM : 0);
 
         Cx<T> vp[E], vm[E];
-        static_for<0, E>([&](auto e) {
-            vp[e] = in[t + e * TH];
-            vm[e] = in[N + t + e * TH];
-        });
+        if (active) {
+            static_for<0, E>([&](auto e) {
+                vp[e] = in[j00 + e * TH];
+                vm[e] = in[N + j00 + e * TH];
+            });
+        } else {
+            static_for<0, E>([&](auto e) { vp[e] = vm[e] = Cx<T>{(T)0, (T)0}; });
+        }
 
         double pin = 0.0;
         if (d.flags & SF_FIRST) {
@@ -515,8 +705,8 @@ struct March {
                 const double x = (double)vp[e].x, y = (double)vp[e].y;
                 s = __builtin_fma(x, x, __builtin_fma(y, y, s));
             });
-            pin = block_sum(s, red, t);
-            if (t == 0 && d.pin) *d.pin = pin;
+            pin = block_sum(s, red, t0);
+            if (t0 == 0 && d.pin) *d.pin = pin;
         }
 
         const PlanScalars &sc = *d.sc;
@@ -524,118 +714,176 @@ struct March {
         const Cx<T> ap = {to_T<T>(sc.apx), to_T<T>(sc.apy)};
         const Cx<T> am = {to_T<T>(sc.amx), to_T<T>(sc.amy)};
         const T invN = (T)(1.0 / (double)N);
-        const int kind = d.strain_kind;
         const int nseg = d.nseg;
         const double X0 = d.x0 - d.x_ref;
 
         const int nend = d.step0 + d.nsteps;
         for (int n = d.step0; n < nend; ++n) {
-            // The tables are loop-invariant; offsetting them by a zero the compiler
-            // cannot see through makes it re-read them each step (from L1/L2)
-            // instead of pinning ~2*E constants per thread in the register file.
+            // Opaque zeros (the compiler cannot see they are zero): the tables
+            // and per-lane offsets are re-derived each step instead of being
+            // hoisted into registers for the whole march, and the inverse
+            // passes re-read the twiddles instead of keeping the forward copies.
             const int oz = n & d.opaque_zero;
-            const gptr<Tw<T>> twn = tw + oz;
-            // a second opaque zero: the inverse passes re-read the twiddles
-            // instead of keeping the forward passes' copies alive across the step
+            const gptr<Tw<T>> twf = tw + oz;
             const gptr<Tw<T>> twi = tw + ((n ^ 1) & d.opaque_zero);
             const gptr<Cx<T>> propn = prop + oz;
-            // per-step opaque thread index: per-lane LDS and table offsets are
-            // recomputed in the loop instead of being hoisted and spilled
-            const int t = threadIdx.x + oz;
-            // ---- Fourier-space propagation of both envelopes (Eq. (12) p+-)
-            static_for<0, P>([&](auto pc) {
+            const int t = t0 + oz;
+            const int w = t >> G::LOG2LANES, l = t & (LANES - 1);
+            Cx<T> *Rp = bufp + w * BUFM;
+            Cx<T> *Rm = bufm + w * BUFM;
+
+            // ---- forward transforms (Eq. (12): F[psi+-]); group-local passes
+            static_for<0, PW>([&](auto pc) {
                 constexpr int p = CV(pc);
-                fwd_compute<p>(vp, vm, twn, t);
-                if constexpr (p + 1 < P) exchange<p, false>(vp, vm, lds, t);
+                if (active) pass_fwd<SW::log2r(p), SW::log2L(p), LANES>(vp, vm, twf, SW::twbase(p), l);
+                if constexpr (p + 1 < PW) gx<p, false>(vp, vm, Rp, Rm, l, active);
             });
-            static_for<0, E>([&](auto e) {
-                const int f = t + e * TH;
-                const Cx<T> kp = gload(propn, f), km = gload(propn, N + f);
-                const Cx<T> a = vp[e], b = vm[e];
-                vp[e] = {fmaT(kp.x, a.x, fmaT(-kp.y, a.y, a.x * invN)),
-                         fmaT(kp.x, a.y, fmaT(kp.y, a.x, a.y * invN))};
-                vm[e] = {fmaT(km.x, b.x, fmaT(-km.y, b.y, b.x * invN)),
-                         fmaT(km.x, b.y, fmaT(km.y, b.x, b.y * invN))};
-            });
-            static_for<0, P>([&](auto pp) {
-                constexpr int p = P - 1 - CV(pp);
-                if constexpr (p + 1 < P) exchange<p, true>(vp, vm, lds, t);
-                inv_compute<p>(vp, vm, twi, t);
+            // ---- cross-group radix-W pass (wave groups only)
+            if constexpr (W > 1) {
+                if (active) {
+                    write_own(Rp, vp, l);
+                    if constexpr (BX == 2) write_own(Rm, vm, l);
+                }
+                __syncthreads();
+                if (active) read_all(bufp, vp, t);
+                if constexpr (BX == 2) {
+                    if (active) read_all(bufm, vm, t);
+                } else {
+                    __syncthreads();
+                    if (active) write_own(Rm, vm, l);
+                    __syncthreads();
+                    if (active) read_all(bufm, vm, t);
+                }
+            }
+            if (active) {
+                if constexpr (W > 1) pass_fwd<G::LOG2G, G::LOG2M, TH>(vp, vm, twf, G::TWFINAL, t);
+                // ---- propagator: sample f = t + TH*e holds frequency bin f
+                static_for<0, E>([&](auto e) {
+                    const int f = t + e * TH;
+                    const Cx<T> kp = gload(propn, f), km = gload(propn, N + f);
+                    const Cx<T> a = vp[e], b = vm[e];
+                    vp[e] = {fmaT(kp.x, a.x, fmaT(-kp.y, a.y, a.x * invN)),
+                             fmaT(kp.x, a.y, fmaT(kp.y, a.x, a.y * invN))};
+                    vm[e] = {fmaT(km.x, b.x, fmaT(-km.y, b.y, b.x * invN)),
+                             fmaT(km.x, b.y, fmaT(km.y, b.x, b.y * invN))};
+                });
+                if constexpr (W > 1) pass_inv<G::LOG2G, G::LOG2M, TH>(vp, vm, twi, G::TWFINAL, t);
+            }
+            // ---- inverse transforms, the forward steps undone in reverse order
+            if constexpr (W > 1) {
+                __syncthreads();
+                if (active) {
+                    write_all(bufp, vp, t);
+                    if constexpr (BX == 2) write_all(bufm, vm, t);
+                }
+                __syncthreads();
+                if (active) read_own(Rp, vp, l);
+                if constexpr (BX == 2) {
+                    if (active) read_own(Rm, vm, l);
+                } else {
+                    __syncthreads();
+                    if (active) write_all(bufm, vm, t);
+                    __syncthreads();
+                    if (active) read_own(Rm, vm, l);
+                }
+            }
+            static_for<0, PW>([&](auto pp) {
+                constexpr int p = PW - 1 - CV(pp);
+                if constexpr (p + 1 < PW) gx<p, true>(vp, vm, Rp, Rm, l, active);
+                if (active) pass_inv<SW::log2r(p), SW::log2L(p), LANES>(vp, vm, twi, SW::twbase(p), l);
             });
 
-            // ---- real-space coupling inside the crystal (Eq. (9)-(12))
-            const gptr<int> sg = seg + (size_t)n * nseg * 2;
-            const int lo0 = sg[0], hi0 = sg[1];
-            const bool all_in = (nseg == 1) & (lo0 <= 0) & (hi0 >= N);
-            auto inside_at = [&](int j) {
-                bool in = all_in | ((j >= lo0) & (j < hi0));
-                for (int k = 1; k < nseg; ++k) in |= (j >= sg[2 * k]) & (j < sg[2 * k + 1]);
-                return in;
-            };
-            const double Z = n * d.dz - d.z_ref;
-            if constexpr (SC == SC_NONE) {
-                static_for<0, E>([&](auto e) {
-                    if (inside_at(t + e * TH)) couple(vp[e], vm[e], d0, ap, am);
+            // ---- real-space coupling inside the crystal (Eq. (9)-(12)).  Outside the
+            // crystal the step is pure propagation: the coefficients become
+            // (0, 0, 0), which leaves both envelopes untouched.
+            if (active) {
+                const int j0 = w + W * l;
+                const gptr<int> sg = seg + (size_t)n * nseg * 2;
+                int lo[kMaxSeg], hi[kMaxSeg];
+                static_for<0, kMaxSeg>([&](auto k) {
+                    lo[k] = CV(k) < nseg ? sg[2 * CV(k)] : 0;
+                    hi[k] = CV(k) < nseg ? sg[2 * CV(k) + 1] : 0;
                 });
-            } else if constexpr (SC == SC_POLY2) {
-                // phase (revolutions) u/d = pa + pb X + pc X^2 along this z; along a
-                // thread's samples X_e = X_t + e D it is quadratic in e, so the
-                // phasors follow P_{e+1} = P_e Q_e, Q_{e+1} = Q_e R with P_0, Q_0, R
-                // from FP64 arguments reduced to one revolution.
-                const double pa = (d.c[0] + Z * (d.c[2] + Z * d.c[5])) * d.inv_d;
-                const double pb = (d.c[1] + Z * d.c[4]) * d.inv_d;
-                const double pc = d.c[3] * d.inv_d;
-                const double D = (double)TH * d.dx;
-                const double Xt = __builtin_fma((double)t, d.dx, X0);
-                Cx<T> P = phasor<T>(__builtin_fma(__builtin_fma(pc, Xt, pb), Xt, pa));
-                Cx<T> Q = phasor<T>(__builtin_fma(pc, __builtin_fma(2.0 * Xt, D, D * D), pb * D));
-                const Cx<T> Rr = phasor<T>(2.0 * pc * D * D);
-                static_for<0, E>([&](auto e) {
-                    if (inside_at(t + e * TH)) {
+                const bool all_in = (nseg == 1) & (lo[0] <= 0) & (hi[0] >= N);
+                auto inside_at = [&](int j) {
+                    bool in = false;
+                    static_for<0, kMaxSeg>([&](auto k) { in |= (j >= lo[k]) & (j < hi[k]); });
+                    return in;
+                };
+                const Cx<T> zero = {(T)0, (T)0};
+                auto sel = [&](bool in, Cx<T> c) { return Cx<T>{in ? c.x : zero.x, in ? c.y : zero.y}; };
+                const double Z = n * d.dz - d.z_ref;
+                // (one straight-line copy: a separate all-inside copy costs registers)
+                if constexpr (SC == SC_NONE) {
+                    static_for<0, E>([&](auto e) {
+                        const bool in = all_in | inside_at(j0 + e * TH);
+                        couple(vp[e], vm[e], sel(in, d0), sel(in, ap), sel(in, am));
+                    });
+                } else if constexpr (SC == SC_POLY2) {
+                    // phase (revolutions) u/d = pa + pb X + pc X^2 along this z; along a
+                    // thread's samples X_e = X_0 + e D it is quadratic in e, so the
+                    // phasors follow P_{e+1} = P_e Q_e, Q_{e+1} = Q_e R with P_0, Q_0, R
+                    // from FP64 arguments reduced to one revolution.
+                    const double pa = (d.c[0] + Z * (d.c[2] + Z * d.c[5])) * d.inv_d;
+                    const double pb = (d.c[1] + Z * d.c[4]) * d.inv_d;
+                    const double pc = d.c[3] * d.inv_d;
+                    const double D = (double)TH * d.dx;
+                    const double Xt = __builtin_fma((double)j0, d.dx, X0);
+                    Cx<T> P = phasor<T>(__builtin_fma(__builtin_fma(pc, Xt, pb), Xt, pa));
+                    Cx<T> Q = phasor<T>(__builtin_fma(pc, __builtin_fma(2.0 * Xt, D, D * D), pb * D));
+                    const Cx<T> Rr = phasor<T>(2.0 * pc * D * D);
+                    auto body = [&](auto e, bool in) {
                         const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
                         const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
-                        couple(vp[e], vm[e], d0, bp, bm);
-                    }
-                    if constexpr (CV(e) + 1 < E) {
-                        P = {fmaT(P.x, Q.x, -P.y * Q.y), fmaT(P.x, Q.y, P.y * Q.x)};
-                        Q = {fmaT(Q.x, Rr.x, -Q.y * Rr.y), fmaT(Q.x, Rr.y, Q.y * Rr.x)};
-                    }
-                });
-            } else {
-                static_for<0, E>([&](auto e) {
-                    const int j = t + e * TH;
-                    if (inside_at(j)) {
-                        const double rev = kind == STRAIN_EDGE
-                                               ? edge_phase_rev(__builtin_fma((double)j, d.dx, X0), Z, d.disl_k,
-                                                                d.disl_q)
-                                               : (double)utab[(size_t)n * N + j];
+                        couple(vp[e], vm[e], sel(in, d0), sel(in, bp), sel(in, bm));
+                        if constexpr (CV(e) + 1 < E) {
+                            P = {fmaT(P.x, Q.x, -P.y * Q.y), fmaT(P.x, Q.y, P.y * Q.x)};
+                            Q = {fmaT(Q.x, Rr.x, -Q.y * Rr.y), fmaT(Q.x, Rr.y, Q.y * Rr.x)};
+                        }
+                    };
+                    static_for<0, E>([&](auto e) { body(e, all_in | inside_at(j0 + e * TH)); });
+                } else {
+                    // dislocation field or tabulated phase (already reduced to one
+                    // revolution when the plan was built)
+                    const bool edge = d.strain_kind == STRAIN_EDGE;
+                    const T dk = (T)d.disl_k, dq = (T)d.disl_q;
+                    const gptr<T> urow = utab + (size_t)n * N;
+                    static_for<0, E>([&](auto e) {
+                        const int j = j0 + e * TH;
+                        const bool in = all_in | inside_at(j);
+                        const T rev = edge ? edge_phase_rev((T)__builtin_fma((double)j, d.dx, X0), (T)Z, dk, dq)
+                                           : urow[j];
                         const Cx<T> P = phasor<T>(rev);
                         const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
                         const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
-                        couple(vp[e], vm[e], d0, bp, bm);
-                    }
-                });
+                        couple(vp[e], vm[e], sel(in, d0), sel(in, bp), sel(in, bm));
+                    });
+                }
             }
         }
 
-        static_for<0, E>([&](auto e) {
-            out[t + e * TH] = vp[e];
-            out[N + t + e * TH] = vm[e];
-        });
+        if (active) {
+            static_for<0, E>([&](auto e) {
+                out[j00 + e * TH] = vp[e];
+                out[N + j00 + e * TH] = vm[e];
+            });
+        }
 
         if ((d.flags & SF_LAST) && d.rt_index >= 0) {
             double sp = 0.0, sm = 0.0;
-            static_for<0, E>([&](auto e) {
-                const int j = t + e * TH;
-                if (j >= d.det_lo && j < d.det_hi) {
-                    const double px = vp[e].x, py = vp[e].y, mx = vm[e].x, my = vm[e].y;
-                    sp = __builtin_fma(px, px, __builtin_fma(py, py, sp));
-                    sm = __builtin_fma(mx, mx, __builtin_fma(my, my, sm));
-                }
-            });
-            sp = block_sum(sp, red, t);
-            sm = block_sum(sm, red, t);
-            if (t == 0) {
+            if (active) {
+                static_for<0, E>([&](auto e) {
+                    const int j = j00 + e * TH;
+                    if (j >= d.det_lo && j < d.det_hi) {
+                        const double px = vp[e].x, py = vp[e].y, mx = vm[e].x, my = vm[e].y;
+                        sp = __builtin_fma(px, px, __builtin_fma(py, py, sp));
+                        sm = __builtin_fma(mx, mx, __builtin_fma(my, my, sm));
+                    }
+                });
+            }
+            sp = block_sum(sp, red, t0);
+            sm = block_sum(sm, red, t0);
+            if (t0 == 0) {
                 if (!(d.flags & SF_FIRST)) pin = d.pin ? *d.pin : 0.0;
                 const double R = pin > 0.0 ? sm / pin : 0.0;
                 const double Tt = pin > 0.0 ? sp / pin : 0.0;
@@ -645,7 +893,6 @@ struct March {
         }
     }
 };
-
 
 // Sizes the march kernels are built for.  Uniform kernels: one solve per
 // workgroup of nx/E threads; mixed kernel: 2^kMixedLog2Th threads, any nx in
@@ -661,5 +908,8 @@ struct Limits<double> {
     static constexpr int uni_lo = 6, uni_hi = 13, mix_lo = 10, mix_hi = 13;
 };
 constexpr int kMixedLog2Th = 9;
+// threads a size uses inside the mixed kernel's 512-thread workgroups (the
+// cross-wave radix must not exceed the samples per thread)
+__host__ __device__ constexpr int mixed_log2th(int log2n) { return log2n >= 12 ? 9 : 8; }
 
 }  // namespace bpm

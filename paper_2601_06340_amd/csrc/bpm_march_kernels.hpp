@@ -6,9 +6,23 @@
 
 namespace bpm {
 
+// Waves per SIMD the LDS footprint allows (1 << LOG2TH threads per workgroup):
+// the register budget is sized for that occupancy, not for an unreachable one.
+template <typename T, int LOG2N, int LOG2E>
+constexpr int lds_waves_per_simd()
+{
+    constexpr size_t bytes = LdsPlan<T, LOG2N, LOG2E>::bytes + 16 * sizeof(double);
+    constexpr int wg_per_cu = (int)(kLdsMax / bytes) < 1 ? 1 : (int)(kLdsMax / bytes);
+    constexpr int waves = wg_per_cu * (((1 << (LOG2N - LOG2E)) + 63) / 64);
+    constexpr int per_simd = (waves + 3) / 4;
+    return per_simd < 1 ? 1 : (per_simd > 8 ? 8 : per_simd);
+}
+
 // One solve per workgroup, every solve of the launch has the same nx.
 template <typename T, int LOG2N, int SC>
-__global__ __launch_bounds__(1 << (LOG2N - uniform_log2e(LOG2N))) void k_march_uniform(
+__global__ __launch_bounds__(1 << (LOG2N - uniform_log2e(LOG2N)))
+__attribute__((amdgpu_waves_per_eu(1, lds_waves_per_simd<T, LOG2N, uniform_log2e(LOG2N)>())))
+void k_march_uniform(
     const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
 {
     constexpr int LOG2E = uniform_log2e(LOG2N);
@@ -30,7 +44,8 @@ __global__ __launch_bounds__(1 << kMixedLog2Th) void k_march_mixed(const SolveDe
     Cx<T> *lds = reinterpret_cast<Cx<T> *>(smem);
     static_for<Limits<T>::mix_lo, Limits<T>::mix_hi + 1>([&](auto l) {
         constexpr int L2 = CV(l);
-        if (d.log2n == L2) March<T, L2, L2 - kMixedLog2Th, SC>::run(d, in_base, out_base, rt, lds, red);
+        if (d.log2n == L2)
+            March<T, L2, L2 - mixed_log2th(L2), SC, 1 << kMixedLog2Th>::run(d, in_base, out_base, rt, lds, red);
     });
 }
 
@@ -59,7 +74,7 @@ size_t mixed_lds_bytes()
     size_t m = 0;
     static_for<Limits<T>::mix_lo, Limits<T>::mix_hi + 1>([&](auto l) {
         constexpr int L2 = CV(l);
-        const size_t b = LdsPlan<T, L2, L2 - kMixedLog2Th>::bytes;
+        const size_t b = LdsPlan<T, L2, L2 - mixed_log2th(L2)>::bytes;
         if (b > m) m = b;
     });
     return m;

@@ -76,35 +76,59 @@ __global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, Cx<T> *prop)
     }
 }
 
-// Twiddle table of one (nx, E) schedule: pass p, entry (m-1)*L + j holds
-// exp(-2 pi i j m / (L r)), m = 1..r-1, j < L.  FP64 sincospi of an exactly
-// reduced integer ratio; FP32 tables store the hi+lo split.
+// Pass radices (log2) of the (nx, E) schedule, as the march kernels run it
+// (Geom): the group-local Stockham passes of M = nx / G points (radix E,
+// remainder last) and, when G > 1, the radix-G pass across the G wave groups.
+__host__ __device__ inline int schedule_radices(int log2n, int log2e, int *lr)
+{
+    const int log2th = log2n - log2e;
+    const int log2w = (use_wave_groups(log2n, log2e) && log2th > 6) ? log2th - 6 : 0;
+    const int log2m = log2n - log2w;
+    const int rem = log2m % log2e;
+    const int pw = (rem ? 1 : 0) + log2m / log2e;
+    int np = 0;
+    for (int p = 0; p < pw; ++p) lr[np++] = (p == pw - 1 && rem) ? rem : log2e;
+    if (log2w > 0) lr[np++] = log2w;
+    return np;
+}
+
+// Twiddle table: pass p (sub-length L, radix r), entry (m-1)*L + j holds the
+// rotation exp(-2 pi i j m / (L r)), m = 1..r-1, j < L.  The exponent is reduced
+// exactly in integers.  FP64 tables store (cos, sin); FP32 tables store the
+// lifting constants p = -tan(phi/2), u = sin(phi) of the angle folded into
+// [-pi/2, pi/2] and the exact sign s (= -1 when the fold took out a half turn).
 template <typename T>
 __global__ void k_twiddles(Tw<T> *tw, int log2n, int log2e)
 {
-    const int REM = log2n % log2e;
-    const int P = (REM ? 1 : 0) + log2n / log2e;
+    int lr[32];
+    const int P = schedule_radices(log2n, log2e, lr);
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     int base = 0, ll = 0;
     for (int p = 0; p < P; ++p) {
-        const int lr = (p == P - 1 && REM) ? REM : log2e;
-        const int L = 1 << ll, r = 1 << lr;
+        const int L = 1 << ll, r = 1 << lr[p];
         const int cnt = L * (r - 1);
         if (idx >= base && idx < base + cnt) {
             const int m = (idx - base) / L + 1, j = (idx - base) % L;
             const long long M = (long long)L * r;
-            const long long jm = ((long long)j * m) % M;
-            double sn, cs;
-            sincospi(-2.0 * (double)jm / (double)M, &sn, &cs);
+            long long q = ((long long)j * m) % M;   // angle -2 pi q / M
+            if (q > M / 2) q -= M;                  // (-M/2, M/2]
             if constexpr (std::is_same<T, float>::value) {
-                const float hx = (float)cs, hy = (float)sn;
-                tw[idx] = {hx, hy, (float)(cs - (double)hx), (float)(sn - (double)hy)};
+                float sgn = 1.0f;
+                if (4 * q > M || 4 * q < -M) {      // |angle| > pi/2: take out -1
+                    q += q > 0 ? -M / 2 : M / 2;
+                    sgn = -1.0f;
+                }
+                const double pl = tan(M_PI * (double)q / (double)M);
+                const double ul = -sinpi(2.0 * (double)q / (double)M);
+                tw[idx] = {(float)pl, (float)ul, sgn, 0.0f};
             } else {
+                double sn, cs;
+                sincospi(-2.0 * (double)q / (double)M, &sn, &cs);
                 tw[idx] = {cs, sn};
             }
         }
         base += cnt;
-        ll += lr;
+        ll += lr[p];
     }
 }
 
@@ -119,28 +143,26 @@ __global__ void k_utab(const double *u, T *tab, size_t count, double inv_d)
 }
 
 // ----------------------------------------------------------------- host side
-template <typename T>
 static int tw_count(int log2n, int log2e)
 {
-    const int REM = log2n % log2e;
-    const int P = (REM ? 1 : 0) + log2n / log2e;
+    int lr[32];
+    const int P = schedule_radices(log2n, log2e, lr);
     int s = 0, ll = 0;
     for (int p = 0; p < P; ++p) {
-        const int lr = (p == P - 1 && REM) ? REM : log2e;
-        s += (1 << ll) * ((1 << lr) - 1);
-        ll += lr;
+        s += (1 << ll) * ((1 << lr[p]) - 1);
+        ll += lr[p];
     }
     return s;
 }
 
 size_t twiddle_bytes(int prec, int log2n, int log2e)
 {
-    return (size_t)tw_count<float>(log2n, log2e) * 16;
+    return (size_t)tw_count(log2n, log2e) * 16;
 }
 
 hipError_t launch_twiddles(void *d_tw, int prec, int log2n, int log2e, hipStream_t s)
 {
-    const int cnt = tw_count<float>(log2n, log2e);
+    const int cnt = tw_count(log2n, log2e);
     if (cnt == 0) return hipSuccess;
     const int bs = 256, gs = (cnt + bs - 1) / bs;
     if (prec == PREC_F32)
@@ -234,7 +256,7 @@ static size_t mixed_lds_T()
     size_t m = 0;
     static_for<Limits<T>::mix_lo, Limits<T>::mix_hi + 1>([&](auto l) {
         constexpr int L2 = CV(l);
-        const size_t b = LdsPlan<T, L2, L2 - kMixedLog2Th>::bytes;
+        const size_t b = LdsPlan<T, L2, L2 - mixed_log2th(L2)>::bytes;
         if (b > m) m = b;
     });
     return m;
@@ -253,6 +275,6 @@ void mixed_shape(int prec, int *threads, size_t *lds_bytes)
 int max_log2n(int prec) { return prec == PREC_F32 ? Limits<float>::uni_hi : Limits<double>::uni_hi; }
 int mixed_min_log2n(int prec) { return prec == PREC_F32 ? Limits<float>::mix_lo : Limits<double>::mix_lo; }
 int mixed_max_log2n(int prec) { return prec == PREC_F32 ? Limits<float>::mix_hi : Limits<double>::mix_hi; }
-int mixed_log2e(int prec, int log2n) { return log2n - kMixedLog2Th; }
+int mixed_log2e(int prec, int log2n) { return log2n - mixed_log2th(log2n); }
 
 }  // namespace bpm

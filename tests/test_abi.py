@@ -61,3 +61,12 @@ def test_oracle_and_product_share_no_code():
         if f.endswith((".c", ".h", ".py")):
             txt = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_2601_06340_amd" not in txt.replace("paper_2601_06340_amd.synth", ""), f
+
+
+def test_twiddle_schedule_matches_kernel_geometry():
+    """The host-side twiddle schedule and the kernel's work split come from the
+    same rule; a mismatch for some sizes once produced wrong transforms."""
+    src = open(os.path.join(ROOT, "paper_2601_06340_amd", "csrc", "bpm_setup.hip")).read()
+    body = src[src.index("inline int schedule_radices"):]
+    body = body[:body.index("}")]
+    assert "use_wave_groups" in body
