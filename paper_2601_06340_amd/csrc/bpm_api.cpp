@@ -116,6 +116,59 @@ bpm_status bpm::twiddle_table(int prec, int log2n, int log2e, const void **out)
     return BPM_OK;
 }
 
+// ------------------------------------------------------------------ propagator cache
+// The propagator table (Eq. (12), P+- with the 1/nx fold) depends only on the
+// precision, nx, dx, dz, lambda and d.  Plans that agree on these share one
+// reference-counted device copy, so a batch of solves that differ in crystal,
+// strain or incident beam reads a single table that stays in L2.
+using PropKey = std::tuple<int, int, double, double, double, double>;
+struct PropEntry {
+    void *ptr;
+    int refs;
+};
+static std::mutex g_prop_mu;
+static std::map<PropKey, PropEntry> g_prop;
+
+static bpm_status prop_acquire(const bpm_plan_desc &d, const PlanParams *d_params, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_prop_mu);
+    const PropKey key{d.precision, d.nx, d.dx_um, d.dz_um, d.lambda_um, d.d_um};
+    auto it = g_prop.find(key);
+    if (it != g_prop.end()) {
+        ++it->second.refs;
+        *out = it->second.ptr;
+        return BPM_OK;
+    }
+    const size_t bytes = 2 * (size_t)d.nx * (d.precision == BPM_F32 ? 8 : 16);
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return hip_fail(e, "propagator table");
+    // built and finished under the lock: a second plan never sees a table in flight
+    e = launch_plan_setup(d_params, nullptr, p, d.precision, d.nx, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        return hip_fail(e, "propagator setup kernel");
+    }
+    g_prop[key] = PropEntry{p, 1};
+    *out = p;
+    return BPM_OK;
+}
+
+static void prop_release(void *p)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_prop_mu);
+    for (auto it = g_prop.begin(); it != g_prop.end(); ++it)
+        if (it->second.ptr == p) {
+            if (--it->second.refs == 0) {
+                (void)hipFree(p);
+                g_prop.erase(it);
+            }
+            return;
+        }
+}
+
 // ------------------------------------------------------------------ plans
 static bool is_finite(double v) { return std::isfinite(v); }
 static bool is_finite(bpm_complex c) { return std::isfinite(c.re) && std::isfinite(c.im); }
@@ -179,7 +232,7 @@ void bpm_plan::release()
 {
     (void)hipFree(d_sc);
     (void)hipFree(d_params);
-    (void)hipFree(d_prop);
+    prop_release(d_prop);
     (void)hipFree(d_seg);
     (void)hipFree(d_utab);
     (void)hipFree(d_pin);
@@ -264,7 +317,6 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
     };
     if ((st = dev_alloc(&p->d_sc, sizeof(PlanScalars), "plan scalars")) != BPM_OK) return bail(st);
     if ((st = dev_alloc(&p->d_params, sizeof(PlanParams), "plan params")) != BPM_OK) return bail(st);
-    if ((st = dev_alloc(&p->d_prop, 2 * nx * elem_bytes(prec), "propagator table")) != BPM_OK) return bail(st);
     if ((st = dev_alloc(&p->d_seg, std::max<size_t>(nz, 1) * d->nseg * 2 * sizeof(int32_t), "mask")) != BPM_OK)
         return bail(st);
     if ((st = dev_alloc(&p->d_pin, sizeof(double), "incident power")) != BPM_OK) return bail(st);
@@ -289,8 +341,9 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
     if (e == hipSuccess && nz > 0)
         e = hipMemcpy(p->d_seg, d->seg, nz * d->nseg * 2 * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(hip_fail(e, "plan upload"));
-    e = launch_plan_setup(p->d_params, p->d_sc, p->d_prop, prec, d->nx, nullptr);
+    e = launch_plan_setup(p->d_params, p->d_sc, nullptr, prec, d->nx, nullptr);
     if (e != hipSuccess) return bail(hip_fail(e, "plan setup kernel"));
+    if ((st = prop_acquire(*d, p->d_params, &p->d_prop)) != BPM_OK) return bail(st);
 
     if (d->strain.kind == BPM_STRAIN_TABLE && nz > 0) {
         double *d_u = nullptr;

@@ -17,7 +17,7 @@ struct bpm_plan {
     size_t device_bytes = 0;
     bpm::PlanScalars *d_sc = nullptr;
     bpm::PlanParams *d_params = nullptr;
-    void *d_prop = nullptr;      // [2][nx] (P - 1)/nx
+    void *d_prop = nullptr;      // [2][nx] (P - 1)/nx, shared through the propagator cache
     int32_t *d_seg = nullptr;    // [nz][nseg][2]
     void *d_utab = nullptr;      // strain table (TABLE kind)
     double *d_pin = nullptr;     // incident power

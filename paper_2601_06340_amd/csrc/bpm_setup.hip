@@ -17,7 +17,7 @@ __global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, Cx<T> *prop)
     const double A = dzh / (2.0 * c);
     const int nx = P.nx;
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (sc && blockIdx.x == 0 && threadIdx.x == 0) {
         // E - 1 = expm1(i A chi0) without cancellation
         const double gx = -A * P.chi0y, gy = A * P.chi0x;  // i A chi0
         const double eg = exp(gx), sgy = sin(gy), shalf = sin(0.5 * gy);
@@ -52,7 +52,7 @@ __global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, Cx<T> *prop)
         sc->amx = cmx * gex - cmy * gey;
         sc->amy = cmx * gey + cmy * gex;
     }
-    if (f < nx) {
+    if (prop && f < nx) {
         const int ff = f < nx / 2 ? f : f - nx;
         const double q = 2.0 * M_PI * (double)ff / ((double)nx * P.dx * k);
         const double invn = 1.0 / (double)nx;
@@ -175,7 +175,7 @@ hipError_t launch_twiddles(void *d_tw, int prec, int log2n, int log2e, hipStream
 hipError_t launch_plan_setup(const PlanParams *d_params, PlanScalars *d_sc, void *d_prop, int prec, int nx,
                              hipStream_t s)
 {
-    const int bs = 256, gs = (nx + bs - 1) / bs;
+    const int bs = 256, gs = d_prop ? (nx + bs - 1) / bs : 1;
     if (prec == PREC_F32)
         hipLaunchKernelGGL(k_plan_setup<float>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (Cx<float> *)d_prop);
     else

@@ -77,6 +77,30 @@ def test_every_uniform_size_random_fields_ragged_mask(prec, log2n):
     check(p, a, 0.3 * b, "uniform-%d" % nx)
 
 
+def test_shared_propagator_table_outlives_its_first_plan():
+    """Plans of the same geometry share one propagator table: destroying the
+    plan that built it leaves the others correct, and a plan that differs only
+    in dz gets a table of its own."""
+    B = bpm()
+    nx, nz = 1024, 60
+    seg = np.tile(np.array([[[100, 900]]], np.int32), (nz, 1, 1))
+    a, _ = synth.random_envelopes(nx, 7)
+    p1 = synth.base_problem(nx, nz, 0.1, 0.05, seg, precision="f64")
+    p2 = dict(p1, chih=complex(-1.2e-6, 5e-9), chihb=complex(-1.2e-6, 5e-9))
+    p3 = dict(p1, dz_um=0.04)
+    first = B.Plan(p1)
+    second = B.Plan(p2)
+    third = B.Plan(p3)
+    first.close()
+    for plan, p, label in ((second, p2, "shared"), (third, p3, "own")):
+        gp, gm, _, _ = plan.propagate(a, None)
+        op, om, _, _ = oracle.propagate(p, a, None)
+        err = rel_pair(gp, gm, op, om)
+        say("   %s table: rel L2 %.3e" % (label, err))
+        assert err <= TOL["f64"][0]
+        plan.close()
+
+
 # ------------------------------------------------------------------ physics workloads
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_flat_bragg_scan_small(prec):
