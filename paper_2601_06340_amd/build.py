@@ -32,6 +32,7 @@ HIPFLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
 
 # keep in sync with Limits<> in csrc/bpm_march.hpp
 UNIFORM = {"float": range(6, 15), "double": range(6, 14)}
+STAGED = {"float": range(15, 17), "double": range(14, 17)}
 MIXED = ("float", "double")
 STRAIN_CLASSES = (0, 1, 2)   # none, polynomial, dislocation/table
 
@@ -54,6 +55,12 @@ def _gen_units() -> list[str]:
                 write("march_%s_%d_sc%d.hip" % (t, l2, sc),
                       '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
                       "template hipError_t launch_uniform<%s, %d, %d>(const SolveDesc *, int, const char *, "
+                      "char *, double *, hipStream_t);\n}\n" % (t, l2, sc))
+        for t, rng in STAGED.items():
+            for l2 in rng:
+                write("march_staged_%s_%d_sc%d.hip" % (t, l2, sc),
+                      '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
+                      "template hipError_t launch_staged<%s, %d, %d>(const SolveDesc *, int, const char *, "
                       "char *, double *, hipStream_t);\n}\n" % (t, l2, sc))
         for t in MIXED:
             write("march_mixed_%s_sc%d.hip" % (t, sc),
@@ -79,7 +86,7 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
     srcs = [os.path.join(CSRC, f) for f in ("bpm_setup.hip", "bpm_api.cpp", "bpm_server.cpp")]
     srcs += _gen_units()
     # largest units first
-    srcs.sort(key=lambda s: ("mixed" not in s, not any(("_%d_" % k) in s for k in (12, 13, 14))))
+    srcs.sort(key=lambda s: ("mixed" not in s, not any(("_%d_" % k) in s for k in (12, 13, 14, 15, 16))))
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))

@@ -101,11 +101,13 @@ bpm_status bpm::twiddle_table(int prec, int log2n, int log2e, const void **out)
         *out = it->second;
         return BPM_OK;
     }
-    const size_t bytes = std::max<size_t>(twiddle_bytes(prec, log2n, log2e), 16);
+    // log2e = 0 names the combined table of a staged size
+    const size_t bytes = std::max<size_t>(log2e ? twiddle_bytes(prec, log2n, log2e) : staged_twiddle_bytes(prec, log2n),
+                                          16);
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) return hip_fail(e, "twiddle table");
-    e = launch_twiddles(p, prec, log2n, log2e, nullptr);
+    e = log2e ? launch_twiddles(p, prec, log2n, log2e, nullptr) : launch_staged_twiddles(p, prec, log2n, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         (void)hipFree(p);
@@ -144,7 +146,10 @@ static bpm_status prop_acquire(const bpm_plan_desc &d, const PlanParams *d_param
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) return hip_fail(e, "propagator table");
     // built and finished under the lock: a second plan never sees a table in flight
-    e = launch_plan_setup(d_params, nullptr, p, d.precision, d.nx, nullptr);
+    int log2n = 0;
+    while ((1 << log2n) < d.nx) ++log2n;
+    const int log2r = is_staged(d.precision, log2n) ? log2n - staged_log2c(d.precision) : 0;
+    e = launch_plan_setup(d_params, nullptr, p, d.precision, d.nx, log2r, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         (void)hipFree(p);
@@ -341,7 +346,7 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
     if (e == hipSuccess && nz > 0)
         e = hipMemcpy(p->d_seg, d->seg, nz * d->nseg * 2 * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(hip_fail(e, "plan upload"));
-    e = launch_plan_setup(p->d_params, p->d_sc, nullptr, prec, d->nx, nullptr);
+    e = launch_plan_setup(p->d_params, p->d_sc, nullptr, prec, d->nx, 0, nullptr);
     if (e != hipSuccess) return bail(hip_fail(e, "plan setup kernel"));
     if ((st = prop_acquire(*d, p->d_params, &p->d_prop)) != BPM_OK) return bail(st);
 
@@ -363,7 +368,8 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
     if (e != hipSuccess) return bail(hip_fail(e, "plan setup"));
 
     const int log2e = uniform_log2e(p->log2n);
-    if ((st = twiddle_table(prec, p->log2n, log2e, &p->tw_uniform)) != BPM_OK) return bail(st);
+    const int tw_key = is_staged(prec, p->log2n) ? 0 : log2e;
+    if ((st = twiddle_table(prec, p->log2n, tw_key, &p->tw_uniform)) != BPM_OK) return bail(st);
     march_shape(prec, p->log2n, &p->threads, &p->lds_bytes);
 
     // single-solve launch descriptor (state at offset 0, R/T at index 0)

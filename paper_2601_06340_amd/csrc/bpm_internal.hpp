@@ -60,22 +60,36 @@ struct SolveDesc {
     uint64_t in_off, out_off;  // byte offsets of the state in the launch's in/out buffers
 };
 
+// Staged (four-step) lane: 2^kStagedLog2Th threads per solve, 2^staged_log2e
+// samples per thread and beam, rows of one wave (2^(6 + log2e) points).
+constexpr int kStagedLog2Th = 9;
+constexpr int staged_log2e(int prec) { return prec == 1 ? 4 : 3; }   // FP32 16, FP64 8
+constexpr int staged_log2c(int prec) { return 6 + staged_log2e(prec); }
+
 // Elements per thread (log2) used for a given nx by the uniform-size kernels.
 constexpr int uniform_log2e(int log2n) { return log2n >= 8 ? 4 : (log2n >= 7 ? 3 : 2); }
 
-// Launchers (bpm_kernels.hip).  All return hipSuccess or the launch error.
+// Launchers (bpm_setup.hip).  All return hipSuccess or the launch error.
+// d_sc or d_prop may be NULL to skip that part; log2r > 0 stores the propagator
+// of a staged size in [k1][k2] order (R = 2^log2r).
 hipError_t launch_plan_setup(const PlanParams *d_params, PlanScalars *d_sc, void *d_prop, int prec,
-                             int nx, hipStream_t s);
+                             int nx, int log2r, hipStream_t s);
 hipError_t launch_twiddles(void *d_tw, int prec, int log2n, int log2e, hipStream_t s);
 size_t twiddle_bytes(int prec, int log2n, int log2e);
+// Staged sizes (four-step lane): whether log2n is one, and its twiddle table
+// [row FFT | column FFT | four-step].
+bool is_staged(int prec, int log2n);
+size_t staged_twiddle_bytes(int prec, int log2n);
+hipError_t launch_staged_twiddles(void *d_tw, int prec, int log2n, hipStream_t s);
 hipError_t launch_utab(const double *d_u, void *d_tab, int prec, size_t count, double inv_d,
                        hipStream_t s);
 // March every solve of a launch.  All descs share prec and strain class `sc`
 // (0 none, 1 polynomial, 2 dislocation/table); if `uniform_log2n` >= 0 they also
-// share nx and use the uniform kernel, otherwise the mixed-size kernel.
+// share nx and use the uniform (or, for staged sizes, the staged) kernel,
+// otherwise the mixed-size kernel.
 hipError_t launch_march(const SolveDesc *d_descs, int n, int prec, int uniform_log2n, int sc,
                         const char *in_base, char *out_base, double *rt, hipStream_t s);
-// Launch shape of the uniform kernel (threads per workgroup, dynamic LDS bytes).
+// Launch shape of the uniform or staged kernel (threads per workgroup, dynamic LDS bytes).
 void march_shape(int prec, int log2n, int *threads, size_t *lds_bytes);
 // Mixed-size kernel: elements-per-thread (log2) it uses for log2n, and its shape.
 int mixed_log2e(int prec, int log2n);

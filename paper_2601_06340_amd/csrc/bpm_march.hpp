@@ -441,16 +441,108 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Real-space coupling of one z-step (Eq. (9)-(12)) for the E samples a thread
+// holds at j0 + JS*e.  Outside the crystal the step is pure propagation: the
+// coefficients become (0, 0, 0), which leaves both envelopes untouched.
+template <typename T, int SC>
+struct Coupler {
+    Cx<T> d0, ap, am;
+    double X0;       // x0 - x_ref
+    int nseg, nx;
+    gptr<int> seg;
+    gptr<T> utab;
+
+    __device__ __forceinline__ void init(const SolveDesc &d, int nx_)
+    {
+        const PlanScalars &sc = *d.sc;
+        d0 = {to_T<T>(sc.d0x), to_T<T>(sc.d0y)};
+        ap = {to_T<T>(sc.apx), to_T<T>(sc.apy)};
+        am = {to_T<T>(sc.amx), to_T<T>(sc.amy)};
+        X0 = d.x0 - d.x_ref;
+        nseg = d.nseg;
+        nx = nx_;
+        seg = to_global<int>(d.seg);
+        utab = to_global<T>(d.utab);
+    }
+
+    template <int E, int JS>
+    __device__ __forceinline__ void apply(Cx<T> *vp, Cx<T> *vm, const SolveDesc &d, int n, int j0) const
+    {
+        const gptr<int> sg = seg + (size_t)n * nseg * 2;
+        int lo[kMaxSeg], hi[kMaxSeg];
+        static_for<0, kMaxSeg>([&](auto k) {
+            lo[k] = CV(k) < nseg ? sg[2 * CV(k)] : 0;
+            hi[k] = CV(k) < nseg ? sg[2 * CV(k) + 1] : 0;
+        });
+        const bool all_in = (nseg == 1) & (lo[0] <= 0) & (hi[0] >= nx);
+        auto inside_at = [&](int j) {
+            bool in = false;
+            static_for<0, kMaxSeg>([&](auto k) { in |= (j >= lo[k]) & (j < hi[k]); });
+            return in;
+        };
+        const Cx<T> zero = {(T)0, (T)0};
+        auto sel = [&](bool in, Cx<T> c) { return Cx<T>{in ? c.x : zero.x, in ? c.y : zero.y}; };
+        const double Z = n * d.dz - d.z_ref;
+        // (one straight-line copy: a separate all-inside copy costs registers)
+        if constexpr (SC == SC_NONE) {
+            static_for<0, E>([&](auto e) {
+                const bool in = all_in | inside_at(j0 + e * JS);
+                couple(vp[e], vm[e], sel(in, d0), sel(in, ap), sel(in, am));
+            });
+        } else if constexpr (SC == SC_POLY2) {
+            // phase (revolutions) u/d = pa + pb X + pc X^2 along this z; along a
+            // thread's samples X_e = X_0 + e D it is quadratic in e, so the
+            // phasors follow P_{e+1} = P_e Q_e, Q_{e+1} = Q_e R with P_0, Q_0, R
+            // from FP64 arguments reduced to one revolution.
+            const double pa = (d.c[0] + Z * (d.c[2] + Z * d.c[5])) * d.inv_d;
+            const double pb = (d.c[1] + Z * d.c[4]) * d.inv_d;
+            const double pc = d.c[3] * d.inv_d;
+            const double D = (double)JS * d.dx;
+            const double Xt = __builtin_fma((double)j0, d.dx, X0);
+            Cx<T> P = phasor<T>(__builtin_fma(__builtin_fma(pc, Xt, pb), Xt, pa));
+            Cx<T> Q = phasor<T>(__builtin_fma(pc, __builtin_fma(2.0 * Xt, D, D * D), pb * D));
+            const Cx<T> Rr = phasor<T>(2.0 * pc * D * D);
+            auto body = [&](auto e, bool in) {
+                const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
+                const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
+                couple(vp[e], vm[e], sel(in, d0), sel(in, bp), sel(in, bm));
+                if constexpr (CV(e) + 1 < E) {
+                    P = {fmaT(P.x, Q.x, -P.y * Q.y), fmaT(P.x, Q.y, P.y * Q.x)};
+                    Q = {fmaT(Q.x, Rr.x, -Q.y * Rr.y), fmaT(Q.x, Rr.y, Q.y * Rr.x)};
+                }
+            };
+            static_for<0, E>([&](auto e) { body(e, all_in | inside_at(j0 + e * JS)); });
+        } else {
+            // dislocation field or tabulated phase (already reduced to one
+            // revolution when the plan was built)
+            const bool edge = d.strain_kind == STRAIN_EDGE;
+            const T dk = (T)d.disl_k, dq = (T)d.disl_q;
+            const gptr<T> urow = utab + (size_t)n * nx;
+            static_for<0, E>([&](auto e) {
+                const int j = j0 + e * JS;
+                const bool in = all_in | inside_at(j);
+                const T rev = edge ? edge_phase_rev((T)__builtin_fma((double)j, d.dx, X0), (T)Z, dk, dq)
+                                   : urow[j];
+                const Cx<T> P = phasor<T>(rev);
+                const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
+                const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
+                couple(vp[e], vm[e], sel(in, d0), sel(in, bp), sel(in, bm));
+            });
+        }
+    }
+};
+
 // One solve marched by the first TH of BLOCK threads (the rest only take part
 // in the workgroup barriers).
-template <typename T, int LOG2N, int LOG2E, int SC, int BLOCK = (1 << (LOG2N - LOG2E))>
+// BXO overrides the LDS plan's beams-per-buffer choice (0 = the plan's).
+template <typename T, int LOG2N, int LOG2E, int SC, int BLOCK = (1 << (LOG2N - LOG2E)), int BXO = 0>
 struct March {
     using LP = LdsPlan<T, LOG2N, LOG2E>;
     using G = typename LP::G;
     using SW = typename G::SW;
     static constexpr int N = G::N, E = G::E, TH = G::TH, W = G::G, LANES = G::LANES, M = G::M;
     static constexpr int PW = SW::P, BUFM = G::BUFM;
-    static constexpr int NB = LP::NBUF, BX = LP::BX;
+    static constexpr int NB = LP::NBUF, BX = BXO ? BXO : LP::BX;
     static_assert(G::WAVE_LOCAL || W == 1, "whole-workgroup groups");
     static_assert(BLOCK >= TH, "block");
 
@@ -655,6 +747,29 @@ struct March {
         }
     }
 
+    // Group-local forward FFT of M points (radix-E Stockham passes with the
+    // group's exchanges through its LDS region Rp/Rm); natural-order samples
+    // l + LANES*e in, bins l + LANES*e out.
+    static __device__ __forceinline__ void fwd_local(Cx<T> *vp, Cx<T> *vm, gptr<Tw<T>> tw, Cx<T> *Rp, Cx<T> *Rm,
+                                                     int l, bool active)
+    {
+        static_for<0, PW>([&](auto pc) {
+            constexpr int p = CV(pc);
+            if (active) pass_fwd<SW::log2r(p), SW::log2L(p), LANES>(vp, vm, tw, SW::twbase(p), l);
+            if constexpr (p + 1 < PW) gx<p, false>(vp, vm, Rp, Rm, l, active);
+        });
+    }
+    // its exact inverse: the same passes in reverse order with the same tables
+    static __device__ __forceinline__ void inv_local(Cx<T> *vp, Cx<T> *vm, gptr<Tw<T>> tw, Cx<T> *Rp, Cx<T> *Rm,
+                                                     int l, bool active)
+    {
+        static_for<0, PW>([&](auto pp) {
+            constexpr int p = PW - 1 - CV(pp);
+            if constexpr (p + 1 < PW) gx<p, true>(vp, vm, Rp, Rm, l, active);
+            if (active) pass_inv<SW::log2r(p), SW::log2L(p), LANES>(vp, vm, tw, SW::twbase(p), l);
+        });
+    }
+
     // |a|^2 sums over the block, FP64, fixed order
     static __device__ __forceinline__ double block_sum(double v, double *red, int t)
     {
@@ -680,8 +795,6 @@ struct March {
         Cx<T> *out = reinterpret_cast<Cx<T> *>(out_base + d.out_off);
         const gptr<Tw<T>> tw = to_global<Tw<T>>(d.tw);
         const gptr<Cx<T>> prop = to_global<Cx<T>>(d.prop);
-        const gptr<int> seg = to_global<int>(d.seg);
-        const gptr<T> utab = to_global<T>(d.utab);
         // sample index of element e of this thread: j0 + TH*e
         const int w0 = t0 >> G::LOG2LANES, l0 = t0 & (LANES - 1);
         const int j00 = w0 + W * l0;
@@ -709,13 +822,9 @@ struct March {
             if (t0 == 0 && d.pin) *d.pin = pin;
         }
 
-        const PlanScalars &sc = *d.sc;
-        const Cx<T> d0 = {to_T<T>(sc.d0x), to_T<T>(sc.d0y)};
-        const Cx<T> ap = {to_T<T>(sc.apx), to_T<T>(sc.apy)};
-        const Cx<T> am = {to_T<T>(sc.amx), to_T<T>(sc.amy)};
+        Coupler<T, SC> cpl;
+        cpl.init(d, N);
         const T invN = (T)(1.0 / (double)N);
-        const int nseg = d.nseg;
-        const double X0 = d.x0 - d.x_ref;
 
         const int nend = d.step0 + d.nsteps;
         for (int n = d.step0; n < nend; ++n) {
@@ -733,11 +842,7 @@ struct March {
             Cx<T> *Rm = bufm + w * BUFM;
 
             // ---- forward transforms (Eq. (12): F[psi+-]); group-local passes
-            static_for<0, PW>([&](auto pc) {
-                constexpr int p = CV(pc);
-                if (active) pass_fwd<SW::log2r(p), SW::log2L(p), LANES>(vp, vm, twf, SW::twbase(p), l);
-                if constexpr (p + 1 < PW) gx<p, false>(vp, vm, Rp, Rm, l, active);
-            });
+            fwd_local(vp, vm, twf, Rp, Rm, l, active);
             // ---- cross-group radix-W pass (wave groups only)
             if constexpr (W > 1) {
                 if (active) {
@@ -787,79 +892,10 @@ struct March {
                     if (active) read_own(Rm, vm, l);
                 }
             }
-            static_for<0, PW>([&](auto pp) {
-                constexpr int p = PW - 1 - CV(pp);
-                if constexpr (p + 1 < PW) gx<p, true>(vp, vm, Rp, Rm, l, active);
-                if (active) pass_inv<SW::log2r(p), SW::log2L(p), LANES>(vp, vm, twi, SW::twbase(p), l);
-            });
+            inv_local(vp, vm, twi, Rp, Rm, l, active);
 
-            // ---- real-space coupling inside the crystal (Eq. (9)-(12)).  Outside the
-            // crystal the step is pure propagation: the coefficients become
-            // (0, 0, 0), which leaves both envelopes untouched.
-            if (active) {
-                const int j0 = w + W * l;
-                const gptr<int> sg = seg + (size_t)n * nseg * 2;
-                int lo[kMaxSeg], hi[kMaxSeg];
-                static_for<0, kMaxSeg>([&](auto k) {
-                    lo[k] = CV(k) < nseg ? sg[2 * CV(k)] : 0;
-                    hi[k] = CV(k) < nseg ? sg[2 * CV(k) + 1] : 0;
-                });
-                const bool all_in = (nseg == 1) & (lo[0] <= 0) & (hi[0] >= N);
-                auto inside_at = [&](int j) {
-                    bool in = false;
-                    static_for<0, kMaxSeg>([&](auto k) { in |= (j >= lo[k]) & (j < hi[k]); });
-                    return in;
-                };
-                const Cx<T> zero = {(T)0, (T)0};
-                auto sel = [&](bool in, Cx<T> c) { return Cx<T>{in ? c.x : zero.x, in ? c.y : zero.y}; };
-                const double Z = n * d.dz - d.z_ref;
-                // (one straight-line copy: a separate all-inside copy costs registers)
-                if constexpr (SC == SC_NONE) {
-                    static_for<0, E>([&](auto e) {
-                        const bool in = all_in | inside_at(j0 + e * TH);
-                        couple(vp[e], vm[e], sel(in, d0), sel(in, ap), sel(in, am));
-                    });
-                } else if constexpr (SC == SC_POLY2) {
-                    // phase (revolutions) u/d = pa + pb X + pc X^2 along this z; along a
-                    // thread's samples X_e = X_0 + e D it is quadratic in e, so the
-                    // phasors follow P_{e+1} = P_e Q_e, Q_{e+1} = Q_e R with P_0, Q_0, R
-                    // from FP64 arguments reduced to one revolution.
-                    const double pa = (d.c[0] + Z * (d.c[2] + Z * d.c[5])) * d.inv_d;
-                    const double pb = (d.c[1] + Z * d.c[4]) * d.inv_d;
-                    const double pc = d.c[3] * d.inv_d;
-                    const double D = (double)TH * d.dx;
-                    const double Xt = __builtin_fma((double)j0, d.dx, X0);
-                    Cx<T> P = phasor<T>(__builtin_fma(__builtin_fma(pc, Xt, pb), Xt, pa));
-                    Cx<T> Q = phasor<T>(__builtin_fma(pc, __builtin_fma(2.0 * Xt, D, D * D), pb * D));
-                    const Cx<T> Rr = phasor<T>(2.0 * pc * D * D);
-                    auto body = [&](auto e, bool in) {
-                        const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
-                        const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
-                        couple(vp[e], vm[e], sel(in, d0), sel(in, bp), sel(in, bm));
-                        if constexpr (CV(e) + 1 < E) {
-                            P = {fmaT(P.x, Q.x, -P.y * Q.y), fmaT(P.x, Q.y, P.y * Q.x)};
-                            Q = {fmaT(Q.x, Rr.x, -Q.y * Rr.y), fmaT(Q.x, Rr.y, Q.y * Rr.x)};
-                        }
-                    };
-                    static_for<0, E>([&](auto e) { body(e, all_in | inside_at(j0 + e * TH)); });
-                } else {
-                    // dislocation field or tabulated phase (already reduced to one
-                    // revolution when the plan was built)
-                    const bool edge = d.strain_kind == STRAIN_EDGE;
-                    const T dk = (T)d.disl_k, dq = (T)d.disl_q;
-                    const gptr<T> urow = utab + (size_t)n * N;
-                    static_for<0, E>([&](auto e) {
-                        const int j = j0 + e * TH;
-                        const bool in = all_in | inside_at(j);
-                        const T rev = edge ? edge_phase_rev((T)__builtin_fma((double)j, d.dx, X0), (T)Z, dk, dq)
-                                           : urow[j];
-                        const Cx<T> P = phasor<T>(rev);
-                        const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
-                        const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
-                        couple(vp[e], vm[e], sel(in, d0), sel(in, bp), sel(in, bm));
-                    });
-                }
-            }
+            // ---- real-space coupling inside the crystal (Eq. (9)-(12))
+            if (active) cpl.template apply<E, TH>(vp, vm, d, n, w + W * l);
         }
 
         if (active) {
@@ -894,18 +930,216 @@ struct March {
     }
 };
 
+// ----------------------------------------------------------------- staged lane
+// Sizes whose two envelopes do not fit one compute unit's registers and LDS.
+// N = R*C with C = 64*E (one wave per row); the transform is the four-step factorisation
+//   X[k1 + R k2] = sum_n2 W_C^{n2 k2} W_N^{n2 k1} sum_n1 W_R^{n1 k1} x[C n1 + n2],
+// and between its halves the field lives in the solve's own state buffer in
+// the layout Y[k1][n2] at k1*C + n2, the same addresses as x[C n1 + n2] for
+// n1 = k1, so entry and exit states stay in natural order.  One z-step:
+//   row phase    (one wave per row k1): W_N^{n2 k1}, C-point FFT, propagator of
+//                frequency k1 + R k2 (table stored in [k1][k2] order), inverse
+//                C-point FFT, inverse W_N^{n2 k1};
+//   column phase (R/E lanes per column n2): inverse R-point DFT, coupling at
+//                x_{C n1 + n2}, then the forward R-point DFT of the next step.
+// One workgroup marches one solve; the two phases are separated by workgroup
+// barriers (the state stays in L2 / the last-level cache between them).
+template <typename T>
+constexpr int staged_prec() { return sizeof(T) == 4 ? PREC_F32 : PREC_F64; }
+
+// both beams in one LDS buffer set per wave when 8 such waves fit
+template <typename T, int LOG2C, int LOG2E>
+constexpr int staged_bx()
+{
+    return (size_t)(1 << kStagedLog2Th) / 64 * 2 * Sched<LOG2C, LOG2E>::bufsz() * sizeof(Cx<T>) <= kLdsMax ? 2 : 1;
+}
+
+template <typename T, int LOG2N, int SC>
+struct Staged {
+    static constexpr int LOG2E = staged_log2e(staged_prec<T>()), E = 1 << LOG2E;
+    static constexpr int N = 1 << LOG2N, LOG2C = staged_log2c(staged_prec<T>()), C = 1 << LOG2C;
+    static constexpr int LOG2R = LOG2N - LOG2C, R = 1 << LOG2R;
+    static constexpr int TH = 1 << kStagedLog2Th, WAVES = TH / 64;
+    static constexpr int BXS = staged_bx<T, LOG2C, LOG2E>();
+    using RowM = March<T, LOG2C, LOG2E, SC, TH, BXS>;
+    using ColM = March<T, LOG2R, LOG2E, SC, TH, BXS>;
+    static_assert(RowM::LANES == 64 && RowM::W == 1, "one wave per row");
+    static_assert(ColM::W == 1 && ColM::LANES <= 64, "columns inside one wave");
+    static constexpr int LC = ColM::LANES;            // lanes per column
+    static constexpr int GPW = 64 / LC;               // columns per wave
+    static constexpr int COLS_PER_ROUND = TH / LC;
+    static constexpr int COL_ROUNDS = C / COLS_PER_ROUND;
+    static constexpr int ROW_ROUNDS = R / WAVES;
+    static_assert(COL_ROUNDS >= 1 && ROW_ROUNDS >= 1, "staged shape");
+    static constexpr int ROW_SLAB = RowM::BX * RowM::BUFM;
+    static constexpr int COL_SLAB = GPW * ColM::BX * ColM::BUFM;
+    static constexpr int SLAB = ROW_SLAB > COL_SLAB ? ROW_SLAB : COL_SLAB;
+    static constexpr size_t lds_bytes = (size_t)WAVES * SLAB * sizeof(Cx<T>);
+    static_assert(lds_bytes <= kLdsMax, "staged LDS");
+    // twiddle table: [row FFT | column FFT | four-step W_N^{n2 k1} at k1*C + n2]
+    static constexpr int TW_COL = RowM::SW::twcount();
+    static constexpr int TW_4 = TW_COL + ColM::SW::twcount();
+    static constexpr int TW_TOTAL = TW_4 + N;
+
+    static __device__ __forceinline__ void load(Cx<T> *vp, Cx<T> *vm, const Cx<T> *src, int base, int stride)
+    {
+        static_for<0, E>([&](auto e) {
+            vp[e] = src[base + e * stride];
+            vm[e] = src[N + base + e * stride];
+        });
+    }
+    static __device__ __forceinline__ void store(Cx<T> *dst, const Cx<T> *vp, const Cx<T> *vm, int base, int stride)
+    {
+        static_for<0, E>([&](auto e) {
+            dst[base + e * stride] = vp[e];
+            dst[N + base + e * stride] = vm[e];
+        });
+    }
+    // |psi+|^2 and |psi-|^2 over the detector interval, samples base + stride*e
+    static __device__ __forceinline__ void det_sums(const Cx<T> *vp, const Cx<T> *vm, const SolveDesc &d, int base,
+                                                    int stride, double &sp, double &sm)
+    {
+        static_for<0, E>([&](auto e) {
+            const int j = base + e * stride;
+            if (j >= d.det_lo && j < d.det_hi) {
+                const double px = vp[e].x, py = vp[e].y, mx = vm[e].x, my = vm[e].y;
+                sp = __builtin_fma(px, px, __builtin_fma(py, py, sp));
+                sm = __builtin_fma(mx, mx, __builtin_fma(my, my, sm));
+            }
+        });
+    }
+
+    static __device__ void run(const SolveDesc &d, const char *in_base, char *out_base, double *rt,
+                               Cx<T> *lds, double *red)
+    {
+        const int t0 = threadIdx.x;
+        const Cx<T> *in = reinterpret_cast<const Cx<T> *>(in_base + d.in_off);
+        Cx<T> *st = reinterpret_cast<Cx<T> *>(out_base + d.out_off);
+        const gptr<Tw<T>> tw = to_global<Tw<T>>(d.tw);
+        const gptr<Cx<T>> prop = to_global<Cx<T>>(d.prop);
+        const int wv = t0 >> 6, lane = t0 & 63;
+        Cx<T> *slab = lds + wv * SLAB;
+        const int gi = lane / LC, lc = lane % LC;    // column within the wave, lane within the column
+        Cx<T> *CRp = slab + gi * (ColM::BX * ColM::BUFM);
+        Cx<T> *CRm = CRp + (ColM::BX == 2 ? ColM::BUFM : 0);
+        Cx<T> *RRp = slab;
+        Cx<T> *RRm = slab + (RowM::BX == 2 ? RowM::BUFM : 0);
+        Coupler<T, SC> cpl;
+        cpl.init(d, N);
+        const T invN = (T)(1.0 / (double)N);
+        const int nend = d.step0 + d.nsteps;
+        const bool rt_out = (d.flags & SF_LAST) && d.rt_index >= 0;
+        double sp = 0.0, sm = 0.0, pin_part = 0.0;
+
+        // ---- entry: natural-order x -> forward column DFTs -> Y
+#pragma unroll 1
+        for (int cr = 0; cr < COL_ROUNDS; ++cr) {
+            const int c = cr * COLS_PER_ROUND + wv * GPW + gi;
+            Cx<T> vp[E], vm[E];
+            load(vp, vm, in, lc * C + c, LC * C);
+            if (d.flags & SF_FIRST) {
+                static_for<0, E>([&](auto e) {
+                    const double x = (double)vp[e].x, y = (double)vp[e].y;
+                    pin_part = __builtin_fma(x, x, __builtin_fma(y, y, pin_part));
+                });
+            }
+            if (d.nsteps > 0) {
+                const gptr<Tw<T>> twc = tw + (TW_COL + (cr & d.opaque_zero));
+                ColM::fwd_local(vp, vm, twc, CRp, CRm, lc, true);
+            } else if (rt_out) {
+                det_sums(vp, vm, d, lc * C + c, LC * C, sp, sm);
+            }
+            store(st, vp, vm, lc * C + c, LC * C);
+        }
+        double pin = 0.0;
+        if (d.flags & SF_FIRST) {
+            pin = RowM::block_sum(pin_part, red, t0);
+            if (t0 == 0 && d.pin) *d.pin = pin;
+        }
+
+        for (int n = d.step0; n < nend; ++n) {
+            __syncthreads();
+            // ---- row phase: propagation in Fourier space (Eq. (12))
+#pragma unroll 1
+            for (int rr = 0; rr < ROW_ROUNDS; ++rr) {
+                const int oz = (n + rr) & d.opaque_zero;
+                const int k1 = rr * WAVES + wv;
+                const int rb = k1 * C + lane + oz;
+                Cx<T> vp[E], vm[E];
+                load(vp, vm, st, rb, 64);
+                static_for<0, E>([&](auto e) {
+                    const Tw<T> w = gload(tw, TW_4 + rb + e * 64);
+                    vp[e] = mul_tw(vp[e], w);
+                    vm[e] = mul_tw(vm[e], w);
+                });
+                RowM::fwd_local(vp, vm, tw + oz, RRp, RRm, lane, true);
+                // bin k2 = lane + 64 e of row k1 is frequency k1 + R k2
+                const gptr<Cx<T>> pr = prop + oz;
+                static_for<0, E>([&](auto e) {
+                    const int f = k1 * C + lane + e * 64;
+                    const Cx<T> kp = gload(pr, f), km = gload(pr, N + f);
+                    const Cx<T> a = vp[e], b = vm[e];
+                    vp[e] = {fmaT(kp.x, a.x, fmaT(-kp.y, a.y, a.x * invN)),
+                             fmaT(kp.x, a.y, fmaT(kp.y, a.x, a.y * invN))};
+                    vm[e] = {fmaT(km.x, b.x, fmaT(-km.y, b.y, b.x * invN)),
+                             fmaT(km.x, b.y, fmaT(km.y, b.x, b.y * invN))};
+                });
+                const int oi = (n + rr + 1) & d.opaque_zero;
+                RowM::inv_local(vp, vm, tw + oi, RRp, RRm, lane, true);
+                const int rbi = k1 * C + lane + oi;
+                static_for<0, E>([&](auto e) {
+                    const Tw<T> w = gload(tw, TW_4 + rbi + e * 64);
+                    vp[e] = mul_tw_inv(vp[e], w);
+                    vm[e] = mul_tw_inv(vm[e], w);
+                });
+                store(st, vp, vm, rb - oz, 64);
+            }
+            __syncthreads();
+            // ---- column phase: inverse column DFTs, coupling (Eq. (9)-(12)),
+            // forward column DFTs of the next step
+            const bool last = n + 1 == nend;
+#pragma unroll 1
+            for (int cr = 0; cr < COL_ROUNDS; ++cr) {
+                const int oz = (n + cr) & d.opaque_zero;
+                const int c = cr * COLS_PER_ROUND + wv * GPW + gi;
+                Cx<T> vp[E], vm[E];
+                load(vp, vm, st, lc * C + c + oz, LC * C);
+                ColM::inv_local(vp, vm, tw + (TW_COL + oz), CRp, CRm, lc, true);
+                cpl.template apply<E, LC * C>(vp, vm, d, n, lc * C + c);
+                if (!last) {
+                    const int of = (n + cr + 1) & d.opaque_zero;
+                    ColM::fwd_local(vp, vm, tw + (TW_COL + of), CRp, CRm, lc, true);
+                } else if (rt_out) {
+                    det_sums(vp, vm, d, lc * C + c, LC * C, sp, sm);
+                }
+                store(st, vp, vm, lc * C + c, LC * C);
+            }
+        }
+
+        if (rt_out) {
+            sp = RowM::block_sum(sp, red, t0);
+            sm = RowM::block_sum(sm, red, t0);
+            if (t0 == 0) {
+                if (!(d.flags & SF_FIRST)) pin = d.pin ? *d.pin : 0.0;
+                rt[2 * d.rt_index] = pin > 0.0 ? sm / pin : 0.0;
+                rt[2 * d.rt_index + 1] = pin > 0.0 ? sp / pin : 0.0;
+            }
+        }
+    }
+};
+
 // Sizes the march kernels are built for.  Uniform kernels: one solve per
 // workgroup of nx/E threads; mixed kernel: 2^kMixedLog2Th threads, any nx in
-// [2^mix_lo, 2^mix_hi] within one grid.
+// [2^mix_lo, 2^mix_hi] within one grid; staged kernels: nx in [2^stg_lo, 2^stg_hi].
 template <typename T>
 struct Limits;
 template <>
 struct Limits<float> {
-    static constexpr int uni_lo = 6, uni_hi = 14, mix_lo = 10, mix_hi = 14;
+    static constexpr int uni_lo = 6, uni_hi = 14, mix_lo = 10, mix_hi = 14, stg_lo = 15, stg_hi = 16;
 };
 template <>
 struct Limits<double> {
-    static constexpr int uni_lo = 6, uni_hi = 13, mix_lo = 10, mix_hi = 13;
+    static constexpr int uni_lo = 6, uni_hi = 13, mix_lo = 10, mix_hi = 13, stg_lo = 14, stg_hi = 16;
 };
 constexpr int kMixedLog2Th = 9;
 // threads a size uses inside the mixed kernel's 512-thread workgroups (the

@@ -1,5 +1,5 @@
-// bpm_march_kernels.hpp — march kernels and their launch logic, instantiated once
-// per precision (march_f32.hip, march_f64.hip).
+// bpm_march_kernels.hpp — march kernels and their launch logic; the build
+// instantiates each (precision, size, strain class) in its own unit.
 #pragma once
 
 #include "bpm_march.hpp"
@@ -65,6 +65,35 @@ hipError_t launch_uniform(const SolveDesc *d_descs, int n, const char *in_base, 
         attr_set = true;
     }
     hipLaunchKernelGGL((k_march_uniform<T, LOG2N, SC>), dim3(n), dim3(th), lds, s, d_descs, n, in_base, out_base, rt);
+    return hipGetLastError();
+}
+
+// One solve per workgroup for the staged sizes (Staged<>): 8 waves, one
+// workgroup per compute unit (LDS), 2 waves per SIMD.
+template <typename T, int LOG2N, int SC>
+__global__ __launch_bounds__(1 << kStagedLog2Th) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_march_staged(const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[16];
+    Staged<T, LOG2N, SC>::run(descs[blockIdx.x], in_base, out_base, rt, reinterpret_cast<Cx<T> *>(smem), red);
+}
+
+template <typename T, int LOG2N, int SC>
+hipError_t launch_staged(const SolveDesc *d_descs, int n, const char *in_base, char *out_base, double *rt,
+                         hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const size_t lds = Staged<T, LOG2N, SC>::lds_bytes;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_staged<T, LOG2N, SC>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_march_staged<T, LOG2N, SC>), dim3(n), dim3(1 << kStagedLog2Th), lds, s, d_descs, n, in_base,
+                       out_base, rt);
     return hipGetLastError();
 }
 

@@ -5,8 +5,10 @@ namespace bpm {
 
 // ----------------------------------------------------------------- setup kernels
 // FP64 plan setup: coupling harmonics and propagator tables (one launch per plan).
+// The table of a staged size is stored in [k1][k2] order (frequency
+// f = k1 + R k2 at k1*(nx/R) + k2, R = 2^log2r); log2r = 0 keeps natural order.
 template <typename T>
-__global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, Cx<T> *prop)
+__global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, Cx<T> *prop, int log2r)
 {
     const PlanParams P = *pp;
     const double k = 2.0 * M_PI / P.lambda;
@@ -71,7 +73,8 @@ __global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, Cx<T> *prop)
                 kx = mag * cos(dzh * c) - 1.0;
                 ky = -mag * sin(dzh * c);
             }
-            prop[beam * nx + f] = {(T)(kx * invn), (T)(ky * invn)};
+            const int pos = log2r ? (f & ((1 << log2r) - 1)) * (nx >> log2r) + (f >> log2r) : f;
+            prop[beam * nx + pos] = {(T)(kx * invn), (T)(ky * invn)};
         }
     }
 }
@@ -97,6 +100,34 @@ __host__ __device__ inline int schedule_radices(int log2n, int log2e, int *lr)
 // exactly in integers.  FP64 tables store (cos, sin); FP32 tables store the
 // lifting constants p = -tan(phi/2), u = sin(phi) of the angle folded into
 // [-pi/2, pi/2] and the exact sign s (= -1 when the fold took out a half turn).
+// Rotation exp(-2 pi i q / M) for an integer exponent q (reduced exactly
+// before any rounding).  FP64 stores (cos, sin); FP32 stores the lifting
+// constants p = -tan(phi/2), u = sin(phi) of the angle folded into
+// [-pi/2, pi/2] and the exact sign s (= -1 when the fold took out a half turn).
+template <typename T>
+__device__ Tw<T> encode_rotation(long long q, long long M)
+{
+    q %= M;
+    if (q < 0) q += M;
+    if (q > M / 2) q -= M;                  // (-M/2, M/2]
+    if constexpr (std::is_same<T, float>::value) {
+        float sgn = 1.0f;
+        if (4 * q > M || 4 * q < -M) {      // |angle| > pi/2: take out -1
+            q += q > 0 ? -M / 2 : M / 2;
+            sgn = -1.0f;
+        }
+        const double pl = tan(M_PI * (double)q / (double)M);
+        const double ul = -sinpi(2.0 * (double)q / (double)M);
+        return {(float)pl, (float)ul, sgn, 0.0f};
+    } else {
+        double sn, cs;
+        sincospi(-2.0 * (double)q / (double)M, &sn, &cs);
+        return {cs, sn};
+    }
+}
+
+// Twiddle table: pass p (sub-length L, radix r), entry (m-1)*L + j holds the
+// rotation exp(-2 pi i j m / (L r)), m = 1..r-1, j < L.
 template <typename T>
 __global__ void k_twiddles(Tw<T> *tw, int log2n, int log2e)
 {
@@ -109,26 +140,21 @@ __global__ void k_twiddles(Tw<T> *tw, int log2n, int log2e)
         const int cnt = L * (r - 1);
         if (idx >= base && idx < base + cnt) {
             const int m = (idx - base) / L + 1, j = (idx - base) % L;
-            const long long M = (long long)L * r;
-            long long q = ((long long)j * m) % M;   // angle -2 pi q / M
-            if (q > M / 2) q -= M;                  // (-M/2, M/2]
-            if constexpr (std::is_same<T, float>::value) {
-                float sgn = 1.0f;
-                if (4 * q > M || 4 * q < -M) {      // |angle| > pi/2: take out -1
-                    q += q > 0 ? -M / 2 : M / 2;
-                    sgn = -1.0f;
-                }
-                const double pl = tan(M_PI * (double)q / (double)M);
-                const double ul = -sinpi(2.0 * (double)q / (double)M);
-                tw[idx] = {(float)pl, (float)ul, sgn, 0.0f};
-            } else {
-                double sn, cs;
-                sincospi(-2.0 * (double)q / (double)M, &sn, &cs);
-                tw[idx] = {cs, sn};
-            }
+            tw[idx] = encode_rotation<T>((long long)j * m, (long long)L * r);
         }
         base += cnt;
         ll += lr[p];
+    }
+}
+
+// Four-step twiddles of a staged size: entry k1*C + n2 = W_N^{n2 k1}.
+template <typename T>
+__global__ void k_twiddles4(Tw<T> *tw, int log2n, int log2c)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < (1 << log2n)) {
+        const long long k1 = idx >> log2c, n2 = idx & ((1 << log2c) - 1);
+        tw[idx] = encode_rotation<T>(n2 * k1, 1ll << log2n);
     }
 }
 
@@ -173,13 +199,65 @@ hipError_t launch_twiddles(void *d_tw, int prec, int log2n, int log2e, hipStream
 }
 
 hipError_t launch_plan_setup(const PlanParams *d_params, PlanScalars *d_sc, void *d_prop, int prec, int nx,
-                             hipStream_t s)
+                             int log2r, hipStream_t s)
 {
     const int bs = 256, gs = d_prop ? (nx + bs - 1) / bs : 1;
     if (prec == PREC_F32)
-        hipLaunchKernelGGL(k_plan_setup<float>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (Cx<float> *)d_prop);
+        hipLaunchKernelGGL(k_plan_setup<float>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (Cx<float> *)d_prop, log2r);
     else
-        hipLaunchKernelGGL(k_plan_setup<double>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (Cx<double> *)d_prop);
+        hipLaunchKernelGGL(k_plan_setup<double>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (Cx<double> *)d_prop,
+                           log2r);
+    return hipGetLastError();
+}
+
+// Staged sizes: twiddle layout [row FFT | column FFT | four-step], as Staged<> reads it.
+template <typename T>
+static bool staged_layout_T(int log2n, int *tw_col, int *tw_4, int *total)
+{
+    bool ok = false;
+    static_for<Limits<T>::stg_lo, Limits<T>::stg_hi + 1>([&](auto l) {
+        using S = Staged<T, CV(l), SC_NONE>;
+        if (log2n == CV(l)) {
+            *tw_col = S::TW_COL;
+            *tw_4 = S::TW_4;
+            *total = S::TW_TOTAL;
+            ok = true;
+        }
+    });
+    return ok;
+}
+
+bool is_staged(int prec, int log2n)
+{
+    return prec == PREC_F32 ? log2n >= Limits<float>::stg_lo : log2n >= Limits<double>::stg_lo;
+}
+
+size_t staged_twiddle_bytes(int prec, int log2n)
+{
+    int a = 0, b = 0, tot = 0;
+    const bool ok = prec == PREC_F32 ? staged_layout_T<float>(log2n, &a, &b, &tot)
+                                     : staged_layout_T<double>(log2n, &a, &b, &tot);
+    return ok ? (size_t)tot * 16 : 0;
+}
+
+hipError_t launch_staged_twiddles(void *d_tw, int prec, int log2n, hipStream_t s)
+{
+    int tw_col = 0, tw_4 = 0, tot = 0;
+    const bool ok = prec == PREC_F32 ? staged_layout_T<float>(log2n, &tw_col, &tw_4, &tot)
+                                     : staged_layout_T<double>(log2n, &tw_col, &tw_4, &tot);
+    const int le = staged_log2e(prec), lc = staged_log2c(prec), log2r = log2n - lc;
+    if (!ok || tw_count(lc, le) != tw_col || tw_col + tw_count(log2r, le) != tw_4) return hipErrorInvalidValue;
+    char *base = static_cast<char *>(d_tw);
+    hipError_t e = launch_twiddles(base, prec, lc, le, s);
+    if (e == hipSuccess) e = launch_twiddles(base + (size_t)tw_col * 16, prec, log2r, le, s);
+    if (e != hipSuccess) return e;
+    const int n = 1 << log2n, bs = 256;
+    if (prec == PREC_F32)
+        hipLaunchKernelGGL(k_twiddles4<float>, dim3((n + bs - 1) / bs), dim3(bs), 0, s,
+                           (Tw<float> *)(base + (size_t)tw_4 * 16), log2n, lc);
+    else
+        hipLaunchKernelGGL(k_twiddles4<double>, dim3((n + bs - 1) / bs), dim3(bs), 0, s,
+                           (Tw<double> *)(base + (size_t)tw_4 * 16), log2n, lc);
     return hipGetLastError();
 }
 
@@ -206,6 +284,8 @@ template <typename T, int LOG2N, int SC>
 hipError_t launch_uniform(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
 template <typename T, int SC>
 hipError_t launch_mixed(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
+template <typename T, int LOG2N, int SC>
+hipError_t launch_staged(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
 
 
 template <typename T, int SC>
@@ -216,6 +296,9 @@ static hipError_t dispatch(const SolveDesc *d_descs, int n, int uniform_log2n, c
     hipError_t err = hipErrorInvalidValue;
     static_for<Limits<T>::uni_lo, Limits<T>::uni_hi + 1>([&](auto l) {
         if (uniform_log2n == CV(l)) err = launch_uniform<T, CV(l), SC>(d_descs, n, in_base, out_base, rt, s);
+    });
+    static_for<Limits<T>::stg_lo, Limits<T>::stg_hi + 1>([&](auto l) {
+        if (uniform_log2n == CV(l)) err = launch_staged<T, CV(l), SC>(d_descs, n, in_base, out_base, rt, s);
     });
     return err;
 }
@@ -248,6 +331,12 @@ static void shape_T(int log2n, int *threads, size_t *lds)
             *lds = LdsPlan<T, L2, uniform_log2e(L2)>::bytes;
         }
     });
+    static_for<Limits<T>::stg_lo, Limits<T>::stg_hi + 1>([&](auto l) {
+        if (log2n == CV(l)) {
+            *threads = 1 << kStagedLog2Th;
+            *lds = Staged<T, CV(l), SC_NONE>::lds_bytes;
+        }
+    });
 }
 
 template <typename T>
@@ -272,7 +361,7 @@ void mixed_shape(int prec, int *threads, size_t *lds_bytes)
     *threads = 1 << kMixedLog2Th;
     *lds_bytes = prec == PREC_F32 ? mixed_lds_T<float>() : mixed_lds_T<double>();
 }
-int max_log2n(int prec) { return prec == PREC_F32 ? Limits<float>::uni_hi : Limits<double>::uni_hi; }
+int max_log2n(int prec) { return prec == PREC_F32 ? Limits<float>::stg_hi : Limits<double>::stg_hi; }
 int mixed_min_log2n(int prec) { return prec == PREC_F32 ? Limits<float>::mix_lo : Limits<double>::mix_lo; }
 int mixed_max_log2n(int prec) { return prec == PREC_F32 ? Limits<float>::mix_hi : Limits<double>::mix_hi; }
 int mixed_log2e(int prec, int log2n) { return log2n - mixed_log2th(log2n); }

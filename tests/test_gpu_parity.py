@@ -61,7 +61,7 @@ def with_prec(p, prec):
 
 # ------------------------------------------------------------------ every kernel size
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("log2n", list(range(6, 15)))
+@pytest.mark.parametrize("log2n", list(range(6, 17)))
 def test_every_uniform_size_random_fields_ragged_mask(prec, log2n):
     B = bpm()
     nx = 1 << log2n
@@ -149,6 +149,37 @@ def test_zero_steps_and_empty_crystal(prec):
     check(p1, a, b, "vacuum")
 
 
+# ------------------------------------------------------------------ staged (four-step) sizes
+@pytest.mark.parametrize("prec,nx", [("f32", 32768), ("f64", 16384), ("f64", 32768)])
+def test_staged_bent_laue(prec, nx):
+    cases = synth.bent_laue(radii_m=(0.5,), nx=nx, nz=240, thickness=6.0, precision=prec)
+    p, psi = cases[0]
+    check(p, psi, label="staged-bent-%d" % nx)
+
+
+@pytest.mark.parametrize("prec,nx", [("f32", 32768), ("f64", 16384)])
+def test_staged_dislocation_trapezoid(prec, nx):
+    p, psi = synth.disl_bragg(nx=nx, nz=300, scale=nx / 32768 * 0.04, precision=prec)
+    check(p, psi, label="staged-disl-%d" % nx)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_staged_strain_table_ragged_two_intervals(prec):
+    nx = 16384 if prec == "f64" else 32768
+    nz = 60
+    seg = np.zeros((nz, 2, 2), np.int32)
+    for n in range(nz):
+        seg[n, 0] = (17 + 13 * n, nx // 3 + 5 * n)
+        seg[n, 1] = (nx // 2 - 7 * n, nx - 19 - 3 * n)
+    rng = synth.SplitMix64(91)
+    u = np.array([[2e-4 * math.sin(0.003 * j + 0.05 * n) + 1e-6 * rng.uniform() for j in range(nx)]
+                  for n in range(nz)])
+    p = synth.base_problem(nx, nz, 0.1, 0.05, seg, precision=prec, det=(nx // 9, nx - nx // 7),
+                           strain={"kind": "table", "u_table": u})
+    a, b = synth.random_envelopes(nx, 5)
+    check(p, a, 0.5 * b, "staged-table")
+
+
 def test_fp32_long_march_error_budget():
     """Nz = 8000 FP32 Bragg solve stays inside the FP32 bars (no linear drift)."""
     cases = synth.flat_bragg_scan(n_angles=1, nx=4096, nz=8000, precision="f32")
@@ -197,6 +228,42 @@ def test_mixed_size_batch_one_launch_matches_oracle(prec):
         say("mixed", i, cases[i][0]["nx"], cases[i][0]["nz"], "%.3e" % err)
         assert err <= tol
         assert abs(rt[2 * i] - oR[i]) <= rtol and abs(rt[2 * i + 1] - oT[i]) <= rtol
+
+
+def test_staged_sizes_in_batch_and_chunked_server_equal_single_solves():
+    """A batch holding staged and register-resident sizes reproduces the single
+    solves bitwise, and so does a staged solve marched in server chunks (its
+    state returns to natural order between launches)."""
+    B = bpm()
+    import torch
+    cases = [synth.bent_laue(radii_m=(0.7,), nx=32768, nz=150, thickness=4.0, precision="f32")[0],
+             synth.flat_bragg_scan(n_angles=1, nx=4096, nz=150, precision="f32")[0],
+             synth.bent_laue(radii_m=(2.0,), nx=65536, nz=90, thickness=3.0, precision="f32")[0]]
+    plans = [B.Plan(p) for p, _ in cases]
+    batch = B.Batch(plans)
+    buf = batch.pack([(psi, None) for _, psi in cases])
+    rt = torch.zeros(2 * len(plans), dtype=torch.float64, device="cuda")
+    batch.run(buf.data_ptr(), buf.data_ptr(), rt.data_ptr())
+    torch.cuda.synchronize()
+    outs = batch.unpack(buf)
+    rt = rt.cpu().numpy()
+    singles = []
+    for i, (pl, (p, psi)) in enumerate(zip(plans, cases)):
+        sp, sm, sR, sT = pl.propagate(psi)
+        singles.append((sp, sm, sR))
+        say("staged batch", i, p["nx"], "bitwise", np.array_equal(outs[i][0], sp))
+        assert np.array_equal(outs[i][0], sp) and np.array_equal(outs[i][1], sm)
+        assert rt[2 * i] == sR and rt[2 * i + 1] == sT
+    op, om, oR, _ = oracle.propagate(*cases[2])
+    assert rel_pair(singles[2][0], singles[2][1], op, om) <= TOL["f32"][0]
+    srv = B.Server(hbm_budget_bytes=1 << 30, max_slots=8, chunk_steps=37)
+    t = srv.submit(*cases[0])
+    assert srv.drain(120.0)
+    r = srv.poll(t)
+    assert r["status"] == 0
+    assert np.array_equal(r["psi_p"], singles[0][0]) and np.array_equal(r["psi_m"], singles[0][1])
+    assert r["R"] == singles[0][2]
+    srv.close()
 
 
 # ------------------------------------------------------------------ server
