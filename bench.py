@@ -7,7 +7,11 @@ envelopes already resident in HBM).  Default workload: the Laue bent-crystal
 case, Nx = 16384, Nz = 8000, dz = 0.025 um, bend radii R = 1, 0.1, 10 m, FP32,
 85 seeded Gaussian beams per radius (255 solves, one per compute unit).
 
-Prints one JSON line (metric, value, roofline, cpu_baseline, ...).
+After the headline it reports, as side legs, one FP64 flat-Bragg solve alone,
+the dislocation batch (Nx 32768), the pulse-component batch (mixed sizes, one
+launch) and the serving mix (p50/p99 latency), and the FP64 oracle on the host.
+
+Prints one JSON line (metric, value, roofline, cpu_baseline, legs, ...).
 """
 from __future__ import annotations
 
@@ -98,6 +102,49 @@ def fp64_plain(bpm, torch, synth):
             "workload": "flat_bragg Nx 4096 Nz 2000, one FP64 solve", "ms": sum(per) / len(per)}
 
 
+def leg_batch(bpm, torch, cases, label, steps=1, warmup=1):
+    """Throughput of one workload batch in one launch per step."""
+    print("leg %s: %d solves" % (label, len(cases)), file=sys.stderr, flush=True)
+    per, total, _, _ = time_batch(bpm, torch, cases, steps, warmup)
+    cs = sum(2.0 * p["nx"] * p["nz"] for p, _ in cases)
+    ms = total / steps
+    return {"value": cs / (ms / 1e3), "unit": "cell-steps/s", "ms_per_step": ms, "solves": len(cases),
+            "cell_steps": cs}
+
+
+def leg_serve(bpm, synth, n_req, rate_hz, budget_gb, chunk_steps):
+    """Serving mix: a seeded Poisson stream submitted in real time to the
+    continuous-batching server; latency = submit -> done on the server clock."""
+    reqs = synth.serve_mix(n_req=n_req, rate_hz=rate_hz)
+    print("leg serving: %d requests at %.0f/s" % (n_req, rate_hz), file=sys.stderr, flush=True)
+    srv = bpm.Server(hbm_budget_bytes=int(budget_gb * (1 << 30)), max_slots=1024, chunk_steps=chunk_steps)
+    t0 = time.perf_counter()
+    tickets = []
+    for r in reqs:
+        dt = t0 + r["t_arrival"] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(r["problem"], r["psi_p0"], want_fields=False))
+    drained = srv.drain(900.0)
+    res = [srv.poll(t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    good = [(r, x) for r, x in zip(reqs, res) if x is not None and x["status"] == 0]
+    lat = sorted((x["t_done"] - x["t_submit"]) * 1e3 for _, x in good)
+
+    def q(v, f):
+        return v[min(len(v) - 1, max(0, int(math.ceil(f * len(v))) - 1))] if v else None
+
+    span = max(x["t_done"] for _, x in good) - min(x["t_submit"] for _, x in good) if good else 0.0
+    cs = sum(2.0 * r["nx"] * r["nz"] for r, _ in good)
+    return {"requests": n_req, "completed": len(good), "drained": bool(drained), "rate_hz": rate_hz,
+            "p50_ms": q(lat, 0.5), "p99_ms": q(lat, 0.99), "max_ms": lat[-1] if lat else None,
+            "value": cs / span if span > 0 else None, "unit": "cell-steps/s",
+            "offered": sum(2.0 * r["nx"] * r["nz"] for r in reqs) / reqs[-1]["t_arrival"],
+            "launches": stats["launches"], "peak_bytes": stats["peak_bytes"], "chunk_steps": chunk_steps,
+            "budget_gb": budget_gb}
+
+
 def cpu_baseline(cases, target_s=12.0):
     """The FP64 oracle on the host cores over a bounded sample of the workload."""
     import oracle
@@ -151,6 +198,13 @@ def main():
     ap.add_argument("--nz", type=int, default=None, help="shorter march (profiling runs only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
+    ap.add_argument("--legs", default="cfg2,cfg3,cfg4",
+                    help="extra workloads after the headline: cfg2 (dislocation, Nx 32768), cfg3 (pulse "
+                         "components, one mixed launch), cfg4 (serving mix); 'none' for the headline only")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-chunk", type=int, default=256)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -212,6 +266,25 @@ def main():
         out["fp64_plain"] = fp64_plain(bpm, torch, synth)
         out["fp32_batched_over_fp64_plain"] = value / out["fp64_plain"]["value"]
     out["R_mean"] = float(np.mean(Rs[0::2]))
+    legs = {}
+    want = set() if args.legs == "none" else set(args.legs.split(","))
+    if "cfg2" in want:
+        legs["cfg2_dislocation"] = dict(
+            leg_batch(bpm, torch, synth.disl_bragg_cores(256), "cfg2"),
+            workload="asymmetric Bragg trapezoid + edge dislocation, Nx 32768, Nz 16000, FP32, "
+                     "256 seeded core positions")
+    if "cfg3" in want:
+        legs["cfg3_td_batch"] = dict(
+            leg_batch(bpm, torch, synth.td_batch(), "cfg3"),
+            workload="1024 spectral components of a 20 fs pulse, Nx 2048-16384, Nz 1000-8000, FP32, "
+                     "one mixed-size launch")
+    if "cfg4" in want:
+        legs["cfg4_serving"] = dict(
+            leg_serve(bpm, synth, args.serve_requests, args.serve_rate, args.serve_budget_gb, args.serve_chunk),
+            workload="Poisson stream, Nx 1024-65536 log-uniform, Nz 500-20000, flat/bent/dislocation/"
+                     "trapezoid, 20% FP64")
+    if legs:
+        out["legs"] = legs
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cases)
     print(json.dumps(out), flush=True)

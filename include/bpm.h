@@ -150,15 +150,19 @@ void bpm_batch_destroy(bpm_batch *batch);
 
 /* --- serving (continuous batching) ------------------------------------------
  * A server owns a device-memory budget and a pool of solve slots.  A worker
- * thread advances all admitted solves together, `chunk_steps` z-steps per
- * launch; between launches it retires finished solves and admits waiting
- * requests whose state and tables fit the budget, so requests that arrive while
- * others run join the next launch.  Per-solve arithmetic does not depend on what
- * else is in the launch, so a result is the same alone and in the mix. */
+ * thread advances all admitted solves together in rounds: per precision one
+ * stream and one launch per strain class that takes every size side by side
+ * (sizes below 1024 launch separately).  A solve of size nx advances
+ * chunk_steps*16384/nx z-steps per round (at least 1), so every class takes
+ * about the same time per round.  While a round runs, the worker builds the
+ * plans and entrance states of requests admitted in arrival order whose state
+ * and tables fit the budget; after it, finished solves are retired and the new
+ * ones join the next round.  Per-solve arithmetic does not depend on what else
+ * is in the launch, so a result is the same alone and in the mix. */
 typedef struct bpm_server_desc {
     size_t hbm_budget_bytes;   /* device bytes the server may hold for admitted solves */
     int32_t max_slots;         /* max solves in flight */
-    int32_t chunk_steps;       /* z-steps per launch (>= 1) */
+    int32_t chunk_steps;       /* z-steps per round at nx = 16384 (>= 1); scaled by 16384/nx */
 } bpm_server_desc;
 
 typedef struct bpm_request {

@@ -63,6 +63,10 @@ def _gen_units() -> list[str]:
                       "template hipError_t launch_staged<%s, %d, %d>(const SolveDesc *, int, const char *, "
                       "char *, double *, hipStream_t);\n}\n" % (t, l2, sc))
         for t in MIXED:
+            write("march_any_%s_sc%d.hip" % (t, sc),
+                  '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
+                  "template hipError_t launch_any<%s, %d>(const SolveDesc *, int, const char *, char *, "
+                  "double *, hipStream_t);\n}\n" % (t, sc))
             write("march_mixed_%s_sc%d.hip" % (t, sc),
                   '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
                   "template hipError_t launch_mixed<%s, %d>(const SolveDesc *, int, const char *, char *, "
@@ -86,7 +90,8 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
     srcs = [os.path.join(CSRC, f) for f in ("bpm_setup.hip", "bpm_api.cpp", "bpm_server.cpp")]
     srcs += _gen_units()
     # largest units first
-    srcs.sort(key=lambda s: ("mixed" not in s, not any(("_%d_" % k) in s for k in (12, 13, 14, 15, 16))))
+    srcs.sort(key=lambda s: ("_any_" not in s, "mixed" not in s,
+                            not any(("_%d_" % k) in s for k in (12, 13, 14, 15, 16))))
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))

@@ -87,6 +87,26 @@ bpm_status bpm::ensure_device()
     return BPM_OK;
 }
 
+// ------------------------------------------------------------------ setup stream
+// Plan setup (table kernels, uploads) runs on a library-owned non-blocking
+// stream per device and waits only for that stream, so creating a plan never
+// waits for marches running on other streams.
+static std::mutex g_setup_mu;
+static std::map<int, hipStream_t> g_setup;
+
+hipStream_t bpm::setup_stream()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_setup_mu);
+    auto it = g_setup.find(dev);
+    if (it != g_setup.end()) return it->second;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+    g_setup[dev] = st;
+    return st;
+}
+
 // ------------------------------------------------------------------ twiddle cache
 // One table per (precision, nx, elements per thread), shared by every plan.
 static std::mutex g_tw_mu;
@@ -107,8 +127,9 @@ bpm_status bpm::twiddle_table(int prec, int log2n, int log2e, const void **out)
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) return hip_fail(e, "twiddle table");
-    e = log2e ? launch_twiddles(p, prec, log2n, log2e, nullptr) : launch_staged_twiddles(p, prec, log2n, nullptr);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    hipStream_t ss = setup_stream();
+    e = log2e ? launch_twiddles(p, prec, log2n, log2e, ss) : launch_staged_twiddles(p, prec, log2n, ss);
+    if (e == hipSuccess) e = hipStreamSynchronize(ss);
     if (e != hipSuccess) {
         (void)hipFree(p);
         return hip_fail(e, "twiddle setup kernel");
@@ -149,8 +170,9 @@ static bpm_status prop_acquire(const bpm_plan_desc &d, const PlanParams *d_param
     int log2n = 0;
     while ((1 << log2n) < d.nx) ++log2n;
     const int log2r = is_staged(d.precision, log2n) ? log2n - staged_log2c(d.precision) : 0;
-    e = launch_plan_setup(d_params, nullptr, p, d.precision, d.nx, log2r, nullptr);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    hipStream_t ss = setup_stream();
+    e = launch_plan_setup(d_params, nullptr, p, d.precision, d.nx, log2r, ss);
+    if (e == hipSuccess) e = hipStreamSynchronize(ss);
     if (e != hipSuccess) {
         (void)hipFree(p);
         return hip_fail(e, "propagator setup kernel");
@@ -342,11 +364,13 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
     pp.chihy = d->chih.im;
     pp.chihbx = d->chihbar.re;
     pp.chihby = d->chihbar.im;
-    hipError_t e = hipMemcpy(p->d_params, &pp, sizeof pp, hipMemcpyHostToDevice);
+    hipStream_t ss = setup_stream();
+    hipError_t e = hipMemcpyAsync(p->d_params, &pp, sizeof pp, hipMemcpyHostToDevice, ss);
     if (e == hipSuccess && nz > 0)
-        e = hipMemcpy(p->d_seg, d->seg, nz * d->nseg * 2 * sizeof(int32_t), hipMemcpyHostToDevice);
+        e = hipMemcpyAsync(p->d_seg, d->seg, nz * d->nseg * 2 * sizeof(int32_t), hipMemcpyHostToDevice, ss);
+    if (e == hipSuccess) e = hipStreamSynchronize(ss);
     if (e != hipSuccess) return bail(hip_fail(e, "plan upload"));
-    e = launch_plan_setup(p->d_params, p->d_sc, nullptr, prec, d->nx, 0, nullptr);
+    e = launch_plan_setup(p->d_params, p->d_sc, nullptr, prec, d->nx, 0, ss);
     if (e != hipSuccess) return bail(hip_fail(e, "plan setup kernel"));
     if ((st = prop_acquire(*d, p->d_params, &p->d_prop)) != BPM_OK) return bail(st);
 
@@ -357,14 +381,14 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
             (void)hipFree(d_u);
             return bail(st);
         }
-        e = hipMemcpy(d_u, d->strain.u_table, nz * nx * sizeof(double), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = launch_utab(d_u, p->d_utab, prec, nz * nx, 1.0 / d->d_um, nullptr);
-        if (e == hipSuccess) e = hipDeviceSynchronize();
+        e = hipMemcpyAsync(d_u, d->strain.u_table, nz * nx * sizeof(double), hipMemcpyHostToDevice, ss);
+        if (e == hipSuccess) e = launch_utab(d_u, p->d_utab, prec, nz * nx, 1.0 / d->d_um, ss);
+        if (e == hipSuccess) e = hipStreamSynchronize(ss);
         (void)hipFree(d_u);
         if (e != hipSuccess) return bail(hip_fail(e, "strain table"));
         p->device_bytes += nz * nx * (prec == BPM_F32 ? 4 : 8);
     }
-    e = hipDeviceSynchronize();
+    e = hipStreamSynchronize(ss);
     if (e != hipSuccess) return bail(hip_fail(e, "plan setup"));
 
     const int log2e = uniform_log2e(p->log2n);
@@ -376,7 +400,8 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
     SolveDesc s;
     p->fill(s, log2e, p->tw_uniform, SF_FIRST | SF_LAST, 0, d->nz, 0, 0, 0);
     if ((st = dev_alloc(&p->d_desc1, sizeof s, "launch descriptor")) != BPM_OK) return bail(st);
-    e = hipMemcpy(p->d_desc1, &s, sizeof s, hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(p->d_desc1, &s, sizeof s, hipMemcpyHostToDevice, ss);
+    if (e == hipSuccess) e = hipStreamSynchronize(ss);
     if (e != hipSuccess) return bail(hip_fail(e, "descriptor upload"));
     *out = p;
     return BPM_OK;
@@ -497,7 +522,7 @@ extern "C" bpm_status bpm_propagate(bpm_plan *p, const bpm_complex *psi_p0, cons
 bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<int> &rt_index,
                                const std::vector<uint64_t> &in_off, const std::vector<uint64_t> &out_off,
                                const std::vector<int> &step0, const std::vector<int> &nsteps,
-                               const std::vector<int> &flags, std::vector<Launch> &launches)
+                               const std::vector<int> &flags, std::vector<Launch> &launches, bool any_size)
 {
     launches.clear();
     for (int prec : {BPM_F32, BPM_F64})
@@ -516,12 +541,31 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
         }
         std::vector<std::vector<int>> groups;
         std::vector<int> group_log2n;
-        if (lo == hi) {
+        if (any_size) {
+            // one launch for every size the any-size kernel takes, the rest per
+            // size; a size always meets the same kernel, whatever else is launched
+            std::vector<int> big;
+            for (int i : idx)
+                if (plans[i]->log2n >= mixed_min_log2n(prec)) big.push_back(i);
+            if (!big.empty()) {
+                groups.push_back(big);
+                group_log2n.push_back(kLaunchAny);
+            }
+            for (int l = lo; l < mixed_min_log2n(prec); ++l) {
+                std::vector<int> g;
+                for (int i : idx)
+                    if (plans[i]->log2n == l) g.push_back(i);
+                if (!g.empty()) {
+                    groups.push_back(g);
+                    group_log2n.push_back(l);
+                }
+            }
+        } else if (lo == hi) {
             groups.push_back(idx);
             group_log2n.push_back(lo);
         } else if (lo >= mixed_min_log2n(prec) && hi <= mixed_max_log2n(prec)) {
             groups.push_back(idx);
-            group_log2n.push_back(-1);
+            group_log2n.push_back(kLaunchMixed);
         } else {
             for (int l = lo; l <= hi; ++l) {
                 std::vector<int> g;
@@ -544,7 +588,7 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
                 const bpm_plan *p = plans[i];
                 const void *tw = p->tw_uniform;
                 int log2e = uniform_log2e(p->log2n);
-                if (L.uniform_log2n < 0) {
+                if (L.uniform_log2n < 0 && !is_staged(prec, p->log2n)) {
                     log2e = mixed_log2e(prec, p->log2n);
                     bpm_status st = twiddle_table(prec, p->log2n, log2e, &tw);
                     if (st != BPM_OK) return st;
@@ -559,7 +603,7 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
     return BPM_OK;
 }
 
-bpm_status bpm::upload_launches(std::vector<Launch> &launches)
+bpm_status bpm::upload_launches(std::vector<Launch> &launches, hipStream_t s)
 {
     for (auto &L : launches) {
         if (!L.d_descs) {
@@ -567,7 +611,11 @@ bpm_status bpm::upload_launches(std::vector<Launch> &launches)
             hipError_t e = hipMalloc((void **)&L.d_descs, std::max<size_t>(L.d_cap, 1) * sizeof(SolveDesc));
             if (e != hipSuccess) return hip_fail(e, "descriptor buffer");
         }
-        hipError_t e = hipMemcpy(L.d_descs, L.host.data(), L.host.size() * sizeof(SolveDesc), hipMemcpyHostToDevice);
+        // on stream s the host copy must stay alive until the stream passes this point
+        hipError_t e = s ? hipMemcpyAsync(L.d_descs, L.host.data(), L.host.size() * sizeof(SolveDesc),
+                                          hipMemcpyHostToDevice, s)
+                         : hipMemcpy(L.d_descs, L.host.data(), L.host.size() * sizeof(SolveDesc),
+                                     hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "descriptor upload");
     }
     return BPM_OK;

@@ -40,6 +40,8 @@ bpm_status ensure_device();
 bpm_status validate_desc(const bpm_plan_desc *d);
 bpm_status check_input(const bpm_plan_desc &d, const bpm_complex *a, const bpm_complex *b);
 bpm_status twiddle_table(int prec, int log2n, int log2e, const void **out);
+// Library-owned non-blocking stream of the current device for plan setup.
+hipStream_t setup_stream();
 
 // One kernel launch over a group of solves.
 struct Launch {
@@ -52,11 +54,17 @@ struct Launch {
     size_t d_cap = 0;
 };
 
+// Group solves into launches: per (precision, strain class), one uniform launch
+// when all share nx, one mixed launch when all sizes fit the mixed kernel, and
+// otherwise per size.  With any_size, every size the any-size kernel takes goes
+// into one launch of it (whatever the mix, so a solve's arithmetic never depends
+// on what else is launched) and smaller sizes per size.  Longest solves first.
 bpm_status build_launches(bpm_plan *const *plans, int n, const std::vector<int> &rt_index,
                           const std::vector<uint64_t> &in_off, const std::vector<uint64_t> &out_off,
                           const std::vector<int> &step0, const std::vector<int> &nsteps,
-                          const std::vector<int> &flags, std::vector<Launch> &launches);
-bpm_status upload_launches(std::vector<Launch> &launches);
+                          const std::vector<int> &flags, std::vector<Launch> &launches, bool any_size = false);
+// Descriptor upload: blocking when s is NULL, else ordered on stream s.
+bpm_status upload_launches(std::vector<Launch> &launches, hipStream_t s = nullptr);
 bpm_status run_launches(const std::vector<Launch> &launches, hipStream_t s, const char *in, char *out,
                         double *rt);
 void free_launches(std::vector<Launch> &launches);

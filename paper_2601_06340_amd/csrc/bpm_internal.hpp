@@ -85,8 +85,11 @@ hipError_t launch_utab(const double *d_u, void *d_tab, int prec, size_t count, d
                        hipStream_t s);
 // March every solve of a launch.  All descs share prec and strain class `sc`
 // (0 none, 1 polynomial, 2 dislocation/table); if `uniform_log2n` >= 0 they also
-// share nx and use the uniform (or, for staged sizes, the staged) kernel,
-// otherwise the mixed-size kernel.
+// share nx and use the uniform (or, for staged sizes, the staged) kernel;
+// kLaunchMixed selects the mixed-size kernel (register-resident sizes from
+// 2^mixed_min_log2n), kLaunchAny the kernel that takes any size from
+// 2^mixed_min_log2n up to the largest.
+constexpr int kLaunchMixed = -1, kLaunchAny = -2;
 hipError_t launch_march(const SolveDesc *d_descs, int n, int prec, int uniform_log2n, int sc,
                         const char *in_base, char *out_base, double *rt, hipStream_t s);
 // Launch shape of the uniform or staged kernel (threads per workgroup, dynamic LDS bytes).

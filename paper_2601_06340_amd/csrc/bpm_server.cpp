@@ -1,13 +1,16 @@
 // bpm_server.cpp — continuous-batching server over the march kernels.
 //
-// A worker thread owns every device resource of admitted solves.  Each round it
-// launches all admitted solves for up to `chunk_steps` z-steps (one uniform-size
-// launch per nx class, each on its own stream so different sizes run side by
-// side), waits, retires the solves that reached nz, and admits waiting requests
-// in arrival order while the device-memory budget and slot count allow.  A
-// solve's arithmetic is the same kernel and schedule as bpm_propagate, and its
-// state crosses chunk boundaries through HBM unchanged, so results do not
-// depend on what else is running.
+// Two threads share the work.  The admission thread takes waiting requests in
+// arrival order while the slot count and device-memory budget allow and builds
+// their plans and entrance states; plan setup waits only for the library's
+// setup stream, so this overlaps the marches.  The march worker runs rounds:
+// every active solve advances a work-balanced number of z-steps (chunk_steps at
+// nx = 16384, scaled by 16384/nx) in one any-size launch per (precision, strain
+// class), so solves of every size run side by side on the device; after the
+// round it retires the solves that reached nz, and the requests set up in the
+// meantime join the next round.  A solve's arithmetic is the same kernel and
+// schedule as bpm_propagate, and its state crosses round boundaries through HBM
+// unchanged, so results do not depend on what else is running.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -66,21 +69,26 @@ struct bpm_server {
     bpm_server_desc cfg{};
     Clock::time_point t0;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::deque<std::shared_ptr<Request>> waiting;
-    std::vector<std::shared_ptr<Request>> active;
+    std::condition_variable cv_work, cv_admit, cv_done;
+    std::deque<std::shared_ptr<Request>> waiting;   // submitted, not admitted
+    std::vector<std::shared_ptr<Request>> ready;     // admitted and set up, not yet marching
+    std::vector<std::shared_ptr<Request>> active;    // marching (worker only)
+    int admitted_slots = 0;                          // admitted and not finished
     std::map<uint64_t, std::shared_ptr<Request>> all;
     uint64_t next_ticket = 1;
     bool stop = false;
     bpm_server_stats stats{};
-    std::thread worker;
+    std::thread worker, setup_thread;
     // worker-owned device resources
-    std::map<int, hipStream_t> streams;  // one per (prec, log2n) class
+    std::map<int, hipStream_t> streams;  // one per precision
     double *d_rt = nullptr;
     std::vector<Launch> launches;
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
     void run();
+    void run_setup();
+    int steps_for(const Request &r) const;
+    bpm_status setup(Request &r, std::vector<char> &host);
     void finish(const std::shared_ptr<Request> &r, int status);
     hipStream_t stream_for(int key);
 };
@@ -115,16 +123,59 @@ void bpm_server::finish(const std::shared_ptr<Request> &r, int status)
     cv_done.notify_all();
 }
 
-void bpm_server::run()
+// z-steps a solve advances per round: chunk_steps at nx = 16384, scaled by
+// 16384/nx so every size class takes about the same time per round.
+int bpm_server::steps_for(const Request &r) const
+{
+    const long long s = (long long)cfg.chunk_steps * 16384 / r.desc.nx;
+    return (int)std::max(1LL, std::min<long long>(s, r.desc.nz - r.step));
+}
+
+// Device setup of one admitted request (plan tables and entrance state).  Runs
+// while the previous round is on the device: plan setup waits only for the
+// library's setup stream.
+bpm_status bpm_server::setup(Request &r, std::vector<char> &host)
+{
+    r.desc.seg = r.seg.data();
+    r.desc.strain.u_table = r.utab.empty() ? nullptr : r.utab.data();
+    bpm_status st = bpm_plan_create(&r.desc, &r.plan);
+    if (st != BPM_OK) return st;
+    const size_t sb = r.plan->state_bytes(), nx = r.desc.nx;
+    hipError_t e = hipMalloc(&r.d_state, sb);
+    if (e != hipSuccess) return hip_fail(e, "server state");
+    host.resize(sb);
+    for (size_t j = 0; j < nx; ++j) {
+        const bpm_complex a = r.psi_p0[j];
+        const bpm_complex b = r.psi_m0.empty() ? bpm_complex{0, 0} : r.psi_m0[j];
+        if (r.desc.precision == BPM_F64) {
+            double *o = (double *)host.data();
+            o[2 * j] = a.re, o[2 * j + 1] = a.im, o[2 * (nx + j)] = b.re, o[2 * (nx + j) + 1] = b.im;
+        } else {
+            float *o = (float *)host.data();
+            o[2 * j] = (float)a.re, o[2 * j + 1] = (float)a.im;
+            o[2 * (nx + j)] = (float)b.re, o[2 * (nx + j) + 1] = (float)b.im;
+        }
+    }
+    hipStream_t ss = setup_stream();
+    e = hipMemcpyAsync(r.d_state, host.data(), sb, hipMemcpyHostToDevice, ss);
+    if (e == hipSuccess) e = hipStreamSynchronize(ss);
+    if (e != hipSuccess) return hip_fail(e, "server state upload");
+    return BPM_OK;
+}
+
+// Admission thread: takes waiting requests in arrival order while slots and
+// the budget allow, builds their plans and entrance states (plan setup waits
+// only for the library's setup stream, so this overlaps the marches), and
+// hands them to the march worker.
+void bpm_server::run_setup()
 {
     std::vector<char> host;
     for (;;) {
-        std::vector<std::shared_ptr<Request>> admit_now;
+        std::shared_ptr<Request> r;
         {
             std::unique_lock<std::mutex> lk(mu);
             for (;;) {
                 if (stop) return;
-                // drop cancelled waiting requests
                 for (auto it = waiting.begin(); it != waiting.end();) {
                     if ((*it)->cancel) {
                         finish(*it, BPM_E_CANCELLED);
@@ -133,70 +184,64 @@ void bpm_server::run()
                         ++it;
                     }
                 }
-                // admit in arrival order while slots and budget allow
-                while (!waiting.empty() && (int)active.size() + (int)admit_now.size() < cfg.max_slots &&
-                       stats.bytes_in_use + waiting.front()->need <= cfg.hbm_budget_bytes) {
-                    auto r = waiting.front();
+                if (!waiting.empty() && admitted_slots < cfg.max_slots &&
+                    stats.bytes_in_use + waiting.front()->need <= cfg.hbm_budget_bytes) {
+                    r = waiting.front();
                     waiting.pop_front();
                     stats.bytes_in_use += r->need;
                     stats.peak_bytes = std::max(stats.peak_bytes, stats.bytes_in_use);
-                    admit_now.push_back(r);
+                    admitted_slots++;
+                    break;
                 }
-                if (!active.empty() || !admit_now.empty()) break;
+                cv_admit.wait(lk);
+            }
+        }
+        bpm_status st = setup(*r, host);
+        std::lock_guard<std::mutex> lk(mu);
+        if (st != BPM_OK) {
+            if (r->plan) bpm_plan_destroy(r->plan);
+            r->plan = nullptr;
+            (void)hipFree(r->d_state);
+            r->d_state = nullptr;
+            stats.bytes_in_use -= r->need;
+            admitted_slots--;
+            finish(r, st);
+            continue;
+        }
+        r->res.t_admit = now();
+        stats.admitted++;
+        ready.push_back(r);
+        cv_work.notify_all();
+    }
+}
+
+// March worker: rounds over every active solve; requests set up by the
+// admission thread join at the start of the next round.
+void bpm_server::run()
+{
+    std::vector<char> host;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            for (;;) {
+                if (stop) return;
+                for (auto &r : ready) active.push_back(r);
+                ready.clear();
+                if (!active.empty()) break;
                 cv_work.wait(lk);
             }
         }
-        // device setup of newly admitted solves (outside the lock)
-        for (auto &r : admit_now) {
-            r->desc.seg = r->seg.data();
-            r->desc.strain.u_table = r->utab.empty() ? nullptr : r->utab.data();
-            bpm_status st = bpm_plan_create(&r->desc, &r->plan);
-            if (st == BPM_OK) {
-                const size_t sb = r->plan->state_bytes();
-                hipError_t e = hipMalloc(&r->d_state, sb);
-                if (e == hipSuccess) {
-                    const size_t nx = r->desc.nx;
-                    host.resize(sb);
-                    for (size_t j = 0; j < nx; ++j) {
-                        const bpm_complex a = r->psi_p0[j];
-                        const bpm_complex b = r->psi_m0.empty() ? bpm_complex{0, 0} : r->psi_m0[j];
-                        if (r->desc.precision == BPM_F64) {
-                            double *o = (double *)host.data();
-                            o[2 * j] = a.re, o[2 * j + 1] = a.im, o[2 * (nx + j)] = b.re, o[2 * (nx + j) + 1] = b.im;
-                        } else {
-                            float *o = (float *)host.data();
-                            o[2 * j] = (float)a.re, o[2 * j + 1] = (float)a.im;
-                            o[2 * (nx + j)] = (float)b.re, o[2 * (nx + j) + 1] = (float)b.im;
-                        }
-                    }
-                    e = hipMemcpy(r->d_state, host.data(), sb, hipMemcpyHostToDevice);
-                }
-                if (e != hipSuccess) st = hip_fail(e, "server state");
-            }
-            std::lock_guard<std::mutex> lk(mu);
-            if (st != BPM_OK) {
-                if (r->plan) bpm_plan_destroy(r->plan);
-                r->plan = nullptr;
-                (void)hipFree(r->d_state);
-                r->d_state = nullptr;
-                stats.bytes_in_use -= r->need;
-                finish(r, st);
-                continue;
-            }
-            r->res.t_admit = now();
-            stats.admitted++;
-            active.push_back(r);
-        }
-        if (active.empty()) continue;
 
-        // one round: every active solve advances min(chunk, remaining) steps
+        // ---- one round: every active solve advances steps_for() z-steps; per
+        // precision one stream and one any-size launch per strain class, so
+        // solves of every size run side by side
         for (size_t i = 0; i < active.size(); ++i) active[i]->slot = (int)i;
-        std::map<int, std::vector<size_t>> cls;  // (prec, log2n) -> active indices
-        for (size_t i = 0; i < active.size(); ++i)
-            cls[active[i]->desc.precision * 64 + active[i]->plan->log2n].push_back(i);
-        free_launches(launches);
+        std::vector<int> adv(active.size(), 0);
         bool ok = true;
-        std::vector<std::pair<hipStream_t, size_t>> issued;
+        free_launches(launches);
+        std::map<int, std::vector<size_t>> cls;
+        for (size_t i = 0; i < active.size(); ++i)
+            cls[active[i]->desc.precision].push_back(i);
         for (auto &kv : cls) {
             const auto &ids = kv.second;
             const int n = (int)ids.size();
@@ -208,69 +253,80 @@ void bpm_server::run()
                 plans[k] = r->plan;
                 rt[k] = r->slot;
                 s0[k] = r->step;
-                ns[k] = std::min(cfg.chunk_steps, r->desc.nz - r->step);
+                ns[k] = adv[ids[k]] = steps_for(*r);
                 fl[k] = (r->step == 0 ? SF_FIRST : 0) | (r->step + ns[k] == r->desc.nz ? SF_LAST : 0);
                 off[k] = (uint64_t)(uintptr_t)r->d_state;
             }
+            hipStream_t cs = stream_for(kv.first);
             std::vector<Launch> ls;
-            bpm_status st = build_launches(plans.data(), n, rt, off, off, s0, ns, fl, ls);
-            if (st == BPM_OK) st = upload_launches(ls);
-            if (st == BPM_OK) st = run_launches(ls, stream_for(kv.first), nullptr, nullptr, d_rt);
+            bpm_status st = build_launches(plans.data(), n, rt, off, off, s0, ns, fl, ls, true);
+            if (st == BPM_OK) st = upload_launches(ls, cs);
+            if (st == BPM_OK) st = run_launches(ls, cs, nullptr, nullptr, d_rt);
             for (auto &L : ls) launches.push_back(std::move(L));
             if (st != BPM_OK) ok = false;
+            std::lock_guard<std::mutex> lk(mu);
             stats.launches++;
         }
+
+        // ---- wait for the round, then retire the solves that reached nz
         for (auto &kv : streams)
             if (hipStreamSynchronize(kv.second) != hipSuccess) ok = false;
-
-        // retire
         std::vector<double> rt(2 * active.size());
         if (ok && hipMemcpy(rt.data(), d_rt, rt.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
             ok = false;
         std::vector<std::shared_ptr<Request>> keep;
-        for (auto &r : active) {
-            const int adv = std::min(cfg.chunk_steps, r->desc.nz - r->step);
-            r->step += adv;
+        bool freed = false;
+        for (size_t i = 0; i < active.size(); ++i) {
+            auto &r = active[i];
+            r->step += adv[i];
             bool fin = !ok || r->step >= r->desc.nz || r->cancel;
             int status = !ok ? BPM_E_DEVICE : (r->cancel && r->step < r->desc.nz ? BPM_E_CANCELLED : BPM_OK);
             if (fin && status == BPM_OK) {
                 const size_t sb = r->plan->state_bytes(), nx = r->desc.nx;
-                host.resize(sb);
-                if (hipMemcpy(host.data(), r->d_state, sb, hipMemcpyDeviceToHost) != hipSuccess) {
-                    status = BPM_E_DEVICE;
-                } else {
-                    for (size_t j = 0; j < nx; ++j) {
-                        double v[4];
-                        if (r->desc.precision == BPM_F64) {
-                            const double *o = (const double *)host.data();
-                            v[0] = o[2 * j], v[1] = o[2 * j + 1], v[2] = o[2 * (nx + j)], v[3] = o[2 * (nx + j) + 1];
-                        } else {
-                            const float *o = (const float *)host.data();
-                            v[0] = o[2 * j], v[1] = o[2 * j + 1], v[2] = o[2 * (nx + j)], v[3] = o[2 * (nx + j) + 1];
+                if (r->out_p || r->out_m) {
+                    host.resize(sb);
+                    if (hipMemcpy(host.data(), r->d_state, sb, hipMemcpyDeviceToHost) != hipSuccess) {
+                        status = BPM_E_DEVICE;
+                    } else {
+                        for (size_t j = 0; j < nx; ++j) {
+                            double v[4];
+                            if (r->desc.precision == BPM_F64) {
+                                const double *o = (const double *)host.data();
+                                v[0] = o[2 * j], v[1] = o[2 * j + 1], v[2] = o[2 * (nx + j)],
+                                v[3] = o[2 * (nx + j) + 1];
+                            } else {
+                                const float *o = (const float *)host.data();
+                                v[0] = o[2 * j], v[1] = o[2 * j + 1], v[2] = o[2 * (nx + j)],
+                                v[3] = o[2 * (nx + j) + 1];
+                            }
+                            if (r->out_p) r->out_p[j] = {v[0], v[1]};
+                            if (r->out_m) r->out_m[j] = {v[2], v[3]};
                         }
-                        if (r->out_p) r->out_p[j] = {v[0], v[1]};
-                        if (r->out_m) r->out_m[j] = {v[2], v[3]};
                     }
-                    r->res.R = rt[2 * r->slot];
-                    r->res.T = rt[2 * r->slot + 1];
-                    if (!std::isfinite(r->res.R) || !std::isfinite(r->res.T)) status = BPM_E_NUMERIC;
                 }
+                r->res.R = rt[2 * r->slot];
+                r->res.T = rt[2 * r->slot + 1];
+                if (!std::isfinite(r->res.R) || !std::isfinite(r->res.T)) status = BPM_E_NUMERIC;
             }
-            std::lock_guard<std::mutex> lk(mu);
-            stats.cell_steps_done += 2.0 * r->desc.nx * adv;
             if (fin) {
                 bpm_plan_destroy(r->plan);
                 r->plan = nullptr;
                 (void)hipFree(r->d_state);
                 r->d_state = nullptr;
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            stats.cell_steps_done += 2.0 * r->desc.nx * adv[i];
+            if (fin) {
                 stats.bytes_in_use -= r->need;
+                admitted_slots--;
                 finish(r, status);
+                freed = true;
             } else {
                 keep.push_back(r);
             }
         }
-        std::lock_guard<std::mutex> lk(mu);
         active.swap(keep);
+        if (freed) cv_admit.notify_all();
     }
 }
 
@@ -292,6 +348,7 @@ extern "C" bpm_status bpm_server_create(const bpm_server_desc *d, bpm_server **o
         return hip_fail(e, "server R/T buffer");
     }
     s->worker = std::thread([s] { s->run(); });
+    s->setup_thread = std::thread([s] { s->run_setup(); });
     *out = s;
     return BPM_OK;
 }
@@ -340,7 +397,7 @@ extern "C" bpm_status bpm_batch_submit(bpm_server *s, const bpm_request *reqs, i
         }
         s->waiting.push_back(r);
     }
-    s->cv_work.notify_all();
+    s->cv_admit.notify_all();
     return ret;
 }
 
@@ -362,6 +419,7 @@ extern "C" bpm_status bpm_cancel(bpm_server *s, uint64_t ticket)
     auto it = s->all.find(ticket);
     if (it == s->all.end()) return fail(BPM_E_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
     it->second->cancel = true;
+    s->cv_admit.notify_all();
     s->cv_work.notify_all();
     return BPM_OK;
 }
@@ -399,7 +457,10 @@ extern "C" void bpm_server_destroy(bpm_server *s)
         s->stop = true;
     }
     s->cv_work.notify_all();
+    s->cv_admit.notify_all();
     if (s->worker.joinable()) s->worker.join();
+    if (s->setup_thread.joinable()) s->setup_thread.join();
+    for (auto &r : s->ready) s->active.push_back(r);
     for (auto &r : s->active) {
         if (r->plan) bpm_plan_destroy(r->plan);
         (void)hipFree(r->d_state);

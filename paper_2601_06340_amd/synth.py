@@ -274,6 +274,25 @@ def disl_bragg(nx: int = 32768, nz: int = 16000, dx: float = 0.1, dz: float = 0.
     return p, psi
 
 
+def disl_bragg_cores(n_cores: int, nx: int = 32768, nz: int = 16000, dx: float = 0.1, dz: float = 0.05,
+                     asymm_deg: float = 10.0, precision: str = "f32", seed: int = SEED_BASE + 2):
+    """``n_cores`` solves of the dislocation trapezoid that differ only in the
+    seeded core position (one crystal mask, shared).  Returns [(problem, psi_p0)]."""
+    base, psi = disl_bragg(nx=nx, nz=nz, dx=dx, dz=dz, asymm_deg=asymm_deg, precision=precision, seed=seed)
+    rng = SplitMix64(seed + 1000)
+    ta = math.tan(math.radians(asymm_deg))
+    ca, sa = math.cos(math.radians(asymm_deg)), math.sin(math.radians(asymm_deg))
+    out = []
+    for _ in range(n_cores):
+        zf = rng.uniform(300.0, 700.0)
+        depth = rng.uniform(2.0, 20.0)
+        xd = (math.floor((1200.0 + zf * ta + depth * ca) / dx) + 0.5) * dx
+        zd = (math.floor((zf - depth * sa) / dz) + 0.5) * dz
+        p = dict(base, strain=dict(base["strain"], x_ref_um=xd, z_ref_um=zd))
+        out.append((p, psi))
+    return out
+
+
 def td_batch(n_comp: int = 1024, sigma_t_fs: float = 20.0, nx_choices=(2048, 4096, 8192, 16384),
              nz_range=(1000, 8000), dx: float = 0.1, dz: float = 0.05, precision: str = "f32",
              seed: int = SEED_BASE + 3):
@@ -326,19 +345,22 @@ def scaled_geometry(kind: str, nx: int, nz: int, dx: float, dz: float, rng: Spli
                             min(rng.uniform(10, 50), 0.05 * Lx), tilt)
     elif kind in ("disl", "trapezoid"):
         xf0, xback = 0.37 * Lx, 0.73 * Lx
-        za, zb = 0.06 * Lz, 0.94 * Lz
-        seg = mask_asym_trapezoid(nz, nx, dx, dz, xf0, 10.0, xback, za, zb)
         ta = math.tan(math.radians(10.0))
+        # the 10-degree entrance face must stay inside the window: a crystal
+        # deeper than 0.9 (xback - xf0) / tan(10 deg) is cut to that depth
+        za = 0.06 * Lz
+        zb = min(0.94 * Lz, za + 0.9 * (xback - xf0) / ta)
+        seg = mask_asym_trapezoid(nz, nx, dx, dz, xf0, 10.0, xback, za, zb)
         strain = None
         if kind == "disl":
-            zf = rng.uniform(0.375, 0.875) * Lz
+            zf = za + rng.uniform(0.375, 0.875) * (zb - za)
             depth = rng.uniform(2.0, 20.0)
             xd = (math.floor((xf0 + zf * ta + depth * math.cos(math.radians(10))) / dx) + 0.5) * dx
             zd = (math.floor((zf - depth * math.sin(math.radians(10))) / dz) + 0.5) * dz
             strain = {"kind": "edge_dislocation", "x_ref_um": xd, "z_ref_um": zd,
                       "b_um": 0.38e-3, "nu": 0.22}
         p = base_problem(nx, nz, dx, dz, seg, precision=precision, strain=strain,
-                         det=(0, _index_at_or_above(xf0 + zb * ta, 0, dx)))
+                         det=(0, min(nx, _index_at_or_above(xf0 + zb * ta, 0, dx))))
         psi = gaussian_beam(nx, dx, 0.3 * Lx, min(50.0, 0.05 * Lx), tilt)
     else:
         raise ValueError(kind)
