@@ -58,14 +58,21 @@ __device__ __forceinline__ gptr<X> to_global(const void *p)
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d2v __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ Cx<float> gload(gptr<Cx<float>> p, size_t i)
+// Loads from read-only tables: a uniform base plus a 32-bit byte offset, so the
+// address is the scalar base with a per-lane 32-bit offset (no 64-bit add per load).
+template <typename V>
+__device__ __forceinline__ V gload_at(const void __attribute__((address_space(1))) *base, uint32_t byte_off)
 {
-    const f2v v = ((gptr<f2v>)p)[i];
+    return *(gptr<V>)((const char __attribute__((address_space(1))) *)base + byte_off);
+}
+__device__ __forceinline__ Cx<float> gload(gptr<Cx<float>> p, uint32_t i)
+{
+    const f2v v = gload_at<f2v>(p, i * (uint32_t)sizeof(f2v));
     return {v.x, v.y};
 }
-__device__ __forceinline__ Cx<double> gload(gptr<Cx<double>> p, size_t i)
+__device__ __forceinline__ Cx<double> gload(gptr<Cx<double>> p, uint32_t i)
 {
-    const d2v v = ((gptr<d2v>)p)[i];
+    const d2v v = gload_at<d2v>(p, i * (uint32_t)sizeof(d2v));
     return {v.x, v.y};
 }
 
@@ -257,14 +264,17 @@ template <typename T>
 struct Tw;
 // FP32: lifting constants of the reduced angle and the exact sign (+1 or -1)
 template <>
-struct alignas(16) Tw<float> {
-    float p, u, s, pad;
+struct Tw<float> {
+    float p, u, s;
 };
+// bytes of one table entry
+__host__ __device__ constexpr size_t tw_bytes(int prec) { return prec == PREC_F32 ? 12 : 16; }
 // FP64: the rotation as a complex number
 template <>
 struct alignas(16) Tw<double> {
     double x, y;
 };
+static_assert(sizeof(Tw<float>) == tw_bytes(PREC_F32) && sizeof(Tw<double>) == tw_bytes(PREC_F64), "table entry");
 
 __device__ __forceinline__ Cx<float> mul_tw(Cx<float> a, const Tw<float> &w)
 {
@@ -284,14 +294,14 @@ __device__ __forceinline__ Cx<double> mul_tw_inv(Cx<double> a, const Tw<double> 
 {
     return {fmaT(a.x, w.x, a.y * w.y), fmaT(a.y, w.x, -a.x * w.y)};
 }
-__device__ __forceinline__ Tw<float> gload(gptr<Tw<float>> p, size_t i)
+__device__ __forceinline__ Tw<float> gload(gptr<Tw<float>> p, uint32_t i)
 {
-    const f4v v = ((gptr<f4v>)p)[i];
-    return {v.x, v.y, v.z, v.w};
+    const uint32_t b = i * 12u;   // three dwords, merged into one 12-byte load
+    return {gload_at<float>(p, b), gload_at<float>(p, b + 4u), gload_at<float>(p, b + 8u)};
 }
-__device__ __forceinline__ Tw<double> gload(gptr<Tw<double>> p, size_t i)
+__device__ __forceinline__ Tw<double> gload(gptr<Tw<double>> p, uint32_t i)
 {
-    const d2v v = ((gptr<d2v>)p)[i];
+    const d2v v = gload_at<d2v>(p, i * (uint32_t)sizeof(d2v));
     return {v.x, v.y};
 }
 
@@ -468,25 +478,31 @@ struct Coupler {
     template <int E, int JS>
     __device__ __forceinline__ void apply(Cx<T> *vp, Cx<T> *vm, const SolveDesc &d, int n, int j0) const
     {
+        static_assert(E <= 32 && (JS & (JS - 1)) == 0, "element mask");
+        constexpr int LOG2JS = __builtin_ctz(JS);
+        // bit e of `inside` <=> sample j0 + JS*e lies in one of the step's
+        // intervals [lo, hi): the inside elements of an interval are the
+        // consecutive range ceil((lo - j0)/JS) <= e < ceil((hi - j0)/JS)
         const gptr<int> sg = seg + (size_t)n * nseg * 2;
-        int lo[kMaxSeg], hi[kMaxSeg];
+        uint32_t inside = 0;
         static_for<0, kMaxSeg>([&](auto k) {
-            lo[k] = CV(k) < nseg ? sg[2 * CV(k)] : 0;
-            hi[k] = CV(k) < nseg ? sg[2 * CV(k) + 1] : 0;
+            if (CV(k) < nseg) {
+                const int lo = sg[2 * CV(k)], hi = sg[2 * CV(k) + 1];
+                const int elo = min(max((lo - j0 + JS - 1) >> LOG2JS, 0), E);
+                const int ehi = min(max((hi - j0 + JS - 1) >> LOG2JS, 0), E);
+                const uint32_t below_hi = ehi >= 32 ? 0xffffffffu : (1u << ehi) - 1u;
+                const uint32_t below_lo = elo >= 32 ? 0xffffffffu : (1u << elo) - 1u;
+                inside |= below_hi & ~below_lo;
+            }
         });
-        const bool all_in = (nseg == 1) & (lo[0] <= 0) & (hi[0] >= nx);
-        auto inside_at = [&](int j) {
-            bool in = false;
-            static_for<0, kMaxSeg>([&](auto k) { in |= (j >= lo[k]) & (j < hi[k]); });
-            return in;
-        };
+        auto inside_at_e = [&](auto e) { return ((inside >> CV(e)) & 1u) != 0u; };
         const Cx<T> zero = {(T)0, (T)0};
         auto sel = [&](bool in, Cx<T> c) { return Cx<T>{in ? c.x : zero.x, in ? c.y : zero.y}; };
         const double Z = n * d.dz - d.z_ref;
         // (one straight-line copy: a separate all-inside copy costs registers)
         if constexpr (SC == SC_NONE) {
             static_for<0, E>([&](auto e) {
-                const bool in = all_in | inside_at(j0 + e * JS);
+                const bool in = inside_at_e(e);
                 couple(vp[e], vm[e], sel(in, d0), sel(in, ap), sel(in, am));
             });
         } else if constexpr (SC == SC_POLY2) {
@@ -511,7 +527,7 @@ struct Coupler {
                     Q = {fmaT(Q.x, Rr.x, -Q.y * Rr.y), fmaT(Q.x, Rr.y, Q.y * Rr.x)};
                 }
             };
-            static_for<0, E>([&](auto e) { body(e, all_in | inside_at(j0 + e * JS)); });
+            static_for<0, E>([&](auto e) { body(e, inside_at_e(e)); });
         } else {
             // dislocation field or tabulated phase (already reduced to one
             // revolution when the plan was built)
@@ -520,7 +536,7 @@ struct Coupler {
             const gptr<T> urow = utab + (size_t)n * nx;
             static_for<0, E>([&](auto e) {
                 const int j = j0 + e * JS;
-                const bool in = all_in | inside_at(j);
+                const bool in = inside_at_e(e);
                 const T rev = edge ? edge_phase_rev((T)__builtin_fma((double)j, d.dx, X0), (T)Z, dk, dq)
                                    : urow[j];
                 const Cx<T> P = phasor<T>(rev);

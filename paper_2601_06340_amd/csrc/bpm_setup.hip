@@ -118,7 +118,7 @@ __device__ Tw<T> encode_rotation(long long q, long long M)
         }
         const double pl = tan(M_PI * (double)q / (double)M);
         const double ul = -sinpi(2.0 * (double)q / (double)M);
-        return {(float)pl, (float)ul, sgn, 0.0f};
+        return {(float)pl, (float)ul, sgn};
     } else {
         double sn, cs;
         sincospi(-2.0 * (double)q / (double)M, &sn, &cs);
@@ -183,7 +183,7 @@ static int tw_count(int log2n, int log2e)
 
 size_t twiddle_bytes(int prec, int log2n, int log2e)
 {
-    return (size_t)tw_count(log2n, log2e) * 16;
+    return (size_t)tw_count(log2n, log2e) * tw_bytes(prec);
 }
 
 hipError_t launch_twiddles(void *d_tw, int prec, int log2n, int log2e, hipStream_t s)
@@ -237,7 +237,7 @@ size_t staged_twiddle_bytes(int prec, int log2n)
     int a = 0, b = 0, tot = 0;
     const bool ok = prec == PREC_F32 ? staged_layout_T<float>(log2n, &a, &b, &tot)
                                      : staged_layout_T<double>(log2n, &a, &b, &tot);
-    return ok ? (size_t)tot * 16 : 0;
+    return ok ? (size_t)tot * tw_bytes(prec) : 0;
 }
 
 hipError_t launch_staged_twiddles(void *d_tw, int prec, int log2n, hipStream_t s)
@@ -249,15 +249,15 @@ hipError_t launch_staged_twiddles(void *d_tw, int prec, int log2n, hipStream_t s
     if (!ok || tw_count(lc, le) != tw_col || tw_col + tw_count(log2r, le) != tw_4) return hipErrorInvalidValue;
     char *base = static_cast<char *>(d_tw);
     hipError_t e = launch_twiddles(base, prec, lc, le, s);
-    if (e == hipSuccess) e = launch_twiddles(base + (size_t)tw_col * 16, prec, log2r, le, s);
+    if (e == hipSuccess) e = launch_twiddles(base + (size_t)tw_col * tw_bytes(prec), prec, log2r, le, s);
     if (e != hipSuccess) return e;
     const int n = 1 << log2n, bs = 256;
     if (prec == PREC_F32)
         hipLaunchKernelGGL(k_twiddles4<float>, dim3((n + bs - 1) / bs), dim3(bs), 0, s,
-                           (Tw<float> *)(base + (size_t)tw_4 * 16), log2n, lc);
+                           (Tw<float> *)(base + (size_t)tw_4 * tw_bytes(prec)), log2n, lc);
     else
         hipLaunchKernelGGL(k_twiddles4<double>, dim3((n + bs - 1) / bs), dim3(bs), 0, s,
-                           (Tw<double> *)(base + (size_t)tw_4 * 16), log2n, lc);
+                           (Tw<double> *)(base + (size_t)tw_4 * tw_bytes(prec)), log2n, lc);
     return hipGetLastError();
 }
 
