@@ -47,6 +47,7 @@ class _Desc(C.Structure):
         ("disl_b_um", C.c_double), ("disl_nu", C.c_double),
         ("u_table", C.POINTER(C.c_double)),
         ("det_lo", C.c_int), ("det_hi", C.c_int),
+        ("split_order", C.c_int),
     ]
 
 
@@ -71,6 +72,13 @@ def lib():
         L.oracle_dft.restype = None
         L.oracle_bessel_series.argtypes = [C.c_double, C.c_double, cd, cd]
         L.oracle_bessel_series.restype = None
+        L.oracle_exp_series.argtypes = [C.c_double, C.c_double, cd, cd]
+        L.oracle_exp_series.restype = None
+        L.oracle_coupling.argtypes = [C.POINTER(_Desc), C.c_double, C.c_int, cd, cd, cd]
+        L.oracle_propagator_frac.argtypes = [C.POINTER(_Desc), C.c_double, cd, cd]
+        L.oracle_split_sequence.argtypes = [C.c_int, cd, cd]
+        L.oracle_strain_phase_z.argtypes = [C.POINTER(_Desc), C.c_int, C.c_int, C.c_double]
+        L.oracle_strain_phase_z.restype = C.c_double
         L.oracle_scalars_get.argtypes = [C.POINTER(_Desc), C.POINTER(_Scalars)]
         L.oracle_propagator.argtypes = [C.POINTER(_Desc), cd, cd]
         L.oracle_strain_phase.argtypes = [C.POINTER(_Desc), C.c_int, C.c_int]
@@ -123,6 +131,7 @@ def _desc(p: dict, keep: _Keep) -> _Desc:
         d.u_table = _dptr(ut)
     d.det_lo = int(p.get("det_lo", 0))
     d.det_hi = int(p.get("det_hi", p["nx"]))
+    d.split_order = int(p.get("split_order", 1))
     return d
 
 
@@ -146,6 +155,47 @@ def bessel_series(y: complex):
     g = np.zeros(1, np.complex128)
     lib().oracle_bessel_series(complex(y).real, complex(y).imag, _dptr(j0), _dptr(g))
     return complex(j0[0]), complex(g[0])
+
+
+def exp_series(y: complex):
+    """cosh(v) and sinh(v)/v as series in y = v^2."""
+    ch = np.zeros(1, np.complex128)
+    sh = np.zeros(1, np.complex128)
+    lib().oracle_exp_series(complex(y).real, complex(y).imag, _dptr(ch), _dptr(sh))
+    return complex(ch[0]), complex(sh[0])
+
+
+def coupling(p: dict, b: float, form: int):
+    """(a0, ap, am) of a coupling sub-step b*dz; form 0 Jacobi-Anger, 1 exponential."""
+    keep = _Keep()
+    d = _desc(p, keep)
+    out = [np.zeros(1, np.complex128) for _ in range(3)]
+    if lib().oracle_coupling(C.byref(d), float(b), int(form), *[_dptr(o) for o in out]):
+        raise ValueError("invalid problem")
+    return tuple(complex(o[0]) for o in out)
+
+
+def propagator_frac(p: dict, a: float):
+    keep = _Keep()
+    d = _desc(p, keep)
+    pp = np.zeros(d.nx, np.complex128)
+    pm = np.zeros(d.nx, np.complex128)
+    if lib().oracle_propagator_frac(C.byref(d), float(a), _dptr(pp), _dptr(pm)):
+        raise ValueError("invalid problem")
+    return pp, pm
+
+
+def split_sequence(order: int):
+    a = np.zeros(8)
+    b = np.zeros(8)
+    m = lib().oracle_split_sequence(int(order), _dptr(a), _dptr(b))
+    return list(a[:m]), list(b[:m])
+
+
+def strain_phase_z(p: dict, j: int, n: int, z: float) -> float:
+    keep = _Keep()
+    d = _desc(p, keep)
+    return lib().oracle_strain_phase_z(C.byref(d), int(j), int(n), float(z))
 
 
 def scalars(p: dict) -> dict:

@@ -101,6 +101,24 @@ void oracle_bessel_series(double complex y, double complex *j0, double complex *
     *g = s1;
 }
 
+/* Exponential of the two-beam coupling generator N = i A [[0, chih], [chihb, 0]]:
+ * N^2 = y I with y = -A^2 chih chihb, so exp(N) = cosh(v) I + (sinh(v)/v) N with
+ * v^2 = y; both series are in y, so no square root is taken. */
+void oracle_exp_series(double complex y, double complex *ch, double complex *sh)
+{
+    double complex t0 = 1.0, s0 = 1.0; /* y^m/(2m)! */
+    double complex t1 = 1.0, s1 = 1.0; /* y^m/(2m+1)! */
+    for (int m = 1; m < 200; m++) {
+        t0 = t0 * y / ((double)(2 * m - 1) * (double)(2 * m));
+        t1 = t1 * y / ((double)(2 * m) * (double)(2 * m + 1));
+        s0 += t0;
+        s1 += t1;
+        if (cabs(t0) <= 1e-18 * cabs(s0) && cabs(t1) <= 1e-18 * cabs(s1)) break;
+    }
+    *ch = s0;
+    *sh = s1;
+}
+
 static int desc_valid(const oracle_desc *d)
 {
     if (!d || !is_pow2(d->nx) || d->nz < 0) return 0;
@@ -108,6 +126,7 @@ static int desc_valid(const oracle_desc *d)
     if (!(d->lambda_um < 2.0 * d->d_um)) return 0;
     if (d->nseg < 0 || (d->nseg > 0 && d->nz > 0 && !d->seg)) return 0;
     if (d->strain_kind == ORACLE_STRAIN_TABLE && !d->u_table && d->nz > 0) return 0;
+    if (d->split_order != 0 && d->split_order != 1 && d->split_order != 2 && d->split_order != 4) return 0;
     return 1;
 }
 
@@ -119,17 +138,47 @@ int oracle_scalars_get(const oracle_desc *d, oracle_scalars *o)
     o->s = o->h / (2.0 * o->k);
     o->c = sqrt(1.0 - o->s * o->s);
     o->dzh = o->k * d->dz_um;
+    return oracle_coupling(d, 1.0, 0, &o->a0, &o->ap, &o->am);
+}
+
+int oracle_coupling(const oracle_desc *d, double b, int form, double complex *a0, double complex *ap,
+                    double complex *am)
+{
+    if (!desc_valid(d)) return -1;
+    double k = 2.0 * M_PI / d->lambda_um, h = 2.0 * M_PI / d->d_um;
+    double s = h / (2.0 * k), c = sqrt(1.0 - s * s);
     double complex chi0 = d->chi0_re + I * d->chi0_im;
     double complex chih = d->chih_re + I * d->chih_im;
     double complex chihb = d->chihb_re + I * d->chihb_im;
-    double A = o->dzh / (2.0 * o->c);
+    double A = b * k * d->dz_um / (2.0 * c);
     double complex E = cexp(I * A * chi0);
     double complex y = -A * A * chih * chihb;
-    double complex j0, g;
-    oracle_bessel_series(y, &j0, &g);
-    o->a0 = j0 * E;
-    o->ap = I * A * chih * g * E;
-    o->am = I * A * chihb * g * E;
+    double complex diag, off;
+    if (form == 0) oracle_bessel_series(y, &diag, &off);
+    else oracle_exp_series(y, &diag, &off);
+    *a0 = diag * E;
+    *ap = I * A * chih * off * E;
+    *am = I * A * chihb * off * E;
+    return 0;
+}
+
+int oracle_split_sequence(int order, double *a, double *b)
+{
+    if (order <= 1) {
+        a[0] = 1.0; b[0] = 1.0;
+        return 1;
+    }
+    if (order == 2) {
+        a[0] = 0.0; a[1] = 1.0;
+        b[0] = 0.5; b[1] = 0.5;
+        return 2;
+    }
+    if (order == 4) {
+        const double t = 1.0 / (2.0 - cbrt(2.0));
+        a[0] = 0.0; a[1] = t; a[2] = 1.0 - 2.0 * t; a[3] = t;
+        b[0] = 0.5 * t; b[1] = 0.5 * (1.0 - t); b[2] = 0.5 * (1.0 - t); b[3] = 0.5 * t;
+        return 4;
+    }
     return 0;
 }
 
@@ -139,8 +188,14 @@ int oracle_scalars_get(const oracle_desc *d, oracle_scalars *o)
  * multiplies both envelopes by the same global phase per step. */
 int oracle_propagator(const oracle_desc *d, double complex *pp, double complex *pm)
 {
+    return oracle_propagator_frac(d, 1.0, pp, pm);
+}
+
+int oracle_propagator_frac(const oracle_desc *d, double a, double complex *pp, double complex *pm)
+{
     oracle_scalars sc;
     if (oracle_scalars_get(d, &sc)) return -1;
+    sc.dzh *= a;
     int n = d->nx;
     for (int f = 0; f < n; f++) {
         int ff = f < n / 2 ? f : f - n;
@@ -167,9 +222,13 @@ int oracle_propagator(const oracle_desc *d, double complex *pp, double complex *
 
 double oracle_strain_phase(const oracle_desc *d, int j, int n)
 {
+    return oracle_strain_phase_z(d, j, n, n * d->dz_um);
+}
+
+double oracle_strain_phase_z(const oracle_desc *d, int j, int n, double z)
+{
     double h = 2.0 * M_PI / d->d_um;
     double x = d->x0_um + j * d->dx_um;
-    double z = n * d->dz_um;
     double X = x - d->x_ref_um, Z = z - d->z_ref_um;
     double u = 0.0;
     switch (d->strain_kind) {
@@ -221,6 +280,63 @@ static double power_sum(const double complex *a, int lo, int hi)
     return s;
 }
 
+/* Coupling of one (sub-)step with coefficients a0, ap, am: mask row n, strain at z. */
+static void couple_step(const oracle_desc *d, double complex *psi_p, double complex *psi_m, int n, double z,
+                        double complex a0, double complex ap, double complex am)
+{
+    for (int j = 0; j < d->nx; j++) {
+        if (!inside_mask(d, j, n)) continue;
+        double complex e = 1.0;
+        if (d->strain_kind != ORACLE_STRAIN_NONE) {
+            double phi = oracle_strain_phase_z(d, j, n, z);
+            e = cos(phi) + I * sin(phi);
+        }
+        double complex p = psi_p[j], m = psi_m[j];
+        psi_p[j] = a0 * p + ap * e * m;
+        psi_m[j] = a0 * m + am * conj(e) * p;
+    }
+}
+
+/* Eq. (13): every step is A(a_1 dz) B(b_1 dz) ... A(a_m dz) B(b_m dz), applied
+ * from the left; B_i sits at z_n + (a_1 + ... + a_i) dz. */
+static int propagate_split(const oracle_desc *d, double complex *psi_p, double complex *psi_m,
+                           const double complex *wf, const double complex *wi)
+{
+    double a[8], b[8];
+    int m = oracle_split_sequence(d->split_order, a, b);
+    if (m == 0) return -1;
+    int n = d->nx;
+    double complex *tp[8], *tm[8], c0[8], cp[8], cm[8];
+    double zoff[8], acc = 0.0;
+    int rc = 0;
+    for (int i = 0; i < m; i++) {
+        tp[i] = tm[i] = NULL;
+        acc += a[i];
+        zoff[i] = acc;
+        if (a[i] != 0.0) {
+            tp[i] = malloc(sizeof(double complex) * (size_t)n);
+            tm[i] = malloc(sizeof(double complex) * (size_t)n);
+            if (!tp[i] || !tm[i]) rc = -2;
+            else oracle_propagator_frac(d, a[i], tp[i], tm[i]);
+        }
+        oracle_coupling(d, b[i], 1, &c0[i], &cp[i], &cm[i]);
+    }
+    for (int step = 0; rc == 0 && step < d->nz; step++) {
+        for (int i = 0; i < m; i++) {
+            if (a[i] != 0.0) {
+                fft_with(psi_p, n, wf);
+                fft_with(psi_m, n, wf);
+                for (int f = 0; f < n; f++) { psi_p[f] *= tp[i][f]; psi_m[f] *= tm[i][f]; }
+                fft_with(psi_p, n, wi);
+                fft_with(psi_m, n, wi);
+            }
+            couple_step(d, psi_p, psi_m, step, (step + zoff[i]) * d->dz_um, c0[i], cp[i], cm[i]);
+        }
+    }
+    for (int i = 0; i < m; i++) { free(tp[i]); free(tm[i]); }
+    return rc;
+}
+
 int oracle_propagate(const oracle_desc *d, double complex *psi_p, double complex *psi_m,
                      double *R, double *T)
 {
@@ -235,7 +351,14 @@ int oracle_propagate(const oracle_desc *d, double complex *psi_p, double complex
     oracle_propagator(d, pp, pm);
     double pin = power_sum(psi_p, 0, n);
 
-    for (int step = 0; step < d->nz; step++) {
+    if (d->split_order > 1) {
+        int rc = propagate_split(d, psi_p, psi_m, wf, wi);
+        free(pp);
+        free(pm);
+        pp = pm = NULL;
+        if (rc) { free(wf); free(wi); return rc; }
+    }
+    for (int step = 0; step < (d->split_order > 1 ? 0 : d->nz); step++) {
         /* Fourier-space propagation of each envelope about its own carrier */
         fft_with(psi_p, n, wf);
         fft_with(psi_m, n, wf);

@@ -15,13 +15,21 @@
  *   k = 2*pi/lambda, h = 2*pi/d, s = h/(2k) = sin(theta_B), c = sqrt(1-s^2),
  *   dzh = k*dz (the normalised step of Eq. (4)).
  *
- * One step n -> n+1:
+ * One step n -> n+1 (split_order 0 or 1, Eq. (12)):
  *   psi_pm <- IDFT( DFT(psi_pm) * exp(i*dzh*(S(q +/- s) - c)) ),   S(p) = sqrt(1-p^2)
  *   inside the crystal mask at (x_j, z_n):
  *      psi_p <- a0*psi_p + ap*exp(+i*phi)*psi_m
  *      psi_m <- a0*psi_m + am*exp(-i*phi)*psi_p        (old values on the right)
  *   with phi = h*u(x_j, z_n) and a0, ap, am the n = 0, +1, -1 harmonics of
  *   exp(i*dzh*delta_eps/(2c)) (Eq. (8)-(11)).
+ *
+ * Higher orders (Eq. (13)): the step is the product A(a_1 dz) B(b_1 dz) ...
+ * A(a_m dz) B(b_m dz), applied from the left, with A the propagation of a
+ * sub-step and B the coupling of a sub-step, taken here as the exponential of
+ * the two-beam coupling generator (the truncated Jacobi-Anger form does not
+ * compose, B(b1) B(b2) != B(b1 + b2), and would leave every splitting first
+ * order).  B_i uses the mask row of step n and the strain at
+ * z_n + (a_1 + ... + a_i) dz.
  */
 #ifndef BPM_ORACLE_H
 #define BPM_ORACLE_H
@@ -52,6 +60,7 @@ typedef struct oracle_desc {
     double disl_b_um, disl_nu;   /* EDGE_DISL Burgers vector length and Poisson ratio */
     const double *u_table;       /* TABLE: [nz][nx] displacement along h (um) */
     int det_lo, det_hi;          /* detector interval for R and T */
+    int split_order;             /* 0 or 1: Eq. (12); 2, 4: the splittings of Eq. (13) */
 } oracle_desc;
 
 /* Plan-level scalars, exposed so that the tests can pin them. */
@@ -67,6 +76,21 @@ void oracle_dft(const double complex *in, double complex *out, int n, int sign);
 
 /* Series for J0(w) and 2*J1(w)/w written in y = -w^2/4 (branch-free, complex y). */
 void oracle_bessel_series(double complex y, double complex *j0, double complex *g);
+/* Series cosh(v) = sum y^m/(2m)! and sinh(v)/v = sum y^m/(2m+1)! in y = v^2. */
+void oracle_exp_series(double complex y, double complex *ch, double complex *sh);
+
+/* Coupling coefficients of a sub-step of b*dz: form 0 = the Jacobi-Anger
+ * harmonics of Eq. (9)-(10), form 1 = the exponential of the two-beam coupling
+ * generator (used by the higher-order splittings). */
+int oracle_coupling(const oracle_desc *d, double b, int form, double complex *a0, double complex *ap,
+                    double complex *am);
+/* Propagator tables of a sub-step of a*dz (a may be negative), 1/nx included. */
+int oracle_propagator_frac(const oracle_desc *d, double a, double complex *pp, double complex *pm);
+/* Step sequence of a splitting order: A(a_i dz) then B(b_i dz) for i = 0..count-1.
+ * Returns the count (0 for an unknown order). */
+int oracle_split_sequence(int order, double *a, double *b);
+/* Strain phase phi = h*u at x_j and height z (TABLE: row n). */
+double oracle_strain_phase_z(const oracle_desc *d, int j, int n, double z);
 
 int oracle_scalars_get(const oracle_desc *d, oracle_scalars *out);
 /* Propagator tables P+[f], P-[f] including the 1/nx of the inverse transform. */

@@ -372,3 +372,118 @@ def test_invalid_problems_rejected():
         p = dict(base, **bad)
         with pytest.raises(ValueError):
             oracle.propagate(p, np.ones(p["nx"], complex))
+
+
+# ------------------------------------------------------------------ higher-order splitting (Eq. (13))
+def _coupling_matrix(p, b, form):
+    a0, ap, am = oracle.coupling(p, b, form)
+    return np.array([[a0, ap], [am, a0]])
+
+
+def test_split_sequences_are_the_printed_coefficients():
+    """Eq. (13): second order a = (0, 1), b = (1/2, 1/2); fourth order with
+    t = 1/(2 - 2^(1/3)) = 1.3512..., a = (0, t, 1-2t, t), b = (t/2, (1-t)/2, (1-t)/2, t/2)."""
+    a, b = oracle.split_sequence(2)
+    assert a == [0.0, 1.0] and b == [0.5, 0.5]
+    a, b = oracle.split_sequence(4)
+    t = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+    assert abs(t - 1.3512) < 1e-4
+    assert np.allclose(a, [0.0, t, 1 - 2 * t, t], rtol=0, atol=1e-15)
+    assert np.allclose(b, [t / 2, (1 - t) / 2, (1 - t) / 2, t / 2], rtol=0, atol=1e-15)
+    assert abs(sum(a) - 1) < 1e-15 and abs(sum(b) - 1) < 1e-15
+    a, b = oracle.split_sequence(1)
+    assert a == [1.0] and b == [1.0]
+
+
+@pytest.mark.parametrize("b", [0.5, 1.0, -0.17560359597982889])
+def test_exponential_coupling_equals_matrix_exponential(b):
+    """Form 1 is exp(i (b dzh / 2c) [[chi0, chih], [chihb, chi0]]) (scipy's expm),
+    also for chih != chihb and large arguments."""
+    import scipy.linalg as sl
+    for chih, chihb, dz in ((synth.CHIH, synth.CHIH, 0.05), (complex(-1.2e-6, 3e-8), complex(-1.7e-6, -2e-8), 0.05),
+                            (synth.CHIH, complex(-1.1e-6, 5e-9), 3.0)):
+        p = small(nx=64, nz=1, dz=dz, chih=chih, chihb=chihb)
+        sc = oracle.scalars(p)
+        A = b * sc["dzh"] / (2 * sc["c"])
+        gen = 1j * A * np.array([[complex(p["chi0"]), chih], [chihb, complex(p["chi0"])]])
+        ref = sl.expm(gen)
+        got = _coupling_matrix(p, b, 1)
+        assert np.abs(got - ref).max() <= 1e-14 * max(1.0, np.abs(ref).max())
+
+
+def test_exponential_coupling_composes_and_jacobi_anger_does_not():
+    """B(1/2) B(1/2) = B(1) for the exponential form (the property the orders of
+    Eq. (13) rest on); the two-beam Jacobi-Anger harmonics miss it at O(dz^2)."""
+    p = small(nx=64, nz=1, dz=0.5, chihb=complex(-1.3e-6, 1e-8))
+    half, full = _coupling_matrix(p, 0.5, 1), _coupling_matrix(p, 1.0, 1)
+    assert np.abs(half @ half - full).max() <= 1e-15
+    half, full = _coupling_matrix(p, 0.5, 0), _coupling_matrix(p, 1.0, 0)
+    assert np.abs(half @ half - full).max() > 1e-6
+
+
+def test_jacobi_anger_and_exponential_forms_differ_at_second_order():
+    """Both forms agree to first order in the step: halving b quarters the gap."""
+    p = small(nx=64, nz=1, dz=0.4)
+    gaps = [np.abs(_coupling_matrix(p, b, 0) - _coupling_matrix(p, b, 1)).max() for b in (1.0, 0.5, 0.25)]
+    assert 3.6 < gaps[0] / gaps[1] < 4.4 and 3.6 < gaps[1] / gaps[2] < 4.4
+
+
+def _continuum_uniform_crystal(p, psi_p0, psi_m0, L):
+    """Exact two-beam evolution over L of an x-uniform crystal: per numpy FFT bin,
+    expm of i k diag(S(q+s)-c, S(q-s)-c) + i (k/2c) [[chi0, chih], [chihb, chi0]]."""
+    import scipy.linalg as sl
+    nx, dx = p["nx"], p["dx_um"]
+    k = 2 * math.pi / p["lambda_um"]
+    s = math.pi / p["d_um"] / k
+    c = math.sqrt(1 - s * s)
+    C = 1j * (k / (2 * c)) * np.array([[complex(p["chi0"]), complex(p["chih"])],
+                                      [complex(p["chihb"]), complex(p["chi0"])]])
+    Fp, Fm = np.fft.fft(psi_p0), np.fft.fft(psi_m0)
+    q = np.fft.fftfreq(nx, dx) * 2 * math.pi / k
+    outp, outm = np.empty_like(Fp), np.empty_like(Fm)
+    for f in range(nx):
+        K = 1j * k * np.diag([math.sqrt(1 - (q[f] + s) ** 2) - c, math.sqrt(1 - (q[f] - s) ** 2) - c])
+        v = sl.expm((K + C) * L) @ np.array([Fp[f], Fm[f]])
+        outp[f], outm[f] = v
+    return np.fft.ifft(outp), np.fft.ifft(outm)
+
+
+@pytest.mark.parametrize("order,rate", [(1, 2.0), (2, 4.0), (4, 16.0)])
+def test_split_orders_converge_to_the_continuum_solution(order, rate):
+    """x-uniform crystal: the march error against the exact two-beam solution
+    falls by 2^order per halving of dz."""
+    nx, L = 64, 24.0
+    xs = np.arange(nx) * 0.5
+    psi_p0 = np.exp(-((xs - 16.0) / 4.0) ** 2) * np.exp(2j * math.pi * 3 * np.arange(nx) / nx)
+    psi_m0 = 0.3 * np.exp(-((xs - 12.0) / 6.0) ** 2)
+    errs = []
+    for dz in (0.8, 0.4, 0.2):
+        nz = int(round(L / dz))
+        p = small(nx=nx, nz=nz, dx=0.5, dz=dz, chih=complex(-4e-6, 2e-8), chi0=complex(-5e-6, 2e-8))
+        p["split_order"] = order
+        ref_p, ref_m = _continuum_uniform_crystal(p, psi_p0, psi_m0, L)
+        gp, gm, _, _ = oracle.propagate(p, psi_p0, psi_m0)
+        errs.append(rel_l2(np.concatenate([gp, gm]), np.concatenate([ref_p, ref_m])))
+    ratios = [errs[i] / errs[i + 1] for i in range(2)]
+    assert all(0.8 * rate < r < 1.25 * rate for r in ratios), (errs, ratios)
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_split_sub_steps_sample_the_strain_at_their_own_height(order):
+    """With a z-dependent strain (bent plate) the self-convergence rate keeps the
+    scheme's order only if each coupling sub-step sees the strain at its own z."""
+    nx, L = 128, 16.0
+    xs = np.arange(nx) * 0.5
+    psi_p0 = np.exp(-((xs - 32.0) / 6.0) ** 2).astype(complex)
+    sols = []
+    for dz in (0.8, 0.4, 0.2, 0.1):
+        nz = int(round(L / dz))
+        p = small(nx=nx, nz=nz, dx=0.5, dz=dz, chih=complex(-4e-6, 2e-8), chi0=complex(-5e-6, 2e-8),
+                  strain={"kind": "poly2", "x_ref_um": 32.0, "z_ref_um": 8.0,
+                          "c": [0.0, 0.0, 0.0, 0.0, 2e-6, 0.0]})
+        p["split_order"] = order
+        gp, gm, _, _ = oracle.propagate(p, psi_p0, None)
+        sols.append(np.concatenate([gp, gm]))
+    d = [np.linalg.norm(sols[i] - sols[i + 1]) for i in range(3)]
+    rate = d[1] / d[2]
+    assert 0.75 * 2 ** order < rate < 1.3 * 2 ** order, (d, rate)
