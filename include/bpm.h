@@ -95,6 +95,14 @@ typedef struct bpm_plan_desc {
     bpm_strain strain;
     int32_t det_lo, det_hi;  /* detector interval for R and T, 0 <= det_lo <= det_hi <= nx */
     int32_t precision;       /* bpm_precision */
+    /* Splitting of each z-step (Eq. (13)).  0 or 1: Eq. (12), propagate then
+     * couple with the Jacobi-Anger harmonics at z_n.  2: B(dz/2) A(dz) B(dz/2);
+     * 4: B(t dz/2) A(t dz) B((1-t) dz/2) A((1-2t) dz) B((1-t) dz/2) A(t dz) B(t dz/2),
+     * t = 1/(2 - 2^(1/3)).  For 2 and 4 a coupling sub-step B(b dz) is the
+     * exponential of the two-beam coupling generator (which composes, so the
+     * orders hold); it uses the mask row of step n and the strain at its own
+     * height z_n + (a_1 + ... + a_i) dz (TABLE strain: row n). */
+    int32_t split_order;
 } bpm_plan_desc;
 
 typedef struct bpm_plan bpm_plan;

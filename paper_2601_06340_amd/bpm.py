@@ -49,7 +49,8 @@ class PlanDesc(C.Structure):
                 ("x0_um", C.c_double), ("lambda_um", C.c_double), ("d_um", C.c_double),
                 ("chi0", Complex), ("chih", Complex), ("chihbar", Complex),
                 ("nseg", C.c_int32), ("seg", C.POINTER(C.c_int32)), ("strain", Strain),
-                ("det_lo", C.c_int32), ("det_hi", C.c_int32), ("precision", C.c_int32)]
+                ("det_lo", C.c_int32), ("det_hi", C.c_int32), ("precision", C.c_int32),
+                ("split_order", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -162,6 +163,7 @@ class _Desc:
         d.det_lo = int(p.get("det_lo", 0))
         d.det_hi = int(p.get("det_hi", p["nx"]))
         d.precision = PRECISION[p.get("precision", "f64")]
+        d.split_order = int(p.get("split_order", 1))
         self.c = d
 
 

@@ -144,7 +144,7 @@ bpm_status bpm::twiddle_table(int prec, int log2n, int log2e, const void **out)
 // precision, nx, dx, dz, lambda and d.  Plans that agree on these share one
 // reference-counted device copy, so a batch of solves that differ in crystal,
 // strain or incident beam reads a single table that stays in L2.
-using PropKey = std::tuple<int, int, double, double, double, double>;
+using PropKey = std::tuple<int, int, double, double, double, double, int>;
 struct PropEntry {
     void *ptr;
     int refs;
@@ -155,23 +155,29 @@ static std::map<PropKey, PropEntry> g_prop;
 static bpm_status prop_acquire(const bpm_plan_desc &d, const PlanParams *d_params, void **out)
 {
     std::lock_guard<std::mutex> lk(g_prop_mu);
-    const PropKey key{d.precision, d.nx, d.dx_um, d.dz_um, d.lambda_um, d.d_um};
+    const int order = d.split_order <= 1 ? 1 : d.split_order;
+    const PropKey key{d.precision, d.nx, d.dx_um, d.dz_um, d.lambda_um, d.d_um, order};
     auto it = g_prop.find(key);
     if (it != g_prop.end()) {
         ++it->second.refs;
         *out = it->second.ptr;
         return BPM_OK;
     }
-    const size_t bytes = 2 * (size_t)d.nx * (d.precision == BPM_F32 ? 8 : 16);
+    // one table per distinct propagation fraction of the splitting
+    int tab[kMaxSub];
+    double afrac[kMaxSub];
+    const int ntab = split_tables(order, tab, afrac);
+    const size_t one = 2 * (size_t)d.nx * (d.precision == BPM_F32 ? 8 : 16);
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = hipMalloc(&p, one * ntab);
     if (e != hipSuccess) return hip_fail(e, "propagator table");
     // built and finished under the lock: a second plan never sees a table in flight
     int log2n = 0;
     while ((1 << log2n) < d.nx) ++log2n;
     const int log2r = is_staged(d.precision, log2n) ? log2n - staged_log2c(d.precision) : 0;
     hipStream_t ss = setup_stream();
-    e = launch_plan_setup(d_params, nullptr, p, d.precision, d.nx, log2r, ss);
+    for (int k = 0; k < ntab && e == hipSuccess; ++k)
+        e = launch_plan_setup(d_params, nullptr, (char *)p + k * one, d.precision, d.nx, log2r, afrac[k], ss);
     if (e == hipSuccess) e = hipStreamSynchronize(ss);
     if (e != hipSuccess) {
         (void)hipFree(p);
@@ -245,6 +251,8 @@ bpm_status bpm::validate_desc(const bpm_plan_desc *d)
         return fail(BPM_E_INVALID, "detector [%d, %d) outside [0, %d]", d->det_lo, d->det_hi, d->nx);
     if (d->precision != BPM_F64 && d->precision != BPM_F32)
         return fail(BPM_E_INVALID, "unknown precision %d", d->precision);
+    if (d->split_order != 0 && d->split_order != 1 && d->split_order != 2 && d->split_order != 4)
+        return fail(BPM_E_INVALID, "split_order = %d: 1 (or 0), 2 or 4", d->split_order);
     int log2n = 0;
     while ((1 << log2n) < d->nx) ++log2n;
     if (log2n > max_log2n(d->precision))
@@ -348,7 +356,10 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
         return bail(st);
     if ((st = dev_alloc(&p->d_pin, sizeof(double), "incident power")) != BPM_OK) return bail(st);
     if ((st = dev_alloc(&p->d_rt, 2 * sizeof(double), "R/T")) != BPM_OK) return bail(st);
-    p->device_bytes = sizeof(PlanScalars) + sizeof(PlanParams) + 2 * nx * elem_bytes(prec) +
+    int tab[kMaxSub];
+    double afrac[kMaxSub];
+    const int ntab = split_tables(d->split_order <= 1 ? 1 : d->split_order, tab, afrac);
+    p->device_bytes = sizeof(PlanScalars) + sizeof(PlanParams) + 2 * nx * elem_bytes(prec) * ntab +
                       std::max<size_t>(nz, 1) * d->nseg * 2 * sizeof(int32_t) + 3 * sizeof(double);
 
     PlanParams pp;
@@ -364,13 +375,14 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
     pp.chihy = d->chih.im;
     pp.chihbx = d->chihbar.re;
     pp.chihby = d->chihbar.im;
+    pp.split_order = d->split_order <= 1 ? 1 : d->split_order;
     hipStream_t ss = setup_stream();
     hipError_t e = hipMemcpyAsync(p->d_params, &pp, sizeof pp, hipMemcpyHostToDevice, ss);
     if (e == hipSuccess && nz > 0)
         e = hipMemcpyAsync(p->d_seg, d->seg, nz * d->nseg * 2 * sizeof(int32_t), hipMemcpyHostToDevice, ss);
     if (e == hipSuccess) e = hipStreamSynchronize(ss);
     if (e != hipSuccess) return bail(hip_fail(e, "plan upload"));
-    e = launch_plan_setup(p->d_params, p->d_sc, nullptr, prec, d->nx, 0, ss);
+    e = launch_plan_setup(p->d_params, p->d_sc, nullptr, prec, d->nx, 0, 1.0, ss);
     if (e != hipSuccess) return bail(hip_fail(e, "plan setup kernel"));
     if ((st = prop_acquire(*d, p->d_params, &p->d_prop)) != BPM_OK) return bail(st);
 

@@ -1,6 +1,7 @@
 // bpm_internal.hpp — structures shared by the host library and the gfx950 kernels.
 #pragma once
 
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 
@@ -18,18 +19,71 @@ __host__ __device__ constexpr int strain_class(int kind)
     return kind == STRAIN_NONE ? SC_NONE : kind == STRAIN_POLY2 ? SC_POLY2 : SC_GENERAL;
 }
 
+// Splitting of one z-step (Eq. (13)): the product A(a_1 dz) B(b_1 dz) ...
+// A(a_m dz) B(b_m dz), applied from the left.  Order 1 is Eq. (12) (a = b = 1);
+// order 2 is a = (0, 1), b = (1/2, 1/2); order 4 is a = (0, t, 1-2t, t),
+// b = (t/2, (1-t)/2, (1-t)/2, t/2) with t = 1/(2 - 2^(1/3)).  Returns m (0 for
+// an order this library does not know).
+__host__ __device__ inline int split_sequence(int order, double *a, double *b)
+{
+    if (order == 0 || order == 1) {
+        a[0] = 1.0, b[0] = 1.0;
+        return 1;
+    }
+    if (order == 2) {
+        a[0] = 0.0, a[1] = 1.0;
+        b[0] = 0.5, b[1] = 0.5;
+        return 2;
+    }
+    if (order == 4) {
+        const double t = 1.0 / (2.0 - cbrt(2.0));
+        a[0] = 0.0, a[1] = t, a[2] = 1.0 - 2.0 * t, a[3] = t;
+        b[0] = 0.5 * t, b[1] = 0.5 * (1.0 - t), b[2] = 0.5 * (1.0 - t), b[3] = 0.5 * t;
+        return 4;
+    }
+    return 0;
+}
+// Propagator tables a splitting needs: one per distinct nonzero a_i, in order
+// of first use; table[i] is the table of sub-step i (-1 when a_i = 0).
+__host__ __device__ inline int split_tables(int order, int *table, double *afrac)
+{
+    double a[4], b[4];
+    const int m = split_sequence(order, a, b);
+    int nt = 0;
+    for (int i = 0; i < m; ++i) {
+        table[i] = -1;
+        if (a[i] == 0.0) continue;
+        for (int k = 0; k < nt; ++k)
+            if (afrac[k] == a[i]) table[i] = k;
+        if (table[i] < 0) {
+            afrac[nt] = a[i];
+            table[i] = nt++;
+        }
+    }
+    return nt;
+}
+constexpr int kMaxSub = 4;
+
+// One coupling sub-step of a z-step: its coefficients, its height (in steps,
+// from z_n) and the propagator table applied before it (-1: none).
+struct SubStep {
+    double d0x, d0y;          // a0 - 1     (harmonic 0, minus one)
+    double apx, apy;          // a+         (harmonic +1, pairs with chi_h)
+    double amx, amy;          // a-         (harmonic -1, pairs with chi_hbar)
+    double zoff;
+    int32_t table, pad;
+};
+
 // Per-plan scalars, produced on the device by the FP64 setup kernel.
 struct PlanScalars {
     double k, h, s, c, dzh;   // 2pi/lambda, 2pi/d, h/(2k), sqrt(1-s^2), k*dz
-    double d0x, d0y;          // a0 - 1     (harmonic 0 of exp(i dzh delta_eps / 2c), minus one)
-    double apx, apy;          // a+         (harmonic +1, pairs with chi_h)
-    double amx, amy;          // a-         (harmonic -1, pairs with chi_hbar)
-    double pad[5];
+    int32_t nsub, order;      // coupling sub-steps per z-step, splitting order
+    SubStep sub[kMaxSub];
 };
 
 // Inputs of the setup kernel (host-filled).
 struct PlanParams {
-    int32_t nx, pad0;
+    int32_t nx, split_order;
     double dx, dz, lambda, d;
     double chi0x, chi0y, chihx, chihy, chihbx, chihby;
 };
@@ -70,10 +124,11 @@ constexpr int staged_log2c(int prec) { return 6 + staged_log2e(prec); }
 constexpr int uniform_log2e(int log2n) { return log2n >= 8 ? 4 : (log2n >= 7 ? 3 : 2); }
 
 // Launchers (bpm_setup.hip).  All return hipSuccess or the launch error.
-// d_sc or d_prop may be NULL to skip that part; log2r > 0 stores the propagator
-// of a staged size in [k1][k2] order (R = 2^log2r).
+// d_sc or d_prop may be NULL to skip that part; d_prop receives the table of a
+// sub-step of afrac*dz; log2r > 0 stores the propagator of a staged size in
+// [k1][k2] order (R = 2^log2r).
 hipError_t launch_plan_setup(const PlanParams *d_params, PlanScalars *d_sc, void *d_prop, int prec,
-                             int nx, int log2r, hipStream_t s);
+                             int nx, int log2r, double afrac, hipStream_t s);
 hipError_t launch_twiddles(void *d_tw, int prec, int log2n, int log2e, hipStream_t s);
 size_t twiddle_bytes(int prec, int log2n, int log2e);
 // Staged sizes (four-step lane): whether log2n is one, and its twiddle table

@@ -451,12 +451,11 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Real-space coupling of one z-step (Eq. (9)-(12)) for the E samples a thread
-// holds at j0 + JS*e.  Outside the crystal the step is pure propagation: the
+// Real-space coupling of one z-step or sub-step (Eq. (9)-(13)) for the E samples
+// a thread holds at j0 + JS*e.  Outside the crystal the step is pure propagation: the
 // coefficients become (0, 0, 0), which leaves both envelopes untouched.
 template <typename T, int SC>
 struct Coupler {
-    Cx<T> d0, ap, am;
     double X0;       // x0 - x_ref
     int nseg, nx;
     gptr<int> seg;
@@ -464,10 +463,6 @@ struct Coupler {
 
     __device__ __forceinline__ void init(const SolveDesc &d, int nx_)
     {
-        const PlanScalars &sc = *d.sc;
-        d0 = {to_T<T>(sc.d0x), to_T<T>(sc.d0y)};
-        ap = {to_T<T>(sc.apx), to_T<T>(sc.apy)};
-        am = {to_T<T>(sc.amx), to_T<T>(sc.amy)};
         X0 = d.x0 - d.x_ref;
         nseg = d.nseg;
         nx = nx_;
@@ -475,9 +470,15 @@ struct Coupler {
         utab = to_global<T>(d.utab);
     }
 
+    // coupling sub-step ss of z-step n (its coefficients, mask row n, strain
+    // at z_n + ss.zoff dz)
     template <int E, int JS>
-    __device__ __forceinline__ void apply(Cx<T> *vp, Cx<T> *vm, const SolveDesc &d, int n, int j0) const
+    __device__ __forceinline__ void apply(Cx<T> *vp, Cx<T> *vm, const SolveDesc &d, int n, int j0,
+                                          const SubStep &ss) const
     {
+        const Cx<T> d0 = {to_T<T>(ss.d0x), to_T<T>(ss.d0y)};
+        const Cx<T> ap = {to_T<T>(ss.apx), to_T<T>(ss.apy)};
+        const Cx<T> am = {to_T<T>(ss.amx), to_T<T>(ss.amy)};
         static_assert(E <= 32 && (JS & (JS - 1)) == 0, "element mask");
         constexpr int LOG2JS = __builtin_ctz(JS);
         // bit e of `inside` <=> sample j0 + JS*e lies in one of the step's
@@ -498,7 +499,7 @@ struct Coupler {
         auto inside_at_e = [&](auto e) { return ((inside >> CV(e)) & 1u) != 0u; };
         const Cx<T> zero = {(T)0, (T)0};
         auto sel = [&](bool in, Cx<T> c) { return Cx<T>{in ? c.x : zero.x, in ? c.y : zero.y}; };
-        const double Z = n * d.dz - d.z_ref;
+        const double Z = (n + ss.zoff) * d.dz - d.z_ref;
         // (one straight-line copy: a separate all-inside copy costs registers)
         if constexpr (SC == SC_NONE) {
             static_for<0, E>([&](auto e) {
@@ -842,76 +843,84 @@ struct March {
         cpl.init(d, N);
         const T invN = (T)(1.0 / (double)N);
 
+        const PlanScalars &scl = *d.sc;
+        const int nsub = scl.nsub;
         const int nend = d.step0 + d.nsteps;
-        for (int n = d.step0; n < nend; ++n) {
+        for (int n = d.step0; n < nend; ++n)
+        for (int i = 0; i < nsub; ++i) {
+            // one sub-step of the splitting: the propagation of its table (none
+            // for a leading coupling), then its coupling
+            const SubStep &ss = scl.sub[i];
             // Opaque zeros (the compiler cannot see they are zero): the tables
-            // and per-lane offsets are re-derived each step instead of being
+            // and per-lane offsets are re-derived each sub-step instead of being
             // hoisted into registers for the whole march, and the inverse
             // passes re-read the twiddles instead of keeping the forward copies.
-            const int oz = n & d.opaque_zero;
+            const int oz = (n + i) & d.opaque_zero;
             const gptr<Tw<T>> twf = tw + oz;
-            const gptr<Tw<T>> twi = tw + ((n ^ 1) & d.opaque_zero);
-            const gptr<Cx<T>> propn = prop + oz;
+            const gptr<Tw<T>> twi = tw + ((n + i + 1) & d.opaque_zero);
+            const gptr<Cx<T>> propn = prop + (oz + ss.table * 2 * N);
             const int t = t0 + oz;
             const int w = t >> G::LOG2LANES, l = t & (LANES - 1);
             Cx<T> *Rp = bufp + w * BUFM;
             Cx<T> *Rm = bufm + w * BUFM;
 
-            // ---- forward transforms (Eq. (12): F[psi+-]); group-local passes
-            fwd_local(vp, vm, twf, Rp, Rm, l, active);
-            // ---- cross-group radix-W pass (wave groups only)
-            if constexpr (W > 1) {
+            if (ss.table >= 0) {
+                // ---- forward transforms (Eq. (12): F[psi+-]); group-local passes
+                fwd_local(vp, vm, twf, Rp, Rm, l, active);
+                // ---- cross-group radix-W pass (wave groups only)
+                if constexpr (W > 1) {
+                    if (active) {
+                        write_own(Rp, vp, l);
+                        if constexpr (BX == 2) write_own(Rm, vm, l);
+                    }
+                    __syncthreads();
+                    if (active) read_all(bufp, vp, t);
+                    if constexpr (BX == 2) {
+                        if (active) read_all(bufm, vm, t);
+                    } else {
+                        __syncthreads();
+                        if (active) write_own(Rm, vm, l);
+                        __syncthreads();
+                        if (active) read_all(bufm, vm, t);
+                    }
+                }
                 if (active) {
-                    write_own(Rp, vp, l);
-                    if constexpr (BX == 2) write_own(Rm, vm, l);
+                    if constexpr (W > 1) pass_fwd<G::LOG2G, G::LOG2M, TH>(vp, vm, twf, G::TWFINAL, t);
+                    // ---- propagator: sample f = t + TH*e holds frequency bin f
+                    static_for<0, E>([&](auto e) {
+                        const int f = t + e * TH;
+                        const Cx<T> kp = gload(propn, f), km = gload(propn, N + f);
+                        const Cx<T> a = vp[e], b = vm[e];
+                        vp[e] = {fmaT(kp.x, a.x, fmaT(-kp.y, a.y, a.x * invN)),
+                                 fmaT(kp.x, a.y, fmaT(kp.y, a.x, a.y * invN))};
+                        vm[e] = {fmaT(km.x, b.x, fmaT(-km.y, b.y, b.x * invN)),
+                                 fmaT(km.x, b.y, fmaT(km.y, b.x, b.y * invN))};
+                    });
+                    if constexpr (W > 1) pass_inv<G::LOG2G, G::LOG2M, TH>(vp, vm, twi, G::TWFINAL, t);
                 }
-                __syncthreads();
-                if (active) read_all(bufp, vp, t);
-                if constexpr (BX == 2) {
-                    if (active) read_all(bufm, vm, t);
-                } else {
+                // ---- inverse transforms, the forward steps undone in reverse order
+                if constexpr (W > 1) {
                     __syncthreads();
-                    if (active) write_own(Rm, vm, l);
+                    if (active) {
+                        write_all(bufp, vp, t);
+                        if constexpr (BX == 2) write_all(bufm, vm, t);
+                    }
                     __syncthreads();
-                    if (active) read_all(bufm, vm, t);
+                    if (active) read_own(Rp, vp, l);
+                    if constexpr (BX == 2) {
+                        if (active) read_own(Rm, vm, l);
+                    } else {
+                        __syncthreads();
+                        if (active) write_all(bufm, vm, t);
+                        __syncthreads();
+                        if (active) read_own(Rm, vm, l);
+                    }
                 }
+                inv_local(vp, vm, twi, Rp, Rm, l, active);
             }
-            if (active) {
-                if constexpr (W > 1) pass_fwd<G::LOG2G, G::LOG2M, TH>(vp, vm, twf, G::TWFINAL, t);
-                // ---- propagator: sample f = t + TH*e holds frequency bin f
-                static_for<0, E>([&](auto e) {
-                    const int f = t + e * TH;
-                    const Cx<T> kp = gload(propn, f), km = gload(propn, N + f);
-                    const Cx<T> a = vp[e], b = vm[e];
-                    vp[e] = {fmaT(kp.x, a.x, fmaT(-kp.y, a.y, a.x * invN)),
-                             fmaT(kp.x, a.y, fmaT(kp.y, a.x, a.y * invN))};
-                    vm[e] = {fmaT(km.x, b.x, fmaT(-km.y, b.y, b.x * invN)),
-                             fmaT(km.x, b.y, fmaT(km.y, b.x, b.y * invN))};
-                });
-                if constexpr (W > 1) pass_inv<G::LOG2G, G::LOG2M, TH>(vp, vm, twi, G::TWFINAL, t);
-            }
-            // ---- inverse transforms, the forward steps undone in reverse order
-            if constexpr (W > 1) {
-                __syncthreads();
-                if (active) {
-                    write_all(bufp, vp, t);
-                    if constexpr (BX == 2) write_all(bufm, vm, t);
-                }
-                __syncthreads();
-                if (active) read_own(Rp, vp, l);
-                if constexpr (BX == 2) {
-                    if (active) read_own(Rm, vm, l);
-                } else {
-                    __syncthreads();
-                    if (active) write_all(bufm, vm, t);
-                    __syncthreads();
-                    if (active) read_own(Rm, vm, l);
-                }
-            }
-            inv_local(vp, vm, twi, Rp, Rm, l, active);
 
-            // ---- real-space coupling inside the crystal (Eq. (9)-(12))
-            if (active) cpl.template apply<E, TH>(vp, vm, d, n, w + W * l);
+            // ---- real-space coupling inside the crystal (Eq. (9)-(13))
+            if (active) cpl.template apply<E, TH>(vp, vm, d, n, w + W * l, ss);
         }
 
         if (active) {
@@ -1046,6 +1055,11 @@ struct Staged {
         const int nend = d.step0 + d.nsteps;
         const bool rt_out = (d.flags & SF_LAST) && d.rt_index >= 0;
         double sp = 0.0, sm = 0.0, pin_part = 0.0;
+        // splitting of a z-step: sub-step 0 may be a leading coupling with no
+        // propagation before it; it runs in the column phase that precedes the step
+        const PlanScalars &scl = *d.sc;
+        const int nsub = scl.nsub;
+        const bool lead = scl.sub[0].table < 0;
 
         // ---- entry: natural-order x -> forward column DFTs -> Y
 #pragma unroll 1
@@ -1060,6 +1074,7 @@ struct Staged {
                 });
             }
             if (d.nsteps > 0) {
+                if (lead) cpl.template apply<E, LC * C>(vp, vm, d, d.step0, lc * C + c, scl.sub[0]);
                 const gptr<Tw<T>> twc = tw + (TW_COL + (cr & d.opaque_zero));
                 ColM::fwd_local(vp, vm, twc, CRp, CRm, lc, true);
             } else if (rt_out) {
@@ -1073,12 +1088,14 @@ struct Staged {
             if (t0 == 0 && d.pin) *d.pin = pin;
         }
 
-        for (int n = d.step0; n < nend; ++n) {
+        for (int n = d.step0; n < nend; ++n)
+        for (int i = lead ? 1 : 0; i < nsub; ++i) {
+            const SubStep &ss = scl.sub[i];
             __syncthreads();
-            // ---- row phase: propagation in Fourier space (Eq. (12))
+            // ---- row phase: propagation in Fourier space (Eq. (12)-(13))
 #pragma unroll 1
             for (int rr = 0; rr < ROW_ROUNDS; ++rr) {
-                const int oz = (n + rr) & d.opaque_zero;
+                const int oz = (n + i + rr) & d.opaque_zero;
                 const int k1 = rr * WAVES + wv;
                 const int rb = k1 * C + lane + oz;
                 Cx<T> vp[E], vm[E];
@@ -1090,7 +1107,7 @@ struct Staged {
                 });
                 RowM::fwd_local(vp, vm, tw + oz, RRp, RRm, lane, true);
                 // bin k2 = lane + 64 e of row k1 is frequency k1 + R k2
-                const gptr<Cx<T>> pr = prop + oz;
+                const gptr<Cx<T>> pr = prop + (oz + ss.table * 2 * N);
                 static_for<0, E>([&](auto e) {
                     const int f = k1 * C + lane + e * 64;
                     const Cx<T> kp = gload(pr, f), km = gload(pr, N + f);
@@ -1100,7 +1117,7 @@ struct Staged {
                     vm[e] = {fmaT(km.x, b.x, fmaT(-km.y, b.y, b.x * invN)),
                              fmaT(km.x, b.y, fmaT(km.y, b.x, b.y * invN))};
                 });
-                const int oi = (n + rr + 1) & d.opaque_zero;
+                const int oi = (n + i + rr + 1) & d.opaque_zero;
                 RowM::inv_local(vp, vm, tw + oi, RRp, RRm, lane, true);
                 const int rbi = k1 * C + lane + oi;
                 static_for<0, E>([&](auto e) {
@@ -1111,19 +1128,21 @@ struct Staged {
                 store(st, vp, vm, rb - oz, 64);
             }
             __syncthreads();
-            // ---- column phase: inverse column DFTs, coupling (Eq. (9)-(12)),
-            // forward column DFTs of the next step
-            const bool last = n + 1 == nend;
+            // ---- column phase: inverse column DFTs, coupling (Eq. (9)-(13)),
+            // then the next step's leading coupling and forward column DFTs
+            const bool step_end = i + 1 == nsub;
+            const bool last = step_end && n + 1 == nend;
 #pragma unroll 1
             for (int cr = 0; cr < COL_ROUNDS; ++cr) {
-                const int oz = (n + cr) & d.opaque_zero;
+                const int oz = (n + i + cr) & d.opaque_zero;
                 const int c = cr * COLS_PER_ROUND + wv * GPW + gi;
                 Cx<T> vp[E], vm[E];
                 load(vp, vm, st, lc * C + c + oz, LC * C);
                 ColM::inv_local(vp, vm, tw + (TW_COL + oz), CRp, CRm, lc, true);
-                cpl.template apply<E, LC * C>(vp, vm, d, n, lc * C + c);
+                cpl.template apply<E, LC * C>(vp, vm, d, n, lc * C + c, ss);
                 if (!last) {
-                    const int of = (n + cr + 1) & d.opaque_zero;
+                    if (step_end && lead) cpl.template apply<E, LC * C>(vp, vm, d, n + 1, lc * C + c, scl.sub[0]);
+                    const int of = (n + i + cr + 1) & d.opaque_zero;
                     ColM::fwd_local(vp, vm, tw + (TW_COL + of), CRp, CRm, lc, true);
                 } else if (rt_out) {
                     det_sums(vp, vm, d, lc * C + c, LC * C, sp, sm);

@@ -56,7 +56,10 @@ struct Request {
 size_t estimate_bytes(const bpm_plan_desc &d)
 {
     const size_t eb = d.precision == BPM_F32 ? 8 : 16;
-    size_t b = 2 * (size_t)d.nx * eb * 2;                           // state + propagator table
+    int tab[kMaxSub];
+    double afrac[kMaxSub];
+    const int ntab = split_tables(d.split_order <= 1 ? 1 : d.split_order, tab, afrac);
+    size_t b = 2 * (size_t)d.nx * eb * (1 + ntab);                  // state + propagator tables
     b += (size_t)std::max(d.nz, 1) * d.nseg * 2 * sizeof(int32_t);  // mask
     if (d.strain.kind == BPM_STRAIN_TABLE) b += (size_t)d.nz * d.nx * (d.precision == BPM_F32 ? 4 : 8);
     b += 4096;                                                       // scalars, descriptors
@@ -127,7 +130,9 @@ void bpm_server::finish(const std::shared_ptr<Request> &r, int status)
 // 16384/nx so every size class takes about the same time per round.
 int bpm_server::steps_for(const Request &r) const
 {
-    const long long s = (long long)cfg.chunk_steps * 16384 / r.desc.nx;
+    // a z-step of a splitting runs one FFT pair per propagation sub-step
+    const int fft_pairs = r.desc.split_order == 4 ? 3 : 1;
+    const long long s = (long long)cfg.chunk_steps * 16384 / r.desc.nx / fft_pairs;
     return (int)std::max(1LL, std::min<long long>(s, r.desc.nz - r.step));
 }
 

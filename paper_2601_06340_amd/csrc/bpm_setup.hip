@@ -5,10 +5,52 @@ namespace bpm {
 
 // ----------------------------------------------------------------- setup kernels
 // FP64 plan setup: coupling harmonics and propagator tables (one launch per plan).
-// The table of a staged size is stored in [k1][k2] order (frequency
+// Coupling coefficients of a sub-step of b*dz (Eq. (8)-(12)), all in FP64:
+// A = b dzh / 2c, E = exp(i A chi0), y = -A^2 chih chihb.  form 0: the
+// Jacobi-Anger harmonics, a0 = J0 E with J0 = sum y^m/(m!)^2 and
+// a+- = i A chi G E with G = sum y^m/(m!(m+1)!); form 1: the exponential of the
+// two-beam coupling generator, cosh/sinh series sum y^m/(2m)! and
+// sum y^m/(2m+1)! in their place.  a0 - 1 is formed without cancellation.
+__device__ void coupling_substep(const PlanParams &P, double A, int form, SubStep &o)
+{
+    // E - 1 = expm1(i A chi0)
+    const double gx = -A * P.chi0y, gy = A * P.chi0x;  // i A chi0
+    const double eg = exp(gx), sgy = sin(gy), shalf = sin(0.5 * gy);
+    const double em1x = expm1(gx) * cos(gy) - 2.0 * shalf * shalf;
+    const double em1y = eg * sgy;
+    const double Ex = 1.0 + em1x, Ey = em1y;
+    const double qx = P.chihx * P.chihbx - P.chihy * P.chihby;
+    const double qy = P.chihx * P.chihby + P.chihy * P.chihbx;
+    const double yx = -A * A * qx, yy = -A * A * qy;
+    double t0x = 1.0, t0y = 0.0, t1x = 1.0, t1y = 0.0;
+    double dmx = 0.0, dmy = 0.0, gxs = 1.0, gys = 0.0;   // diagonal series - 1, off-diagonal series
+    for (int m = 1; m < 60; ++m) {
+        const double r0 = form == 0 ? (double)m * m : (double)(2 * m - 1) * (2 * m);
+        const double r1 = form == 0 ? (double)m * (m + 1) : (double)(2 * m) * (2 * m + 1);
+        const double nx0 = (t0x * yx - t0y * yy) / r0, ny0 = (t0x * yy + t0y * yx) / r0;
+        const double nx1 = (t1x * yx - t1y * yy) / r1, ny1 = (t1x * yy + t1y * yx) / r1;
+        t0x = nx0; t0y = ny0; t1x = nx1; t1y = ny1;
+        dmx += t0x; dmy += t0y; gxs += t1x; gys += t1y;
+        if (fabs(t0x) + fabs(t0y) + fabs(t1x) + fabs(t1y) < 1e-20) break;
+    }
+    // a0 - 1 = (D - 1) E + (E - 1)
+    o.d0x = (dmx * Ex - dmy * Ey) + em1x;
+    o.d0y = (dmx * Ey + dmy * Ex) + em1y;
+    const double gex = gxs * Ex - gys * Ey, gey = gxs * Ey + gys * Ex;
+    const double cpx = -A * P.chihy, cpy = A * P.chihx;    // i A chih
+    const double cmx = -A * P.chihby, cmy = A * P.chihbx;  // i A chihb
+    o.apx = cpx * gex - cpy * gey;
+    o.apy = cpx * gey + cpy * gex;
+    o.amx = cmx * gex - cmy * gey;
+    o.amy = cmx * gey + cmy * gex;
+}
+
+// FP64 plan setup.  sc != NULL: plan scalars and the coupling sub-steps of the
+// splitting; prop != NULL: the propagator table (P - 1)/nx of a sub-step of
+// afrac*dz.  The table of a staged size is stored in [k1][k2] order (frequency
 // f = k1 + R k2 at k1*(nx/R) + k2, R = 2^log2r); log2r = 0 keeps natural order.
 template <typename T>
-__global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, Cx<T> *prop, int log2r)
+__global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, Cx<T> *prop, int log2r, double afrac)
 {
     const PlanParams P = *pp;
     const double k = 2.0 * M_PI / P.lambda;
@@ -16,43 +58,25 @@ __global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, Cx<T> *prop,
     const double s = h / (2.0 * k);
     const double c = sqrt(1.0 - s * s);
     const double dzh = k * P.dz;
-    const double A = dzh / (2.0 * c);
     const int nx = P.nx;
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (sc && blockIdx.x == 0 && threadIdx.x == 0) {
-        // E - 1 = expm1(i A chi0) without cancellation
-        const double gx = -A * P.chi0y, gy = A * P.chi0x;  // i A chi0
-        const double eg = exp(gx), sgy = sin(gy), shalf = sin(0.5 * gy);
-        const double em1x = expm1(gx) * cos(gy) - 2.0 * shalf * shalf;
-        const double em1y = eg * sgy;
-        const double Ex = 1.0 + em1x, Ey = em1y;
-        // y = -A^2 chih chihb; J0 - 1 = sum_{m>=1} y^m/(m!)^2, G = sum_m y^m/(m!(m+1)!)
-        const double qx = P.chihx * P.chihbx - P.chihy * P.chihby;
-        const double qy = P.chihx * P.chihby + P.chihy * P.chihbx;
-        const double yx = -A * A * qx, yy = -A * A * qy;
-        double t0x = 1.0, t0y = 0.0, t1x = 1.0, t1y = 0.0;
-        double j0mx = 0.0, j0my = 0.0, gxs = 1.0, gys = 0.0;
-        for (int m = 1; m < 60; ++m) {
-            double nx0 = (t0x * yx - t0y * yy) / ((double)m * m);
-            double ny0 = (t0x * yy + t0y * yx) / ((double)m * m);
-            double nx1 = (t1x * yx - t1y * yy) / ((double)m * (m + 1));
-            double ny1 = (t1x * yy + t1y * yx) / ((double)m * (m + 1));
-            t0x = nx0; t0y = ny0; t1x = nx1; t1y = ny1;
-            j0mx += t0x; j0my += t0y; gxs += t1x; gys += t1y;
-            if (fabs(t0x) + fabs(t0y) + fabs(t1x) + fabs(t1y) < 1e-20) break;
-        }
-        // a0 - 1 = (J0 - 1) E + (E - 1)
         sc->k = k; sc->h = h; sc->s = s; sc->c = c; sc->dzh = dzh;
-        sc->d0x = (j0mx * Ex - j0my * Ey) + em1x;
-        sc->d0y = (j0mx * Ey + j0my * Ex) + em1y;
-        // a+ = i A chih G E, a- = i A chihb G E
-        const double gex = gxs * Ex - gys * Ey, gey = gxs * Ey + gys * Ex;
-        const double cpx = -A * P.chihy, cpy = A * P.chihx;    // i A chih
-        const double cmx = -A * P.chihby, cmy = A * P.chihbx;  // i A chihb
-        sc->apx = cpx * gex - cpy * gey;
-        sc->apy = cpx * gey + cpy * gex;
-        sc->amx = cmx * gex - cmy * gey;
-        sc->amy = cmx * gey + cmy * gex;
+        double a[kMaxSub], b[kMaxSub], af[kMaxSub];
+        int tab[kMaxSub];
+        const int m = split_sequence(P.split_order, a, b);
+        split_tables(P.split_order, tab, af);
+        sc->nsub = m;
+        sc->order = P.split_order;
+        // Eq. (12) couples at z_n after the propagation; the splittings put
+        // sub-step i at z_n + (a_1 + ... + a_i) dz
+        double acc = 0.0;
+        for (int i = 0; i < m; ++i) {
+            acc += a[i];
+            coupling_substep(P, b[i] * dzh / (2.0 * c), P.split_order >= 2 ? 1 : 0, sc->sub[i]);
+            sc->sub[i].zoff = P.split_order >= 2 ? acc : 0.0;
+            sc->sub[i].table = tab[i];
+        }
     }
     if (prop && f < nx) {
         const int ff = f < nx / 2 ? f : f - nx;
@@ -64,14 +88,14 @@ __global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, Cx<T> *prop,
             double kx, ky;  // P - 1
             if (fabs(pq) <= 1.0) {
                 const double S = sqrt(1.0 - pq * pq);
-                const double th = -dzh * (q * q + 2.0 * sg * s * q) / (S + c);
+                const double th = -afrac * dzh * (q * q + 2.0 * sg * s * q) / (S + c);
                 const double sh = sin(0.5 * th);
                 kx = -2.0 * sh * sh;
                 ky = sin(th);
             } else {
-                const double mag = exp(-dzh * sqrt(pq * pq - 1.0));
-                kx = mag * cos(dzh * c) - 1.0;
-                ky = -mag * sin(dzh * c);
+                const double mag = exp(-afrac * dzh * sqrt(pq * pq - 1.0));
+                kx = mag * cos(afrac * dzh * c) - 1.0;
+                ky = -mag * sin(afrac * dzh * c);
             }
             const int pos = log2r ? (f & ((1 << log2r) - 1)) * (nx >> log2r) + (f >> log2r) : f;
             prop[beam * nx + pos] = {(T)(kx * invn), (T)(ky * invn)};
@@ -199,14 +223,15 @@ hipError_t launch_twiddles(void *d_tw, int prec, int log2n, int log2e, hipStream
 }
 
 hipError_t launch_plan_setup(const PlanParams *d_params, PlanScalars *d_sc, void *d_prop, int prec, int nx,
-                             int log2r, hipStream_t s)
+                             int log2r, double afrac, hipStream_t s)
 {
     const int bs = 256, gs = d_prop ? (nx + bs - 1) / bs : 1;
     if (prec == PREC_F32)
-        hipLaunchKernelGGL(k_plan_setup<float>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (Cx<float> *)d_prop, log2r);
+        hipLaunchKernelGGL(k_plan_setup<float>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (Cx<float> *)d_prop, log2r,
+                           afrac);
     else
         hipLaunchKernelGGL(k_plan_setup<double>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (Cx<double> *)d_prop,
-                           log2r);
+                           log2r, afrac);
     return hipGetLastError();
 }
 

@@ -180,6 +180,72 @@ def test_staged_strain_table_ragged_two_intervals(prec):
     check(p, a, 0.5 * b, "staged-table")
 
 
+# ------------------------------------------------------------------ higher-order splittings (Eq. (13))
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("prec,nx", [("f64", 1024), ("f32", 1024), ("f64", 8192), ("f32", 16384),
+                                     ("f64", 16384), ("f32", 32768)])
+def test_split_order_bent_laue(order, prec, nx):
+    """z-dependent strain: every coupling sub-step samples its own height."""
+    p, psi = synth.bent_laue(radii_m=(0.3,), nx=nx, nz=60, thickness=2.0, precision=prec)[0]
+    p["split_order"] = order
+    check(p, psi, label="split%d-bent-%d" % (order, nx))
+
+
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_split_order_masks_dislocation_and_table(order, prec):
+    p, psi = synth.flat_bragg_scan(n_angles=1, nx=2048, nz=120, precision=prec)[0]
+    p["split_order"] = order
+    check(p, psi, label="split%d-bragg" % order)
+    p, psi = synth.disl_bragg(nx=4096, nz=150, scale=0.125, precision=prec)
+    p["split_order"] = order
+    check(p, psi, label="split%d-disl" % order)
+    nx, nz = 512, 80
+    rng = synth.SplitMix64(5)
+    u = np.array([[3e-5 * math.sin(0.02 * j + 0.1 * n) + 1e-6 * rng.uniform() for j in range(nx)]
+                  for n in range(nz)])
+    seg = np.zeros((nz, 2, 2), np.int32)
+    for n in range(nz):
+        seg[n, 0] = (20 + n, 200)
+        seg[n, 1] = (260, 500 - n)
+    p = synth.base_problem(nx, nz, 0.1, 0.05, seg, precision=prec, strain={"kind": "table", "u_table": u})
+    p["split_order"] = order
+    a, b = synth.random_envelopes(nx, 3)
+    check(p, a, 0.2 * b, "split%d-table" % order)
+
+
+def test_split_orders_mixed_in_one_batch_and_chunked_server():
+    B = bpm()
+    import torch
+    cases = []
+    for k, (order, nx) in enumerate(((1, 2048), (2, 4096), (4, 1024), (2, 32768), (4, 16384))):
+        p, psi = synth.bent_laue(radii_m=(0.5 + k,), nx=nx, nz=40 + 7 * k, thickness=1.5, precision="f32")[0]
+        p["split_order"] = order
+        cases.append((p, psi))
+    plans = [B.Plan(p) for p, _ in cases]
+    batch = B.Batch(plans)
+    buf = batch.pack([(psi, None) for _, psi in cases])
+    rt = torch.zeros(2 * len(plans), dtype=torch.float64, device="cuda")
+    batch.run(buf.data_ptr(), buf.data_ptr(), rt.data_ptr())
+    torch.cuda.synchronize()
+    outs = batch.unpack(buf)
+    for i, (p, psi) in enumerate(cases):
+        op, om, oR, _ = oracle.propagate(p, psi)
+        err = rel_pair(outs[i][0], outs[i][1], op, om)
+        say("split batch", i, p["split_order"], p["nx"], "%.3e" % err)
+        assert err <= TOL["f32"][0]
+        assert abs(rt.cpu().numpy()[2 * i] - oR) <= TOL["f32"][1]
+    srv = B.Server(hbm_budget_bytes=1 << 30, max_slots=8, chunk_steps=5)
+    ts = [srv.submit(p, psi) for p, psi in cases]
+    assert srv.drain(120.0)
+    for t, (p, psi) in zip(ts, cases):
+        r = srv.poll(t)
+        assert r["status"] == 0
+        op, om, _, _ = oracle.propagate(p, psi)
+        assert rel_pair(r["psi_p"], r["psi_m"], op, om) <= TOL["f32"][0]
+    srv.close()
+
+
 def test_fp32_long_march_error_budget():
     """Nz = 8000 FP32 Bragg solve stays inside the FP32 bars (no linear drift)."""
     cases = synth.flat_bragg_scan(n_angles=1, nx=4096, nz=8000, precision="f32")
