@@ -159,7 +159,7 @@ void bpm_batch_destroy(bpm_batch *batch);
 /* --- serving (continuous batching) ------------------------------------------
  * A server owns a device-memory budget and a pool of solve slots.  A worker
  * thread advances all admitted solves together in rounds: per precision one
- * stream and one launch per strain class that takes every size side by side
+ * stream and one launch that takes every size and strain class side by side
  * (sizes below 1024 launch separately).  A solve of size nx advances
  * chunk_steps*16384/nx z-steps per round (at least 1), so every class takes
  * about the same time per round.  While a round runs, the worker builds the

@@ -63,14 +63,15 @@ def _gen_units() -> list[str]:
                       "template hipError_t launch_staged<%s, %d, %d>(const SolveDesc *, int, const char *, "
                       "char *, double *, hipStream_t);\n}\n" % (t, l2, sc))
         for t in MIXED:
-            write("march_any_%s_sc%d.hip" % (t, sc),
-                  '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
-                  "template hipError_t launch_any<%s, %d>(const SolveDesc *, int, const char *, char *, "
-                  "double *, hipStream_t);\n}\n" % (t, sc))
             write("march_mixed_%s_sc%d.hip" % (t, sc),
                   '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
                   "template hipError_t launch_mixed<%s, %d>(const SolveDesc *, int, const char *, char *, "
                   "double *, hipStream_t);\n}\n" % (t, sc))
+    for t in MIXED:
+        write("march_any_%s.hip" % t,
+              '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
+              "template hipError_t launch_any<%s>(const SolveDesc *, int, const char *, char *, "
+              "double *, hipStream_t);\n}\n" % t)
     return units
 
 

@@ -537,14 +537,57 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
                                const std::vector<int> &flags, std::vector<Launch> &launches, bool any_size)
 {
     launches.clear();
+    // longest first: the hardware dispatcher then balances uneven solves
+    auto cost = [&](int i) {
+        const int pairs = plans[i]->desc.split_order == 4 ? 3 : 1;
+        return (double)nsteps[i] * pairs * plans[i]->desc.nx * (plans[i]->log2n + 4);
+    };
+    auto emit = [&](int prec, int sc, int group_log2n, const std::vector<int> &g) -> bpm_status {
+        Launch L;
+        L.prec = prec;
+        L.sc = sc;
+        L.uniform_log2n = group_log2n;
+        std::vector<SolveDesc> descs(g.size());
+        for (size_t k = 0; k < g.size(); ++k) {
+            const int i = g[k];
+            const bpm_plan *p = plans[i];
+            const void *tw = p->tw_uniform;
+            int log2e = uniform_log2e(p->log2n);
+            if (group_log2n < 0 && !is_staged(prec, p->log2n)) {
+                log2e = mixed_log2e(prec, p->log2n);
+                bpm_status st = twiddle_table(prec, p->log2n, log2e, &tw);
+                if (st != BPM_OK) return st;
+            }
+            p->fill(descs[k], log2e, tw, flags[i], step0[i], nsteps[i], in_off[i], out_off[i], rt_index[i]);
+        }
+        L.n = (int)descs.size();
+        L.host = descs;
+        launches.push_back(std::move(L));
+        return BPM_OK;
+    };
+    if (any_size) {
+        // every size the any-size kernel takes, of every strain class, in one
+        // launch per precision (a size always meets the same kernel, whatever
+        // else is launched); smaller sizes below, per size and strain class
+        for (int prec : {BPM_F32, BPM_F64}) {
+            std::vector<int> big;
+            for (int i = 0; i < n; ++i)
+                if (plans[i]->desc.precision == prec && plans[i]->log2n >= mixed_min_log2n(prec)) big.push_back(i);
+            std::stable_sort(big.begin(), big.end(), [&](int a, int b) { return cost(a) > cost(b); });
+            if (!big.empty()) {
+                bpm_status st = emit(prec, SC_NONE, kLaunchAny, big);
+                if (st != BPM_OK) return st;
+            }
+        }
+    }
     for (int prec : {BPM_F32, BPM_F64})
     for (int sc : {0, 1, 2}) {
         std::vector<int> idx;
         for (int i = 0; i < n; ++i)
-            if (plans[i]->desc.precision == prec && strain_class(plans[i]->desc.strain.kind) == sc) idx.push_back(i);
+            if (plans[i]->desc.precision == prec && strain_class(plans[i]->desc.strain.kind) == sc &&
+                !(any_size && plans[i]->log2n >= mixed_min_log2n(prec)))
+                idx.push_back(i);
         if (idx.empty()) continue;
-        // longest first: the hardware dispatcher then balances uneven solves
-        auto cost = [&](int i) { return (double)nsteps[i] * plans[i]->desc.nx * (plans[i]->log2n + 4); };
         std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost(a) > cost(b); });
         int lo = 99, hi = -1;
         for (int i : idx) {
@@ -554,16 +597,7 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
         std::vector<std::vector<int>> groups;
         std::vector<int> group_log2n;
         if (any_size) {
-            // one launch for every size the any-size kernel takes, the rest per
-            // size; a size always meets the same kernel, whatever else is launched
-            std::vector<int> big;
-            for (int i : idx)
-                if (plans[i]->log2n >= mixed_min_log2n(prec)) big.push_back(i);
-            if (!big.empty()) {
-                groups.push_back(big);
-                group_log2n.push_back(kLaunchAny);
-            }
-            for (int l = lo; l < mixed_min_log2n(prec); ++l) {
+            for (int l = lo; l <= hi; ++l) {
                 std::vector<int> g;
                 for (int i : idx)
                     if (plans[i]->log2n == l) g.push_back(i);
@@ -590,26 +624,8 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
             }
         }
         for (size_t gi = 0; gi < groups.size(); ++gi) {
-            Launch L;
-            L.prec = prec;
-            L.sc = sc;
-            L.uniform_log2n = group_log2n[gi];
-            std::vector<SolveDesc> descs(groups[gi].size());
-            for (size_t k = 0; k < groups[gi].size(); ++k) {
-                const int i = groups[gi][k];
-                const bpm_plan *p = plans[i];
-                const void *tw = p->tw_uniform;
-                int log2e = uniform_log2e(p->log2n);
-                if (L.uniform_log2n < 0 && !is_staged(prec, p->log2n)) {
-                    log2e = mixed_log2e(prec, p->log2n);
-                    bpm_status st = twiddle_table(prec, p->log2n, log2e, &tw);
-                    if (st != BPM_OK) return st;
-                }
-                p->fill(descs[k], log2e, tw, flags[i], step0[i], nsteps[i], in_off[i], out_off[i], rt_index[i]);
-            }
-            L.n = (int)descs.size();
-            L.host = descs;
-            launches.push_back(std::move(L));
+            bpm_status st = emit(prec, sc, group_log2n[gi], groups[gi]);
+            if (st != BPM_OK) return st;
         }
     }
     return BPM_OK;

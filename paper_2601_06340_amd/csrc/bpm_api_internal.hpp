@@ -56,9 +56,10 @@ struct Launch {
 
 // Group solves into launches: per (precision, strain class), one uniform launch
 // when all share nx, one mixed launch when all sizes fit the mixed kernel, and
-// otherwise per size.  With any_size, every size the any-size kernel takes goes
-// into one launch of it (whatever the mix, so a solve's arithmetic never depends
-// on what else is launched) and smaller sizes per size.  Longest solves first.
+// otherwise per size.  With any_size, every solve of a size the any-size kernel
+// takes, of any strain class, goes into one launch of it per precision (whatever
+// the mix, so a solve's arithmetic never depends on what else is launched) and
+// smaller sizes per size.  Longest solves first.
 bpm_status build_launches(bpm_plan *const *plans, int n, const std::vector<int> &rt_index,
                           const std::vector<uint64_t> &in_off, const std::vector<uint64_t> &out_off,
                           const std::vector<int> &step0, const std::vector<int> &nsteps,

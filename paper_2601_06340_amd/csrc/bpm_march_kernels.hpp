@@ -128,18 +128,14 @@ hipError_t launch_mixed(const SolveDesc *d_descs, int n, const char *in_base, ch
     return hipGetLastError();
 }
 
-// Any size from 2^mix_lo to 2^stg_hi in one grid (the server's launches): 512
-// threads per workgroup, register-resident sizes as in the mixed kernel, the
-// larger ones through the staged lane.
+// Any size from 2^mix_lo to 2^stg_hi and any strain class in one grid (the
+// server's launches): 512 threads per workgroup, register-resident sizes as in
+// the mixed kernel, the larger ones through the staged lane; each workgroup
+// branches on its solve's size and strain class.
 template <typename T, int SC>
-__global__ __launch_bounds__(1 << kMixedLog2Th) __attribute__((amdgpu_waves_per_eu(1, 2)))
-void k_march_any(const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
+__device__ __forceinline__ void march_any_sc(const SolveDesc &d, const char *in_base, char *out_base, double *rt,
+                                             Cx<T> *lds, double *red)
 {
-    static_assert(kMixedLog2Th == kStagedLog2Th, "one workgroup shape");
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[16];
-    const SolveDesc &d = descs[blockIdx.x];
-    Cx<T> *lds = reinterpret_cast<Cx<T> *>(smem);
     static_for<Limits<T>::mix_lo, Limits<T>::mix_hi + 1>([&](auto l) {
         constexpr int L2 = CV(l);
         if (d.log2n == L2)
@@ -148,6 +144,21 @@ void k_march_any(const SolveDesc *descs, int n, const char *in_base, char *out_b
     static_for<Limits<T>::stg_lo, Limits<T>::stg_hi + 1>([&](auto l) {
         if (d.log2n == CV(l)) Staged<T, CV(l), SC>::run(d, in_base, out_base, rt, lds, red);
     });
+}
+
+template <typename T>
+__global__ __launch_bounds__(1 << kMixedLog2Th) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_march_any(const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
+{
+    static_assert(kMixedLog2Th == kStagedLog2Th, "one workgroup shape");
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[16];
+    const SolveDesc &d = descs[blockIdx.x];
+    Cx<T> *lds = reinterpret_cast<Cx<T> *>(smem);
+    const int sc = strain_class(d.strain_kind);
+    if (sc == SC_NONE) march_any_sc<T, SC_NONE>(d, in_base, out_base, rt, lds, red);
+    else if (sc == SC_POLY2) march_any_sc<T, SC_POLY2>(d, in_base, out_base, rt, lds, red);
+    else march_any_sc<T, SC_GENERAL>(d, in_base, out_base, rt, lds, red);
 }
 
 template <typename T>
@@ -161,7 +172,7 @@ size_t any_lds_bytes()
     return m;
 }
 
-template <typename T, int SC>
+template <typename T>
 hipError_t launch_any(const SolveDesc *d_descs, int n, const char *in_base, char *out_base, double *rt,
                       hipStream_t s)
 {
@@ -169,13 +180,12 @@ hipError_t launch_any(const SolveDesc *d_descs, int n, const char *in_base, char
     const size_t lds = any_lds_bytes<T>();
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_any<T, SC>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_any<T>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_march_any<T, SC>), dim3(n), dim3(1 << kMixedLog2Th), lds, s, d_descs, n, in_base, out_base,
-                       rt);
+    hipLaunchKernelGGL((k_march_any<T>), dim3(n), dim3(1 << kMixedLog2Th), lds, s, d_descs, n, in_base, out_base, rt);
     return hipGetLastError();
 }
 

@@ -5,8 +5,8 @@
 // their plans and entrance states; plan setup waits only for the library's
 // setup stream, so this overlaps the marches.  The march worker runs rounds:
 // every active solve advances a work-balanced number of z-steps (chunk_steps at
-// nx = 16384, scaled by 16384/nx) in one any-size launch per (precision, strain
-// class), so solves of every size run side by side on the device; after the
+// nx = 16384, scaled by 16384/nx) in one any-size launch per precision, so
+// solves of every size and strain class run side by side on the device; after the
 // round it retires the solves that reached nz, and the requests set up in the
 // meantime join the next round.  A solve's arithmetic is the same kernel and
 // schedule as bpm_propagate, and its state crosses round boundaries through HBM
@@ -238,8 +238,8 @@ void bpm_server::run()
         }
 
         // ---- one round: every active solve advances steps_for() z-steps; per
-        // precision one stream and one any-size launch per strain class, so
-        // solves of every size run side by side
+        // precision one stream and one any-size launch, so solves of every size
+        // and strain class run side by side
         for (size_t i = 0; i < active.size(); ++i) active[i]->slot = (int)i;
         std::vector<int> adv(active.size(), 0);
         bool ok = true;

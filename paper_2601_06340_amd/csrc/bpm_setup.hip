@@ -311,7 +311,7 @@ template <typename T, int SC>
 hipError_t launch_mixed(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
 template <typename T, int LOG2N, int SC>
 hipError_t launch_staged(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
-template <typename T, int SC>
+template <typename T>
 hipError_t launch_any(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
 
 
@@ -319,7 +319,7 @@ template <typename T, int SC>
 static hipError_t dispatch(const SolveDesc *d_descs, int n, int uniform_log2n, const char *in_base, char *out_base,
                            double *rt, hipStream_t s)
 {
-    if (uniform_log2n == kLaunchAny) return launch_any<T, SC>(d_descs, n, in_base, out_base, rt, s);
+    if (uniform_log2n == kLaunchAny) return launch_any<T>(d_descs, n, in_base, out_base, rt, s);
     if (uniform_log2n < 0) return launch_mixed<T, SC>(d_descs, n, in_base, out_base, rt, s);
     hipError_t err = hipErrorInvalidValue;
     static_for<Limits<T>::uni_lo, Limits<T>::uni_hi + 1>([&](auto l) {
