@@ -114,11 +114,14 @@ struct SolveDesc {
     uint64_t in_off, out_off;  // byte offsets of the state in the launch's in/out buffers
 };
 
-// Staged (four-step) lane: 2^kStagedLog2Th threads per solve, 2^staged_log2e
-// samples per thread and beam, rows of one wave (2^(6 + log2e) points).
-constexpr int kStagedLog2Th = 9;
-constexpr int staged_log2e(int prec) { return prec == 1 ? 4 : 3; }   // FP32 16, FP64 8
+// Staged (four-step) lane: 2^staged_log2e samples per thread and beam, rows of
+// one wave (2^(6 + log2e) points); its own kernel runs staged_log2th threads
+// per solve (FP32 1024: sixteen waves keep more state loads in flight), the
+// any-size kernel 2^kStagedAnyLog2Th.
+constexpr int kStagedAnyLog2Th = 9;
+constexpr int staged_log2e(int prec) { return 3; }
 constexpr int staged_log2c(int prec) { return 6 + staged_log2e(prec); }
+constexpr int staged_log2th(int prec) { return prec == 1 ? 10 : 9; }
 
 // Elements per thread (log2) used for a given nx by the uniform-size kernels.
 constexpr int uniform_log2e(int log2n) { return log2n >= 8 ? 4 : (log2n >= 7 ? 3 : 2); }

@@ -972,20 +972,20 @@ struct March {
 template <typename T>
 constexpr int staged_prec() { return sizeof(T) == 4 ? PREC_F32 : PREC_F64; }
 
-// both beams in one LDS buffer set per wave when 8 such waves fit
-template <typename T, int LOG2C, int LOG2E>
+// both beams in one LDS buffer set per wave when all the waves' sets fit
+template <typename T, int LOG2C, int LOG2E, int LOG2TH>
 constexpr int staged_bx()
 {
-    return (size_t)(1 << kStagedLog2Th) / 64 * 2 * Sched<LOG2C, LOG2E>::bufsz() * sizeof(Cx<T>) <= kLdsMax ? 2 : 1;
+    return (size_t)(1 << LOG2TH) / 64 * 2 * Sched<LOG2C, LOG2E>::bufsz() * sizeof(Cx<T>) <= kLdsMax ? 2 : 1;
 }
 
-template <typename T, int LOG2N, int SC>
+template <typename T, int LOG2N, int SC, int LOG2TH = staged_log2th(staged_prec<T>())>
 struct Staged {
     static constexpr int LOG2E = staged_log2e(staged_prec<T>()), E = 1 << LOG2E;
     static constexpr int N = 1 << LOG2N, LOG2C = staged_log2c(staged_prec<T>()), C = 1 << LOG2C;
     static constexpr int LOG2R = LOG2N - LOG2C, R = 1 << LOG2R;
-    static constexpr int TH = 1 << kStagedLog2Th, WAVES = TH / 64;
-    static constexpr int BXS = staged_bx<T, LOG2C, LOG2E>();
+    static constexpr int TH = 1 << LOG2TH, WAVES = TH / 64;
+    static constexpr int BXS = staged_bx<T, LOG2C, LOG2E, LOG2TH>();
     using RowM = March<T, LOG2C, LOG2E, SC, TH, BXS>;
     using ColM = March<T, LOG2R, LOG2E, SC, TH, BXS>;
     static_assert(RowM::LANES == 64 && RowM::W == 1, "one wave per row");

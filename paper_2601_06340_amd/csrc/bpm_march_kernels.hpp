@@ -68,10 +68,11 @@ hipError_t launch_uniform(const SolveDesc *d_descs, int n, const char *in_base, 
     return hipGetLastError();
 }
 
-// One solve per workgroup for the staged sizes (Staged<>): 8 waves, one
-// workgroup per compute unit (LDS), 2 waves per SIMD.
+// One solve per workgroup for the staged sizes (Staged<>): one workgroup per
+// compute unit (LDS), TH/256 waves per SIMD.
 template <typename T, int LOG2N, int SC>
-__global__ __launch_bounds__(1 << kStagedLog2Th) __attribute__((amdgpu_waves_per_eu(1, 2)))
+__global__ __launch_bounds__(1 << staged_log2th(staged_prec<T>()))
+__attribute__((amdgpu_waves_per_eu(1, (1 << staged_log2th(staged_prec<T>())) / 256)))
 void k_march_staged(const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -92,7 +93,7 @@ hipError_t launch_staged(const SolveDesc *d_descs, int n, const char *in_base, c
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_march_staged<T, LOG2N, SC>), dim3(n), dim3(1 << kStagedLog2Th), lds, s, d_descs, n, in_base,
+    hipLaunchKernelGGL((k_march_staged<T, LOG2N, SC>), dim3(n), dim3(Staged<T, LOG2N, SC>::TH), lds, s, d_descs, n, in_base,
                        out_base, rt);
     return hipGetLastError();
 }
@@ -142,7 +143,7 @@ __device__ __forceinline__ void march_any_sc(const SolveDesc &d, const char *in_
             March<T, L2, L2 - mixed_log2th(L2), SC, 1 << kMixedLog2Th>::run(d, in_base, out_base, rt, lds, red);
     });
     static_for<Limits<T>::stg_lo, Limits<T>::stg_hi + 1>([&](auto l) {
-        if (d.log2n == CV(l)) Staged<T, CV(l), SC>::run(d, in_base, out_base, rt, lds, red);
+        if (d.log2n == CV(l)) Staged<T, CV(l), SC, kStagedAnyLog2Th>::run(d, in_base, out_base, rt, lds, red);
     });
 }
 
@@ -150,7 +151,7 @@ template <typename T>
 __global__ __launch_bounds__(1 << kMixedLog2Th) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void k_march_any(const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
 {
-    static_assert(kMixedLog2Th == kStagedLog2Th, "one workgroup shape");
+    static_assert(kMixedLog2Th == kStagedAnyLog2Th, "one workgroup shape");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[16];
     const SolveDesc &d = descs[blockIdx.x];
@@ -166,7 +167,7 @@ size_t any_lds_bytes()
 {
     size_t m = mixed_lds_bytes<T>();
     static_for<Limits<T>::stg_lo, Limits<T>::stg_hi + 1>([&](auto l) {
-        const size_t b = Staged<T, CV(l), SC_NONE>::lds_bytes;
+        const size_t b = Staged<T, CV(l), SC_NONE, kStagedAnyLog2Th>::lds_bytes;
         if (b > m) m = b;
     });
     return m;

@@ -361,7 +361,7 @@ static void shape_T(int log2n, int *threads, size_t *lds)
     });
     static_for<Limits<T>::stg_lo, Limits<T>::stg_hi + 1>([&](auto l) {
         if (log2n == CV(l)) {
-            *threads = 1 << kStagedLog2Th;
+            *threads = Staged<T, CV(l), SC_NONE>::TH;
             *lds = Staged<T, CV(l), SC_NONE>::lds_bytes;
         }
     });
