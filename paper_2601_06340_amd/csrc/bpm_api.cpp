@@ -314,6 +314,11 @@ void bpm_plan::fill(SolveDesc &s, int log2e, const void *tw, int flags, int step
     for (int i = 0; i < 6; ++i) s.c[i] = desc.strain.c[i];
     s.disl_k = desc.strain.b_um / (2.0 * M_PI * desc.d_um);
     s.disl_q = 1.0 / (2.0 * (1.0 - desc.strain.nu));
+    // a Burgers vector that is a whole number of plane spacings winds the phase
+    // by whole turns: exp(i h u) then has the algebraic factor ((X + i Z)/r)^m
+    const double bd = desc.strain.b_um / desc.d_um, m = std::nearbyint(bd);
+    s.disl_m = (desc.strain.kind == BPM_STRAIN_EDGE_DISLOCATION && std::fabs(bd - m) <= 1e-9 * std::fabs(bd) &&
+                std::fabs(m) >= 1 && std::fabs(m) <= 8) ? (int32_t)m : 0;
     s.in_off = in_off;
     s.out_off = out_off;
     (void)log2e;

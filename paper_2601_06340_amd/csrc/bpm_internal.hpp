@@ -100,7 +100,8 @@ struct SolveDesc {
     int32_t det_lo, det_hi, step0, nsteps;   // run z-steps [step0, step0 + nsteps)
     int32_t flags;
     int32_t opaque_zero;                     // always 0 (keeps per-step table reads in the loop)
-    int32_t rt_index, pad2;                  // R,T go to RT[2*rt_index], -1 = none
+    int32_t rt_index;                        // R,T go to RT[2*rt_index], -1 = none
+    int32_t disl_m;                          // EDGE: b/d when it is a whole number 1..8 (else 0)
     const PlanScalars *sc;
     const void *prop;        // [2][nx] (P - 1)/nx in solve precision
     const void *tw;          // twiddle table of the (nx, elements-per-thread, precision) schedule

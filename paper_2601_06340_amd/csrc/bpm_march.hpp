@@ -417,6 +417,27 @@ __device__ __forceinline__ double edge_phase_rev(double X, double Z, double k, d
     return k * a;
 }
 
+// exp(i m atan2(Z, X)) for a whole winding number m (|m| <= 8) without the
+// arctangent: ((X + i Z)/r)^m, by squaring; 1 at the core itself.
+template <typename T>
+__device__ __forceinline__ Cx<T> winding_phasor(T X, T Z, T r2, int m)
+{
+    Cx<T> w = {(T)1, (T)0};
+    if (r2 > (T)0) {
+        const T ir = (T)1 / sqrt(r2);
+        w = {X * ir, Z * ir};
+    }
+    if (m < 0) w.y = -w.y;
+    int k = m < 0 ? -m : m;
+    Cx<T> p = {(T)1, (T)0};
+    while (k) {
+        if (k & 1) p = {fmaT(p.x, w.x, -p.y * w.y), fmaT(p.x, w.y, p.y * w.x)};
+        w = {fmaT(w.x, w.x, -w.y * w.y), (T)2 * w.x * w.y};
+        k >>= 1;
+    }
+    return p;
+}
+
 __device__ __forceinline__ void sincospi_T(float x, float *s, float *c) { sincospif(x, s, c); }
 __device__ __forceinline__ void sincospi_T(double x, double *s, double *c) { sincospi(x, s, c); }
 
@@ -535,6 +556,23 @@ struct Coupler {
             const bool edge = d.strain_kind == STRAIN_EDGE;
             const T dk = (T)d.disl_k, dq = (T)d.disl_q;
             const gptr<T> urow = utab + (size_t)n * nx;
+            const int m = d.disl_m;
+            if (edge && m != 0) {
+                // whole winding number: exp(i h u) = ((X + i Z)/r)^m exp(2 pi i k q X Z / r^2)
+                static_for<0, E>([&](auto e) {
+                    const int j = j0 + e * JS;
+                    const bool in = inside_at_e(e);
+                    const T X = (T)__builtin_fma((double)j, d.dx, X0), Zt = (T)Z;
+                    const T r2 = fmaT(X, X, Zt * Zt);
+                    const Cx<T> W = winding_phasor<T>(X, Zt, r2, m);
+                    const Cx<T> S = phasor<T>(r2 > (T)0 ? dk * (X * Zt * dq / r2) : (T)0);
+                    const Cx<T> P = {fmaT(W.x, S.x, -W.y * S.y), fmaT(W.x, S.y, W.y * S.x)};
+                    const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
+                    const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
+                    couple(vp[e], vm[e], sel(in, d0), sel(in, bp), sel(in, bm));
+                });
+                return;
+            }
             static_for<0, E>([&](auto e) {
                 const int j = j0 + e * JS;
                 const bool in = inside_at_e(e);

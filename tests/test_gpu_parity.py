@@ -122,6 +122,15 @@ def test_dislocation_trapezoid_small(prec):
     check(p, psi, label="disl")
 
 
+@pytest.mark.parametrize("prec,nx", [("f64", 4096), ("f32", 4096), ("f32", 32768)])
+def test_dislocation_with_fractional_burgers_vector(prec, nx):
+    """b/d not a whole number (the library's general arctangent path; whole
+    numbers take the algebraic winding path, covered above)."""
+    p, psi = synth.disl_bragg(nx=nx, nz=200, scale=nx / 32768 * 0.125 if nx > 4096 else 0.125, precision=prec)
+    p["strain"] = dict(p["strain"], b_um=0.3e-3)
+    check(p, psi, label="disl-frac-b-%d" % nx)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_strain_table_and_two_interval_mask(prec):
     nx, nz = 1024, 300
