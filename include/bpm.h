@@ -142,6 +142,17 @@ bpm_status bpm_propagate(bpm_plan *plan, const bpm_complex *psi_p0, const bpm_co
 bpm_status bpm_propagate_device(bpm_plan *plan, void *stream, const void *d_in, void *d_out,
                                 double *d_RT);
 
+/* Far field (the far-field images of the paper's Sec. 7): the exit envelopes of
+ * `plan` propagated through vacuum over distance_um along z in one FFT-based
+ * step, each envelope about its own carrier (its own propagator, no coupling):
+ * the field on the plane distance_um beyond the crystal's exit plane.  d_in and
+ * d_out hold one solve's state as for bpm_propagate_device (may be equal),
+ * enqueued on `stream`.  The library keeps one vacuum plan per plan for the
+ * last distance used (created on first use; a new distance rebuilds it and
+ * waits for the device).  BPM_E_INVALID for a NULL pointer or a distance that
+ * is not finite and > 0. */
+bpm_status bpm_far_field(bpm_plan *plan, double distance_um, void *stream, const void *d_in, void *d_out);
+
 /* --- batches (many solves in one launch) ------------------------------------
  * A batch groups plans (any mix of nx, nz, wavelength, crystal, strain) into
  * one kernel launch per precision; solves are ordered longest first so the

@@ -89,6 +89,7 @@ SIGNATURES = {
     "bpm_propagate": (C.c_int, [C.c_void_p, C.POINTER(Complex), C.POINTER(Complex), C.POINTER(Complex),
                                 C.POINTER(Complex), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "bpm_propagate_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bpm_far_field": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bpm_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
     "bpm_batch_layout": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "bpm_batch_run": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -199,6 +200,21 @@ class Plan:
     def propagate_device(self, d_in: int, d_out: int, d_rt: int | None = None, stream: int | None = None):
         """Asynchronous march on device buffers (raw pointers, plan precision)."""
         _check(lib().bpm_propagate_device(self.handle, stream, d_in, d_out, d_rt))
+
+    def far_field_device(self, distance_um: float, d_in: int, d_out: int, stream: int | None = None):
+        """Vacuum propagation of a device state over distance_um (bpm_far_field)."""
+        _check(lib().bpm_far_field(self.handle, float(distance_um), stream, d_in, d_out))
+
+    def far_field(self, distance_um: float, psi_p, psi_m=None):
+        """Host arrays in and out (copies through a device state of the plan's precision)."""
+        st = torch.zeros(2 * self.nx, dtype=self.cdtype)
+        st[: self.nx] = torch.from_numpy(np.asarray(psi_p, np.complex128)).to(self.cdtype)
+        if psi_m is not None:
+            st[self.nx:] = torch.from_numpy(np.asarray(psi_m, np.complex128)).to(self.cdtype)
+        d = st.to("cuda")
+        self.far_field_device(distance_um, d.data_ptr(), d.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        out = d.cpu().to(torch.complex128).numpy()
+        return out[: self.nx], out[self.nx:]
 
     def close(self):
         if getattr(self, "handle", None):

@@ -265,6 +265,11 @@ static size_t elem_bytes(int prec) { return prec == BPM_F32 ? 8 : 16; }
 
 void bpm_plan::release()
 {
+    if (far) {
+        far->release();
+        delete far;
+        far = nullptr;
+    }
     (void)hipFree(d_sc);
     (void)hipFree(d_params);
     prop_release(d_prop);
@@ -459,6 +464,36 @@ extern "C" bpm_status bpm_propagate_device(bpm_plan *p, void *stream, const void
                                 d_RT ? d_RT : p->d_rt, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "march launch");
     return BPM_OK;
+}
+
+extern "C" bpm_status bpm_far_field(bpm_plan *p, double distance_um, void *stream, const void *d_in, void *d_out)
+{
+    if (!p || !d_in || !d_out) return fail(BPM_E_INVALID, "NULL argument");
+    if (!std::isfinite(distance_um) || distance_um <= 0.0)
+        return fail(BPM_E_INVALID, "far-field distance must be finite and > 0");
+    if (!p->far || p->far_um != distance_um) {
+        if (p->far) {
+            bpm_plan_destroy(p->far);
+            p->far = nullptr;
+        }
+        // one vacuum step: the crystal plan's grid, wavelength and reflection
+        // (the carriers), no crystal, no strain
+        bpm_plan_desc v = p->desc;
+        static const int32_t empty[2] = {0, 0};
+        v.nz = 1;
+        v.dz_um = distance_um;
+        v.nseg = 1;
+        v.seg = empty;
+        std::memset(&v.strain, 0, sizeof v.strain);
+        v.strain.kind = BPM_STRAIN_NONE;
+        v.split_order = 1;
+        v.det_lo = 0;
+        v.det_hi = v.nx;
+        bpm_status st = bpm_plan_create(&v, &p->far);
+        if (st != BPM_OK) return st;
+        p->far_um = distance_um;
+    }
+    return bpm_propagate_device(p->far, stream, d_in, d_out, nullptr);
 }
 
 // host complex128 <-> device state in plan precision

@@ -25,6 +25,8 @@ struct bpm_plan {
     const void *tw_uniform = nullptr;   // shared twiddle table
     void *d_state = nullptr;     // staging for bpm_propagate
     double *d_rt = nullptr;      // R/T scratch
+    bpm_plan *far = nullptr;     // vacuum plan of bpm_far_field (one step of far_um)
+    double far_um = 0.0;
 
     void release();
     size_t state_bytes() const;

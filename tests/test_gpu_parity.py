@@ -101,6 +101,28 @@ def test_shared_propagator_table_outlives_its_first_plan():
         plan.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_far_field_equals_one_vacuum_step(prec):
+    """bpm_far_field: exit envelopes of a crystal solve carried 2 m and 4 m through
+    vacuum, against the oracle's single vacuum step of that length."""
+    B = bpm()
+    p, psi = synth.flat_bragg_scan(n_angles=1, nx=4096, nz=200, precision=prec)[0]
+    plan = B.Plan(p)
+    ep, em, _, _ = plan.propagate(psi)
+    tol = TOL[prec][0]
+    for D in (2.0e6, 4.0e6, 2.0e6):
+        fp, fm = plan.far_field(D, ep, em)
+        v = dict(p, nz=1, dz_um=D, seg=synth.mask_empty(1), strain={"kind": "none"})
+        op, om, _, _ = oracle.propagate(v, ep, em)
+        err = rel_pair(fp, fm, op, om)
+        say("   far field %.0e um rel L2 %.3e" % (D, err))
+        assert err <= tol
+    with pytest.raises(B.BpmError) as e:
+        plan.far_field(-1.0, ep, em)
+    assert e.value.status == B.E_INVALID
+    plan.close()
+
+
 # ------------------------------------------------------------------ physics workloads
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_flat_bragg_scan_small(prec):

@@ -487,3 +487,24 @@ def test_split_sub_steps_sample_the_strain_at_their_own_height(order):
     d = [np.linalg.norm(sols[i] - sols[i + 1]) for i in range(3)]
     rate = d[1] / d[2]
     assert 0.75 * 2 ** order < rate < 1.3 * 2 ** order, (d, rate)
+
+
+def test_far_field_step_spreads_a_gaussian_as_the_paraxial_beam():
+    """One vacuum step of D (the far-field step): on the z-planes a Gaussian of
+    amplitude radius w0 about the + carrier drifts by D tan(theta_B) and its
+    radius grows as w0^2 (1 + (2 D / (k w0^2 c^3))^2), c = cos(theta_B)."""
+    nx, dx, w0, D = 65536, 0.1, 1.0, 5000.0
+    xs = np.arange(nx) * dx
+    xc = 1000.0
+    psi = np.exp(-((xs - xc) / w0) ** 2).astype(complex)
+    p = synth.base_problem(nx, 1, dx, D, synth.mask_empty(1))
+    gp, _, _, _ = oracle.propagate(p, psi, None)
+    k = 2 * math.pi / p["lambda_um"]
+    s = p["lambda_um"] / (2 * p["d_um"])
+    c = math.sqrt(1 - s * s)
+    I = np.abs(gp) ** 2
+    mean = float(np.sum(xs * I) / np.sum(I))
+    var = float(np.sum((xs - mean) ** 2 * I) / np.sum(I))
+    assert abs(mean - (xc + D * s / c)) < 1e-3
+    w2 = w0 * w0 * (1 + (2 * D / (k * w0 * w0 * c ** 3)) ** 2)
+    assert abs(4 * var / w2 - 1) < 1e-4
