@@ -79,6 +79,7 @@ def lib():
         L.oracle_split_sequence.argtypes = [C.c_int, cd, cd]
         L.oracle_strain_phase_z.argtypes = [C.POINTER(_Desc), C.c_int, C.c_int, C.c_double]
         L.oracle_strain_phase_z.restype = C.c_double
+        L.oracle_td_assemble.argtypes = [C.POINTER(_Desc), C.c_int, cd, cd]
         L.oracle_scalars_get.argtypes = [C.POINTER(_Desc), C.POINTER(_Scalars)]
         L.oracle_propagator.argtypes = [C.POINTER(_Desc), cd, cd]
         L.oracle_strain_phase.argtypes = [C.POINTER(_Desc), C.c_int, C.c_int]
@@ -268,3 +269,20 @@ def propagate_batch(problems: list, psi0: list, nthreads: int | None = None):
         raise ValueError("oracle_propagate_batch failed (%d)" % rc)
     outs = [(b[: len(b) // 2].copy(), b[len(b) // 2:].copy()) for b in bufs]
     return outs, R[:n].copy(), T[:n].copy()
+
+
+def td_assemble(problems: list, exits: list):
+    """Time-domain assembly of M components: exits[m] = (psi_p, psi_m) at the exit
+    plane.  Returns out[2][nx][M] (beam, x sample, time sample)."""
+    keep = _Keep()
+    M = len(problems)
+    arr = (_Desc * M)(*[_desc(p, keep) for p in problems])
+    nx = int(problems[0]["nx"])
+    psi = np.zeros((M, 2, nx), np.complex128)
+    for m, (a, b) in enumerate(exits):
+        psi[m, 0] = a
+        psi[m, 1] = b
+    out = np.zeros((2, nx, M), np.complex128)
+    if lib().oracle_td_assemble(arr, M, _dptr(psi), _dptr(out)):
+        raise ValueError("invalid components")
+    return out

@@ -444,3 +444,35 @@ int oracle_propagate_batch(const oracle_desc *descs, int n, double complex **psi
     free(th);
     return b.status;
 }
+
+/* ------------------------------------------------------------- time domain */
+
+int oracle_td_assemble(const oracle_desc *descs, int M, const double complex *psi, double complex *out)
+{
+    if (M <= 0 || !descs || !psi || !out) return -1;
+    int nx = descs[0].nx;
+    for (int m = 0; m < M; m++)
+        if (!desc_valid(&descs[m]) || descs[m].nx != nx) return -1;
+    double complex *carrier = malloc(sizeof(double complex) * (size_t)M);
+    double complex *w = malloc(sizeof(double complex) * (size_t)M);
+    if (!carrier || !w) { free(carrier); free(w); return -2; }
+    for (int m = 0; m < M; m++) {
+        const oracle_desc *d = &descs[m];
+        double k = 2.0 * M_PI / d->lambda_um;
+        double s = d->lambda_um / (2.0 * d->d_um);
+        double L = d->nz * d->dz_um;
+        carrier[m] = cexp(I * k * sqrt(1.0 - s * s) * L);
+    }
+    for (int q = 0; q < M; q++) w[q] = cexp(-2.0 * M_PI * I * (double)q / (double)M);
+    for (int b = 0; b < 2; b++)
+        for (int j = 0; j < nx; j++)
+            for (int k = 0; k < M; k++) {
+                double complex acc = 0.0;
+                for (int m = 0; m < M; m++)
+                    acc += psi[((size_t)m * 2 + b) * nx + j] * carrier[m] * w[((long long)m * k) % M];
+                out[((size_t)b * nx + j) * M + k] = acc;
+            }
+    free(carrier);
+    free(w);
+    return 0;
+}

@@ -103,6 +103,16 @@ double oracle_strain_phase(const oracle_desc *d, int j, int n);
 int oracle_propagate(const oracle_desc *d, double complex *psi_p, double complex *psi_m,
                      double *R, double *T);
 
+/* Time-domain assembly of M spectral components marched to their exit planes
+ * z = L_m = nz_m dz_m (the time-dependent method of Sec. 8): for every x sample
+ * and beam b,
+ *   out[b][j][k] = sum_m psi[m][b][j] exp(i k_m c_m L_m) exp(-2 pi i m k / M),
+ * the exponential restoring each component's carrier phase along z (the
+ * constant the reduced propagator drops), k_m = 2 pi / lambda_m,
+ * c_m = sqrt(1 - (lambda_m / 2 d_m)^2).  psi is [M][2][nx]; out is [2][nx][M].
+ * A direct sum over m (no FFT). */
+int oracle_td_assemble(const oracle_desc *descs, int M, const double complex *psi, double complex *out);
+
 /* Many independent solves on a pool of nthreads POSIX threads (one solve per thread
  * at a time).  psi arrays are [n][2][nx] in the caller's packing: psi[i] points at
  * solve i's psi_p, followed by its psi_m. */

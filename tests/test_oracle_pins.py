@@ -508,3 +508,56 @@ def test_far_field_step_spreads_a_gaussian_as_the_paraxial_beam():
     assert abs(mean - (xc + D * s / c)) < 1e-3
     w2 = w0 * w0 * (1 + (2 * D / (k * w0 * w0 * c ** 3)) ** 2)
     assert abs(4 * var / w2 - 1) < 1e-4
+
+
+# ------------------------------------------------------------------ time-domain assembly (Sec. 8)
+def _components(M, nx=8, nz=0, dz=0.05, de_mev=0.385):
+    hbar_c = synth.HC_KEV_ANGSTROM
+    out = []
+    for m in range(M):
+        e_kev = synth.E0_KEV + (m - M // 2) * de_mev * 1e-6
+        lam = hbar_c / e_kev * 1e-4
+        out.append(synth.base_problem(nx, nz, 0.1, dz, synth.mask_empty(nz), lambda_um=lam))
+    return out
+
+
+def test_td_assembly_is_the_inverse_time_dft():
+    """With no propagation (carrier factor 1): a single component gives a flat
+    trace; a linear spectral phase exp(2 pi i m k0 / M) moves the pulse to time
+    sample k0; Parseval holds."""
+    M, nx = 32, 8
+    comps = _components(M, nx)
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal(nx) + 1j * rng.standard_normal(nx)
+    exits = [(a if m == 5 else np.zeros(nx), np.zeros(nx)) for m in range(M)]
+    out = oracle.td_assemble(comps, exits)
+    assert np.allclose(np.abs(out[0]), np.abs(a)[:, None], rtol=1e-13, atol=0)
+    k0 = 11
+    g = np.exp(-((np.arange(M) - M / 2) / 6.0) ** 2)
+    exits = [(a * g[m] * np.exp(2j * np.pi * m * k0 / M), 0.5 * a * g[m]) for m in range(M)]
+    out = oracle.td_assemble(comps, exits)
+    assert int(np.argmax(np.abs(out[0, 0]))) == k0 and int(np.argmax(np.abs(out[1, 0]))) == 0
+    lhs = np.sum(np.abs(out) ** 2, axis=2)
+    rhs = M * np.array([sum(abs(e[b][j]) ** 2 for e in exits) for b in range(2) for j in range(nx)]).reshape(2, nx)
+    assert np.allclose(lhs, rhs, rtol=1e-12)
+
+
+def test_td_assembly_places_a_vacuum_pulse_at_its_group_delay():
+    """x-uniform components carried through vacuum over L keep their envelopes
+    (the q = 0 bin of the reduced propagator is 1); the restored carriers
+    exp(i k_m c_m L) then delay the assembled pulse by L / (v cos(theta_B)),
+    v the speed of light: the peak sits at that fraction of the period
+    2 pi hbar / dE."""
+    M, dz, nz, de_mev = 128, 2.0, 500, 0.385
+    L = nz * dz
+    comps = _components(M, nx=8, nz=nz, dz=dz, de_mev=de_mev)
+    g = np.exp(-((np.arange(M) - M / 2) / 12.0) ** 2)
+    exits = [(np.full(8, g[m], complex), np.zeros(8)) for m in range(M)]
+    out = oracle.td_assemble(comps, exits)
+    s = comps[M // 2]["lambda_um"] / (2 * comps[M // 2]["d_um"])
+    c_um_per_s = 2.99792458e14
+    tau = L / (c_um_per_s * math.sqrt(1 - s * s))
+    period = 2 * math.pi * 6.582119569e-16 / (de_mev * 1e-3)
+    want = (tau / period * M) % M
+    got = int(np.argmax(np.abs(out[0, 0])))
+    assert abs(got - want) <= 1.0, (got, want)
