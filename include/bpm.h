@@ -167,6 +167,21 @@ bpm_status bpm_batch_run(bpm_batch *batch, void *stream, const void *d_in, void 
                          double *d_RT);
 void bpm_batch_destroy(bpm_batch *batch);
 
+/* Time-domain assembly (the time-dependent method of Sec. 8).  The batch holds
+ * M spectral components of one pulse (M a power of two, 128 <= M <= 2048),
+ * ordered by ascending frequency at equal spacing, all on one x grid (same nx,
+ * dx, x0) and precision, each marched to its exit plane z = L_m = nz_m dz_m;
+ * d_state is the batch's packed state after bpm_batch_run.  Writes
+ *   out[b][j][k] = sum_m psi_{b,m}(x_j) exp(i k_m c_m L_m) exp(-2 pi i m k / M)
+ * for beams b = +, -, samples j and time samples k (t_k = k T / M,
+ * T = 2 pi / frequency spacing): the field's time trace at the exit plane up
+ * to a common phase per k.  exp(i k_m c_m L_m), c_m = sqrt(1 - (lambda_m/2d)^2),
+ * restores the carrier phase along z the reduced propagator drops (FP64,
+ * reduced exactly).  d_out: caller-owned [2][nx][M] complex in the batch
+ * precision (8 B FP32, 16 B FP64).  Enqueued on `stream`.  BPM_E_INVALID for
+ * another M or mixed grids. */
+bpm_status bpm_td_assemble(bpm_batch *batch, void *stream, const void *d_state, void *d_out);
+
 /* --- serving (continuous batching) ------------------------------------------
  * A server owns a device-memory budget and a pool of solve slots.  A worker
  * thread advances all admitted solves together in rounds: per precision one

@@ -94,6 +94,7 @@ SIGNATURES = {
     "bpm_batch_layout": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "bpm_batch_run": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bpm_batch_destroy": (None, [C.c_void_p]),
+    "bpm_td_assemble": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bpm_server_create": (C.c_int, [C.POINTER(ServerDesc), C.POINTER(C.c_void_p)]),
     "bpm_batch_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.c_int32, C.POINTER(C.c_uint64)]),
     "bpm_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Result)]),
@@ -245,6 +246,14 @@ class Batch:
 
     def run(self, d_in: int, d_out: int, d_rt: int | None = None, stream: int | None = None):
         _check(lib().bpm_batch_run(self.handle, stream, d_in, d_out, d_rt))
+
+    def td_assemble(self, d_state: int, stream: int | None = None) -> torch.Tensor:
+        """Time-domain assembly of the batch's exit envelopes (bpm_td_assemble):
+        a [2, nx, M] complex tensor on the device."""
+        p = self.plans[0]
+        out = torch.empty((2, p.nx, len(self.plans)), dtype=p.cdtype, device="cuda")
+        _check(lib().bpm_td_assemble(self.handle, stream, d_state, out.data_ptr()))
+        return out
 
     def pack(self, psis: list, device="cuda") -> torch.Tensor:
         """Device byte buffer holding every solve's entrance state at its offset."""

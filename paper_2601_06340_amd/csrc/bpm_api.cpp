@@ -711,6 +711,10 @@ struct bpm_batch {
     size_t total = 0;
     std::vector<Launch> launches;
     double *d_rt_scratch = nullptr;
+    // time-domain assembly (built on first use)
+    uint64_t *d_td_offs = nullptr;
+    double *d_td_par = nullptr;
+    void *d_td_ph = nullptr;
 };
 
 extern "C" bpm_status bpm_batch_create(bpm_plan *const *plans, int32_t n, bpm_batch **out)
@@ -768,5 +772,58 @@ extern "C" void bpm_batch_destroy(bpm_batch *b)
     (void)hipDeviceSynchronize();
     free_launches(b->launches);
     (void)hipFree(b->d_rt_scratch);
+    (void)hipFree(b->d_td_offs);
+    (void)hipFree(b->d_td_par);
+    (void)hipFree(b->d_td_ph);
     delete b;
+}
+
+extern "C" bpm_status bpm_td_assemble(bpm_batch *b, void *stream, const void *d_state, void *d_out)
+{
+    if (!b || !d_state || !d_out) return fail(BPM_E_INVALID, "NULL argument");
+    const int M = (int)b->plans.size();
+    int log2m = 0;
+    while ((1 << log2m) < M) ++log2m;
+    if ((1 << log2m) != M || log2m < kTdLog2MMin || log2m > kTdLog2MMax)
+        return fail(BPM_E_INVALID, "time-domain assembly needs 2^%d..2^%d components, got %d", kTdLog2MMin,
+                    kTdLog2MMax, M);
+    const bpm_plan_desc &d0 = b->plans[0]->desc;
+    for (const bpm_plan *p : b->plans) {
+        const bpm_plan_desc &d = p->desc;
+        if (d.nx != d0.nx || d.dx_um != d0.dx_um || d.x0_um != d0.x0_um || d.precision != d0.precision)
+            return fail(BPM_E_INVALID, "time-domain assembly needs one x grid and one precision for all components");
+    }
+    if (!b->d_td_offs) {
+        std::vector<uint64_t> offs(M);
+        std::vector<double> par(3 * (size_t)M);
+        for (int m = 0; m < M; ++m) {
+            const bpm_plan_desc &d = b->plans[m]->desc;
+            offs[m] = b->offsets[m];
+            par[3 * m] = d.lambda_um;
+            par[3 * m + 1] = d.d_um;
+            par[3 * m + 2] = d.nz * d.dz_um;
+        }
+        const size_t eb = d0.precision == BPM_F32 ? 8 : 16;
+        hipError_t e = hipMalloc((void **)&b->d_td_offs, M * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipMalloc((void **)&b->d_td_par, par.size() * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc(&b->d_td_ph, M * eb);
+        if (e == hipSuccess) e = hipMemcpy(b->d_td_offs, offs.data(), M * sizeof(uint64_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(b->d_td_par, par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(b->d_td_offs);
+            (void)hipFree(b->d_td_par);
+            (void)hipFree(b->d_td_ph);
+            b->d_td_offs = nullptr;
+            b->d_td_par = nullptr;
+            b->d_td_ph = nullptr;
+            return hip_fail(e, "time-domain assembly tables");
+        }
+    }
+    const void *tw = nullptr;
+    bpm_status st = twiddle_table(d0.precision, log2m, log2m - 6, &tw);
+    if (st != BPM_OK) return st;
+    hipError_t e = launch_td(d0.precision, log2m, (const char *)d_state, b->d_td_offs, b->d_td_par, b->d_td_ph, tw,
+                             d0.nx, d_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "time-domain assembly launch");
+    return BPM_OK;
 }

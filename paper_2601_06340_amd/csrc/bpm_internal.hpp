@@ -151,6 +151,11 @@ hipError_t launch_utab(const double *d_u, void *d_tab, int prec, size_t count, d
 constexpr int kLaunchMixed = -1, kLaunchAny = -2;
 hipError_t launch_march(const SolveDesc *d_descs, int n, int prec, int uniform_log2n, int sc,
                         const char *in_base, char *out_base, double *rt, hipStream_t s);
+// Time-domain assembly (bpm_td.hip): 2^kTdLog2MMin..2^kTdLog2MMax components.
+// par holds (lambda, d, L) per component; ph receives the carriers (M complex).
+constexpr int kTdLog2MMin = 7, kTdLog2MMax = 11;
+hipError_t launch_td(int prec, int log2m, const char *state, const uint64_t *offs, const double *par, void *ph,
+                     const void *tw, int nx, void *out, hipStream_t s);
 // Launch shape of the uniform or staged kernel (threads per workgroup, dynamic LDS bytes).
 void march_shape(int prec, int log2n, int *threads, size_t *lds_bytes);
 // Mixed-size kernel: elements-per-thread (log2) it uses for log2n, and its shape.

@@ -363,6 +363,54 @@ def test_staged_sizes_in_batch_and_chunked_server_equal_single_solves():
     srv.close()
 
 
+# ------------------------------------------------------------------ time-domain assembly
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_td_assembly_matches_oracle(prec):
+    """128 pulse components on one grid, marched in one batch, assembled in time:
+    the assembly alone (on the GPU's own exit envelopes) and end to end against
+    the oracle's march and assembly."""
+    B = bpm()
+    import torch
+    cases = synth.td_batch(n_comp=128, nx_choices=(1024,), nz_range=(60, 100), precision=prec)
+    plans = [B.Plan(p) for p, _ in cases]
+    batch = B.Batch(plans)
+    buf = batch.pack([(psi, None) for _, psi in cases])
+    batch.run(buf.data_ptr(), buf.data_ptr())
+    td = batch.td_assemble(buf.data_ptr())
+    torch.cuda.synchronize()
+    td = td.cpu().to(torch.complex128).numpy()
+    exits = batch.unpack(buf)
+    ref = oracle.td_assemble([p for p, _ in cases], [(a, b) for a, b in exits])
+    err = float(np.linalg.norm(td - ref) / np.linalg.norm(ref))
+    say("   td assembly alone rel L2 %.3e" % err)
+    assert err <= (1e-13 if prec == "f64" else 2e-6)
+    ores, _, _ = oracle.propagate_batch([p for p, _ in cases], [(psi, None) for _, psi in cases])
+    ref2 = oracle.td_assemble([p for p, _ in cases], [(a, b) for a, b in ores])
+    err2 = float(np.linalg.norm(td - ref2) / np.linalg.norm(ref2))
+    say("   td march + assembly rel L2 %.3e" % err2)
+    assert err2 <= TOL[prec][0]
+
+
+def test_td_assembly_largest_m_and_invalid_m():
+    B = bpm()
+    import torch
+    cases = synth.td_batch(n_comp=2048, nx_choices=(64,), nz_range=(5, 9), precision="f32")
+    plans = [B.Plan(p) for p, _ in cases]
+    batch = B.Batch(plans)
+    buf = batch.pack([(psi, None) for _, psi in cases])
+    batch.run(buf.data_ptr(), buf.data_ptr())
+    td = batch.td_assemble(buf.data_ptr()).cpu().to(torch.complex128).numpy()
+    exits = batch.unpack(buf)
+    ref = oracle.td_assemble([p for p, _ in cases], [(a, b) for a, b in exits])
+    err = float(np.linalg.norm(td - ref) / np.linalg.norm(ref))
+    say("   td M=2048 rel L2 %.3e" % err)
+    assert err <= 2e-6
+    bad = B.Batch(plans[:100])
+    with pytest.raises(B.BpmError) as e:
+        bad.td_assemble(buf.data_ptr())
+    assert e.value.status == B.E_INVALID
+
+
 # ------------------------------------------------------------------ server
 def test_server_alone_equals_in_mix_and_matches_oracle():
     B = bpm()
