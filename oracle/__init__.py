@@ -48,6 +48,7 @@ class _Desc(C.Structure):
         ("u_table", C.POINTER(C.c_double)),
         ("det_lo", C.c_int), ("det_hi", C.c_int),
         ("split_order", C.c_int),
+        ("ny", C.c_int), ("dy_um", C.c_double),
     ]
 
 
@@ -133,6 +134,10 @@ def _desc(p: dict, keep: _Keep) -> _Desc:
     d.det_lo = int(p.get("det_lo", 0))
     d.det_hi = int(p.get("det_hi", p["nx"]))
     d.split_order = int(p.get("split_order", 1))
+    d.ny = int(p.get("ny", 1))
+    d.dy_um = float(p.get("dy_um", 0.0))
+    if d.ny > 1:
+        d.nseg = int(seg.shape[2]) if seg.ndim == 4 else 1
     return d
 
 

@@ -127,6 +127,7 @@ static int desc_valid(const oracle_desc *d)
     if (d->nseg < 0 || (d->nseg > 0 && d->nz > 0 && !d->seg)) return 0;
     if (d->strain_kind == ORACLE_STRAIN_TABLE && !d->u_table && d->nz > 0) return 0;
     if (d->split_order != 0 && d->split_order != 1 && d->split_order != 2 && d->split_order != 4) return 0;
+    if (d->ny > 1 && (!is_pow2(d->ny) || !(d->dy_um > 0))) return 0;
     return 1;
 }
 
@@ -337,10 +338,137 @@ static int propagate_split(const oracle_desc *d, double complex *psi_p, double c
     return rc;
 }
 
+/* ------------------------------------------------------------- 3D --------- */
+
+int oracle_propagator_2d(const oracle_desc *d, double a, double complex *pp, double complex *pm)
+{
+    oracle_scalars sc;
+    if (oracle_scalars_get(d, &sc) || d->ny < 2) return -1;
+    int nx = d->nx, ny = d->ny;
+    double dzh = a * sc.dzh;
+    for (int fy = 0; fy < ny; fy++) {
+        int gy = fy < ny / 2 ? fy : fy - ny;
+        double qy = 2.0 * M_PI * (double)gy / ((double)ny * d->dy_um * sc.k);
+        for (int fx = 0; fx < nx; fx++) {
+            int gx = fx < nx / 2 ? fx : fx - nx;
+            double qx = 2.0 * M_PI * (double)gx / ((double)nx * d->dx_um * sc.k);
+            for (int b = 0; b < 2; b++) {
+                double sg = b == 0 ? 1.0 : -1.0;
+                double px = qx + sg * sc.s;
+                double r = 1.0 - px * px - qy * qy;
+                double complex P;
+                if (r >= 0.0) {
+                    /* S - c = -(qx^2 +/- 2 s qx + qy^2) / (S + c) */
+                    double S = sqrt(r);
+                    P = cexp(-I * dzh * (qx * qx + 2.0 * sg * sc.s * qx + qy * qy) / (S + sc.c));
+                } else {
+                    P = exp(-dzh * sqrt(-r)) * cexp(-I * dzh * sc.c);
+                }
+                P /= (double)nx * (double)ny;
+                if (b == 0) pp[(size_t)fy * nx + fx] = P; else pm[(size_t)fy * nx + fx] = P;
+            }
+        }
+    }
+    return 0;
+}
+
+/* 2D transform of an [ny][nx] array: every row, then every column. */
+static void fft2_with(double complex *a, int nx, int ny, const double complex *wx, const double complex *wy,
+                      double complex *col)
+{
+    for (int i = 0; i < ny; i++) fft_with(a + (size_t)i * nx, nx, wx);
+    for (int j = 0; j < nx; j++) {
+        for (int i = 0; i < ny; i++) col[i] = a[(size_t)i * nx + j];
+        fft_with(col, ny, wy);
+        for (int i = 0; i < ny; i++) a[(size_t)i * nx + j] = col[i];
+    }
+}
+
+static void couple_3d(const oracle_desc *d, double complex *psi_p, double complex *psi_m, int n, double z,
+                      double complex a0, double complex ap, double complex am)
+{
+    double h = 2.0 * M_PI / d->d_um;
+    for (int i = 0; i < d->ny; i++)
+        for (int j = 0; j < d->nx; j++) {
+            int in = 0;
+            for (int k = 0; k < d->nseg; k++) {
+                const int *iv = d->seg + (((size_t)n * d->ny + i) * d->nseg + k) * 2;
+                if (j >= iv[0] && j < iv[1]) in = 1;
+            }
+            if (!in) continue;
+            double complex e = 1.0;
+            if (d->strain_kind == ORACLE_STRAIN_TABLE) {
+                double phi = h * d->u_table[((size_t)n * d->ny + i) * d->nx + j];
+                e = cos(phi) + I * sin(phi);
+            } else if (d->strain_kind != ORACLE_STRAIN_NONE) {
+                double phi = oracle_strain_phase_z(d, j, n, z);
+                e = cos(phi) + I * sin(phi);
+            }
+            size_t q = (size_t)i * d->nx + j;
+            double complex p = psi_p[q], m = psi_m[q];
+            psi_p[q] = a0 * p + ap * e * m;
+            psi_m[q] = a0 * m + am * conj(e) * p;
+        }
+}
+
+static int propagate_3d(const oracle_desc *d, double complex *psi_p, double complex *psi_m, double *R, double *T)
+{
+    int nx = d->nx, ny = d->ny;
+    size_t N = (size_t)nx * ny;
+    double a[8], b[8];
+    int m = oracle_split_sequence(d->split_order, a, b);
+    int form = d->split_order > 1 ? 1 : 0;
+    double complex *tp[8], *tm[8], c0[8], cp[8], cm[8];
+    double zoff[8], acc = 0.0;
+    double complex *wfx = twiddles(nx, -1), *wix = twiddles(nx, +1);
+    double complex *wfy = twiddles(ny, -1), *wiy = twiddles(ny, +1);
+    double complex *col = malloc(sizeof(double complex) * (size_t)ny);
+    int rc = (wfx && wix && wfy && wiy && col) ? 0 : -2;
+    for (int i = 0; i < m; i++) {
+        tp[i] = tm[i] = NULL;
+        acc += a[i];
+        zoff[i] = form ? acc : 0.0;     /* Eq. (12) couples at z_n; the splittings at their own height */
+        if (a[i] != 0.0 && rc == 0) {
+            tp[i] = malloc(sizeof(double complex) * N);
+            tm[i] = malloc(sizeof(double complex) * N);
+            if (!tp[i] || !tm[i]) rc = -2;
+            else oracle_propagator_2d(d, a[i], tp[i], tm[i]);
+        }
+        oracle_coupling(d, b[i], form, &c0[i], &cp[i], &cm[i]);
+    }
+    double pin = 0.0;
+    for (int i = 0; i < ny; i++) pin += power_sum(psi_p + (size_t)i * nx, 0, nx);
+    for (int step = 0; rc == 0 && step < d->nz; step++)
+        for (int i = 0; i < m; i++) {
+            if (a[i] != 0.0) {
+                fft2_with(psi_p, nx, ny, wfx, wfy, col);
+                fft2_with(psi_m, nx, ny, wfx, wfy, col);
+                for (size_t f = 0; f < N; f++) { psi_p[f] *= tp[i][f]; psi_m[f] *= tm[i][f]; }
+                fft2_with(psi_p, nx, ny, wix, wiy, col);
+                fft2_with(psi_m, nx, ny, wix, wiy, col);
+            }
+            couple_3d(d, psi_p, psi_m, step, (step + zoff[i]) * d->dz_um, c0[i], cp[i], cm[i]);
+        }
+    int lo = d->det_lo < 0 ? 0 : d->det_lo;
+    int hi = d->det_hi > nx ? nx : d->det_hi;
+    if (hi < lo) hi = lo;
+    double r = 0.0, t = 0.0;
+    for (int i = 0; i < ny; i++) {
+        r += power_sum(psi_m + (size_t)i * nx, lo, hi);
+        t += power_sum(psi_p + (size_t)i * nx, lo, hi);
+    }
+    if (R) *R = pin > 0 ? r / pin : 0.0;
+    if (T) *T = pin > 0 ? t / pin : 0.0;
+    for (int i = 0; i < m; i++) { free(tp[i]); free(tm[i]); }
+    free(wfx); free(wix); free(wfy); free(wiy); free(col);
+    return rc;
+}
+
 int oracle_propagate(const oracle_desc *d, double complex *psi_p, double complex *psi_m,
                      double *R, double *T)
 {
     if (!desc_valid(d)) return -1;
+    if (d->ny > 1) return propagate_3d(d, psi_p, psi_m, R, T);
     int n = d->nx;
     oracle_scalars sc;
     oracle_scalars_get(d, &sc);

@@ -61,6 +61,8 @@ typedef struct oracle_desc {
     const double *u_table;       /* TABLE: [nz][nx] displacement along h (um) */
     int det_lo, det_hi;          /* detector interval for R and T */
     int split_order;             /* 0 or 1: Eq. (12); 2, 4: the splittings of Eq. (13) */
+    int ny;                      /* 0 or 1: the x-z problem; > 1: 3D envelopes [ny][nx] */
+    double dy_um;
 } oracle_desc;
 
 /* Plan-level scalars, exposed so that the tests can pin them. */
@@ -102,6 +104,15 @@ double oracle_strain_phase(const oracle_desc *d, int j, int n);
  * R and T may be NULL.  Returns 0 or a negative error code. */
 int oracle_propagate(const oracle_desc *d, double complex *psi_p, double complex *psi_m,
                      double *R, double *T);
+
+/* 3D envelopes (ny > 1): psi_p and psi_m are [ny][nx]; each step propagates with
+ * the 2D transform over (x, y) and exp(i dzh (S(qx +/- s, qy) - c)),
+ * S(p, r) = sqrt(1 - p^2 - r^2), qy = 2 pi fy / (ny dy k), and couples at
+ * (x_j, y_i, z): mask intervals along x per (step, row) [nz][ny][nseg][2],
+ * POLY2 and edge-dislocation strain independent of y, TABLE strain [nz][ny][nx].
+ * R and T sum the detector interval of every row.  oracle_propagate takes this
+ * path when ny > 1; the 2D propagator tables are [ny][nx]. */
+int oracle_propagator_2d(const oracle_desc *d, double a, double complex *pp, double complex *pm);
 
 /* Time-domain assembly of M spectral components marched to their exit planes
  * z = L_m = nz_m dz_m (the time-dependent method of Sec. 8): for every x sample

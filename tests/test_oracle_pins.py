@@ -561,3 +561,75 @@ def test_td_assembly_places_a_vacuum_pulse_at_its_group_delay():
     want = (tau / period * M) % M
     got = int(np.argmax(np.abs(out[0, 0])))
     assert abs(got - want) <= 1.0, (got, want)
+
+
+# ------------------------------------------------------------------ 3D envelopes (2D transform per step)
+def _problem3d(nx, ny, nz, dx, dy, dz, seg3, **kw):
+    p = synth.base_problem(nx, nz, dx, dz, seg3, **kw)
+    p["ny"], p["dy_um"] = ny, dy
+    return p
+
+
+def test_3d_march_of_a_y_uniform_field_is_the_2d_march_in_every_row():
+    nx, ny, nz = 128, 16, 60
+    seg2 = synth.mask_asym_trapezoid(nz, nx, 0.1, 0.05, 3.0, 10.0, 9.0, 0.2, 2.8)
+    seg3 = np.repeat(seg2[:, None, :, :], ny, axis=1)
+    a, b = synth.random_envelopes(nx, 21)
+    strain = {"kind": "poly2", "x_ref_um": 6.0, "z_ref_um": 1.5, "c": [0, 0, 0, 0, 3e-5, 0]}
+    for order in (1, 2):
+        p2 = synth.base_problem(nx, nz, 0.1, 0.05, seg2, strain=strain, det=(10, 100))
+        p2["split_order"] = order
+        p3 = _problem3d(nx, ny, nz, 0.1, 0.2, 0.05, seg3, strain=strain, det=(10, 100))
+        p3["split_order"] = order
+        r2 = oracle.propagate(p2, a, 0.5 * b)
+        A = np.tile(a, (ny, 1))
+        Bm = np.tile(0.5 * b, (ny, 1))
+        r3 = oracle.propagate(p3, A, Bm)
+        for i in range(ny):
+            assert rel_l2(r3[0][i], r2[0]) < 1e-12 and rel_l2(r3[1][i], r2[1]) < 1e-12
+        assert abs(r3[2] - r2[2]) < 1e-13 and abs(r3[3] - r2[3]) < 1e-13
+
+
+def test_3d_uniform_crystal_matches_per_bin_matrix_evolution():
+    """Full mask, no strain: every 2D Fourier bin evolves by the 2x2 matrix
+    [[a0, a+], [a-, a0]] diag(P+(qx, qy), P-(qx, qy)) per step, with P from the
+    plain formula exp(i k dz (sqrt(1 - (qx +/- s)^2 - qy^2) - c))."""
+    nx, ny, nz, dx, dy, dz = 64, 32, 50, 0.2, 0.3, 0.1
+    seg3 = np.zeros((nz, ny, 1, 2), np.int32)
+    seg3[:, :, 0, 1] = nx
+    p = _problem3d(nx, ny, nz, dx, dy, dz, seg3, chih=complex(-3e-6, 1e-8))
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
+    Bm = rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
+    gp, gm, _, _ = oracle.propagate(p, A, Bm)
+    sc = oracle.scalars(p)
+    k, s, c = sc["k"], sc["s"], sc["c"]
+    qx = np.fft.fftfreq(nx, dx) * 2 * math.pi / k
+    qy = np.fft.fftfreq(ny, dy) * 2 * math.pi / k
+    QY, QX = np.meshgrid(qy, qx, indexing="ij")
+    Pp = np.exp(1j * k * dz * (np.sqrt(1 - (QX + s) ** 2 - QY ** 2) - c))
+    Pm = np.exp(1j * k * dz * (np.sqrt(1 - (QX - s) ** 2 - QY ** 2) - c))
+    Fa, Fb = np.fft.fft2(A), np.fft.fft2(Bm)
+    for _ in range(nz):
+        Fa, Fb = Fa * Pp, Fb * Pm
+        Fa, Fb = sc["a0"] * Fa + sc["ap"] * Fb, sc["a0"] * Fb + sc["am"] * Fa
+    assert rel_l2(gp, np.fft.ifft2(Fa)) < 2e-10 and rel_l2(gm, np.fft.ifft2(Fb)) < 2e-10
+
+
+def test_3d_vacuum_gaussian_spreads_along_y_with_distance_over_cos_theta():
+    """One vacuum step of D: a Gaussian of radius w0 along y grows as
+    w0^2 (1 + (2 D / (c k w0^2))^2) (the y part of S(q+s, qy) - c is -qy^2/2c),
+    with no drift along y; the norm is kept."""
+    nx, ny, dy, w0, D = 8, 4096, 0.1, 1.0, 3000.0
+    ys = (np.arange(ny) - ny / 2) * dy
+    field = np.tile(np.exp(-(ys / w0) ** 2)[:, None], (1, nx)).astype(complex)
+    seg3 = np.zeros((1, ny, 1, 2), np.int32)
+    p = _problem3d(nx, ny, 1, 0.1, dy, D, seg3)
+    gp, _, _, _ = oracle.propagate(p, field, None)
+    I = np.abs(gp[:, 0]) ** 2
+    mean = float(np.sum(ys * I) / np.sum(I))
+    var = float(np.sum((ys - mean) ** 2 * I) / np.sum(I))
+    sc = oracle.scalars(p)
+    w2 = w0 * w0 * (1 + (2 * D / (sc["c"] * sc["k"] * w0 * w0)) ** 2)
+    assert abs(mean) < 1e-9 and abs(4 * var / w2 - 1) < 1e-4
+    assert abs(np.sum(np.abs(gp) ** 2) / np.sum(np.abs(field) ** 2) - 1) < 1e-12
