@@ -198,9 +198,10 @@ def main():
     ap.add_argument("--nz", type=int, default=None, help="shorter march (profiling runs only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
-    ap.add_argument("--legs", default="cfg2,cfg3,cfg4",
+    ap.add_argument("--legs", default="cfg2,cfg3,3d,cfg4",
                     help="extra workloads after the headline: cfg2 (dislocation, Nx 32768), cfg3 (pulse "
-                         "components, one mixed launch), cfg4 (serving mix); 'none' for the headline only")
+                         "components, one mixed launch), 3d (the paper's 3D case), cfg4 (serving mix); "
+                         "'none' for the headline only")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
@@ -278,6 +279,16 @@ def main():
             leg_batch(bpm, torch, synth.td_batch(), "cfg3"),
             workload="1024 spectral components of a 20 fs pulse, Nx 2048-16384, Nz 1000-8000, FP32, "
                      "one mixed-size launch")
+    if "3d" in want:
+        cube = [synth.cube_3d(seed=synth.SEED_BASE + 5 + k) for k in range(256)]
+        one = leg_batch(bpm, torch, cube[:1], "3d single", steps=1, warmup=1)
+        many = leg_batch(bpm, torch, cube, "3d batch", steps=1, warmup=1)
+        legs["paper_3d"] = {
+            "workload": "3D envelopes 512 x 256 x 300 steps (the paper's 300 x 200 x 300 3D case padded to "
+                        "powers of two), 10 um cube with an edge dislocation, FP32",
+            "single_solve_ms": one["ms_per_step"], "single_value": one["value"],
+            "batch_solves": many["solves"], "value": many["value"], "unit": "cell-steps/s",
+            "paper_context": "about 13 s per realization on a Perlmutter node (Python package; CPU or GPU not stated)"}
     if "cfg4" in want:
         legs["cfg4_serving"] = dict(
             leg_serve(bpm, synth, args.serve_requests, args.serve_rate, args.serve_budget_gb, args.serve_chunk),

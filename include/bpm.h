@@ -103,6 +103,17 @@ typedef struct bpm_plan_desc {
      * orders hold); it uses the mask row of step n and the strain at its own
      * height z_n + (a_1 + ... + a_i) dz (TABLE strain: row n). */
     int32_t split_order;
+    /* 3D envelopes (the paper's 3D form, Eq. (4) with a 2D transverse transform):
+     * ny = 0 or 1 is the x-z problem described above.  ny > 1 (a power of two,
+     * 16 <= ny <= 256, with nx = 512) marches envelopes psi[ny][nx] (row i at
+     * y_i = i*dy_um, periodic) through the 2D transform over (x, y) and the
+     * propagator exp(i dzh (S(qx +/- s, qy) - c)), S(p, r) = sqrt(1 - p^2 - r^2).
+     * Then seg is [nz][ny][nseg][2] (intervals along x per step and row), a
+     * TABLE strain is [nz][ny][nx], POLY2 and EDGE_DISLOCATION do not depend
+     * on y, R/T sum the detector interval [det_lo, det_hi) of every row, and
+     * every state and host buffer holds ny*nx samples per beam. */
+    int32_t ny;
+    double dy_um;
 } bpm_plan_desc;
 
 typedef struct bpm_plan bpm_plan;

@@ -50,7 +50,7 @@ class PlanDesc(C.Structure):
                 ("chi0", Complex), ("chih", Complex), ("chihbar", Complex),
                 ("nseg", C.c_int32), ("seg", C.POINTER(C.c_int32)), ("strain", Strain),
                 ("det_lo", C.c_int32), ("det_hi", C.c_int32), ("precision", C.c_int32),
-                ("split_order", C.c_int32)]
+                ("split_order", C.c_int32), ("ny", C.c_int32), ("dy_um", C.c_double)]
 
 
 class PlanInfo(C.Structure):
@@ -148,7 +148,12 @@ class _Desc:
             v = complex(p.get(key, p["chih"]))
             setattr(d, name, Complex(v.real, v.imag))
         self.seg = np.ascontiguousarray(p["seg"], dtype=np.int32)
-        d.nseg = int(self.seg.shape[1]) if self.seg.ndim == 3 else 1
+        d.ny = int(p.get("ny", 1))
+        d.dy_um = float(p.get("dy_um", 0.0))
+        if d.ny > 1:   # 3D: [nz][ny][nseg][2]
+            d.nseg = int(self.seg.shape[2]) if self.seg.ndim == 4 else 1
+        else:
+            d.nseg = int(self.seg.shape[1]) if self.seg.ndim == 3 else 1
         d.seg = self.seg.ctypes.data_as(C.POINTER(C.c_int32))
         st = p.get("strain") or {"kind": "none"}
         d.strain.kind = STRAIN[st.get("kind", "none")]
@@ -181,6 +186,9 @@ class Plan:
         _check(lib().bpm_plan_info_get(h, C.byref(info)))
         self.info = info
         self.nx = info.nx
+        self.ny = max(1, int(problem.get("ny", 1)))
+        self.cells = self.nx * self.ny              # samples per beam
+        self.shape = (self.ny, self.nx) if self.ny > 1 else (self.nx,)
         self.precision = "f32" if info.precision == F32 else "f64"
 
     @property
@@ -189,14 +197,14 @@ class Plan:
 
     def propagate(self, psi_p0, psi_m0=None):
         """Blocking march from host arrays.  Returns (psi_p, psi_m, R, T)."""
-        a = np.ascontiguousarray(psi_p0, dtype=np.complex128)
-        b = None if psi_m0 is None else np.ascontiguousarray(psi_m0, dtype=np.complex128)
-        op = np.empty(self.nx, np.complex128)
-        om = np.empty(self.nx, np.complex128)
+        a = np.ascontiguousarray(psi_p0, dtype=np.complex128).reshape(-1)
+        b = None if psi_m0 is None else np.ascontiguousarray(psi_m0, dtype=np.complex128).reshape(-1)
+        op = np.empty(self.cells, np.complex128)
+        om = np.empty(self.cells, np.complex128)
         R, T = C.c_double(), C.c_double()
         _check(lib().bpm_propagate(self.handle, _cbuf(a), None if b is None else _cbuf(b),
                                    _cbuf(op), _cbuf(om), C.byref(R), C.byref(T)))
-        return op, om, R.value, T.value
+        return op.reshape(self.shape), om.reshape(self.shape), R.value, T.value
 
     def propagate_device(self, d_in: int, d_out: int, d_rt: int | None = None, stream: int | None = None):
         """Asynchronous march on device buffers (raw pointers, plan precision)."""
@@ -208,14 +216,15 @@ class Plan:
 
     def far_field(self, distance_um: float, psi_p, psi_m=None):
         """Host arrays in and out (copies through a device state of the plan's precision)."""
-        st = torch.zeros(2 * self.nx, dtype=self.cdtype)
-        st[: self.nx] = torch.from_numpy(np.asarray(psi_p, np.complex128)).to(self.cdtype)
+        n = self.cells
+        st = torch.zeros(2 * n, dtype=self.cdtype)
+        st[:n] = torch.from_numpy(np.asarray(psi_p, np.complex128).reshape(-1)).to(self.cdtype)
         if psi_m is not None:
-            st[self.nx:] = torch.from_numpy(np.asarray(psi_m, np.complex128)).to(self.cdtype)
+            st[n:] = torch.from_numpy(np.asarray(psi_m, np.complex128).reshape(-1)).to(self.cdtype)
         d = st.to("cuda")
         self.far_field_device(distance_um, d.data_ptr(), d.data_ptr(), torch.cuda.current_stream().cuda_stream)
         out = d.cpu().to(torch.complex128).numpy()
-        return out[: self.nx], out[self.nx:]
+        return out[:n].reshape(self.shape), out[n:].reshape(self.shape)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -259,10 +268,10 @@ class Batch:
         """Device byte buffer holding every solve's entrance state at its offset."""
         buf = torch.zeros(self.total_bytes, dtype=torch.uint8, device=device)
         for p, off, (a, b) in zip(self.plans, self.offsets, psis):
-            st = torch.zeros(2 * p.nx, dtype=p.cdtype)
-            st[: p.nx] = torch.from_numpy(np.asarray(a, np.complex128)).to(p.cdtype)
+            st = torch.zeros(2 * p.cells, dtype=p.cdtype)
+            st[: p.cells] = torch.from_numpy(np.asarray(a, np.complex128).reshape(-1)).to(p.cdtype)
             if b is not None:
-                st[p.nx:] = torch.from_numpy(np.asarray(b, np.complex128)).to(p.cdtype)
+                st[p.cells:] = torch.from_numpy(np.asarray(b, np.complex128).reshape(-1)).to(p.cdtype)
             raw = st.view(torch.uint8)
             buf[off: off + raw.numel()].copy_(raw.to(device))
         return buf
@@ -272,9 +281,9 @@ class Batch:
         host = buf.cpu()
         out = []
         for p, off in zip(self.plans, self.offsets):
-            nb = 2 * p.nx * (8 if p.precision == "f32" else 16)
+            nb = 2 * p.cells * (8 if p.precision == "f32" else 16)
             st = host[off: off + nb].view(p.cdtype).numpy().astype(np.complex128)
-            out.append((st[: p.nx], st[p.nx:]))
+            out.append((st[: p.cells].reshape(p.shape), st[p.cells:].reshape(p.shape)))
         return out
 
     def close(self):
@@ -301,18 +310,19 @@ class Server:
 
     def submit(self, problem: dict, psi_p0, psi_m0=None, want_fields: bool = True) -> int:
         desc = _Desc(problem)
-        a = np.ascontiguousarray(psi_p0, dtype=np.complex128)
-        b = None if psi_m0 is None else np.ascontiguousarray(psi_m0, dtype=np.complex128)
-        nx = int(problem["nx"])
-        op = np.empty(nx, np.complex128) if want_fields else None
-        om = np.empty(nx, np.complex128) if want_fields else None
+        a = np.ascontiguousarray(psi_p0, dtype=np.complex128).reshape(-1)
+        b = None if psi_m0 is None else np.ascontiguousarray(psi_m0, dtype=np.complex128).reshape(-1)
+        ny = max(1, int(problem.get("ny", 1)))
+        shape = (ny, int(problem["nx"])) if ny > 1 else (int(problem["nx"]),)
+        op = np.empty(shape, np.complex128) if want_fields else None
+        om = np.empty(shape, np.complex128) if want_fields else None
         req = Request(C.pointer(desc.c), _cbuf(a), None if b is None else _cbuf(b),
                       None if op is None else _cbuf(op), None if om is None else _cbuf(om))
         t = C.c_uint64()
         rc = lib().bpm_batch_submit(self.handle, C.byref(req), 1, C.byref(t))
         if rc not in (OK, E_BUDGET):
             _check(rc)
-        self._keep[int(t.value)] = (op, om)
+        self._keep[int(t.value)] = (op, om, a, b, desc)
         return int(t.value)
 
     def poll(self, ticket: int):
@@ -322,7 +332,7 @@ class Server:
         if rc == E_PENDING:
             return None
         _check(rc)
-        op, om = self._keep.get(ticket, (None, None))
+        op, om = self._keep.get(ticket, (None, None))[:2]
         return {"status": r.status, "R": r.R, "T": r.T, "t_submit": r.t_submit,
                 "t_admit": r.t_admit, "t_done": r.t_done, "psi_p": op, "psi_m": om}
 

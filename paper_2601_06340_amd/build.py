@@ -33,6 +33,7 @@ HIPFLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
 # keep in sync with Limits<> in csrc/bpm_march.hpp
 UNIFORM = {"float": range(6, 15), "double": range(6, 14)}
 STAGED = {"float": range(15, 17), "double": range(14, 17)}
+THREE_D_LOG2NY = range(4, 9)   # 3D envelopes: ny = 16..256 rows of nx = 512
 MIXED = ("float", "double")
 STRAIN_CLASSES = (0, 1, 2)   # none, polynomial, dislocation/table
 
@@ -63,6 +64,11 @@ def _gen_units() -> list[str]:
                       "template hipError_t launch_staged<%s, %d, %d>(const SolveDesc *, int, const char *, "
                       "char *, double *, hipStream_t);\n}\n" % (t, l2, sc))
         for t in MIXED:
+            for l2y in THREE_D_LOG2NY:
+                write("march_3d_%s_%d_sc%d.hip" % (t, l2y, sc),
+                      '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
+                      "template hipError_t launch_3d<%s, %d, %d>(const SolveDesc *, int, const char *, char *, "
+                      "double *, hipStream_t);\n}\n" % (t, l2y, sc))
             write("march_mixed_%s_sc%d.hip" % (t, sc),
                   '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
                   "template hipError_t launch_mixed<%s, %d>(const SolveDesc *, int, const char *, char *, "

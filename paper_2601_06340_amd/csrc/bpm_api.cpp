@@ -121,14 +121,19 @@ bpm_status bpm::twiddle_table(int prec, int log2n, int log2e, const void **out)
         *out = it->second;
         return BPM_OK;
     }
-    // log2e = 0 names the combined table of a staged size
-    const size_t bytes = std::max<size_t>(log2e ? twiddle_bytes(prec, log2n, log2e) : staged_twiddle_bytes(prec, log2n),
+    // log2e = 0 names the combined table of a staged size, -1 that of 3D
+    // envelopes with log2(ny) = log2n - 9
+    const size_t bytes = std::max<size_t>(log2e > 0    ? twiddle_bytes(prec, log2n, log2e)
+                                          : log2e == 0 ? staged_twiddle_bytes(prec, log2n)
+                                                       : twiddle3d_bytes(prec, log2n - k3DLog2Nx),
                                           16);
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) return hip_fail(e, "twiddle table");
     hipStream_t ss = setup_stream();
-    e = log2e ? launch_twiddles(p, prec, log2n, log2e, ss) : launch_staged_twiddles(p, prec, log2n, ss);
+    e = log2e > 0    ? launch_twiddles(p, prec, log2n, log2e, ss)
+        : log2e == 0 ? launch_staged_twiddles(p, prec, log2n, ss)
+                     : launch_twiddles_3d(p, prec, log2n - k3DLog2Nx, ss);
     if (e == hipSuccess) e = hipStreamSynchronize(ss);
     if (e != hipSuccess) {
         (void)hipFree(p);
@@ -144,7 +149,7 @@ bpm_status bpm::twiddle_table(int prec, int log2n, int log2e, const void **out)
 // precision, nx, dx, dz, lambda and d.  Plans that agree on these share one
 // reference-counted device copy, so a batch of solves that differ in crystal,
 // strain or incident beam reads a single table that stays in L2.
-using PropKey = std::tuple<int, int, double, double, double, double, int>;
+using PropKey = std::tuple<int, int, double, double, double, double, int, int, double>;
 struct PropEntry {
     void *ptr;
     int refs;
@@ -156,7 +161,8 @@ static bpm_status prop_acquire(const bpm_plan_desc &d, const PlanParams *d_param
 {
     std::lock_guard<std::mutex> lk(g_prop_mu);
     const int order = d.split_order <= 1 ? 1 : d.split_order;
-    const PropKey key{d.precision, d.nx, d.dx_um, d.dz_um, d.lambda_um, d.d_um, order};
+    const int ny = d.ny > 1 ? d.ny : 1;
+    const PropKey key{d.precision, d.nx, d.dx_um, d.dz_um, d.lambda_um, d.d_um, order, ny, ny > 1 ? d.dy_um : 0.0};
     auto it = g_prop.find(key);
     if (it != g_prop.end()) {
         ++it->second.refs;
@@ -167,17 +173,17 @@ static bpm_status prop_acquire(const bpm_plan_desc &d, const PlanParams *d_param
     int tab[kMaxSub];
     double afrac[kMaxSub];
     const int ntab = split_tables(order, tab, afrac);
-    const size_t one = 2 * (size_t)d.nx * (d.precision == BPM_F32 ? 8 : 16);
+    const size_t one = 2 * (size_t)d.nx * ny * (d.precision == BPM_F32 ? 8 : 16);
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, one * ntab);
     if (e != hipSuccess) return hip_fail(e, "propagator table");
     // built and finished under the lock: a second plan never sees a table in flight
     int log2n = 0;
     while ((1 << log2n) < d.nx) ++log2n;
-    const int log2r = is_staged(d.precision, log2n) ? log2n - staged_log2c(d.precision) : 0;
+    const int log2r = ny == 1 && is_staged(d.precision, log2n) ? log2n - staged_log2c(d.precision) : 0;
     hipStream_t ss = setup_stream();
     for (int k = 0; k < ntab && e == hipSuccess; ++k)
-        e = launch_plan_setup(d_params, nullptr, (char *)p + k * one, d.precision, d.nx, log2r, afrac[k], ss);
+        e = launch_plan_setup(d_params, nullptr, (char *)p + k * one, d.precision, d.nx * ny, log2r, afrac[k], ss);
     if (e == hipSuccess) e = hipStreamSynchronize(ss);
     if (e != hipSuccess) {
         (void)hipFree(p);
@@ -220,10 +226,21 @@ bpm_status bpm::validate_desc(const bpm_plan_desc *d)
     if (!(d->lambda_um < 2.0 * d->d_um)) return fail(BPM_E_INVALID, "lambda >= 2d: no Bragg angle");
     if (!is_finite(d->chi0) || !is_finite(d->chih) || !is_finite(d->chihbar))
         return fail(BPM_E_INVALID, "susceptibilities must be finite");
+    const bool d3 = d->ny > 1;
+    if (d->ny < 0) return fail(BPM_E_INVALID, "ny = %d < 0", d->ny);
+    if (d3) {
+        if ((d->ny & (d->ny - 1)) || d->ny < (1 << k3DLog2NyMin) || d->ny > (1 << k3DLog2NyMax))
+            return fail(BPM_E_UNSUPPORTED, "3D envelopes need ny a power of two in [%d, %d], got %d", 1 << k3DLog2NyMin,
+                        1 << k3DLog2NyMax, d->ny);
+        if (d->nx != (1 << k3DLog2Nx))
+            return fail(BPM_E_UNSUPPORTED, "3D envelopes need nx = %d, got %d", 1 << k3DLog2Nx, d->nx);
+        if (!is_finite(d->dy_um) || d->dy_um <= 0) return fail(BPM_E_INVALID, "dy must be finite and > 0");
+    }
+    const long long rows = (long long)d->nz * (d3 ? d->ny : 1);
     if (d->nseg < 1) return fail(BPM_E_INVALID, "nseg = %d < 1", d->nseg);
     if (d->nseg > 4) return fail(BPM_E_UNSUPPORTED, "nseg = %d: at most 4 mask intervals per step", d->nseg);
     if (d->nz > 0 && !d->seg) return fail(BPM_E_INVALID, "seg is NULL");
-    for (long long i = 0; i < (long long)d->nz * d->nseg; ++i) {
+    for (long long i = 0; i < rows * d->nseg; ++i) {
         const int lo = d->seg[2 * i], hi = d->seg[2 * i + 1];
         if (lo < 0 || hi < 0 || lo > d->nx || hi > d->nx)
             return fail(BPM_E_INVALID, "mask interval %lld = [%d, %d) outside [0, %d]", i, lo, hi, d->nx);
@@ -242,7 +259,7 @@ bpm_status bpm::validate_desc(const bpm_plan_desc *d)
         break;
     case BPM_STRAIN_TABLE:
         if (d->nz > 0 && !st.u_table) return fail(BPM_E_INVALID, "u_table is NULL");
-        for (long long i = 0; i < (long long)d->nz * d->nx; ++i)
+        for (long long i = 0; i < rows * d->nx; ++i)
             if (!is_finite(st.u_table[i])) return fail(BPM_E_INVALID, "u_table[%lld] not finite", i);
         break;
     default: return fail(BPM_E_INVALID, "unknown strain kind %d", st.kind);
@@ -287,7 +304,7 @@ void bpm_plan::release()
     d_desc1 = nullptr;
 }
 
-size_t bpm_plan::state_bytes() const { return 2 * (size_t)desc.nx * elem_bytes(desc.precision); }
+size_t bpm_plan::state_bytes() const { return 2 * cells() * elem_bytes(desc.precision); }
 
 void bpm_plan::fill(SolveDesc &s, int log2e, const void *tw, int flags, int step0, int nsteps, uint64_t in_off,
                     uint64_t out_off, int rt_index) const
@@ -352,8 +369,13 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
     p->desc.strain.u_table = nullptr;
     p->log2n = 0;
     while ((1 << p->log2n) < d->nx) ++p->log2n;
+    if (d->ny > 1) {
+        while ((1 << p->log2ny) < d->ny) ++p->log2ny;
+        p->log2n += p->log2ny;   // 3D: log2 of the samples per beam
+    }
+    p->launch_kind = p->log2ny ? kLaunch3D + p->log2ny : p->log2n;
     const int prec = d->precision;
-    const size_t nx = d->nx, nz = d->nz;
+    const size_t nx = p->cells(), nz = d->nz, rows = std::max<size_t>(p->rows(), 1);   // nx: samples per beam
 
     auto bail = [&](bpm_status s) {
         p->release();
@@ -362,15 +384,14 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
     };
     if ((st = dev_alloc(&p->d_sc, sizeof(PlanScalars), "plan scalars")) != BPM_OK) return bail(st);
     if ((st = dev_alloc(&p->d_params, sizeof(PlanParams), "plan params")) != BPM_OK) return bail(st);
-    if ((st = dev_alloc(&p->d_seg, std::max<size_t>(nz, 1) * d->nseg * 2 * sizeof(int32_t), "mask")) != BPM_OK)
-        return bail(st);
+    if ((st = dev_alloc(&p->d_seg, rows * d->nseg * 2 * sizeof(int32_t), "mask")) != BPM_OK) return bail(st);
     if ((st = dev_alloc(&p->d_pin, sizeof(double), "incident power")) != BPM_OK) return bail(st);
     if ((st = dev_alloc(&p->d_rt, 2 * sizeof(double), "R/T")) != BPM_OK) return bail(st);
     int tab[kMaxSub];
     double afrac[kMaxSub];
     const int ntab = split_tables(d->split_order <= 1 ? 1 : d->split_order, tab, afrac);
     p->device_bytes = sizeof(PlanScalars) + sizeof(PlanParams) + 2 * nx * elem_bytes(prec) * ntab +
-                      std::max<size_t>(nz, 1) * d->nseg * 2 * sizeof(int32_t) + 3 * sizeof(double);
+                      rows * d->nseg * 2 * sizeof(int32_t) + 3 * sizeof(double);
 
     PlanParams pp;
     std::memset(&pp, 0, sizeof pp);
@@ -386,10 +407,12 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
     pp.chihbx = d->chihbar.re;
     pp.chihby = d->chihbar.im;
     pp.split_order = d->split_order <= 1 ? 1 : d->split_order;
+    pp.ny = d->ny > 1 ? d->ny : 1;
+    pp.dy = d->ny > 1 ? d->dy_um : 0.0;
     hipStream_t ss = setup_stream();
     hipError_t e = hipMemcpyAsync(p->d_params, &pp, sizeof pp, hipMemcpyHostToDevice, ss);
     if (e == hipSuccess && nz > 0)
-        e = hipMemcpyAsync(p->d_seg, d->seg, nz * d->nseg * 2 * sizeof(int32_t), hipMemcpyHostToDevice, ss);
+        e = hipMemcpyAsync(p->d_seg, d->seg, p->rows() * d->nseg * 2 * sizeof(int32_t), hipMemcpyHostToDevice, ss);
     if (e == hipSuccess) e = hipStreamSynchronize(ss);
     if (e != hipSuccess) return bail(hip_fail(e, "plan upload"));
     e = launch_plan_setup(p->d_params, p->d_sc, nullptr, prec, d->nx, 0, 1.0, ss);
@@ -414,9 +437,10 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
     if (e != hipSuccess) return bail(hip_fail(e, "plan setup"));
 
     const int log2e = uniform_log2e(p->log2n);
-    const int tw_key = is_staged(prec, p->log2n) ? 0 : log2e;
+    const int tw_key = p->log2ny ? -1 : is_staged(prec, p->log2n) ? 0 : log2e;
     if ((st = twiddle_table(prec, p->log2n, tw_key, &p->tw_uniform)) != BPM_OK) return bail(st);
-    march_shape(prec, p->log2n, &p->threads, &p->lds_bytes);
+    if (p->log2ny) march_shape_3d(prec, p->log2ny, &p->threads, &p->lds_bytes);
+    else march_shape(prec, p->log2n, &p->threads, &p->lds_bytes);
 
     // single-solve launch descriptor (state at offset 0, R/T at index 0)
     SolveDesc s;
@@ -446,7 +470,7 @@ extern "C" bpm_status bpm_plan_info_get(const bpm_plan *p, bpm_plan_info *info)
     info->threads_per_solve = p->threads;
     info->state_bytes = p->state_bytes();
     info->device_bytes = p->device_bytes;
-    info->cell_steps = 2.0 * p->desc.nx * (double)p->desc.nz;
+    info->cell_steps = 2.0 * (double)p->cells() * (double)p->desc.nz;
     return BPM_OK;
 }
 
@@ -459,7 +483,7 @@ extern "C" int32_t bpm_max_nx(int32_t precision)
 extern "C" bpm_status bpm_propagate_device(bpm_plan *p, void *stream, const void *d_in, void *d_out, double *d_RT)
 {
     if (!p || !d_in || !d_out) return fail(BPM_E_INVALID, "NULL argument");
-    hipError_t e = launch_march(p->d_desc1, 1, p->desc.precision, p->log2n, strain_class(p->desc.strain.kind),
+    hipError_t e = launch_march(p->d_desc1, 1, p->desc.precision, p->launch_kind, strain_class(p->desc.strain.kind),
                                 (const char *)d_in, (char *)d_out,
                                 d_RT ? d_RT : p->d_rt, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "march launch");
@@ -479,11 +503,11 @@ extern "C" bpm_status bpm_far_field(bpm_plan *p, double distance_um, void *strea
         // one vacuum step: the crystal plan's grid, wavelength and reflection
         // (the carriers), no crystal, no strain
         bpm_plan_desc v = p->desc;
-        static const int32_t empty[2] = {0, 0};
+        const std::vector<int32_t> empty(2 * (size_t)std::max(1, p->desc.ny), 0);   // one empty interval per row
         v.nz = 1;
         v.dz_um = distance_um;
         v.nseg = 1;
-        v.seg = empty;
+        v.seg = empty.data();
         std::memset(&v.strain, 0, sizeof v.strain);
         v.strain.kind = BPM_STRAIN_NONE;
         v.split_order = 1;
@@ -499,7 +523,7 @@ extern "C" bpm_status bpm_far_field(bpm_plan *p, double distance_um, void *strea
 // host complex128 <-> device state in plan precision
 static void pack_state(const bpm_plan *p, const bpm_complex *a, const bpm_complex *b, std::vector<char> &buf)
 {
-    const size_t nx = p->desc.nx;
+    const size_t nx = p->cells();   // samples per beam
     buf.resize(p->state_bytes());
     if (p->desc.precision == BPM_F64) {
         double *o = (double *)buf.data();
@@ -522,7 +546,7 @@ static void pack_state(const bpm_plan *p, const bpm_complex *a, const bpm_comple
 
 static void unpack_state(const bpm_plan *p, const std::vector<char> &buf, bpm_complex *a, bpm_complex *b)
 {
-    const size_t nx = p->desc.nx;
+    const size_t nx = p->cells();   // samples per beam
     for (size_t j = 0; j < nx; ++j) {
         double v[4];
         if (p->desc.precision == BPM_F64) {
@@ -540,9 +564,10 @@ static void unpack_state(const bpm_plan *p, const std::vector<char> &buf, bpm_co
 bpm_status bpm::check_input(const bpm_plan_desc &d, const bpm_complex *a, const bpm_complex *b)
 {
     if (!a) return fail(BPM_E_INVALID, "psi_p0 is NULL");
-    for (int j = 0; j < d.nx; ++j) {
+    const long long cells = (long long)d.nx * (d.ny > 1 ? d.ny : 1);
+    for (long long j = 0; j < cells; ++j) {
         if (!is_finite(a[j]) || (b && !is_finite(b[j])))
-            return fail(BPM_E_NUMERIC, "non-finite entrance envelope at j = %d", j);
+            return fail(BPM_E_NUMERIC, "non-finite entrance envelope at sample %lld", j);
     }
     return BPM_OK;
 }
@@ -580,7 +605,7 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
     // longest first: the hardware dispatcher then balances uneven solves
     auto cost = [&](int i) {
         const int pairs = plans[i]->desc.split_order == 4 ? 3 : 1;
-        return (double)nsteps[i] * pairs * plans[i]->desc.nx * (plans[i]->log2n + 4);
+        return (double)nsteps[i] * pairs * plans[i]->cells() * (plans[i]->log2n + 4);
     };
     auto emit = [&](int prec, int sc, int group_log2n, const std::vector<int> &g) -> bpm_status {
         Launch L;
@@ -605,6 +630,21 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
         launches.push_back(std::move(L));
         return BPM_OK;
     };
+    // 3D envelopes: one launch per (precision, strain class, ny)
+    for (int prec : {BPM_F32, BPM_F64})
+        for (int sc : {0, 1, 2})
+            for (int l = k3DLog2NyMin; l <= k3DLog2NyMax; ++l) {
+                std::vector<int> g;
+                for (int i = 0; i < n; ++i)
+                    if (plans[i]->log2ny == l && plans[i]->desc.precision == prec &&
+                        strain_class(plans[i]->desc.strain.kind) == sc)
+                        g.push_back(i);
+                std::stable_sort(g.begin(), g.end(), [&](int a, int b) { return cost(a) > cost(b); });
+                if (!g.empty()) {
+                    bpm_status st = emit(prec, sc, kLaunch3D + l, g);
+                    if (st != BPM_OK) return st;
+                }
+            }
     if (any_size) {
         // every size the any-size kernel takes, of every strain class, in one
         // launch per precision (a size always meets the same kernel, whatever
@@ -612,7 +652,8 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
         for (int prec : {BPM_F32, BPM_F64}) {
             std::vector<int> big;
             for (int i = 0; i < n; ++i)
-                if (plans[i]->desc.precision == prec && plans[i]->log2n >= mixed_min_log2n(prec)) big.push_back(i);
+                if (plans[i]->desc.precision == prec && !plans[i]->log2ny && plans[i]->log2n >= mixed_min_log2n(prec))
+                    big.push_back(i);
             std::stable_sort(big.begin(), big.end(), [&](int a, int b) { return cost(a) > cost(b); });
             if (!big.empty()) {
                 bpm_status st = emit(prec, SC_NONE, kLaunchAny, big);
@@ -625,7 +666,7 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
         std::vector<int> idx;
         for (int i = 0; i < n; ++i)
             if (plans[i]->desc.precision == prec && strain_class(plans[i]->desc.strain.kind) == sc &&
-                !(any_size && plans[i]->log2n >= mixed_min_log2n(prec)))
+                !plans[i]->log2ny && !(any_size && plans[i]->log2n >= mixed_min_log2n(prec)))
                 idx.push_back(i);
         if (idx.empty()) continue;
         std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost(a) > cost(b); });
@@ -792,6 +833,7 @@ extern "C" bpm_status bpm_td_assemble(bpm_batch *b, void *stream, const void *d_
         const bpm_plan_desc &d = p->desc;
         if (d.nx != d0.nx || d.dx_um != d0.dx_um || d.x0_um != d0.x0_um || d.precision != d0.precision)
             return fail(BPM_E_INVALID, "time-domain assembly needs one x grid and one precision for all components");
+        if (d.ny > 1) return fail(BPM_E_UNSUPPORTED, "time-domain assembly of 3D envelopes is not built");
     }
     if (!b->d_td_offs) {
         std::vector<uint64_t> offs(M);

@@ -27,6 +27,11 @@ struct bpm_plan {
     double *d_rt = nullptr;      // R/T scratch
     bpm_plan *far = nullptr;     // vacuum plan of bpm_far_field (one step of far_um)
     double far_um = 0.0;
+    int log2ny = 0;              // 3D envelopes: log2(ny), else 0
+    int launch_kind = 0;         // launch_march's size argument for this plan alone
+
+    size_t cells() const { return (size_t)desc.nx * (log2ny ? (size_t)1 << log2ny : 1); }
+    size_t rows() const { return (size_t)desc.nz * (log2ny ? (size_t)1 << log2ny : 1); }
 
     void release();
     size_t state_bytes() const;

@@ -86,7 +86,14 @@ struct PlanParams {
     int32_t nx, split_order;
     double dx, dz, lambda, d;
     double chi0x, chi0y, chihx, chihy, chihbx, chihby;
+    int32_t ny, pad;          // ny > 1: 3D envelopes [ny][nx]
+    double dy;
 };
+
+// 3D envelopes: nx = 2^k3DLog2Nx (one wave per x row), ny = 2^k3DLog2NyMin..2^k3DLog2NyMax.
+constexpr int k3DLog2Nx = 9, k3DLog2NyMin = 4, k3DLog2NyMax = 8;
+// launch kind of a 3D group: kLaunch3D + log2(ny)
+constexpr int kLaunch3D = 100;
 
 // Flags of one solve in one launch.
 enum SolveFlags : int32_t {
@@ -129,15 +136,20 @@ constexpr int uniform_log2e(int log2n) { return log2n >= 8 ? 4 : (log2n >= 7 ? 3
 
 // Launchers (bpm_setup.hip).  All return hipSuccess or the launch error.
 // d_sc or d_prop may be NULL to skip that part; d_prop receives the table of a
-// sub-step of afrac*dz; log2r > 0 stores the propagator of a staged size in
+// sub-step of afrac*dz over `cells` = nx (or nx*ny for 3D, [ky][kx] order)
+// entries per beam; log2r > 0 stores the propagator of a staged size in
 // [k1][k2] order (R = 2^log2r).
 hipError_t launch_plan_setup(const PlanParams *d_params, PlanScalars *d_sc, void *d_prop, int prec,
-                             int nx, int log2r, double afrac, hipStream_t s);
+                             int cells, int log2r, double afrac, hipStream_t s);
 hipError_t launch_twiddles(void *d_tw, int prec, int log2n, int log2e, hipStream_t s);
 size_t twiddle_bytes(int prec, int log2n, int log2e);
 // Staged sizes (four-step lane): whether log2n is one, and its twiddle table
 // [row FFT | column FFT | four-step].
 bool is_staged(int prec, int log2n);
+// 3D envelopes: twiddle table [row FFT | column FFT] and launch shape.
+size_t twiddle3d_bytes(int prec, int log2ny);
+hipError_t launch_twiddles_3d(void *d_tw, int prec, int log2ny, hipStream_t s);
+void march_shape_3d(int prec, int log2ny, int *threads, size_t *lds_bytes);
 size_t staged_twiddle_bytes(int prec, int log2n);
 hipError_t launch_staged_twiddles(void *d_tw, int prec, int log2n, hipStream_t s);
 hipError_t launch_utab(const double *d_u, void *d_tab, int prec, size_t count, double inv_d,

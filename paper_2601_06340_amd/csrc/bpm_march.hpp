@@ -585,6 +585,53 @@ struct Coupler {
             });
         }
     }
+
+    // 3D envelopes [NY][nx]: the E samples a thread holds are the rows y0 + YS*e
+    // of column x; the mask is read per row, analytic strain does not depend on y
+    template <int E, int YS, int NY>
+    __device__ __forceinline__ void apply3d(Cx<T> *vp, Cx<T> *vm, const SolveDesc &d, int n, int x, int y0,
+                                            const SubStep &ss) const
+    {
+        const Cx<T> d0 = {to_T<T>(ss.d0x), to_T<T>(ss.d0y)};
+        const Cx<T> ap = {to_T<T>(ss.apx), to_T<T>(ss.apy)};
+        const Cx<T> am = {to_T<T>(ss.amx), to_T<T>(ss.amy)};
+        const Cx<T> zero = {(T)0, (T)0};
+        auto sel = [&](bool in, Cx<T> c) { return Cx<T>{in ? c.x : zero.x, in ? c.y : zero.y}; };
+        const double Z = (n + ss.zoff) * d.dz - d.z_ref;
+        const double Xd = __builtin_fma((double)x, d.dx, X0);
+        Cx<T> P = {(T)1, (T)0};
+        if constexpr (SC == SC_POLY2) {
+            const double pa = (d.c[0] + Z * (d.c[2] + Z * d.c[5])) * d.inv_d;
+            const double pb = (d.c[1] + Z * d.c[4]) * d.inv_d;
+            const double pc = d.c[3] * d.inv_d;
+            P = phasor<T>(__builtin_fma(__builtin_fma(pc, Xd, pb), Xd, pa));
+        } else if constexpr (SC == SC_GENERAL) {
+            if (d.strain_kind == STRAIN_EDGE) {
+                const T X = (T)Xd, Zt = (T)Z, dk = (T)d.disl_k, dq = (T)d.disl_q;
+                if (d.disl_m != 0) {
+                    const T r2 = fmaT(X, X, Zt * Zt);
+                    const Cx<T> W = winding_phasor<T>(X, Zt, r2, d.disl_m);
+                    const Cx<T> S = phasor<T>(r2 > (T)0 ? dk * (X * Zt * dq / r2) : (T)0);
+                    P = {fmaT(W.x, S.x, -W.y * S.y), fmaT(W.x, S.y, W.y * S.x)};
+                } else {
+                    P = phasor<T>(edge_phase_rev(X, Zt, dk, dq));
+                }
+            }
+        }
+        const bool table = SC == SC_GENERAL && d.strain_kind == STRAIN_TABLE;
+        static_for<0, E>([&](auto e) {
+            const int row = n * NY + y0 + YS * CV(e);
+            const gptr<int> sg = seg + (size_t)row * nseg * 2;
+            bool in = false;
+            static_for<0, kMaxSeg>([&](auto k) {
+                if (CV(k) < nseg) in |= (x >= sg[2 * CV(k)]) & (x < sg[2 * CV(k) + 1]);
+            });
+            const Cx<T> Pe = table ? phasor<T>(utab[(size_t)row * nx + x]) : P;
+            const Cx<T> bp = {fmaT(ap.x, Pe.x, -ap.y * Pe.y), fmaT(ap.x, Pe.y, ap.y * Pe.x)};
+            const Cx<T> bm = {fmaT(am.x, Pe.x, am.y * Pe.y), fmaT(am.y, Pe.x, -am.x * Pe.y)};
+            couple(vp[e], vm[e], sel(in, d0), sel(in, bp), sel(in, bm));
+        });
+    }
 };
 
 // One solve marched by the first TH of BLOCK threads (the rest only take part
@@ -1017,7 +1064,10 @@ constexpr int staged_bx()
     return (size_t)(1 << LOG2TH) / 64 * 2 * Sched<LOG2C, LOG2E>::bufsz() * sizeof(Cx<T>) <= kLdsMax ? 2 : 1;
 }
 
-template <typename T, int LOG2N, int SC, int LOG2TH = staged_log2th(staged_prec<T>())>
+// D3: 3D envelopes, ny = R rows of nx = C samples: the same two phases are the
+// 2D transform over (y, x) (no four-step twiddle), the propagator table is
+// [ky][kx], and the coupling reads the mask per row.
+template <typename T, int LOG2N, int SC, int LOG2TH = staged_log2th(staged_prec<T>()), bool D3 = false>
 struct Staged {
     static constexpr int LOG2E = staged_log2e(staged_prec<T>()), E = 1 << LOG2E;
     static constexpr int N = 1 << LOG2N, LOG2C = staged_log2c(staged_prec<T>()), C = 1 << LOG2C;
@@ -1042,7 +1092,7 @@ struct Staged {
     // twiddle table: [row FFT | column FFT | four-step W_N^{n2 k1} at k1*C + n2]
     static constexpr int TW_COL = RowM::SW::twcount();
     static constexpr int TW_4 = TW_COL + ColM::SW::twcount();
-    static constexpr int TW_TOTAL = TW_4 + N;
+    static constexpr int TW_TOTAL = D3 ? TW_4 : TW_4 + N;
 
     static __device__ __forceinline__ void load(Cx<T> *vp, Cx<T> *vm, const Cx<T> *src, int base, int stride)
     {
@@ -1059,17 +1109,26 @@ struct Staged {
         });
     }
     // |psi+|^2 and |psi-|^2 over the detector interval, samples base + stride*e
+    // (3D: the interval of x = sample mod C in every row)
     static __device__ __forceinline__ void det_sums(const Cx<T> *vp, const Cx<T> *vm, const SolveDesc &d, int base,
                                                     int stride, double &sp, double &sm)
     {
         static_for<0, E>([&](auto e) {
-            const int j = base + e * stride;
+            const int j = D3 ? ((base + e * stride) & (C - 1)) : base + e * stride;
             if (j >= d.det_lo && j < d.det_hi) {
                 const double px = vp[e].x, py = vp[e].y, mx = vm[e].x, my = vm[e].y;
                 sp = __builtin_fma(px, px, __builtin_fma(py, py, sp));
                 sm = __builtin_fma(mx, mx, __builtin_fma(my, my, sm));
             }
         });
+    }
+
+    // coupling of the column held by (lane lc of) column c: samples C*(lc + LC*e) + c
+    static __device__ __forceinline__ void couple_at(const Coupler<T, SC> &cpl, Cx<T> *vp, Cx<T> *vm,
+                                                     const SolveDesc &d, int n, int lc, int c, const SubStep &ss)
+    {
+        if constexpr (D3) cpl.template apply3d<E, LC, R>(vp, vm, d, n, c, lc, ss);
+        else cpl.template apply<E, LC * C>(vp, vm, d, n, lc * C + c, ss);
     }
 
     static __device__ void run(const SolveDesc &d, const char *in_base, char *out_base, double *rt,
@@ -1088,7 +1147,7 @@ struct Staged {
         Cx<T> *RRp = slab;
         Cx<T> *RRm = slab + (RowM::BX == 2 ? RowM::BUFM : 0);
         Coupler<T, SC> cpl;
-        cpl.init(d, N);
+        cpl.init(d, D3 ? C : N);
         const T invN = (T)(1.0 / (double)N);
         const int nend = d.step0 + d.nsteps;
         const bool rt_out = (d.flags & SF_LAST) && d.rt_index >= 0;
@@ -1112,7 +1171,7 @@ struct Staged {
                 });
             }
             if (d.nsteps > 0) {
-                if (lead) cpl.template apply<E, LC * C>(vp, vm, d, d.step0, lc * C + c, scl.sub[0]);
+                if (lead) couple_at(cpl, vp, vm, d, d.step0, lc, c, scl.sub[0]);
                 const gptr<Tw<T>> twc = tw + (TW_COL + (cr & d.opaque_zero));
                 ColM::fwd_local(vp, vm, twc, CRp, CRm, lc, true);
             } else if (rt_out) {
@@ -1138,11 +1197,13 @@ struct Staged {
                 const int rb = k1 * C + lane + oz;
                 Cx<T> vp[E], vm[E];
                 load(vp, vm, st, rb, 64);
-                static_for<0, E>([&](auto e) {
-                    const Tw<T> w = gload(tw, TW_4 + rb + e * 64);
-                    vp[e] = mul_tw(vp[e], w);
-                    vm[e] = mul_tw(vm[e], w);
-                });
+                if constexpr (!D3) {
+                    static_for<0, E>([&](auto e) {
+                        const Tw<T> w = gload(tw, TW_4 + rb + e * 64);
+                        vp[e] = mul_tw(vp[e], w);
+                        vm[e] = mul_tw(vm[e], w);
+                    });
+                }
                 RowM::fwd_local(vp, vm, tw + oz, RRp, RRm, lane, true);
                 // bin k2 = lane + 64 e of row k1 is frequency k1 + R k2
                 const gptr<Cx<T>> pr = prop + (oz + ss.table * 2 * N);
@@ -1158,11 +1219,13 @@ struct Staged {
                 const int oi = (n + i + rr + 1) & d.opaque_zero;
                 RowM::inv_local(vp, vm, tw + oi, RRp, RRm, lane, true);
                 const int rbi = k1 * C + lane + oi;
-                static_for<0, E>([&](auto e) {
-                    const Tw<T> w = gload(tw, TW_4 + rbi + e * 64);
-                    vp[e] = mul_tw_inv(vp[e], w);
-                    vm[e] = mul_tw_inv(vm[e], w);
-                });
+                if constexpr (!D3) {
+                    static_for<0, E>([&](auto e) {
+                        const Tw<T> w = gload(tw, TW_4 + rbi + e * 64);
+                        vp[e] = mul_tw_inv(vp[e], w);
+                        vm[e] = mul_tw_inv(vm[e], w);
+                    });
+                }
                 store(st, vp, vm, rb - oz, 64);
             }
             __syncthreads();
@@ -1177,9 +1240,9 @@ struct Staged {
                 Cx<T> vp[E], vm[E];
                 load(vp, vm, st, lc * C + c + oz, LC * C);
                 ColM::inv_local(vp, vm, tw + (TW_COL + oz), CRp, CRm, lc, true);
-                cpl.template apply<E, LC * C>(vp, vm, d, n, lc * C + c, ss);
+                couple_at(cpl, vp, vm, d, n, lc, c, ss);
                 if (!last) {
-                    if (step_end && lead) cpl.template apply<E, LC * C>(vp, vm, d, n + 1, lc * C + c, scl.sub[0]);
+                    if (step_end && lead) couple_at(cpl, vp, vm, d, n + 1, lc, c, scl.sub[0]);
                     const int of = (n + i + cr + 1) & d.opaque_zero;
                     ColM::fwd_local(vp, vm, tw + (TW_COL + of), CRp, CRm, lc, true);
                 } else if (rt_out) {

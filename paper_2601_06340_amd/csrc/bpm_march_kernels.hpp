@@ -98,6 +98,38 @@ hipError_t launch_staged(const SolveDesc *d_descs, int n, const char *in_base, c
     return hipGetLastError();
 }
 
+// 3D envelopes [ny][nx = 512]: one solve per workgroup, the staged lane's two
+// phases as the 2D transform (Staged<> with D3).
+template <typename T, int LOG2NY, int SC>
+using Stage3D = Staged<T, k3DLog2Nx + LOG2NY, SC, staged_log2th(staged_prec<T>()), true>;
+
+template <typename T, int LOG2NY, int SC>
+__global__ __launch_bounds__(1 << staged_log2th(staged_prec<T>()))
+__attribute__((amdgpu_waves_per_eu(1, (1 << staged_log2th(staged_prec<T>())) / 256)))
+void k_march_3d(const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[16];
+    Stage3D<T, LOG2NY, SC>::run(descs[blockIdx.x], in_base, out_base, rt, reinterpret_cast<Cx<T> *>(smem), red);
+}
+
+template <typename T, int LOG2NY, int SC>
+hipError_t launch_3d(const SolveDesc *d_descs, int n, const char *in_base, char *out_base, double *rt, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const size_t lds = Stage3D<T, LOG2NY, SC>::lds_bytes;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_3d<T, LOG2NY, SC>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_march_3d<T, LOG2NY, SC>), dim3(n), dim3(Stage3D<T, LOG2NY, SC>::TH), lds, s, d_descs, n,
+                       in_base, out_base, rt);
+    return hipGetLastError();
+}
+
 template <typename T>
 size_t mixed_lds_bytes()
 {

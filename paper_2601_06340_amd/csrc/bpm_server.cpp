@@ -59,9 +59,10 @@ size_t estimate_bytes(const bpm_plan_desc &d)
     int tab[kMaxSub];
     double afrac[kMaxSub];
     const int ntab = split_tables(d.split_order <= 1 ? 1 : d.split_order, tab, afrac);
-    size_t b = 2 * (size_t)d.nx * eb * (1 + ntab);                  // state + propagator tables
-    b += (size_t)std::max(d.nz, 1) * d.nseg * 2 * sizeof(int32_t);  // mask
-    if (d.strain.kind == BPM_STRAIN_TABLE) b += (size_t)d.nz * d.nx * (d.precision == BPM_F32 ? 4 : 8);
+    const size_t ny = d.ny > 1 ? d.ny : 1;
+    size_t b = 2 * (size_t)d.nx * ny * eb * (1 + ntab);                  // state + propagator tables
+    b += (size_t)std::max(d.nz, 1) * ny * d.nseg * 2 * sizeof(int32_t);  // mask
+    if (d.strain.kind == BPM_STRAIN_TABLE) b += (size_t)d.nz * ny * d.nx * (d.precision == BPM_F32 ? 4 : 8);
     b += 4096;                                                       // scalars, descriptors
     return b;
 }
@@ -132,7 +133,8 @@ int bpm_server::steps_for(const Request &r) const
 {
     // a z-step of a splitting runs one FFT pair per propagation sub-step
     const int fft_pairs = r.desc.split_order == 4 ? 3 : 1;
-    const long long s = (long long)cfg.chunk_steps * 16384 / r.desc.nx / fft_pairs;
+    const long long cells = (long long)r.desc.nx * (r.desc.ny > 1 ? r.desc.ny : 1);
+    const long long s = (long long)cfg.chunk_steps * 16384 / cells / fft_pairs;
     return (int)std::max(1LL, std::min<long long>(s, r.desc.nz - r.step));
 }
 
@@ -145,7 +147,7 @@ bpm_status bpm_server::setup(Request &r, std::vector<char> &host)
     r.desc.strain.u_table = r.utab.empty() ? nullptr : r.utab.data();
     bpm_status st = bpm_plan_create(&r.desc, &r.plan);
     if (st != BPM_OK) return st;
-    const size_t sb = r.plan->state_bytes(), nx = r.desc.nx;
+    const size_t sb = r.plan->state_bytes(), nx = r.plan->cells();   // samples per beam
     hipError_t e = hipMalloc(&r.d_state, sb);
     if (e != hipSuccess) return hip_fail(e, "server state");
     host.resize(sb);
@@ -287,7 +289,7 @@ void bpm_server::run()
             bool fin = !ok || r->step >= r->desc.nz || r->cancel;
             int status = !ok ? BPM_E_DEVICE : (r->cancel && r->step < r->desc.nz ? BPM_E_CANCELLED : BPM_OK);
             if (fin && status == BPM_OK) {
-                const size_t sb = r->plan->state_bytes(), nx = r->desc.nx;
+                const size_t sb = r->plan->state_bytes(), nx = r->plan->cells();
                 if (r->out_p || r->out_m) {
                     host.resize(sb);
                     if (hipMemcpy(host.data(), r->d_state, sb, hipMemcpyDeviceToHost) != hipSuccess) {
@@ -320,7 +322,7 @@ void bpm_server::run()
                 r->d_state = nullptr;
             }
             std::lock_guard<std::mutex> lk(mu);
-            stats.cell_steps_done += 2.0 * r->desc.nx * adv[i];
+            stats.cell_steps_done += 2.0 * (double)r->plan->cells() * adv[i];
             if (fin) {
                 stats.bytes_in_use -= r->need;
                 admitted_slots--;
@@ -374,10 +376,12 @@ extern "C" bpm_status bpm_batch_submit(bpm_server *s, const bpm_request *reqs, i
         }
         auto r = std::make_shared<Request>();
         r->desc = *d;
-        r->seg.assign(d->seg, d->seg + (size_t)d->nz * d->nseg * 2);
-        if (d->strain.kind == BPM_STRAIN_TABLE) r->utab.assign(d->strain.u_table, d->strain.u_table + (size_t)d->nz * d->nx);
-        r->psi_p0.assign(reqs[i].psi_p0, reqs[i].psi_p0 + d->nx);
-        if (reqs[i].psi_m0) r->psi_m0.assign(reqs[i].psi_m0, reqs[i].psi_m0 + d->nx);
+        const size_t ny = d->ny > 1 ? d->ny : 1, cells = (size_t)d->nx * ny;
+        r->seg.assign(d->seg, d->seg + (size_t)d->nz * ny * d->nseg * 2);
+        if (d->strain.kind == BPM_STRAIN_TABLE)
+            r->utab.assign(d->strain.u_table, d->strain.u_table + (size_t)d->nz * cells);
+        r->psi_p0.assign(reqs[i].psi_p0, reqs[i].psi_p0 + cells);
+        if (reqs[i].psi_m0) r->psi_m0.assign(reqs[i].psi_m0, reqs[i].psi_m0 + cells);
         r->out_p = reqs[i].psi_p_out;
         r->out_m = reqs[i].psi_m_out;
         r->need = estimate_bytes(*d);

@@ -78,27 +78,34 @@ __global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, Cx<T> *prop,
             sc->sub[i].table = tab[i];
         }
     }
-    if (prop && f < nx) {
-        const int ff = f < nx / 2 ? f : f - nx;
-        const double q = 2.0 * M_PI * (double)ff / ((double)nx * P.dx * k);
-        const double invn = 1.0 / (double)nx;
+    const int ny = P.ny > 1 ? P.ny : 1;
+    const int cells = nx * ny;
+    if (prop && f < cells) {
+        // frequency bin (fx, fy) of entry f; 3D tables are [ky][kx]
+        const int fx = ny > 1 ? f % nx : f, fy = ny > 1 ? f / nx : 0;
+        const int gx = fx < nx / 2 ? fx : fx - nx, gy = fy < ny / 2 ? fy : fy - ny;
+        const double q = 2.0 * M_PI * (double)gx / ((double)nx * P.dx * k);
+        const double qy = ny > 1 ? 2.0 * M_PI * (double)gy / ((double)ny * P.dy * k) : 0.0;
+        const double invn = 1.0 / (double)cells;
         for (int beam = 0; beam < 2; ++beam) {
             const double sg = beam == 0 ? 1.0 : -1.0;
             const double pq = q + sg * s;
+            const double r = 1.0 - pq * pq - qy * qy;
             double kx, ky;  // P - 1
-            if (fabs(pq) <= 1.0) {
-                const double S = sqrt(1.0 - pq * pq);
-                const double th = -afrac * dzh * (q * q + 2.0 * sg * s * q) / (S + c);
+            if (r >= 0.0) {
+                // S - c = -(q^2 +/- 2 s q + qy^2) / (S + c)
+                const double S = sqrt(r);
+                const double th = -afrac * dzh * (q * q + 2.0 * sg * s * q + qy * qy) / (S + c);
                 const double sh = sin(0.5 * th);
                 kx = -2.0 * sh * sh;
                 ky = sin(th);
             } else {
-                const double mag = exp(-afrac * dzh * sqrt(pq * pq - 1.0));
+                const double mag = exp(-afrac * dzh * sqrt(-r));
                 kx = mag * cos(afrac * dzh * c) - 1.0;
                 ky = -mag * sin(afrac * dzh * c);
             }
             const int pos = log2r ? (f & ((1 << log2r) - 1)) * (nx >> log2r) + (f >> log2r) : f;
-            prop[beam * nx + pos] = {(T)(kx * invn), (T)(ky * invn)};
+            prop[beam * cells + pos] = {(T)(kx * invn), (T)(ky * invn)};
         }
     }
 }
@@ -222,10 +229,10 @@ hipError_t launch_twiddles(void *d_tw, int prec, int log2n, int log2e, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_plan_setup(const PlanParams *d_params, PlanScalars *d_sc, void *d_prop, int prec, int nx,
+hipError_t launch_plan_setup(const PlanParams *d_params, PlanScalars *d_sc, void *d_prop, int prec, int cells,
                              int log2r, double afrac, hipStream_t s)
 {
-    const int bs = 256, gs = d_prop ? (nx + bs - 1) / bs : 1;
+    const int bs = 256, gs = d_prop ? (cells + bs - 1) / bs : 1;
     if (prec == PREC_F32)
         hipLaunchKernelGGL(k_plan_setup<float>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (Cx<float> *)d_prop, log2r,
                            afrac);
@@ -250,6 +257,62 @@ static bool staged_layout_T(int log2n, int *tw_col, int *tw_4, int *total)
         }
     });
     return ok;
+}
+
+// 3D twiddle table [row FFT | column FFT], as Staged<..., D3> reads it.
+template <typename T>
+static bool layout_3d_T(int log2ny, int *tw_col, int *total)
+{
+    bool ok = false;
+    static_for<k3DLog2NyMin, k3DLog2NyMax + 1>([&](auto l) {
+        using S = Staged<T, k3DLog2Nx + CV(l), SC_NONE, staged_log2th(staged_prec<T>()), true>;
+        if (log2ny == CV(l)) {
+            *tw_col = S::TW_COL;
+            *total = S::TW_TOTAL;
+            ok = true;
+        }
+    });
+    return ok;
+}
+
+size_t twiddle3d_bytes(int prec, int log2ny)
+{
+    int a = 0, tot = 0;
+    const bool ok = prec == PREC_F32 ? layout_3d_T<float>(log2ny, &a, &tot) : layout_3d_T<double>(log2ny, &a, &tot);
+    return ok ? (size_t)tot * tw_bytes(prec) : 0;
+}
+
+hipError_t launch_twiddles_3d(void *d_tw, int prec, int log2ny, hipStream_t s)
+{
+    int tw_col = 0, tot = 0;
+    const bool ok = prec == PREC_F32 ? layout_3d_T<float>(log2ny, &tw_col, &tot)
+                                     : layout_3d_T<double>(log2ny, &tw_col, &tot);
+    const int le = staged_log2e(prec);
+    if (!ok || tw_count(k3DLog2Nx, le) != tw_col || tw_col + tw_count(log2ny, le) != tot) return hipErrorInvalidValue;
+    char *base = static_cast<char *>(d_tw);
+    hipError_t e = launch_twiddles(base, prec, k3DLog2Nx, le, s);
+    if (e == hipSuccess) e = launch_twiddles(base + (size_t)tw_col * tw_bytes(prec), prec, log2ny, le, s);
+    return e;
+}
+
+template <typename T>
+static void shape_3d_T(int log2ny, int *threads, size_t *lds)
+{
+    *threads = 0;
+    *lds = 0;
+    static_for<k3DLog2NyMin, k3DLog2NyMax + 1>([&](auto l) {
+        using S = Staged<T, k3DLog2Nx + CV(l), SC_NONE, staged_log2th(staged_prec<T>()), true>;
+        if (log2ny == CV(l)) {
+            *threads = S::TH;
+            *lds = S::lds_bytes;
+        }
+    });
+}
+
+void march_shape_3d(int prec, int log2ny, int *threads, size_t *lds_bytes)
+{
+    if (prec == PREC_F32) shape_3d_T<float>(log2ny, threads, lds_bytes);
+    else shape_3d_T<double>(log2ny, threads, lds_bytes);
 }
 
 bool is_staged(int prec, int log2n)
@@ -313,6 +376,8 @@ template <typename T, int LOG2N, int SC>
 hipError_t launch_staged(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
 template <typename T>
 hipError_t launch_any(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
+template <typename T, int LOG2NY, int SC>
+hipError_t launch_3d(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
 
 
 template <typename T, int SC>
@@ -320,6 +385,13 @@ static hipError_t dispatch(const SolveDesc *d_descs, int n, int uniform_log2n, c
                            double *rt, hipStream_t s)
 {
     if (uniform_log2n == kLaunchAny) return launch_any<T>(d_descs, n, in_base, out_base, rt, s);
+    if (uniform_log2n >= kLaunch3D) {
+        hipError_t err = hipErrorInvalidValue;
+        static_for<k3DLog2NyMin, k3DLog2NyMax + 1>([&](auto l) {
+            if (uniform_log2n == kLaunch3D + CV(l)) err = launch_3d<T, CV(l), SC>(d_descs, n, in_base, out_base, rt, s);
+        });
+        return err;
+    }
     if (uniform_log2n < 0) return launch_mixed<T, SC>(d_descs, n, in_base, out_base, rt, s);
     hipError_t err = hipErrorInvalidValue;
     static_for<Limits<T>::uni_lo, Limits<T>::uni_hi + 1>([&](auto l) {

@@ -293,6 +293,39 @@ def disl_bragg_cores(n_cores: int, nx: int = 32768, nz: int = 16000, dx: float =
     return out
 
 
+def cube_3d(nx: int = 512, ny: int = 256, nz: int = 300, dx: float = 0.05, dy: float = 0.05,
+            dz: float = 0.05, side: float = 10.0, precision: str = "f32", dislocation: bool = True,
+            seed: int = SEED_BASE + 5):
+    """3D envelopes: a cube of the given side in a (nx dx) x (ny dy) x (nz dz)
+    window (the 300 x 200 x 300 grid of the paper's 3D case padded to powers of
+    two), a Gaussian beam in x and y, and optionally an edge dislocation through
+    the cube centre (line along y, b = 4 d along h, half-cell offsets).
+    Returns (problem, psi_p0 [ny][nx])."""
+    rng = SplitMix64(seed)
+    Lx, Ly, Lz = nx * dx, ny * dy, nz * dz
+    xa, ya, za = 0.3 * Lx, 0.5 * (Ly - side), 0.5 * (Lz - side)
+    ja, jb = _index_at_or_above(xa, 0.0, dx), _index_at_or_above(xa + side, 0.0, dx)
+    seg = np.zeros((nz, ny, 1, 2), np.int32)
+    for n in range(nz):
+        if za <= n * dz < za + side:
+            for i in range(ny):
+                if ya <= i * dy < ya + side:
+                    seg[n, i, 0] = (ja, jb)
+    strain = None
+    if dislocation:
+        xd = (math.floor((xa + 0.5 * side + rng.uniform(-0.5, 0.5)) / dx) + 0.5) * dx
+        zd = (math.floor((za + 0.5 * side + rng.uniform(-0.5, 0.5)) / dz) + 0.5) * dz
+        strain = {"kind": "edge_dislocation", "x_ref_um": xd, "z_ref_um": zd, "b_um": 4 * D_UM, "nu": 0.22}
+    p = base_problem(nx, nz, dx, dz, seg, precision=precision, strain=strain)
+    p["ny"], p["dy_um"] = ny, dy
+    xs = np.arange(nx) * dx
+    ys = np.arange(ny) * dy
+    g = gaussian_beam(nx, dx, 0.2 * Lx, 3.0, envelope_tilt(LAMBDA_UM, D_UM, REFRACTION_URAD * 1e-6))
+    psi = np.exp(-((ys - 0.5 * Ly) / 3.0) ** 2)[:, None] * g[None, :]
+    del xs
+    return p, psi.astype(np.complex128)
+
+
 def td_batch(n_comp: int = 1024, sigma_t_fs: float = 20.0, nx_choices=(2048, 4096, 8192, 16384),
              nz_range=(1000, 8000), dx: float = 0.1, dz: float = 0.05, precision: str = "f32",
              seed: int = SEED_BASE + 3):

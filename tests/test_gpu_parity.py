@@ -32,8 +32,8 @@ def say(*a):
 
 
 def rel_pair(gp, gm, op, om):
-    g = np.concatenate([gp, gm])
-    o = np.concatenate([op, om])
+    g = np.concatenate([np.ravel(gp), np.ravel(gm)])
+    o = np.concatenate([np.ravel(op), np.ravel(om)])
     return float(np.linalg.norm(g - o) / np.linalg.norm(o))
 
 
@@ -361,6 +361,73 @@ def test_staged_sizes_in_batch_and_chunked_server_equal_single_solves():
     assert np.array_equal(r["psi_p"], singles[0][0]) and np.array_equal(r["psi_m"], singles[0][1])
     assert r["R"] == singles[0][2]
     srv.close()
+
+
+# ------------------------------------------------------------------ 3D envelopes
+def _problem3d(ny, nz, prec, strain=None, order=1, seed=0):
+    nx, dx, dy, dz = 512, 0.1, 0.2, 0.05
+    seg = np.zeros((nz, ny, 2, 2), np.int32)
+    for n in range(nz):
+        for i in range(ny):   # a ragged crystal section that changes with y and z
+            seg[n, i, 0] = (40 + (7 * i + 3 * n) % 50, 200 + (5 * i) % 60)
+            seg[n, i, 1] = (300 - (2 * n) % 40, 470 - (3 * i + n) % 30)
+    p = synth.base_problem(nx, nz, dx, dz, seg, precision=prec, strain=strain, det=(30, 480))
+    p["ny"], p["dy_um"] = ny, dy
+    p["split_order"] = order
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
+    b = 0.3 * (rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx)))
+    return p, a, b
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("ny", [16, 64, 256])
+def test_3d_random_fields_ragged_row_masks(prec, ny):
+    p, a, b = _problem3d(ny, 30, prec, seed=ny)
+    check(p, a, b, "3d-%d" % ny)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_3d_strain_kinds_and_splitting(prec):
+    poly = {"kind": "poly2", "x_ref_um": 25.0, "z_ref_um": 1.0, "c": [0, 1e-5, 0, 0, 4e-5, 0]}
+    p, a, b = _problem3d(32, 40, prec, strain=poly, seed=1)
+    check(p, a, b, "3d-poly2")
+    p, a, b = _problem3d(32, 40, prec, strain=poly, order=2, seed=2)
+    check(p, a, b, "3d-poly2-split2")
+    disl = {"kind": "edge_dislocation", "x_ref_um": 25.05, "z_ref_um": 1.025, "b_um": 0.38e-3, "nu": 0.22}
+    p, a, b = _problem3d(32, 40, prec, strain=disl, seed=3)
+    check(p, a, b, "3d-disl")
+    rng = synth.SplitMix64(11)
+    u = np.array([[[2e-5 * math.sin(0.01 * j + 0.3 * i + 0.1 * n) + 1e-6 * rng.uniform() for j in range(512)]
+                   for i in range(16)] for n in range(20)])
+    p, a, b = _problem3d(16, 20, prec, strain={"kind": "table", "u_table": u}, seed=4)
+    check(p, a, b, "3d-table")
+
+
+def test_3d_batch_with_2d_solves_and_far_field():
+    """3D and 2D solves in one batch reproduce their single solves bitwise; the
+    far field of a 3D exit field equals the oracle's 3D vacuum step."""
+    B = bpm()
+    import torch
+    p3, a3, b3 = _problem3d(64, 25, "f32", seed=9)
+    p2, psi2 = synth.flat_bragg_scan(n_angles=1, nx=4096, nz=25, precision="f32")[0]
+    plans = [B.Plan(p3), B.Plan(p2)]
+    batch = B.Batch(plans)
+    buf = batch.pack([(a3, b3), (psi2, None)])
+    batch.run(buf.data_ptr(), buf.data_ptr())
+    torch.cuda.synchronize()
+    outs = batch.unpack(buf)
+    s3 = plans[0].propagate(a3, b3)
+    s2 = plans[1].propagate(psi2)
+    assert np.array_equal(outs[0][0], s3[0]) and np.array_equal(outs[0][1], s3[1])
+    assert np.array_equal(outs[1][0], s2[0])
+    fp, fm = plans[0].far_field(1.0e6, s3[0], s3[1])
+    ny = p3["ny"]
+    v = dict(p3, nz=1, dz_um=1.0e6, seg=np.zeros((1, ny, 1, 2), np.int32), strain={"kind": "none"})
+    op, om, _, _ = oracle.propagate(v, s3[0], s3[1])
+    err = rel_pair(fp.reshape(-1), fm.reshape(-1), op.reshape(-1), om.reshape(-1))
+    say("   3d far field rel L2 %.3e" % err)
+    assert err <= TOL["f32"][0]
 
 
 # ------------------------------------------------------------------ time-domain assembly
