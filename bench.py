@@ -97,16 +97,21 @@ def fp64_plain(bpm, torch, synth):
     """One FP64 solve alone on the GPU (the flat Bragg case: Nx 4096, Nz 2000)."""
     p, psi = synth.flat_bragg_scan(n_angles=1, precision="f64")[0]
     per, total, _, _ = time_batch(bpm, torch, [(p, psi)], 3, 1)
-    cs = 2.0 * p["nx"] * p["nz"]
+    cs = cell_steps(p)
     return {"value": cs / (sum(per) / len(per) / 1e3), "unit": "cell-steps/s",
             "workload": "flat_bragg Nx 4096 Nz 2000, one FP64 solve", "ms": sum(per) / len(per)}
+
+
+def cell_steps(p) -> float:
+    """Cells times z-steps of one solve, both beams (nx ny nz, ny = 1 in 2D)."""
+    return 2.0 * p["nx"] * max(1, int(p.get("ny", 1))) * p["nz"]
 
 
 def leg_batch(bpm, torch, cases, label, steps=1, warmup=1):
     """Throughput of one workload batch in one launch per step."""
     print("leg %s: %d solves" % (label, len(cases)), file=sys.stderr, flush=True)
     per, total, _, _ = time_batch(bpm, torch, cases, steps, warmup)
-    cs = sum(2.0 * p["nx"] * p["nz"] for p, _ in cases)
+    cs = sum(cell_steps(p) for p, _ in cases)
     ms = total / steps
     return {"value": cs / (ms / 1e3), "unit": "cell-steps/s", "ms_per_step": ms, "solves": len(cases),
             "cell_steps": cs}
@@ -136,11 +141,11 @@ def leg_serve(bpm, synth, n_req, rate_hz, budget_gb, chunk_steps):
         return v[min(len(v) - 1, max(0, int(math.ceil(f * len(v))) - 1))] if v else None
 
     span = max(x["t_done"] for _, x in good) - min(x["t_submit"] for _, x in good) if good else 0.0
-    cs = sum(2.0 * r["nx"] * r["nz"] for r, _ in good)
+    cs = sum(cell_steps(r) for r, _ in good)
     return {"requests": n_req, "completed": len(good), "drained": bool(drained), "rate_hz": rate_hz,
             "p50_ms": q(lat, 0.5), "p99_ms": q(lat, 0.99), "max_ms": lat[-1] if lat else None,
             "value": cs / span if span > 0 else None, "unit": "cell-steps/s",
-            "offered": sum(2.0 * r["nx"] * r["nz"] for r in reqs) / reqs[-1]["t_arrival"],
+            "offered": sum(cell_steps(r) for r in reqs) / reqs[-1]["t_arrival"],
             "launches": stats["launches"], "peak_bytes": stats["peak_bytes"], "chunk_steps": chunk_steps,
             "budget_gb": budget_gb}
 
@@ -166,7 +171,7 @@ def cpu_baseline(cases, target_s=12.0):
     t = time.perf_counter()
     oracle.propagate_batch([q for q, _ in sample], [(psi, None) for _, psi in sample], nthreads=cores)
     wall = time.perf_counter() - t
-    cs = sum(2.0 * q["nx"] * q["nz"] for q, _ in sample)
+    cs = sum(cell_steps(q) for q, _ in sample)
     return {"value": cs / wall, "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
             "sample": "%d of the %d solves, first %d of %d z-steps each, one solve per thread (%.1f s wall)"
                       % (nsolve, len(cases), nz, p0["nz"], wall)}
@@ -237,7 +242,7 @@ def main():
               file=sys.stderr)
     cases, cfg = workload(args.workload, args.beams_per_radius, args.nz)
     print("workload %s: %d solves" % (cfg["workload"], len(cases)), file=sys.stderr, flush=True)
-    launch_cs = sum(2.0 * p["nx"] * p["nz"] for p, _ in cases)
+    launch_cs = sum(cell_steps(p) for p, _ in cases)
     per, total_ms, wall, Rs = time_batch(bpm, torch, cases, args.steps, args.warmup)
     ms = total_ms / args.steps
     value = launch_cs / (ms / 1e3)
@@ -252,7 +257,7 @@ def main():
     prec = cases[0][0]["precision"]
     kernel = ("k_march_uniform<%s,%d>" % ("float" if prec == "f32" else "double", int(math.log2(nx)))
               if uniform else "k_march_mixed<%s>" % ("float" if prec == "f32" else "double"))
-    flop_cs = (sum((10 * math.log2(p["nx"]) + 26) * 2 * p["nx"] * p["nz"] for p, _ in cases) / launch_cs)
+    flop_cs = (sum((10 * math.log2(p["nx"]) + 26) * cell_steps(p) for p, _ in cases) / launch_cs)
     achieved = flop_cs * launch_cs / (sum(per) / len(per) / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / ALU_PEAK_TFLOPS, "traffic": traffic_entry(kernel, launch_cs),

@@ -285,6 +285,7 @@ void bpm_server::run()
         bool freed = false;
         for (size_t i = 0; i < active.size(); ++i) {
             auto &r = active[i];
+            const double cells = (double)r->plan->cells();   // before the plan is released
             r->step += adv[i];
             bool fin = !ok || r->step >= r->desc.nz || r->cancel;
             int status = !ok ? BPM_E_DEVICE : (r->cancel && r->step < r->desc.nz ? BPM_E_CANCELLED : BPM_OK);
@@ -322,7 +323,7 @@ void bpm_server::run()
                 r->d_state = nullptr;
             }
             std::lock_guard<std::mutex> lk(mu);
-            stats.cell_steps_done += 2.0 * (double)r->plan->cells() * adv[i];
+            stats.cell_steps_done += 2.0 * cells * adv[i];
             if (fin) {
                 stats.bytes_in_use -= r->need;
                 admitted_slots--;

@@ -450,7 +450,9 @@ def test_td_assembly_matches_oracle(prec):
     ref = oracle.td_assemble([p for p, _ in cases], [(a, b) for a, b in exits])
     err = float(np.linalg.norm(td - ref) / np.linalg.norm(ref))
     say("   td assembly alone rel L2 %.3e" % err)
-    assert err <= (1e-13 if prec == "f64" else 2e-6)
+    # the carrier phase k c L is ~3e5 rad: FP64 evaluations of it (oracle and
+    # kernel) each carry ~|k c L| 2^-52 ~ 6e-11 rad
+    assert err <= (1e-10 if prec == "f64" else 2e-6)
     ores, _, _ = oracle.propagate_batch([p for p, _ in cases], [(psi, None) for _, psi in cases])
     ref2 = oracle.td_assemble([p for p, _ in cases], [(a, b) for a, b in ores])
     err2 = float(np.linalg.norm(td - ref2) / np.linalg.norm(ref2))
