@@ -76,6 +76,67 @@ __device__ __forceinline__ Cx<double> gload(gptr<Cx<double>> p, uint32_t i)
     return {v.x, v.y};
 }
 
+// Tables and solve states behind buffer resources.  The resource holds the
+// buffer's base address and byte size in scalar registers; an access adds a
+// per-lane 32-bit byte offset and a wave-uniform byte offset (scalar), so it
+// costs no vector-ALU address arithmetic, where a per-lane 64-bit global address
+// costs two instructions.  Reads at or past the size return zero and writes
+// there are dropped.
+constexpr int kRawBufferWord3 = 0x00020000;  // untyped 32-bit elements (gfx9 family)
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef unsigned u3v __attribute__((ext_vector_type(3)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+struct BufView {
+    __amdgpu_buffer_rsrc_t r;
+    int base;  // wave-uniform byte offset of every load
+};
+// (every argument is the same across the wave; reading them from the first lane
+// lets the compiler keep the resource in scalar registers)
+__device__ __forceinline__ BufView buf_view(const void *p, uint32_t bytes, int base = 0)
+{
+    const uint64_t a = (uint64_t)p;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+    void *q = (void *)(lo | (hi << 32));
+    return {__builtin_amdgcn_make_buffer_rsrc(q, (short)0, __builtin_amdgcn_readfirstlane((int)bytes), kRawBufferWord3),
+            __builtin_amdgcn_readfirstlane(base)};
+}
+// (bytes is the same across the wave)
+__device__ __forceinline__ BufView operator+(BufView t, int bytes)
+{
+    return {t.r, __builtin_amdgcn_readfirstlane(t.base + bytes)};
+}
+__device__ __forceinline__ float f_of(unsigned u) { return __builtin_bit_cast(float, u); }
+__device__ __forceinline__ double d_of(unsigned lo, unsigned hi) { return __builtin_bit_cast(double, (u2v){lo, hi}); }
+// element at byte offset lane_off (per lane) + uni_off (wave-uniform)
+__device__ __forceinline__ Cx<float> tload_cx(const BufView &t, Cx<float> *, int lane_off, int uni_off)
+{
+    const u2v v = __builtin_amdgcn_raw_buffer_load_b64(t.r, lane_off, t.base + uni_off, 0);
+    return {f_of(v.x), f_of(v.y)};
+}
+__device__ __forceinline__ Cx<double> tload_cx(const BufView &t, Cx<double> *, int lane_off, int uni_off)
+{
+    const u4v v = __builtin_amdgcn_raw_buffer_load_b128(t.r, lane_off, t.base + uni_off, 0);
+    return {d_of(v.x, v.y), d_of(v.z, v.w)};
+}
+// complex entry i of a table of Cx<T>, split as lane index + uniform index
+template <typename T>
+__device__ __forceinline__ Cx<T> tload_cx(const BufView &t, int lane_i, int uni_i)
+{
+    return tload_cx(t, (Cx<T> *)nullptr, lane_i * (int)sizeof(Cx<T>), uni_i * (int)sizeof(Cx<T>));
+}
+__device__ __forceinline__ void tstore_cx(const BufView &t, Cx<float> v, int lane_i, int uni_i)
+{
+    const u2v w = {__builtin_bit_cast(unsigned, v.x), __builtin_bit_cast(unsigned, v.y)};
+    __builtin_amdgcn_raw_buffer_store_b64(w, t.r, lane_i * 8, t.base + uni_i * 8, 0);
+}
+__device__ __forceinline__ void tstore_cx(const BufView &t, Cx<double> v, int lane_i, int uni_i)
+{
+    const u2v a = __builtin_bit_cast(u2v, v.x), b = __builtin_bit_cast(u2v, v.y);
+    const u4v w = {a.x, a.y, b.x, b.y};
+    __builtin_amdgcn_raw_buffer_store_b128(w, t.r, lane_i * 16, t.base + uni_i * 16, 0);
+}
+
 template <typename T>
 __device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>
@@ -294,15 +355,27 @@ __device__ __forceinline__ Cx<double> mul_tw_inv(Cx<double> a, const Tw<double> 
 {
     return {fmaT(a.x, w.x, a.y * w.y), fmaT(a.y, w.x, -a.x * w.y)};
 }
-__device__ __forceinline__ Tw<float> gload(gptr<Tw<float>> p, uint32_t i)
+// FP32 rotations whose angle never exceeds pi/2 (their table sign is +1)
+__device__ __forceinline__ Cx<float> mul_tw_nosign(Cx<float> a, const Tw<float> &w) { return lift(a, w.p, w.u); }
+__device__ __forceinline__ Cx<float> mul_tw_inv_nosign(Cx<float> a, const Tw<float> &w) { return lift(a, -w.p, -w.u); }
+__device__ __forceinline__ Cx<double> mul_tw_nosign(Cx<double> a, const Tw<double> &w) { return mul_tw(a, w); }
+__device__ __forceinline__ Cx<double> mul_tw_inv_nosign(Cx<double> a, const Tw<double> &w) { return mul_tw_inv(a, w); }
+
+// twiddle entry lane_i + uni_i of a table (lane index per lane, uniform index per wave)
+__device__ __forceinline__ Tw<float> tload_tw(const BufView &t, Tw<float> *, int lane_i, int uni_i)
 {
-    const uint32_t b = i * 12u;   // three dwords, merged into one 12-byte load
-    return {gload_at<float>(p, b), gload_at<float>(p, b + 4u), gload_at<float>(p, b + 8u)};
+    const u3v v = __builtin_amdgcn_raw_buffer_load_b96(t.r, lane_i * 12, t.base + uni_i * 12, 0);
+    return {f_of(v.x), f_of(v.y), f_of(v.z)};
 }
-__device__ __forceinline__ Tw<double> gload(gptr<Tw<double>> p, uint32_t i)
+__device__ __forceinline__ Tw<double> tload_tw(const BufView &t, Tw<double> *, int lane_i, int uni_i)
 {
-    const d2v v = gload_at<d2v>(p, i * (uint32_t)sizeof(d2v));
-    return {v.x, v.y};
+    const u4v v = __builtin_amdgcn_raw_buffer_load_b128(t.r, lane_i * 16, t.base + uni_i * 16, 0);
+    return {d_of(v.x, v.y), d_of(v.z, v.w)};
+}
+template <typename T>
+__device__ __forceinline__ Tw<T> tload_tw(const BufView &t, int lane_i, int uni_i)
+{
+    return tload_tw(t, (Tw<T> *)nullptr, lane_i, uni_i);
 }
 
 // ----------------------------------------------------------------- schedule
@@ -463,6 +536,28 @@ __device__ __forceinline__ void couple(Cx<T> &vp, Cx<T> &vm, Cx<T> d0, Cx<T> bp,
           fmaT(bm.x, a.y, fmaT(bm.y, a.x, fmaT(d0.x, b.y, fmaT(d0.y, b.x, b.y))))};
 }
 
+// couple() where the sample is inside the crystal; outside, both envelopes
+// keep their propagated values (pure propagation)
+template <typename T>
+__device__ __forceinline__ void couple_sel(Cx<T> &vp, Cx<T> &vm, bool in, Cx<T> d0, Cx<T> bp, Cx<T> bm)
+{
+    Cx<T> a = vp, b = vm;
+    couple(a, b, d0, bp, bm);
+    vp = {in ? a.x : vp.x, in ? a.y : vp.y};
+    vm = {in ? b.x : vm.x, in ? b.y : vm.y};
+}
+
+// a value the whole wave holds, moved to scalar registers
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const u2v h = __builtin_bit_cast(u2v, v);
+    return d_of((unsigned)__builtin_amdgcn_readfirstlane((int)h.x), (unsigned)__builtin_amdgcn_readfirstlane((int)h.y));
+}
+
 // Orders this wave's LDS writes before its following LDS reads (LDS executes a
 // wave's instructions in order; this keeps the compiler from reordering them).
 __device__ __forceinline__ void wave_lds_sync()
@@ -481,7 +576,10 @@ struct Coupler {
     int nseg, nx;
     gptr<int> seg;
     gptr<T> utab;
+    Cx<T> rr;        // polynomial strain: phasor of the phase's second difference along a thread's samples
 
+    // JS: sample stride between a thread's elements
+    template <int JS>
     __device__ __forceinline__ void init(const SolveDesc &d, int nx_)
     {
         X0 = d.x0 - d.x_ref;
@@ -489,6 +587,12 @@ struct Coupler {
         nx = nx_;
         seg = to_global<int>(d.seg);
         utab = to_global<T>(d.utab);
+        if constexpr (SC == SC_POLY2) {
+            // the second difference 2 pc D^2 (D = JS dx) does not depend on z
+            const double D = (double)JS * d.dx;
+            const Cx<T> r = phasor<T>(2.0 * (d.c[3] * d.inv_d) * D * D);
+            rr = {wave_uniform(r.x), wave_uniform(r.y)};
+        }
     }
 
     // coupling sub-step ss of z-step n (its coefficients, mask row n, strain
@@ -518,38 +622,33 @@ struct Coupler {
             }
         });
         auto inside_at_e = [&](auto e) { return ((inside >> CV(e)) & 1u) != 0u; };
-        const Cx<T> zero = {(T)0, (T)0};
-        auto sel = [&](bool in, Cx<T> c) { return Cx<T>{in ? c.x : zero.x, in ? c.y : zero.y}; };
         const double Z = (n + ss.zoff) * d.dz - d.z_ref;
         // (one straight-line copy: a separate all-inside copy costs registers)
         if constexpr (SC == SC_NONE) {
-            static_for<0, E>([&](auto e) {
-                const bool in = inside_at_e(e);
-                couple(vp[e], vm[e], sel(in, d0), sel(in, ap), sel(in, am));
-            });
+            static_for<0, E>([&](auto e) { couple_sel(vp[e], vm[e], inside_at_e(e), d0, ap, am); });
         } else if constexpr (SC == SC_POLY2) {
             // phase (revolutions) u/d = pa + pb X + pc X^2 along this z; along a
-            // thread's samples X_e = X_0 + e D it is quadratic in e, so the
-            // phasors follow P_{e+1} = P_e Q_e, Q_{e+1} = Q_e R with P_0, Q_0, R
-            // from FP64 arguments reduced to one revolution.
+            // thread's samples X_e = X_0 + e D it is quadratic in e: with
+            // P_e = exp(2 pi i u_e/d), P_{e+1} = P_e Q_e and Q_{e+1} = Q_e R, so the
+            // coefficients bp_e = ap P_e and bm_e = am conj(P_e) advance by Q_e and
+            // conj(Q_e); P_0, Q_0 and R from FP64 arguments reduced to one revolution.
             const double pa = (d.c[0] + Z * (d.c[2] + Z * d.c[5])) * d.inv_d;
             const double pb = (d.c[1] + Z * d.c[4]) * d.inv_d;
             const double pc = d.c[3] * d.inv_d;
             const double D = (double)JS * d.dx;
             const double Xt = __builtin_fma((double)j0, d.dx, X0);
-            Cx<T> P = phasor<T>(__builtin_fma(__builtin_fma(pc, Xt, pb), Xt, pa));
+            const Cx<T> P = phasor<T>(__builtin_fma(__builtin_fma(pc, Xt, pb), Xt, pa));
             Cx<T> Q = phasor<T>(__builtin_fma(pc, __builtin_fma(2.0 * Xt, D, D * D), pb * D));
-            const Cx<T> Rr = phasor<T>(2.0 * pc * D * D);
-            auto body = [&](auto e, bool in) {
-                const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
-                const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
-                couple(vp[e], vm[e], sel(in, d0), sel(in, bp), sel(in, bm));
+            Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
+            Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
+            static_for<0, E>([&](auto e) {
+                couple_sel(vp[e], vm[e], inside_at_e(e), d0, bp, bm);
                 if constexpr (CV(e) + 1 < E) {
-                    P = {fmaT(P.x, Q.x, -P.y * Q.y), fmaT(P.x, Q.y, P.y * Q.x)};
-                    Q = {fmaT(Q.x, Rr.x, -Q.y * Rr.y), fmaT(Q.x, Rr.y, Q.y * Rr.x)};
+                    bp = {fmaT(bp.x, Q.x, -bp.y * Q.y), fmaT(bp.x, Q.y, bp.y * Q.x)};
+                    bm = {fmaT(bm.x, Q.x, bm.y * Q.y), fmaT(bm.y, Q.x, -bm.x * Q.y)};
+                    Q = {fmaT(Q.x, rr.x, -Q.y * rr.y), fmaT(Q.x, rr.y, Q.y * rr.x)};
                 }
-            };
-            static_for<0, E>([&](auto e) { body(e, inside_at_e(e)); });
+            });
         } else {
             // dislocation field or tabulated phase (already reduced to one
             // revolution when the plan was built)
@@ -569,7 +668,7 @@ struct Coupler {
                     const Cx<T> P = {fmaT(W.x, S.x, -W.y * S.y), fmaT(W.x, S.y, W.y * S.x)};
                     const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
                     const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
-                    couple(vp[e], vm[e], sel(in, d0), sel(in, bp), sel(in, bm));
+                    couple_sel(vp[e], vm[e], in, d0, bp, bm);
                 });
                 return;
             }
@@ -581,7 +680,7 @@ struct Coupler {
                 const Cx<T> P = phasor<T>(rev);
                 const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
                 const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
-                couple(vp[e], vm[e], sel(in, d0), sel(in, bp), sel(in, bm));
+                couple_sel(vp[e], vm[e], in, d0, bp, bm);
             });
         }
     }
@@ -595,8 +694,6 @@ struct Coupler {
         const Cx<T> d0 = {to_T<T>(ss.d0x), to_T<T>(ss.d0y)};
         const Cx<T> ap = {to_T<T>(ss.apx), to_T<T>(ss.apy)};
         const Cx<T> am = {to_T<T>(ss.amx), to_T<T>(ss.amy)};
-        const Cx<T> zero = {(T)0, (T)0};
-        auto sel = [&](bool in, Cx<T> c) { return Cx<T>{in ? c.x : zero.x, in ? c.y : zero.y}; };
         const double Z = (n + ss.zoff) * d.dz - d.z_ref;
         const double Xd = __builtin_fma((double)x, d.dx, X0);
         Cx<T> P = {(T)1, (T)0};
@@ -629,7 +726,7 @@ struct Coupler {
             const Cx<T> Pe = table ? phasor<T>(utab[(size_t)row * nx + x]) : P;
             const Cx<T> bp = {fmaT(ap.x, Pe.x, -ap.y * Pe.y), fmaT(ap.x, Pe.y, ap.y * Pe.x)};
             const Cx<T> bm = {fmaT(am.x, Pe.x, am.y * Pe.y), fmaT(am.y, Pe.x, -am.x * Pe.y)};
-            couple(vp[e], vm[e], sel(in, d0), sel(in, bp), sel(in, bm));
+            couple_sel(vp[e], vm[e], in, d0, bp, bm);
         });
     }
 };
@@ -645,13 +742,15 @@ struct March {
     static constexpr int N = G::N, E = G::E, TH = G::TH, W = G::G, LANES = G::LANES, M = G::M;
     static constexpr int PW = SW::P, BUFM = G::BUFM;
     static constexpr int NB = LP::NBUF, BX = BXO ? BXO : LP::BX;
+    // twiddle entries: the group-local passes, then the cross-group pass (radix W, sub-length M)
+    static constexpr int TW_ENTRIES = G::TWFINAL + (W > 1 ? M * (W - 1) : 0);
     static_assert(G::WAVE_LOCAL || W == 1, "whole-workgroup groups");
     static_assert(BLOCK >= TH, "block");
 
     // ---- one Stockham pass over a set of threads: radix 2^LR, sub-length 2^LL,
     // EE samples per thread, THR threads (thread tid), twiddles at tw[twb + ...]
     template <int LR, int LL, int THR>
-    static __device__ __forceinline__ void pass_fwd(Cx<T> *vp, Cx<T> *vm, gptr<Tw<T>> tw, int twb, int tid)
+    static __device__ __forceinline__ void pass_fwd(Cx<T> *vp, Cx<T> *vm, const BufView &tw, int twb, int tid)
     {
         constexpr int r = 1 << LR, EPR = E / r, L = 1 << LL;
         static_for<0, EPR>([&](auto i) {
@@ -663,9 +762,15 @@ struct March {
             if constexpr (L > 1) {
                 const int j = (tid + i * THR) & (L - 1);
                 static_for<1, r>([&](auto m) {
-                    const Tw<T> w = gload(tw, twb + (m - 1) * L + j);
-                    ap[m] = mul_tw(ap[m], w);
-                    am[m] = mul_tw(am[m], w);
+                    const Tw<T> w = tload_tw<T>(tw, j, twb + (m - 1) * L);
+                    // angle 2 pi j m / (L r) < pi/2 for m <= r/4: no sign taken out
+                    if constexpr (4 * CV(m) <= r) {
+                        ap[m] = mul_tw_nosign(ap[m], w);
+                        am[m] = mul_tw_nosign(am[m], w);
+                    } else {
+                        ap[m] = mul_tw(ap[m], w);
+                        am[m] = mul_tw(am[m], w);
+                    }
                 });
             }
             Dft<T, r, false>::run(ap);
@@ -677,7 +782,7 @@ struct March {
         });
     }
     template <int LR, int LL, int THR>
-    static __device__ __forceinline__ void pass_inv(Cx<T> *vp, Cx<T> *vm, gptr<Tw<T>> tw, int twb, int tid)
+    static __device__ __forceinline__ void pass_inv(Cx<T> *vp, Cx<T> *vm, const BufView &tw, int twb, int tid)
     {
         constexpr int r = 1 << LR, EPR = E / r, L = 1 << LL;
         static_for<0, EPR>([&](auto i) {
@@ -691,9 +796,14 @@ struct March {
             if constexpr (L > 1) {
                 const int j = (tid + i * THR) & (L - 1);
                 static_for<1, r>([&](auto m) {
-                    const Tw<T> w = gload(tw, twb + (m - 1) * L + j);
-                    ap[m] = mul_tw_inv(ap[m], w);
-                    am[m] = mul_tw_inv(am[m], w);
+                    const Tw<T> w = tload_tw<T>(tw, j, twb + (m - 1) * L);
+                    if constexpr (4 * CV(m) <= r) {
+                        ap[m] = mul_tw_inv_nosign(ap[m], w);
+                        am[m] = mul_tw_inv_nosign(am[m], w);
+                    } else {
+                        ap[m] = mul_tw_inv(ap[m], w);
+                        am[m] = mul_tw_inv(am[m], w);
+                    }
                 });
             }
             static_for<0, r>([&](auto m) {
@@ -852,7 +962,7 @@ struct March {
     // Group-local forward FFT of M points (radix-E Stockham passes with the
     // group's exchanges through its LDS region Rp/Rm); natural-order samples
     // l + LANES*e in, bins l + LANES*e out.
-    static __device__ __forceinline__ void fwd_local(Cx<T> *vp, Cx<T> *vm, gptr<Tw<T>> tw, Cx<T> *Rp, Cx<T> *Rm,
+    static __device__ __forceinline__ void fwd_local(Cx<T> *vp, Cx<T> *vm, const BufView &tw, Cx<T> *Rp, Cx<T> *Rm,
                                                      int l, bool active)
     {
         static_for<0, PW>([&](auto pc) {
@@ -862,7 +972,7 @@ struct March {
         });
     }
     // its exact inverse: the same passes in reverse order with the same tables
-    static __device__ __forceinline__ void inv_local(Cx<T> *vp, Cx<T> *vm, gptr<Tw<T>> tw, Cx<T> *Rp, Cx<T> *Rm,
+    static __device__ __forceinline__ void inv_local(Cx<T> *vp, Cx<T> *vm, const BufView &tw, Cx<T> *Rp, Cx<T> *Rm,
                                                      int l, bool active)
     {
         static_for<0, PW>([&](auto pp) {
@@ -895,8 +1005,8 @@ struct March {
         const bool active = (BLOCK == TH) || (t0 < TH);
         const Cx<T> *in = reinterpret_cast<const Cx<T> *>(in_base + d.in_off);
         Cx<T> *out = reinterpret_cast<Cx<T> *>(out_base + d.out_off);
-        const gptr<Tw<T>> tw = to_global<Tw<T>>(d.tw);
-        const gptr<Cx<T>> prop = to_global<Cx<T>>(d.prop);
+        const BufView tw = buf_view(d.tw, TW_ENTRIES * (uint32_t)sizeof(Tw<T>));
+        const Cx<T> *prop = reinterpret_cast<const Cx<T> *>(d.prop);
         // sample index of element e of this thread: j0 + TH*e
         const int w0 = t0 >> G::LOG2LANES, l0 = t0 & (LANES - 1);
         const int j00 = w0 + W * l0;
@@ -925,7 +1035,7 @@ struct March {
         }
 
         Coupler<T, SC> cpl;
-        cpl.init(d, N);
+        cpl.template init<TH>(d, N);
         const T invN = (T)(1.0 / (double)N);
 
         const PlanScalars &scl = *d.sc;
@@ -941,9 +1051,9 @@ struct March {
             // hoisted into registers for the whole march, and the inverse
             // passes re-read the twiddles instead of keeping the forward copies.
             const int oz = (n + i) & d.opaque_zero;
-            const gptr<Tw<T>> twf = tw + oz;
-            const gptr<Tw<T>> twi = tw + ((n + i + 1) & d.opaque_zero);
-            const gptr<Cx<T>> propn = prop + (oz + ss.table * 2 * N);
+            const BufView twf = tw + oz * (int)sizeof(Tw<T>);
+            const BufView twi = tw + ((n + i + 1) & d.opaque_zero) * (int)sizeof(Tw<T>);
+            const BufView propn = buf_view(prop + ss.table * 2 * N, 2 * N * (uint32_t)sizeof(Cx<T>), oz * (int)sizeof(Cx<T>));
             const int t = t0 + oz;
             const int w = t >> G::LOG2LANES, l = t & (LANES - 1);
             Cx<T> *Rp = bufp + w * BUFM;
@@ -973,8 +1083,7 @@ struct March {
                     if constexpr (W > 1) pass_fwd<G::LOG2G, G::LOG2M, TH>(vp, vm, twf, G::TWFINAL, t);
                     // ---- propagator: sample f = t + TH*e holds frequency bin f
                     static_for<0, E>([&](auto e) {
-                        const int f = t + e * TH;
-                        const Cx<T> kp = gload(propn, f), km = gload(propn, N + f);
+                        const Cx<T> kp = tload_cx<T>(propn, t, e * TH), km = tload_cx<T>(propn, t, N + e * TH);
                         const Cx<T> a = vp[e], b = vm[e];
                         vp[e] = {fmaT(kp.x, a.x, fmaT(-kp.y, a.y, a.x * invN)),
                                  fmaT(kp.x, a.y, fmaT(kp.y, a.x, a.y * invN))};
@@ -1094,18 +1203,20 @@ struct Staged {
     static constexpr int TW_4 = TW_COL + ColM::SW::twcount();
     static constexpr int TW_TOTAL = D3 ? TW_4 : TW_4 + N;
 
-    static __device__ __forceinline__ void load(Cx<T> *vp, Cx<T> *vm, const Cx<T> *src, int base, int stride)
+    // samples base + stride*e of both beams (beam - at +N) of a state [2][N]
+    static __device__ __forceinline__ void load(Cx<T> *vp, Cx<T> *vm, const BufView &src, int base, int stride)
     {
         static_for<0, E>([&](auto e) {
-            vp[e] = src[base + e * stride];
-            vm[e] = src[N + base + e * stride];
+            vp[e] = tload_cx<T>(src, base, e * stride);
+            vm[e] = tload_cx<T>(src, base, N + e * stride);
         });
     }
-    static __device__ __forceinline__ void store(Cx<T> *dst, const Cx<T> *vp, const Cx<T> *vm, int base, int stride)
+    static __device__ __forceinline__ void store(const BufView &dst, const Cx<T> *vp, const Cx<T> *vm, int base,
+                                                 int stride)
     {
         static_for<0, E>([&](auto e) {
-            dst[base + e * stride] = vp[e];
-            dst[N + base + e * stride] = vm[e];
+            tstore_cx(dst, vp[e], base, e * stride);
+            tstore_cx(dst, vm[e], base, N + e * stride);
         });
     }
     // |psi+|^2 and |psi-|^2 over the detector interval, samples base + stride*e
@@ -1135,10 +1246,12 @@ struct Staged {
                                Cx<T> *lds, double *red)
     {
         const int t0 = threadIdx.x;
-        const Cx<T> *in = reinterpret_cast<const Cx<T> *>(in_base + d.in_off);
-        Cx<T> *st = reinterpret_cast<Cx<T> *>(out_base + d.out_off);
-        const gptr<Tw<T>> tw = to_global<Tw<T>>(d.tw);
-        const gptr<Cx<T>> prop = to_global<Cx<T>>(d.prop);
+        constexpr uint32_t SB = 2 * N * (uint32_t)sizeof(Cx<T>);
+        const BufView in = buf_view(in_base + d.in_off, SB);
+        const BufView st = buf_view(out_base + d.out_off, SB);   // the solve's state [2][N]
+        const BufView tw = buf_view(d.tw, TW_TOTAL * (uint32_t)sizeof(Tw<T>));
+        const Cx<T> *prop = reinterpret_cast<const Cx<T> *>(d.prop);
+        constexpr int TWB = (int)sizeof(Tw<T>);
         const int wv = t0 >> 6, lane = t0 & 63;
         Cx<T> *slab = lds + wv * SLAB;
         const int gi = lane / LC, lc = lane % LC;    // column within the wave, lane within the column
@@ -1147,7 +1260,7 @@ struct Staged {
         Cx<T> *RRp = slab;
         Cx<T> *RRm = slab + (RowM::BX == 2 ? RowM::BUFM : 0);
         Coupler<T, SC> cpl;
-        cpl.init(d, D3 ? C : N);
+        cpl.template init<LC * C>(d, D3 ? C : N);
         const T invN = (T)(1.0 / (double)N);
         const int nend = d.step0 + d.nsteps;
         const bool rt_out = (d.flags & SF_LAST) && d.rt_index >= 0;
@@ -1172,8 +1285,7 @@ struct Staged {
             }
             if (d.nsteps > 0) {
                 if (lead) couple_at(cpl, vp, vm, d, d.step0, lc, c, scl.sub[0]);
-                const gptr<Tw<T>> twc = tw + (TW_COL + (cr & d.opaque_zero));
-                ColM::fwd_local(vp, vm, twc, CRp, CRm, lc, true);
+                ColM::fwd_local(vp, vm, tw + (TW_COL + (cr & d.opaque_zero)) * TWB, CRp, CRm, lc, true);
             } else if (rt_out) {
                 det_sums(vp, vm, d, lc * C + c, LC * C, sp, sm);
             }
@@ -1199,17 +1311,18 @@ struct Staged {
                 load(vp, vm, st, rb, 64);
                 if constexpr (!D3) {
                     static_for<0, E>([&](auto e) {
-                        const Tw<T> w = gload(tw, TW_4 + rb + e * 64);
+                        const Tw<T> w = tload_tw<T>(tw, rb, TW_4 + e * 64);
                         vp[e] = mul_tw(vp[e], w);
                         vm[e] = mul_tw(vm[e], w);
                     });
                 }
-                RowM::fwd_local(vp, vm, tw + oz, RRp, RRm, lane, true);
+                RowM::fwd_local(vp, vm, tw + oz * TWB, RRp, RRm, lane, true);
                 // bin k2 = lane + 64 e of row k1 is frequency k1 + R k2
-                const gptr<Cx<T>> pr = prop + (oz + ss.table * 2 * N);
+                const BufView pr = buf_view(prop + ss.table * 2 * N, 2 * N * (uint32_t)sizeof(Cx<T>),
+                                        oz * (int)sizeof(Cx<T>));
                 static_for<0, E>([&](auto e) {
-                    const int f = k1 * C + lane + e * 64;
-                    const Cx<T> kp = gload(pr, f), km = gload(pr, N + f);
+                    const int f = k1 * C + lane;
+                    const Cx<T> kp = tload_cx<T>(pr, f, e * 64), km = tload_cx<T>(pr, f, N + e * 64);
                     const Cx<T> a = vp[e], b = vm[e];
                     vp[e] = {fmaT(kp.x, a.x, fmaT(-kp.y, a.y, a.x * invN)),
                              fmaT(kp.x, a.y, fmaT(kp.y, a.x, a.y * invN))};
@@ -1217,11 +1330,11 @@ struct Staged {
                              fmaT(km.x, b.y, fmaT(km.y, b.x, b.y * invN))};
                 });
                 const int oi = (n + i + rr + 1) & d.opaque_zero;
-                RowM::inv_local(vp, vm, tw + oi, RRp, RRm, lane, true);
+                RowM::inv_local(vp, vm, tw + oi * TWB, RRp, RRm, lane, true);
                 const int rbi = k1 * C + lane + oi;
                 if constexpr (!D3) {
                     static_for<0, E>([&](auto e) {
-                        const Tw<T> w = gload(tw, TW_4 + rbi + e * 64);
+                        const Tw<T> w = tload_tw<T>(tw, rbi, TW_4 + e * 64);
                         vp[e] = mul_tw_inv(vp[e], w);
                         vm[e] = mul_tw_inv(vm[e], w);
                     });
@@ -1239,12 +1352,12 @@ struct Staged {
                 const int c = cr * COLS_PER_ROUND + wv * GPW + gi;
                 Cx<T> vp[E], vm[E];
                 load(vp, vm, st, lc * C + c + oz, LC * C);
-                ColM::inv_local(vp, vm, tw + (TW_COL + oz), CRp, CRm, lc, true);
+                ColM::inv_local(vp, vm, tw + (TW_COL + oz) * TWB, CRp, CRm, lc, true);
                 couple_at(cpl, vp, vm, d, n, lc, c, ss);
                 if (!last) {
                     if (step_end && lead) couple_at(cpl, vp, vm, d, n + 1, lc, c, scl.sub[0]);
                     const int of = (n + i + cr + 1) & d.opaque_zero;
-                    ColM::fwd_local(vp, vm, tw + (TW_COL + of), CRp, CRm, lc, true);
+                    ColM::fwd_local(vp, vm, tw + (TW_COL + of) * TWB, CRp, CRm, lc, true);
                 } else if (rt_out) {
                     det_sums(vp, vm, d, lc * C + c, LC * C, sp, sm);
                 }

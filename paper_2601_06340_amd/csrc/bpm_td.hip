@@ -51,7 +51,7 @@ __global__ __launch_bounds__(64 * kTdWaves) void k_td_assemble(const char *state
         vp[e] = cmul(s[x], c);
         vm[e] = cmul(s[nx + x], c);
     });
-    MF::fwd_local(vp, vm, to_global<Tw<T>>(tw), R, R, lane, true);
+    MF::fwd_local(vp, vm, buf_view(tw, MF::TW_ENTRIES * (uint32_t)sizeof(Tw<T>)), R, R, lane, true);
     static_for<0, E>([&](auto e) {
         const int k = lane + 64 * CV(e);
         out[(size_t)x * MM + k] = vp[e];
