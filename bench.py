@@ -93,6 +93,33 @@ def time_batch(bpm, torch, cases, steps, warmup):
     return per, total_ms, wall, Rs
 
 
+def time_single(bpm, torch, case, steps, warmup):
+    """One solve through the single-solve entry point (bpm_propagate_device):
+    staged sizes and 3D envelopes spread over the whole device."""
+    p, psi = case
+    plan = bpm.Plan(p)
+    one = bpm.Batch([plan])   # packs the entrance state
+    d_in = one.pack([(psi, None)])
+    d_out = torch.empty_like(d_in)
+    rt = torch.zeros(2, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    sid = stream.cuda_stream
+    for _ in range(warmup):
+        plan.propagate_device(d_in.data_ptr(), d_out.data_ptr(), rt.data_ptr(), sid)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for k in range(steps):
+        plan.propagate_device(d_in.data_ptr(), d_out.data_ptr(), rt.data_ptr(), sid)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    one.close()
+    plan.close()
+    ms = sum(per) / len(per)
+    return {"ms": ms, "value": cell_steps(p) / (ms / 1e3)}
+
+
 def fp64_plain(bpm, torch, synth):
     """One FP64 solve alone on the GPU (the flat Bragg case: Nx 4096, Nz 2000)."""
     p, psi = synth.flat_bragg_scan(n_angles=1, precision="f64")[0]
@@ -286,14 +313,26 @@ def main():
                      "one mixed-size launch")
     if "3d" in want:
         cube = [synth.cube_3d(seed=synth.SEED_BASE + 5 + k) for k in range(256)]
-        one = leg_batch(bpm, torch, cube[:1], "3d single", steps=1, warmup=1)
+        print("leg 3d single (wide lane)", file=sys.stderr, flush=True)
+        wide = time_single(bpm, torch, cube[0], steps=3, warmup=1)
+        one = leg_batch(bpm, torch, cube[:1], "3d single, one workgroup", steps=1, warmup=1)
         many = leg_batch(bpm, torch, cube, "3d batch", steps=1, warmup=1)
         legs["paper_3d"] = {
             "workload": "3D envelopes 512 x 256 x 300 steps (the paper's 300 x 200 x 300 3D case padded to "
                         "powers of two), 10 um cube with an edge dislocation, FP32",
-            "single_solve_ms": one["ms_per_step"], "single_value": one["value"],
+            "single_solve_ms": wide["ms"], "single_value": wide["value"],
+            "single_one_workgroup_ms": one["ms_per_step"],
             "batch_solves": many["solves"], "value": many["value"], "unit": "cell-steps/s",
             "paper_context": "about 13 s per realization on a Perlmutter node (Python package; CPU or GPU not stated)"}
+        print("leg single large solves (wide lane)", file=sys.stderr, flush=True)
+        big = {}
+        for prec in ("f32", "f64"):
+            case = synth.flat_bragg_scan(n_angles=1, nx=65536, nz=2000, precision=prec)[0]
+            big[prec] = time_single(bpm, torch, case, steps=2, warmup=1)
+        legs["single_large"] = {
+            "workload": "one flat-Bragg solve Nx 65536 x Nz 2000 alone through bpm_propagate_device (wide lane)",
+            "f32_ms": big["f32"]["ms"], "f32_value": big["f32"]["value"],
+            "f64_ms": big["f64"]["ms"], "f64_value": big["f64"]["value"], "unit": "cell-steps/s"}
     if "cfg4" in want:
         legs["cfg4_serving"] = dict(
             leg_serve(bpm, synth, args.serve_requests, args.serve_rate, args.serve_budget_gb, args.serve_chunk),

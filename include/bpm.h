@@ -149,7 +149,16 @@ bpm_status bpm_propagate(bpm_plan *plan, const bpm_complex *psi_p0, const bpm_co
 /* Asynchronous march on device buffers owned by the caller, enqueued on
  * `stream` (a hipStream_t; NULL = default stream).  d_in and d_out each hold
  * one solve's state (psi+ then psi-, plan precision); they may be equal.
- * d_RT receives R, T (2 doubles) or may be NULL. */
+ * d_RT receives R, T (2 doubles) or may be NULL.
+ * A plan of a staged size (FP32 nx >= 32768, FP64 nx >= 16384) or of 3D
+ * envelopes marched this way (and by bpm_propagate) is spread over the whole
+ * device: per coupling sub-step one launch over its rows and one over its
+ * columns, z-steps replayed from a recorded graph of 32 steps (recorded on the
+ * first call with nz >= 32).  Its envelopes equal a batch's one-workgroup march
+ * bitwise; R and T are the same sums grouped per workgroup.  The plan keeps the
+ * march's control block and partial sums, so calls on one plan must not
+ * overlap (a plan is single-threaded); to march many solves at once use a
+ * batch. */
 bpm_status bpm_propagate_device(bpm_plan *plan, void *stream, const void *d_in, void *d_out,
                                 double *d_RT);
 

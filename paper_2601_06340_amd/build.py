@@ -62,13 +62,17 @@ def _gen_units() -> list[str]:
                 write("march_staged_%s_%d_sc%d.hip" % (t, l2, sc),
                       '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
                       "template hipError_t launch_staged<%s, %d, %d>(const SolveDesc *, int, const char *, "
-                      "char *, double *, hipStream_t);\n}\n" % (t, l2, sc))
+                      "char *, double *, hipStream_t);\n"
+                      "template hipError_t launch_wide_T<%s, %d, %d, false>(int, const WideArgs &, hipStream_t, "
+                      "WideShape *);\n}\n" % (t, l2, sc, t, l2, sc))
         for t in MIXED:
             for l2y in THREE_D_LOG2NY:
                 write("march_3d_%s_%d_sc%d.hip" % (t, l2y, sc),
                       '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
                       "template hipError_t launch_3d<%s, %d, %d>(const SolveDesc *, int, const char *, char *, "
-                      "double *, hipStream_t);\n}\n" % (t, l2y, sc))
+                      "double *, hipStream_t);\n"
+                      "template hipError_t launch_wide_T<%s, %d, %d, true>(int, const WideArgs &, hipStream_t, "
+                      "WideShape *);\n}\n" % (t, l2y, sc, t, 9 + l2y, sc))
             write("march_mixed_%s_sc%d.hip" % (t, sc),
                   '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
                   "template hipError_t launch_mixed<%s, %d>(const SolveDesc *, int, const char *, char *, "

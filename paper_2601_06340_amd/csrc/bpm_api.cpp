@@ -296,6 +296,14 @@ void bpm_plan::release()
     (void)hipFree(d_desc1);
     (void)hipFree(d_state);
     (void)hipFree(d_rt);
+    if (wide_exec) (void)hipGraphExecDestroy(wide_exec);
+    if (wide_graph) (void)hipGraphDestroy(wide_graph);
+    (void)hipFree(d_wide_ctl);
+    (void)hipFree(d_wide_part);
+    wide_exec = nullptr;
+    wide_graph = nullptr;
+    d_wide_ctl = nullptr;
+    d_wide_part = nullptr;
     d_sc = nullptr;
     d_params = nullptr;
     d_prop = d_utab = d_state = nullptr;
@@ -442,6 +450,19 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
     if (p->log2ny) march_shape_3d(prec, p->log2ny, &p->threads, &p->lds_bytes);
     else march_shape(prec, p->log2n, &p->threads, &p->lds_bytes);
 
+    // wide lane of a staged size or 3D solve marched alone
+    if (wide_kind(prec, p->launch_kind)) {
+        WideShape sh{};
+        const WideArgs none{};
+        if ((e = launch_wide(prec, p->launch_kind, strain_class(d->strain.kind), -1, none, ss, &sh)) != hipSuccess)
+            return bail(hip_fail(e, "wide lane shape"));
+        p->wide_blocks = sh.col_blocks;
+        if ((st = dev_alloc((void **)&p->d_wide_ctl, sizeof(WideCtl), "wide control block")) != BPM_OK) return bail(st);
+        if ((st = dev_alloc((void **)&p->d_wide_part, 3 * sizeof(double) * sh.col_blocks, "wide partial sums")) !=
+            BPM_OK)
+            return bail(st);
+    }
+
     // single-solve launch descriptor (state at offset 0, R/T at index 0)
     SolveDesc s;
     p->fill(s, log2e, p->tw_uniform, SF_FIRST | SF_LAST, 0, d->nz, 0, 0, 0);
@@ -480,9 +501,77 @@ extern "C" int32_t bpm_max_nx(int32_t precision)
     return 1 << max_log2n(precision);
 }
 
+// ---- wide lane: one staged-size or 3D solve over the whole device
+constexpr int kWideGraphSteps = 32;   // z-steps per recorded graph
+
+// the launches of z-step base + k (every sub-step: row phase, column phase)
+static hipError_t wide_step(const bpm_plan *p, int k, hipStream_t s)
+{
+    double a[kMaxSub], b[kMaxSub];
+    const int nsub = split_sequence(p->desc.split_order <= 1 ? 1 : p->desc.split_order, a, b);
+    const bool lead = a[0] == 0.0;   // sub-step 0 couples before any propagation (entry / previous step)
+    const int prec = p->desc.precision, sc = strain_class(p->desc.strain.kind);
+    hipError_t e = hipSuccess;
+    for (int i = lead ? 1 : 0; i < nsub && e == hipSuccess; ++i) {
+        const WideArgs w{p->d_desc1, p->d_wide_ctl, k, i, p->d_wide_part};
+        e = launch_wide(prec, p->launch_kind, sc, WIDE_ROWS, w, s, nullptr);
+        if (e == hipSuccess) e = launch_wide(prec, p->launch_kind, sc, WIDE_COLS, w, s, nullptr);
+    }
+    return e;
+}
+
+// Record kWideGraphSteps z-steps as one graph (once per plan); without a
+// graph the steps are launched one by one.
+static void wide_record(bpm_plan *p)
+{
+    p->wide_tried = true;
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int k = 0; k < kWideGraphSteps && e == hipSuccess; ++k) e = wide_step(p, k, cs);
+        const hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e2;
+    }
+    hipGraphExec_t x = nullptr;
+    if (e == hipSuccess && g) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e == hipSuccess && x) {
+        p->wide_graph = g;
+        p->wide_exec = x;
+    } else if (g) {
+        (void)hipGraphDestroy(g);
+    }
+    (void)hipGetLastError();
+    (void)hipStreamDestroy(cs);
+}
+
+static bpm_status propagate_wide(bpm_plan *p, hipStream_t s, const char *in, char *out, double *rt)
+{
+    const int prec = p->desc.precision, sc = strain_class(p->desc.strain.kind), nz = p->desc.nz;
+    if (!p->wide_tried && nz >= kWideGraphSteps) wide_record(p);
+    const WideArgs w{p->d_desc1, p->d_wide_ctl, 0, 0, p->d_wide_part};
+    hipError_t e = launch_wide_ctl(p->d_wide_ctl, 0, in, out, s);
+    if (e == hipSuccess) e = launch_wide(prec, p->launch_kind, sc, WIDE_ENTRY, w, s, nullptr);
+    int n = 0;
+    for (; e == hipSuccess && p->wide_exec && n + kWideGraphSteps <= nz; n += kWideGraphSteps) {
+        if (n > 0) e = launch_wide_ctl(p->d_wide_ctl, n, in, out, s);
+        if (e == hipSuccess) e = hipGraphLaunch(p->wide_exec, s);
+    }
+    for (; e == hipSuccess && n < nz; ++n) {
+        e = launch_wide_ctl(p->d_wide_ctl, n, in, out, s);
+        if (e == hipSuccess) e = wide_step(p, 0, s);
+    }
+    if (e == hipSuccess) e = launch_wide_finish(p->d_desc1, p->d_wide_part, p->wide_blocks, rt, s);
+    if (e != hipSuccess) return hip_fail(e, "wide march launch");
+    return BPM_OK;
+}
+
 extern "C" bpm_status bpm_propagate_device(bpm_plan *p, void *stream, const void *d_in, void *d_out, double *d_RT)
 {
     if (!p || !d_in || !d_out) return fail(BPM_E_INVALID, "NULL argument");
+    if (p->d_wide_ctl)
+        return propagate_wide(p, (hipStream_t)stream, (const char *)d_in, (char *)d_out, d_RT ? d_RT : p->d_rt);
     hipError_t e = launch_march(p->d_desc1, 1, p->desc.precision, p->launch_kind, strain_class(p->desc.strain.kind),
                                 (const char *)d_in, (char *)d_out,
                                 d_RT ? d_RT : p->d_rt, (hipStream_t)stream);

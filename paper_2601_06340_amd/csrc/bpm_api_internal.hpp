@@ -29,6 +29,14 @@ struct bpm_plan {
     double far_um = 0.0;
     int log2ny = 0;              // 3D envelopes: log2(ny), else 0
     int launch_kind = 0;         // launch_march's size argument for this plan alone
+    // wide lane (staged sizes and 3D marched alone): control block, partial
+    // sums, and a recorded graph of kWideGraphSteps z-steps
+    bpm::WideCtl *d_wide_ctl = nullptr;
+    double *d_wide_part = nullptr;
+    int wide_blocks = 0;         // column-phase workgroups (partial sums)
+    hipGraph_t wide_graph = nullptr;
+    hipGraphExec_t wide_exec = nullptr;
+    bool wide_tried = false;     // graph recording attempted
 
     size_t cells() const { return (size_t)desc.nx * (log2ny ? (size_t)1 << log2ny : 1); }
     size_t rows() const { return (size_t)desc.nz * (log2ny ? (size_t)1 << log2ny : 1); }

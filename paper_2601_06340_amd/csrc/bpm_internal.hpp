@@ -131,6 +131,33 @@ constexpr int staged_log2e(int prec) { return 3; }
 constexpr int staged_log2c(int prec) { return 6 + staged_log2e(prec); }
 constexpr int staged_log2th(int prec) { return prec == 1 ? 10 : 9; }
 
+// Wide lane: one staged-size or 3D solve spread over the device, two launches
+// (row phase, column phase) per coupling sub-step.  The control block carries
+// what changes from call to call, so recorded step graphs stay valid.
+struct WideCtl {
+    int32_t base, pad;   // z-step of the graph's step k = 0
+    const char *in;      // entrance state (entry phase)
+    char *out;           // the solve's state
+};
+enum WidePhase { WIDE_ENTRY = 0, WIDE_ROWS = 1, WIDE_COLS = 2 };
+struct WideArgs {
+    const SolveDesc *desc;   // one descriptor (state at in/out offsets of the control block's buffers)
+    const WideCtl *ctl;
+    int k, i;                // step base + k, sub-step i
+    double *part;            // [3][blocks] partial sums: incident power, |psi+|^2, |psi-|^2
+};
+struct WideShape {
+    int row_blocks, col_blocks;
+    size_t lds_bytes;
+};
+// launch one phase of a wide march (kind: log2 nx of a staged size or
+// kLaunch3D + log2 ny); shape (may be NULL) receives the grid sizes
+hipError_t launch_wide(int prec, int kind, int sc, int phase, const WideArgs &a, hipStream_t s, WideShape *shape);
+hipError_t launch_wide_finish(const SolveDesc *desc, const double *part, int nblk, double *rt, hipStream_t s);
+hipError_t launch_wide_ctl(WideCtl *ctl, int base, const char *in, char *out, hipStream_t s);
+// does a plan of this kind have a wide form
+bool wide_kind(int prec, int kind);
+
 // Elements per thread (log2) used for a given nx by the uniform-size kernels.
 constexpr int uniform_log2e(int log2n) { return log2n >= 8 ? 4 : (log2n >= 7 ? 3 : 2); }
 

@@ -1242,127 +1242,159 @@ struct Staged {
         else cpl.template apply<E, LC * C>(vp, vm, d, n, lc * C + c, ss);
     }
 
+    // Per-wave view of one solve: buffers, this wave's LDS slab, its column
+    // (gi) and lane within the column (lc), and the coupling context.
+    struct Ctx {
+        BufView in, st, tw;
+        const Cx<T> *prop;
+        Cx<T> *CRp, *CRm, *RRp, *RRm;
+        Coupler<T, SC> cpl;
+        int lane, gi, lc;
+        T invN;
+        const PlanScalars *scl;
+        bool lead;   // sub-step 0 is a leading coupling (no propagation before it)
+
+        __device__ __forceinline__ void init(const SolveDesc &d, const char *in_base, char *out_base, Cx<T> *slab,
+                                             int lane_)
+        {
+            constexpr uint32_t SB = 2 * N * (uint32_t)sizeof(Cx<T>);
+            in = buf_view(in_base + d.in_off, SB);
+            st = buf_view(out_base + d.out_off, SB);   // the solve's state [2][N]
+            tw = buf_view(d.tw, TW_TOTAL * (uint32_t)sizeof(Tw<T>));
+            prop = reinterpret_cast<const Cx<T> *>(d.prop);
+            lane = lane_;
+            gi = lane / LC;
+            lc = lane % LC;
+            CRp = slab + gi * (ColM::BX * ColM::BUFM);
+            CRm = CRp + (ColM::BX == 2 ? ColM::BUFM : 0);
+            RRp = slab;
+            RRm = slab + (RowM::BX == 2 ? RowM::BUFM : 0);
+            cpl.template init<LC * C>(d, D3 ? C : N);
+            invN = (T)(1.0 / (double)N);
+            scl = d.sc;
+            lead = scl->sub[0].table < 0;
+        }
+    };
+    static constexpr int TWB = (int)sizeof(Tw<T>);
+
+    // Entry of column c (this wave's group of lanes): natural-order samples in,
+    // the incident power, a leading coupling, the forward column DFT, state out
+    // as Y (with no z-step to run, the detector sums of the entrance state).
+    static __device__ __forceinline__ void entry_col(const Ctx &x, const SolveDesc &d, int c, int oz, bool rt_out,
+                                                     double &pin_part, double &sp, double &sm)
+    {
+        Cx<T> vp[E], vm[E];
+        load(vp, vm, x.in, x.lc * C + c, LC * C);
+        if (d.flags & SF_FIRST) {
+            static_for<0, E>([&](auto e) {
+                const double a = (double)vp[e].x, b = (double)vp[e].y;
+                pin_part = __builtin_fma(a, a, __builtin_fma(b, b, pin_part));
+            });
+        }
+        if (d.nsteps > 0) {
+            if (x.lead) couple_at(x.cpl, vp, vm, d, d.step0, x.lc, c, x.scl->sub[0]);
+            ColM::fwd_local(vp, vm, x.tw + (TW_COL + oz) * TWB, x.CRp, x.CRm, x.lc, true);
+        } else if (rt_out) {
+            det_sums(vp, vm, d, x.lc * C + c, LC * C, sp, sm);
+        }
+        store(x.st, vp, vm, x.lc * C + c, LC * C);
+    }
+
+    // Row phase of row k1 (one wave): propagation in Fourier space of sub-step
+    // ss (Eq. (12)-(13)); oz, oi are opaque zeros.
+    static __device__ __forceinline__ void row(const Ctx &x, const SubStep &ss, int k1, int oz, int oi)
+    {
+        const int rb = k1 * C + x.lane + oz;
+        Cx<T> vp[E], vm[E];
+        load(vp, vm, x.st, rb, 64);
+        if constexpr (!D3) {
+            static_for<0, E>([&](auto e) {
+                const Tw<T> w = tload_tw<T>(x.tw, rb, TW_4 + e * 64);
+                vp[e] = mul_tw(vp[e], w);
+                vm[e] = mul_tw(vm[e], w);
+            });
+        }
+        RowM::fwd_local(vp, vm, x.tw + oz * TWB, x.RRp, x.RRm, x.lane, true);
+        // bin k2 = lane + 64 e of row k1 is frequency k1 + R k2
+        const BufView pr = buf_view(x.prop + ss.table * 2 * N, 2 * N * (uint32_t)sizeof(Cx<T>),
+                                    oz * (int)sizeof(Cx<T>));
+        const T invN = x.invN;
+        static_for<0, E>([&](auto e) {
+            const int f = k1 * C + x.lane;
+            const Cx<T> kp = tload_cx<T>(pr, f, e * 64), km = tload_cx<T>(pr, f, N + e * 64);
+            const Cx<T> a = vp[e], b = vm[e];
+            vp[e] = {fmaT(kp.x, a.x, fmaT(-kp.y, a.y, a.x * invN)), fmaT(kp.x, a.y, fmaT(kp.y, a.x, a.y * invN))};
+            vm[e] = {fmaT(km.x, b.x, fmaT(-km.y, b.y, b.x * invN)), fmaT(km.x, b.y, fmaT(km.y, b.x, b.y * invN))};
+        });
+        RowM::inv_local(vp, vm, x.tw + oi * TWB, x.RRp, x.RRm, x.lane, true);
+        const int rbi = k1 * C + x.lane + oi;
+        if constexpr (!D3) {
+            static_for<0, E>([&](auto e) {
+                const Tw<T> w = tload_tw<T>(x.tw, rbi, TW_4 + e * 64);
+                vp[e] = mul_tw_inv(vp[e], w);
+                vm[e] = mul_tw_inv(vm[e], w);
+            });
+        }
+        store(x.st, vp, vm, rb - oz, 64);
+    }
+
+    // Column phase of column c for sub-step i of z-step n: inverse column DFT,
+    // coupling (Eq. (9)-(13)), then, unless the march ends here, the next step's
+    // leading coupling and forward column DFT; at the end the detector sums.
+    static __device__ __forceinline__ void col(const Ctx &x, const SolveDesc &d, int n, int i, int c, int oz,
+                                               int of, bool rt_out, double &sp, double &sm)
+    {
+        const int nsub = x.scl->nsub;
+        const bool step_end = i + 1 == nsub;
+        const bool last = step_end && n + 1 == d.step0 + d.nsteps;
+        Cx<T> vp[E], vm[E];
+        load(vp, vm, x.st, x.lc * C + c + oz, LC * C);
+        ColM::inv_local(vp, vm, x.tw + (TW_COL + oz) * TWB, x.CRp, x.CRm, x.lc, true);
+        couple_at(x.cpl, vp, vm, d, n, x.lc, c, x.scl->sub[i]);
+        if (!last) {
+            if (step_end && x.lead) couple_at(x.cpl, vp, vm, d, n + 1, x.lc, c, x.scl->sub[0]);
+            ColM::fwd_local(vp, vm, x.tw + (TW_COL + of) * TWB, x.CRp, x.CRm, x.lc, true);
+        } else if (rt_out) {
+            det_sums(vp, vm, d, x.lc * C + c, LC * C, sp, sm);
+        }
+        store(x.st, vp, vm, x.lc * C + c, LC * C);
+    }
+
+    // One workgroup marches the solve: entry, then per sub-step the row phase
+    // and the column phase, separated by workgroup barriers.
     static __device__ void run(const SolveDesc &d, const char *in_base, char *out_base, double *rt,
                                Cx<T> *lds, double *red)
     {
         const int t0 = threadIdx.x;
-        constexpr uint32_t SB = 2 * N * (uint32_t)sizeof(Cx<T>);
-        const BufView in = buf_view(in_base + d.in_off, SB);
-        const BufView st = buf_view(out_base + d.out_off, SB);   // the solve's state [2][N]
-        const BufView tw = buf_view(d.tw, TW_TOTAL * (uint32_t)sizeof(Tw<T>));
-        const Cx<T> *prop = reinterpret_cast<const Cx<T> *>(d.prop);
-        constexpr int TWB = (int)sizeof(Tw<T>);
-        const int wv = t0 >> 6, lane = t0 & 63;
-        Cx<T> *slab = lds + wv * SLAB;
-        const int gi = lane / LC, lc = lane % LC;    // column within the wave, lane within the column
-        Cx<T> *CRp = slab + gi * (ColM::BX * ColM::BUFM);
-        Cx<T> *CRm = CRp + (ColM::BX == 2 ? ColM::BUFM : 0);
-        Cx<T> *RRp = slab;
-        Cx<T> *RRm = slab + (RowM::BX == 2 ? RowM::BUFM : 0);
-        Coupler<T, SC> cpl;
-        cpl.template init<LC * C>(d, D3 ? C : N);
-        const T invN = (T)(1.0 / (double)N);
+        const int wv = t0 >> 6;
+        Ctx x;
+        x.init(d, in_base, out_base, lds + wv * SLAB, t0 & 63);
         const int nend = d.step0 + d.nsteps;
         const bool rt_out = (d.flags & SF_LAST) && d.rt_index >= 0;
         double sp = 0.0, sm = 0.0, pin_part = 0.0;
-        // splitting of a z-step: sub-step 0 may be a leading coupling with no
-        // propagation before it; it runs in the column phase that precedes the step
-        const PlanScalars &scl = *d.sc;
-        const int nsub = scl.nsub;
-        const bool lead = scl.sub[0].table < 0;
 
-        // ---- entry: natural-order x -> forward column DFTs -> Y
 #pragma unroll 1
-        for (int cr = 0; cr < COL_ROUNDS; ++cr) {
-            const int c = cr * COLS_PER_ROUND + wv * GPW + gi;
-            Cx<T> vp[E], vm[E];
-            load(vp, vm, in, lc * C + c, LC * C);
-            if (d.flags & SF_FIRST) {
-                static_for<0, E>([&](auto e) {
-                    const double x = (double)vp[e].x, y = (double)vp[e].y;
-                    pin_part = __builtin_fma(x, x, __builtin_fma(y, y, pin_part));
-                });
-            }
-            if (d.nsteps > 0) {
-                if (lead) couple_at(cpl, vp, vm, d, d.step0, lc, c, scl.sub[0]);
-                ColM::fwd_local(vp, vm, tw + (TW_COL + (cr & d.opaque_zero)) * TWB, CRp, CRm, lc, true);
-            } else if (rt_out) {
-                det_sums(vp, vm, d, lc * C + c, LC * C, sp, sm);
-            }
-            store(st, vp, vm, lc * C + c, LC * C);
-        }
+        for (int cr = 0; cr < COL_ROUNDS; ++cr)
+            entry_col(x, d, cr * COLS_PER_ROUND + wv * GPW + x.gi, cr & d.opaque_zero, rt_out, pin_part, sp, sm);
         double pin = 0.0;
         if (d.flags & SF_FIRST) {
             pin = RowM::block_sum(pin_part, red, t0);
             if (t0 == 0 && d.pin) *d.pin = pin;
         }
 
+        const int nsub = x.scl->nsub;
         for (int n = d.step0; n < nend; ++n)
-        for (int i = lead ? 1 : 0; i < nsub; ++i) {
-            const SubStep &ss = scl.sub[i];
+        for (int i = x.lead ? 1 : 0; i < nsub; ++i) {
+            const SubStep &ss = x.scl->sub[i];
             __syncthreads();
-            // ---- row phase: propagation in Fourier space (Eq. (12)-(13))
 #pragma unroll 1
-            for (int rr = 0; rr < ROW_ROUNDS; ++rr) {
-                const int oz = (n + i + rr) & d.opaque_zero;
-                const int k1 = rr * WAVES + wv;
-                const int rb = k1 * C + lane + oz;
-                Cx<T> vp[E], vm[E];
-                load(vp, vm, st, rb, 64);
-                if constexpr (!D3) {
-                    static_for<0, E>([&](auto e) {
-                        const Tw<T> w = tload_tw<T>(tw, rb, TW_4 + e * 64);
-                        vp[e] = mul_tw(vp[e], w);
-                        vm[e] = mul_tw(vm[e], w);
-                    });
-                }
-                RowM::fwd_local(vp, vm, tw + oz * TWB, RRp, RRm, lane, true);
-                // bin k2 = lane + 64 e of row k1 is frequency k1 + R k2
-                const BufView pr = buf_view(prop + ss.table * 2 * N, 2 * N * (uint32_t)sizeof(Cx<T>),
-                                        oz * (int)sizeof(Cx<T>));
-                static_for<0, E>([&](auto e) {
-                    const int f = k1 * C + lane;
-                    const Cx<T> kp = tload_cx<T>(pr, f, e * 64), km = tload_cx<T>(pr, f, N + e * 64);
-                    const Cx<T> a = vp[e], b = vm[e];
-                    vp[e] = {fmaT(kp.x, a.x, fmaT(-kp.y, a.y, a.x * invN)),
-                             fmaT(kp.x, a.y, fmaT(kp.y, a.x, a.y * invN))};
-                    vm[e] = {fmaT(km.x, b.x, fmaT(-km.y, b.y, b.x * invN)),
-                             fmaT(km.x, b.y, fmaT(km.y, b.x, b.y * invN))};
-                });
-                const int oi = (n + i + rr + 1) & d.opaque_zero;
-                RowM::inv_local(vp, vm, tw + oi * TWB, RRp, RRm, lane, true);
-                const int rbi = k1 * C + lane + oi;
-                if constexpr (!D3) {
-                    static_for<0, E>([&](auto e) {
-                        const Tw<T> w = tload_tw<T>(tw, rbi, TW_4 + e * 64);
-                        vp[e] = mul_tw_inv(vp[e], w);
-                        vm[e] = mul_tw_inv(vm[e], w);
-                    });
-                }
-                store(st, vp, vm, rb - oz, 64);
-            }
+            for (int rr = 0; rr < ROW_ROUNDS; ++rr)
+                row(x, ss, rr * WAVES + wv, (n + i + rr) & d.opaque_zero, (n + i + rr + 1) & d.opaque_zero);
             __syncthreads();
-            // ---- column phase: inverse column DFTs, coupling (Eq. (9)-(13)),
-            // then the next step's leading coupling and forward column DFTs
-            const bool step_end = i + 1 == nsub;
-            const bool last = step_end && n + 1 == nend;
 #pragma unroll 1
-            for (int cr = 0; cr < COL_ROUNDS; ++cr) {
-                const int oz = (n + i + cr) & d.opaque_zero;
-                const int c = cr * COLS_PER_ROUND + wv * GPW + gi;
-                Cx<T> vp[E], vm[E];
-                load(vp, vm, st, lc * C + c + oz, LC * C);
-                ColM::inv_local(vp, vm, tw + (TW_COL + oz) * TWB, CRp, CRm, lc, true);
-                couple_at(cpl, vp, vm, d, n, lc, c, ss);
-                if (!last) {
-                    if (step_end && lead) couple_at(cpl, vp, vm, d, n + 1, lc, c, scl.sub[0]);
-                    const int of = (n + i + cr + 1) & d.opaque_zero;
-                    ColM::fwd_local(vp, vm, tw + (TW_COL + of) * TWB, CRp, CRm, lc, true);
-                } else if (rt_out) {
-                    det_sums(vp, vm, d, lc * C + c, LC * C, sp, sm);
-                }
-                store(st, vp, vm, lc * C + c, LC * C);
-            }
+            for (int cr = 0; cr < COL_ROUNDS; ++cr)
+                col(x, d, n, i, cr * COLS_PER_ROUND + wv * GPW + x.gi, (n + i + cr) & d.opaque_zero,
+                    (n + i + cr + 1) & d.opaque_zero, rt_out, sp, sm);
         }
 
         if (rt_out) {

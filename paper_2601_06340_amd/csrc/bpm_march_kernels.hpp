@@ -130,6 +130,101 @@ hipError_t launch_3d(const SolveDesc *d_descs, int n, const char *in_base, char 
     return hipGetLastError();
 }
 
+// ----------------------------------------------------------------- wide lane
+// One staged-size or 3D solve over the whole device.  Every sub-step of a
+// z-step is two launches: the row phase, one 64-thread workgroup per row, and
+// the column phase, one 64-thread workgroup per 64/LC columns; the state stays in
+// the solve's buffer (L2 / last-level cache) between them.  The per-row and
+// per-column arithmetic is the one-workgroup staged march's, so the envelopes
+// agree with it bitwise.  The kernels read the step base and the buffers from a
+// control block, so a recorded graph of steps k = 0..K-1 (z-step base + k)
+// replays for any step and any buffers.
+template <typename T, int LOG2N, int SC, bool D3>
+using Wide = Staged<T, LOG2N, SC, 6, D3>;
+
+template <typename T, int LOG2N, int SC, bool D3>
+__global__ __launch_bounds__(64) void k_wide_entry(const SolveDesc *descs, const WideCtl *ctl, double *part)
+{
+    using S = Wide<T, LOG2N, SC, D3>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SolveDesc &d = descs[0];
+    typename S::Ctx x;
+    x.init(d, ctl->in, ctl->out, reinterpret_cast<Cx<T> *>(smem), threadIdx.x);
+    const bool rt_out = (d.flags & SF_LAST) && d.rt_index >= 0;
+    double pin = 0.0, sp = 0.0, sm = 0.0;
+    S::entry_col(x, d, blockIdx.x * S::COLS_PER_ROUND + x.gi, 0, rt_out, pin, sp, sm);
+    pin = S::RowM::block_sum(pin, nullptr, threadIdx.x);
+    sp = S::RowM::block_sum(sp, nullptr, threadIdx.x);
+    sm = S::RowM::block_sum(sm, nullptr, threadIdx.x);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = pin;
+        part[3 * blockIdx.x + 1] = sp;
+        part[3 * blockIdx.x + 2] = sm;
+    }
+}
+
+template <typename T, int LOG2N, int SC, bool D3>
+__global__ __launch_bounds__(64) void k_wide_rows(const SolveDesc *descs, const WideCtl *ctl, int i)
+{
+    using S = Wide<T, LOG2N, SC, D3>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SolveDesc &d = descs[0];
+    typename S::Ctx x;
+    x.init(d, ctl->out, ctl->out, reinterpret_cast<Cx<T> *>(smem), threadIdx.x);
+    S::row(x, x.scl->sub[i], blockIdx.x, 0, 0);
+}
+
+template <typename T, int LOG2N, int SC, bool D3>
+__global__ __launch_bounds__(64) void k_wide_cols(const SolveDesc *descs, const WideCtl *ctl, int k, int i,
+                                                  double *part)
+{
+    using S = Wide<T, LOG2N, SC, D3>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SolveDesc &d = descs[0];
+    typename S::Ctx x;
+    x.init(d, ctl->out, ctl->out, reinterpret_cast<Cx<T> *>(smem), threadIdx.x);
+    const int n = ctl->base + k;
+    const bool rt_out = (d.flags & SF_LAST) && d.rt_index >= 0;
+    double sp = 0.0, sm = 0.0;
+    S::col(x, d, n, i, blockIdx.x * S::COLS_PER_ROUND + x.gi, 0, 0, rt_out, sp, sm);
+    if (rt_out && i + 1 == x.scl->nsub && n + 1 == d.step0 + d.nsteps) {
+        sp = S::RowM::block_sum(sp, nullptr, threadIdx.x);
+        sm = S::RowM::block_sum(sm, nullptr, threadIdx.x);
+        if (threadIdx.x == 0) {
+            part[3 * blockIdx.x + 1] = sp;
+            part[3 * blockIdx.x + 2] = sm;
+        }
+    }
+}
+
+template <typename T, int LOG2N, int SC, bool D3>
+hipError_t launch_wide_T(int phase, const WideArgs &a, hipStream_t s, WideShape *shape)
+{
+    using S = Wide<T, LOG2N, SC, D3>;
+    if (shape) {
+        shape->row_blocks = S::ROW_ROUNDS;
+        shape->col_blocks = S::COL_ROUNDS;
+        shape->lds_bytes = S::lds_bytes;
+    }
+    const size_t lds = S::lds_bytes;
+    switch (phase) {
+    case WIDE_ENTRY:
+        hipLaunchKernelGGL((k_wide_entry<T, LOG2N, SC, D3>), dim3(S::COL_ROUNDS), dim3(64), lds, s, a.desc, a.ctl,
+                           a.part);
+        break;
+    case WIDE_ROWS:
+        hipLaunchKernelGGL((k_wide_rows<T, LOG2N, SC, D3>), dim3(S::ROW_ROUNDS), dim3(64), lds, s, a.desc, a.ctl, a.i);
+        break;
+    case WIDE_COLS:
+        hipLaunchKernelGGL((k_wide_cols<T, LOG2N, SC, D3>), dim3(S::COL_ROUNDS), dim3(64), lds, s, a.desc, a.ctl, a.k,
+                           a.i, a.part);
+        break;
+    default:
+        return hipSuccess;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 size_t mixed_lds_bytes()
 {

@@ -403,6 +403,91 @@ static hipError_t dispatch(const SolveDesc *d_descs, int n, int uniform_log2n, c
     return err;
 }
 
+// ---- wide lane
+template <typename T, int LOG2N, int SC, bool D3>
+hipError_t launch_wide_T(int, const WideArgs &, hipStream_t, WideShape *);
+
+template <typename T, int SC>
+static hipError_t wide_dispatch(int kind, int phase, const WideArgs &a, hipStream_t s, WideShape *shape)
+{
+    hipError_t err = hipErrorInvalidValue;
+    if (kind >= kLaunch3D) {
+        static_for<k3DLog2NyMin, k3DLog2NyMax + 1>([&](auto l) {
+            if (kind == kLaunch3D + CV(l)) err = launch_wide_T<T, k3DLog2Nx + CV(l), SC, true>(phase, a, s, shape);
+        });
+        return err;
+    }
+    static_for<Limits<T>::stg_lo, Limits<T>::stg_hi + 1>([&](auto l) {
+        if (kind == CV(l)) err = launch_wide_T<T, CV(l), SC, false>(phase, a, s, shape);
+    });
+    return err;
+}
+
+template <typename T>
+static hipError_t wide_dispatch_sc(int kind, int sc, int phase, const WideArgs &a, hipStream_t s, WideShape *shape)
+{
+    if (sc == SC_NONE) return wide_dispatch<T, SC_NONE>(kind, phase, a, s, shape);
+    if (sc == SC_POLY2) return wide_dispatch<T, SC_POLY2>(kind, phase, a, s, shape);
+    return wide_dispatch<T, SC_GENERAL>(kind, phase, a, s, shape);
+}
+
+hipError_t launch_wide(int prec, int kind, int sc, int phase, const WideArgs &a, hipStream_t s, WideShape *shape)
+{
+    if (prec == PREC_F32) return wide_dispatch_sc<float>(kind, sc, phase, a, s, shape);
+    return wide_dispatch_sc<double>(kind, sc, phase, a, s, shape);
+}
+
+bool wide_kind(int prec, int kind)
+{
+    if (kind >= kLaunch3D) return kind - kLaunch3D >= k3DLog2NyMin && kind - kLaunch3D <= k3DLog2NyMax;
+    if (prec == PREC_F32) return kind >= Limits<float>::stg_lo && kind <= Limits<float>::stg_hi;
+    return kind >= Limits<double>::stg_lo && kind <= Limits<double>::stg_hi;
+}
+
+// R and T of a wide march from its per-workgroup partial sums, summed in
+// workgroup order in FP64; the incident power is stored when the march began.
+__global__ void k_wide_finish(const SolveDesc *descs, const double *part, int nblk, double *rt)
+{
+    if (threadIdx.x != 0) return;
+    const SolveDesc &d = descs[0];
+    double pin = 0.0, sp = 0.0, sm = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        pin += part[3 * b];
+        sp += part[3 * b + 1];
+        sm += part[3 * b + 2];
+    }
+    if (d.flags & SF_FIRST) {
+        if (d.pin) *d.pin = pin;
+    } else {
+        pin = d.pin ? *d.pin : 0.0;
+    }
+    if ((d.flags & SF_LAST) && d.rt_index >= 0) {
+        rt[2 * d.rt_index] = pin > 0.0 ? sm / pin : 0.0;
+        rt[2 * d.rt_index + 1] = pin > 0.0 ? sp / pin : 0.0;
+    }
+}
+
+__global__ void k_wide_ctl(WideCtl *ctl, int base, const char *in, char *out)
+{
+    if (threadIdx.x == 0) {
+        ctl->base = base;
+        ctl->in = in;
+        ctl->out = out;
+    }
+}
+
+hipError_t launch_wide_finish(const SolveDesc *desc, const double *part, int nblk, double *rt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_wide_finish, dim3(1), dim3(64), 0, s, desc, part, nblk, rt);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_ctl(WideCtl *ctl, int base, const char *in, char *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_wide_ctl, dim3(1), dim3(64), 0, s, ctl, base, in, out);
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t dispatch_sc(const SolveDesc *d_descs, int n, int uniform_log2n, int sc, const char *in_base,
                               char *out_base, double *rt, hipStream_t s)

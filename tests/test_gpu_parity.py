@@ -16,6 +16,10 @@ from paper_2601_06340_amd import synth
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": (1e-10, 1e-12), "f32": (1e-4, 1e-5)}
+# R and T of the same envelopes summed in two groupings (per thread vs per
+# workgroup): FP64 sums of n <= 2^18 non-negative terms, whose rounding-order
+# differences are of order sqrt(n) 2^-53 ~ 6e-14
+SUM_ORDER_RTOL = 1e-13
 
 
 def bpm():
@@ -350,7 +354,8 @@ def test_staged_sizes_in_batch_and_chunked_server_equal_single_solves():
         singles.append((sp, sm, sR))
         say("staged batch", i, p["nx"], "bitwise", np.array_equal(outs[i][0], sp))
         assert np.array_equal(outs[i][0], sp) and np.array_equal(outs[i][1], sm)
-        assert rt[2 * i] == sR and rt[2 * i + 1] == sT
+        # a staged size marched alone runs in the wide lane: R, T summed per workgroup
+        assert abs(rt[2 * i] - sR) <= SUM_ORDER_RTOL * abs(sR) and abs(rt[2 * i + 1] - sT) <= SUM_ORDER_RTOL * abs(sT)
     op, om, oR, _ = oracle.propagate(*cases[2])
     assert rel_pair(singles[2][0], singles[2][1], op, om) <= TOL["f32"][0]
     srv = B.Server(hbm_budget_bytes=1 << 30, max_slots=8, chunk_steps=37)
@@ -362,8 +367,104 @@ def test_staged_sizes_in_batch_and_chunked_server_equal_single_solves():
     # the server marches staged sizes in the any-size kernel (512-thread
     # workgroups), a single solve in the staged kernel (1024 threads in FP32):
     # same envelopes, FP64 power sums grouped differently
-    assert abs(r["R"] - singles[0][2]) <= 4e-16 * abs(singles[0][2])
+    assert abs(r["R"] - singles[0][2]) <= SUM_ORDER_RTOL * abs(singles[0][2])
     srv.close()
+
+
+# ------------------------------------------------------------------ wide lane
+def _wide_case(name):
+    """Staged-size and 3D solves for the wide lane: graph blocks of 32 steps plus
+    remainders, every splitting order (order 2 starts with a leading coupling)."""
+    disl = {"kind": "edge_dislocation", "x_ref_um": 25.5, "z_ref_um": 1.2, "b_um": 4 * synth.D_UM, "nu": 0.22}
+    if name == "f32-32768-bent":
+        p, psi = synth.bent_laue(radii_m=(0.7,), nx=32768, nz=70, thickness=4.0, precision="f32")[0]
+        return p, psi, None
+    if name == "f64-16384-bragg-o2":
+        p, psi = synth.flat_bragg_scan(n_angles=1, nx=16384, nz=40, precision="f64")[0]
+        p["split_order"] = 2
+        return p, psi, None
+    if name == "f32-65536-disl-o4":
+        p, psi = synth.disl_bragg(nx=65536, nz=33, scale=0.125, precision="f32")
+        p["split_order"] = 4
+        return p, psi, None
+    if name == "f64-65536-bent-short":
+        p, psi = synth.bent_laue(radii_m=(2.0,), nx=65536, nz=20, thickness=1.0, precision="f64")[0]
+        return p, psi, None
+    if name == "3d-f32-256-disl":
+        p, a, b = _problem3d(256, 40, "f32", strain=disl)
+        return p, a, b
+    if name == "3d-f64-16-o2":
+        p, a, b = _problem3d(16, 35, "f64", order=2)
+        return p, a, b
+    raise KeyError(name)
+
+
+WIDE_CASES = ["f32-32768-bent", "f64-16384-bragg-o2", "f32-65536-disl-o4", "f64-65536-bent-short",
+              "3d-f32-256-disl", "3d-f64-16-o2"]
+
+
+@pytest.mark.parametrize("name", WIDE_CASES)
+def test_wide_lane_matches_one_workgroup_march_and_oracle(name):
+    """A staged-size or 3D solve marched alone spreads over the device (row and
+    column launches, graphs of 32 steps): its envelopes equal the one-workgroup
+    march's bitwise on every call (three calls on fresh buffers with other
+    device work in between replay the recorded graph), and R, T agree to a few
+    ulps (partial sums per workgroup instead of per thread)."""
+    B = bpm()
+    import torch
+    p, a, b = _wide_case(name)
+    say("wide", name, "nx", p["nx"], "ny", p.get("ny", 1), "nz", p["nz"], p["precision"])
+    plan = B.Plan(p)
+    one = B.Batch([plan])
+    buf = one.pack([(a, b)])
+    rt1 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    one.run(buf.data_ptr(), buf.data_ptr(), rt1.data_ptr())
+    torch.cuda.synchronize()
+    ref = one.unpack(buf)[0]
+    rt1 = rt1.cpu().numpy()
+    for rep in range(3):
+        src = one.pack([(a, b)])
+        dst = torch.empty_like(src)
+        rt = torch.zeros(2, dtype=torch.float64, device="cuda")
+        plan.propagate_device(src.data_ptr(), dst.data_ptr(), rt.data_ptr())
+        junk = torch.randn(1 << 20, device="cuda").sum()   # unrelated device work between replays
+        torch.cuda.synchronize()
+        got = one.unpack(dst)[0]
+        rt = rt.cpu().numpy()
+        say("   call", rep, "bitwise", np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]),
+            "R %.17g vs %.17g" % (rt[0], rt1[0]), float(junk) * 0)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+        assert abs(rt[0] - rt1[0]) <= SUM_ORDER_RTOL * abs(rt1[0])
+        assert abs(rt[1] - rt1[1]) <= SUM_ORDER_RTOL * abs(rt1[1])
+    op, om, oR, oT = oracle.propagate(p, a, b)
+    err = rel_pair(got[0], got[1], op, om)
+    tol, rtol = TOL[p["precision"]]
+    say("   oracle rel L2 %.3e  dR %.2e" % (err, abs(rt[0] - oR)))
+    assert err <= tol and abs(rt[0] - oR) <= rtol and abs(rt[1] - oT) <= rtol
+    one.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("name", ["f32-32768-bent", "3d-f64-16-o2"])
+def test_one_workgroup_staged_and_3d_march_matches_oracle(name):
+    """The one-workgroup staged / 3D march (what batches and the server run)
+    against the oracle directly."""
+    B = bpm()
+    import torch
+    p, a, b = _wide_case(name)
+    plan = B.Plan(p)
+    one = B.Batch([plan])
+    buf = one.pack([(a, b)])
+    rt = torch.zeros(2, dtype=torch.float64, device="cuda")
+    one.run(buf.data_ptr(), buf.data_ptr(), rt.data_ptr())
+    torch.cuda.synchronize()
+    got = one.unpack(buf)[0]
+    op, om, oR, _ = oracle.propagate(p, a, b)
+    err = rel_pair(got[0], got[1], op, om)
+    say("one-workgroup", name, "rel L2 %.3e" % err)
+    assert err <= TOL[p["precision"]][0] and abs(rt.cpu().numpy()[0] - oR) <= TOL[p["precision"]][1]
+    one.close()
+    plan.close()
 
 
 # ------------------------------------------------------------------ 3D envelopes
