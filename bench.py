@@ -173,7 +173,8 @@ def leg_serve(bpm, synth, n_req, rate_hz, budget_gb, chunk_steps):
             "p50_ms": q(lat, 0.5), "p99_ms": q(lat, 0.99), "max_ms": lat[-1] if lat else None,
             "value": cs / span if span > 0 else None, "unit": "cell-steps/s",
             "offered": sum(cell_steps(r) for r in reqs) / reqs[-1]["t_arrival"],
-            "launches": stats["launches"], "peak_bytes": stats["peak_bytes"], "chunk_steps": chunk_steps,
+            "launches": stats["launches"], "wide_lane_solves": stats["wide"], "peak_bytes": stats["peak_bytes"],
+            "chunk_steps": chunk_steps,
             "budget_gb": budget_gb}
 
 

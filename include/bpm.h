@@ -212,7 +212,14 @@ bpm_status bpm_td_assemble(bpm_batch *batch, void *stream, const void *d_state, 
  * plans and entrance states of requests admitted in arrival order whose state
  * and tables fit the budget; after it, finished solves are retired and the new
  * ones join the next round.  Per-solve arithmetic does not depend on what else
- * is in the launch, so a result is the same alone and in the mix. */
+ * is in the launch, so a result is the same alone and in the mix.
+ * Long solves of a staged size or 3D envelopes (an estimated one-workgroup march
+ * of more than 0.5 s; at most 4 at a time, and only while at most 64 other
+ * solves are in the rounds: under load the one-workgroup march does more work
+ * per second) are marched in the wide lane of
+ * bpm_propagate_device instead, 2*chunk_steps z-steps per round spread over the
+ * device on a stream of their own; their envelopes are the same bitwise, R and
+ * T the same sums grouped per workgroup. */
 typedef struct bpm_server_desc {
     size_t hbm_budget_bytes;   /* device bytes the server may hold for admitted solves */
     int32_t max_slots;         /* max solves in flight */
@@ -238,6 +245,7 @@ typedef struct bpm_server_stats {
     int64_t launches;
     double cell_steps_done;
     size_t bytes_in_use, peak_bytes;
+    int64_t wide;   /* solves marched in the wide lane (long staged-size / 3D solves, see bpm_server_create) */
 } bpm_server_stats;
 
 bpm_status bpm_server_create(const bpm_server_desc *desc, bpm_server **out);

@@ -78,7 +78,7 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
                 ("cancelled", C.c_int64), ("failed", C.c_int64), ("launches", C.c_int64),
                 ("cell_steps_done", C.c_double), ("bytes_in_use", C.c_size_t),
-                ("peak_bytes", C.c_size_t)]
+                ("peak_bytes", C.c_size_t), ("wide", C.c_int64)]
 
 
 # name -> (restype, argtypes); every entry point declared in include/bpm.h

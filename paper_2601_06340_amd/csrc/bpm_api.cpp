@@ -546,20 +546,21 @@ static void wide_record(bpm_plan *p)
     (void)hipStreamDestroy(cs);
 }
 
-static bpm_status propagate_wide(bpm_plan *p, hipStream_t s, const char *in, char *out, double *rt)
+bpm_status bpm::propagate_wide(bpm_plan *p, hipStream_t s, const char *in, char *out, double *rt, int step0,
+                               int nsteps, int flags)
 {
-    const int prec = p->desc.precision, sc = strain_class(p->desc.strain.kind), nz = p->desc.nz;
-    if (!p->wide_tried && nz >= kWideGraphSteps) wide_record(p);
+    const int prec = p->desc.precision, sc = strain_class(p->desc.strain.kind), end = step0 + nsteps;
+    if (!p->wide_tried && nsteps >= kWideGraphSteps) wide_record(p);
     const WideArgs w{p->d_desc1, p->d_wide_ctl, 0, 0, p->d_wide_part};
-    hipError_t e = launch_wide_ctl(p->d_wide_ctl, 0, in, out, s);
+    hipError_t e = launch_wide_ctl(p->d_wide_ctl, p->d_desc1, step0, in, out, step0, nsteps, flags, s);
     if (e == hipSuccess) e = launch_wide(prec, p->launch_kind, sc, WIDE_ENTRY, w, s, nullptr);
-    int n = 0;
-    for (; e == hipSuccess && p->wide_exec && n + kWideGraphSteps <= nz; n += kWideGraphSteps) {
-        if (n > 0) e = launch_wide_ctl(p->d_wide_ctl, n, in, out, s);
+    int n = step0;
+    for (; e == hipSuccess && p->wide_exec && n + kWideGraphSteps <= end; n += kWideGraphSteps) {
+        if (n > step0) e = launch_wide_ctl(p->d_wide_ctl, p->d_desc1, n, in, out, step0, nsteps, flags, s);
         if (e == hipSuccess) e = hipGraphLaunch(p->wide_exec, s);
     }
-    for (; e == hipSuccess && n < nz; ++n) {
-        e = launch_wide_ctl(p->d_wide_ctl, n, in, out, s);
+    for (; e == hipSuccess && n < end; ++n) {
+        e = launch_wide_ctl(p->d_wide_ctl, p->d_desc1, n, in, out, step0, nsteps, flags, s);
         if (e == hipSuccess) e = wide_step(p, 0, s);
     }
     if (e == hipSuccess) e = launch_wide_finish(p->d_desc1, p->d_wide_part, p->wide_blocks, rt, s);
@@ -571,7 +572,8 @@ extern "C" bpm_status bpm_propagate_device(bpm_plan *p, void *stream, const void
 {
     if (!p || !d_in || !d_out) return fail(BPM_E_INVALID, "NULL argument");
     if (p->d_wide_ctl)
-        return propagate_wide(p, (hipStream_t)stream, (const char *)d_in, (char *)d_out, d_RT ? d_RT : p->d_rt);
+        return propagate_wide(p, (hipStream_t)stream, (const char *)d_in, (char *)d_out, d_RT ? d_RT : p->d_rt, 0,
+                              p->desc.nz, SF_FIRST | SF_LAST);
     hipError_t e = launch_march(p->d_desc1, 1, p->desc.precision, p->launch_kind, strain_class(p->desc.strain.kind),
                                 (const char *)d_in, (char *)d_out,
                                 d_RT ? d_RT : p->d_rt, (hipStream_t)stream);

@@ -57,6 +57,12 @@ bpm_status check_input(const bpm_plan_desc &d, const bpm_complex *a, const bpm_c
 bpm_status twiddle_table(int prec, int log2n, int log2e, const void **out);
 // Library-owned non-blocking stream of the current device for plan setup.
 hipStream_t setup_stream();
+// z-steps [step0, step0 + nsteps) of a plan that has a wide form (p->d_wide_ctl
+// set) over the device, enqueued on s: natural-order state in `in`, out to
+// `out`; flags SF_FIRST (store the incident power) and SF_LAST (R, T to rt,
+// 2 doubles) as for the march kernels.
+bpm_status propagate_wide(bpm_plan *p, hipStream_t s, const char *in, char *out, double *rt, int step0, int nsteps,
+                          int flags);
 
 // One kernel launch over a group of solves.
 struct Launch {

@@ -154,7 +154,9 @@ struct WideShape {
 // kLaunch3D + log2 ny); shape (may be NULL) receives the grid sizes
 hipError_t launch_wide(int prec, int kind, int sc, int phase, const WideArgs &a, hipStream_t s, WideShape *shape);
 hipError_t launch_wide_finish(const SolveDesc *desc, const double *part, int nblk, double *rt, hipStream_t s);
-hipError_t launch_wide_ctl(WideCtl *ctl, int base, const char *in, char *out, hipStream_t s);
+// the control block's step base and buffers, and the descriptor's step range and flags
+hipError_t launch_wide_ctl(WideCtl *ctl, SolveDesc *desc, int base, const char *in, char *out, int step0, int nsteps,
+                           int flags, hipStream_t s);
 // does a plan of this kind have a wide form
 bool wide_kind(int prec, int kind);
 

@@ -9,8 +9,16 @@
 // solves of every size and strain class run side by side on the device; after the
 // round it retires the solves that reached nz, and the requests set up in the
 // meantime join the next round.  A solve's arithmetic is the same kernel and
-// schedule as bpm_propagate, and its state crosses round boundaries through HBM
-// unchanged, so results do not depend on what else is running.
+// schedule whatever else runs, and its state crosses round boundaries through
+// HBM unchanged, so results do not depend on what else is running.
+//
+// Long solves of a staged size or 3D envelopes (estimated one-workgroup march
+// time above kWideMinSeconds; at most kMaxWide at a time, and only while at
+// most kWideMaxRegular other solves march in the rounds) run in the wide lane
+// instead: each round advances them kWideChunkFactor * chunk_steps z-steps
+// spread over the device on a stream of their own, alongside the round's
+// launches, and the round waits for them too.  Their envelopes are the
+// one-workgroup march's bitwise.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,10 +56,28 @@ struct Request {
     void *d_state = nullptr;
     int step = 0;
     int slot = -1;
+    int wide_lane = -1;             // >= 0: marched by the wide lane on this stream of the pool
     // result
     bool done = false;
     bpm_result res{};
 };
+
+constexpr int kMaxWide = 4;              // wide-lane solves at once
+constexpr double kWideMinSeconds = 0.5;  // one-workgroup march time above which a solve goes wide
+constexpr int kWideChunkFactor = 2;      // wide-lane z-steps per round = factor * chunk_steps
+// The wide lane is launch-rate bound: it shortens a long solve's latency when
+// the device has room, but under load the one-workgroup march gets more work
+// done.  A solve goes wide only while at most this many others march in the rounds.
+constexpr int kWideMaxRegular = 64;
+
+// Rough one-workgroup march time of a request: staged-lane rate of one
+// workgroup, about 1e9 cell-steps/s in FP32 and 5e8 in FP64.
+double one_workgroup_seconds(const bpm_plan_desc &d)
+{
+    const double cells = (double)d.nx * (d.ny > 1 ? d.ny : 1);
+    const double pairs = d.split_order == 4 ? 3.0 : 1.0;
+    return 2.0 * cells * d.nz * pairs / (d.precision == BPM_F32 ? 1.0e9 : 5.0e8);
+}
 
 size_t estimate_bytes(const bpm_plan_desc &d)
 {
@@ -87,6 +113,8 @@ struct bpm_server {
     std::map<int, hipStream_t> streams;  // one per precision
     double *d_rt = nullptr;
     std::vector<Launch> launches;
+    hipStream_t wide_streams[kMaxWide] = {};
+    bool wide_busy[kMaxWide] = {};
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
     void run();
@@ -95,6 +123,7 @@ struct bpm_server {
     bpm_status setup(Request &r, std::vector<char> &host);
     void finish(const std::shared_ptr<Request> &r, int status);
     hipStream_t stream_for(int key);
+    int retire(Request &r, int status, const double *rt);
 };
 
 hipStream_t bpm_server::stream_for(int key)
@@ -222,11 +251,38 @@ void bpm_server::run_setup()
     }
 }
 
+// Results of a solve that reached its end (status BPM_OK so far): exit
+// envelopes to the request's buffers, R and T from rt; returns the final status.
+int bpm_server::retire(Request &r, int status, const double *rt)
+{
+    if (status != BPM_OK) return status;
+    const size_t sb = r.plan->state_bytes(), nx = r.plan->cells();
+    if (r.out_p || r.out_m) {
+        std::vector<char> host(sb);
+        if (hipMemcpy(host.data(), r.d_state, sb, hipMemcpyDeviceToHost) != hipSuccess) return BPM_E_DEVICE;
+        for (size_t j = 0; j < nx; ++j) {
+            double v[4];
+            if (r.desc.precision == BPM_F64) {
+                const double *o = (const double *)host.data();
+                v[0] = o[2 * j], v[1] = o[2 * j + 1], v[2] = o[2 * (nx + j)], v[3] = o[2 * (nx + j) + 1];
+            } else {
+                const float *o = (const float *)host.data();
+                v[0] = o[2 * j], v[1] = o[2 * j + 1], v[2] = o[2 * (nx + j)], v[3] = o[2 * (nx + j) + 1];
+            }
+            if (r.out_p) r.out_p[j] = {v[0], v[1]};
+            if (r.out_m) r.out_m[j] = {v[2], v[3]};
+        }
+    }
+    r.res.R = rt[0];
+    r.res.T = rt[1];
+    if (!std::isfinite(r.res.R) || !std::isfinite(r.res.T)) return BPM_E_NUMERIC;
+    return BPM_OK;
+}
+
 // March worker: rounds over every active solve; requests set up by the
 // admission thread join at the start of the next round.
 void bpm_server::run()
 {
-    std::vector<char> host;
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(mu);
@@ -239,16 +295,51 @@ void bpm_server::run()
             }
         }
 
-        // ---- one round: every active solve advances steps_for() z-steps; per
-        // precision one stream and one any-size launch, so solves of every size
-        // and strain class run side by side
-        for (size_t i = 0; i < active.size(); ++i) active[i]->slot = (int)i;
+        // ---- long staged / 3D solves that have not started take a free wide
+        // lane while the device has room
+        int regular = 0;
+        for (auto &r : active) regular += r->wide_lane < 0;
+        for (auto &r : active) {
+            if (r->wide_lane >= 0 || r->step != 0 || !r->plan->d_wide_ctl ||
+                one_workgroup_seconds(r->desc) <= kWideMinSeconds || regular - 1 > kWideMaxRegular)
+                continue;
+            for (int k = 0; k < kMaxWide && r->wide_lane < 0; ++k) {
+                if (wide_busy[k]) continue;
+                if (!wide_streams[k] && hipStreamCreateWithFlags(&wide_streams[k], hipStreamNonBlocking) != hipSuccess) {
+                    wide_streams[k] = nullptr;
+                    continue;
+                }
+                wide_busy[k] = true;
+                r->wide_lane = k;
+                regular--;
+                std::lock_guard<std::mutex> lk(mu);
+                stats.wide++;
+            }
+        }
+
+        // ---- one round: every active solve advances steps_for() z-steps (wide
+        // solves kWideChunkFactor * chunk_steps); per precision one stream and
+        // one any-size launch, so solves of every size and strain class run
+        // side by side, and each wide solve on its own stream
         std::vector<int> adv(active.size(), 0);
         bool ok = true;
+        std::vector<size_t> reg;   // solves of the any-size launches
+        for (size_t i = 0; i < active.size(); ++i) {
+            auto &r = active[i];
+            if (r->wide_lane < 0) {
+                r->slot = (int)reg.size();
+                reg.push_back(i);
+                continue;
+            }
+            adv[i] = std::min(kWideChunkFactor * cfg.chunk_steps, r->desc.nz - r->step);
+            const int fl = (r->step == 0 ? SF_FIRST : 0) | (r->step + adv[i] == r->desc.nz ? SF_LAST : 0);
+            if (propagate_wide(r->plan, wide_streams[r->wide_lane], (const char *)r->d_state, (char *)r->d_state,
+                               r->plan->d_rt, r->step, adv[i], fl) != BPM_OK)
+                ok = false;
+        }
         free_launches(launches);
         std::map<int, std::vector<size_t>> cls;
-        for (size_t i = 0; i < active.size(); ++i)
-            cls[active[i]->desc.precision].push_back(i);
+        for (size_t i : reg) cls[active[i]->desc.precision].push_back(i);
         for (auto &kv : cls) {
             const auto &ids = kv.second;
             const int n = (int)ids.size();
@@ -278,52 +369,41 @@ void bpm_server::run()
         // ---- wait for the round, then retire the solves that reached nz
         for (auto &kv : streams)
             if (hipStreamSynchronize(kv.second) != hipSuccess) ok = false;
-        std::vector<double> rt(2 * active.size());
-        if (ok && hipMemcpy(rt.data(), d_rt, rt.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        for (auto &ws : wide_streams)
+            if (ws && hipStreamSynchronize(ws) != hipSuccess) ok = false;
+        std::vector<double> rt(2 * reg.size());
+        if (!reg.empty() && ok &&
+            hipMemcpy(rt.data(), d_rt, rt.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
             ok = false;
         std::vector<std::shared_ptr<Request>> keep;
         bool freed = false;
         for (size_t i = 0; i < active.size(); ++i) {
             auto &r = active[i];
             const double cells = (double)r->plan->cells();   // before the plan is released
+            const double steps_done = adv[i];
             r->step += adv[i];
-            bool fin = !ok || r->step >= r->desc.nz || r->cancel;
+            const bool fin = !ok || r->step >= r->desc.nz || r->cancel;
             int status = !ok ? BPM_E_DEVICE : (r->cancel && r->step < r->desc.nz ? BPM_E_CANCELLED : BPM_OK);
             if (fin && status == BPM_OK) {
-                const size_t sb = r->plan->state_bytes(), nx = r->plan->cells();
-                if (r->out_p || r->out_m) {
-                    host.resize(sb);
-                    if (hipMemcpy(host.data(), r->d_state, sb, hipMemcpyDeviceToHost) != hipSuccess) {
+                double wrt[2] = {0.0, 0.0};
+                const double *prt = &wrt[0];
+                if (r->wide_lane >= 0) {
+                    if (hipMemcpy(wrt, r->plan->d_rt, sizeof wrt, hipMemcpyDeviceToHost) != hipSuccess)
                         status = BPM_E_DEVICE;
-                    } else {
-                        for (size_t j = 0; j < nx; ++j) {
-                            double v[4];
-                            if (r->desc.precision == BPM_F64) {
-                                const double *o = (const double *)host.data();
-                                v[0] = o[2 * j], v[1] = o[2 * j + 1], v[2] = o[2 * (nx + j)],
-                                v[3] = o[2 * (nx + j) + 1];
-                            } else {
-                                const float *o = (const float *)host.data();
-                                v[0] = o[2 * j], v[1] = o[2 * j + 1], v[2] = o[2 * (nx + j)],
-                                v[3] = o[2 * (nx + j) + 1];
-                            }
-                            if (r->out_p) r->out_p[j] = {v[0], v[1]};
-                            if (r->out_m) r->out_m[j] = {v[2], v[3]};
-                        }
-                    }
+                } else {
+                    prt = &rt[2 * r->slot];
                 }
-                r->res.R = rt[2 * r->slot];
-                r->res.T = rt[2 * r->slot + 1];
-                if (!std::isfinite(r->res.R) || !std::isfinite(r->res.T)) status = BPM_E_NUMERIC;
+                status = retire(*r, status, prt);
             }
             if (fin) {
                 bpm_plan_destroy(r->plan);
                 r->plan = nullptr;
                 (void)hipFree(r->d_state);
                 r->d_state = nullptr;
+                if (r->wide_lane >= 0) wide_busy[r->wide_lane] = false;
             }
             std::lock_guard<std::mutex> lk(mu);
-            stats.cell_steps_done += 2.0 * cells * adv[i];
+            stats.cell_steps_done += 2.0 * cells * steps_done;
             if (fin) {
                 stats.bytes_in_use -= r->need;
                 admitted_slots--;
@@ -475,6 +555,8 @@ extern "C" void bpm_server_destroy(bpm_server *s)
         if (r->plan) bpm_plan_destroy(r->plan);
         (void)hipFree(r->d_state);
     }
+    for (auto &ws : s->wide_streams)
+        if (ws) (void)hipStreamDestroy(ws);
     free_launches(s->launches);
     for (auto &kv : s->streams)
         if (kv.second) (void)hipStreamDestroy(kv.second);

@@ -467,12 +467,16 @@ __global__ void k_wide_finish(const SolveDesc *descs, const double *part, int nb
     }
 }
 
-__global__ void k_wide_ctl(WideCtl *ctl, int base, const char *in, char *out)
+__global__ void k_wide_ctl(WideCtl *ctl, SolveDesc *desc, int base, const char *in, char *out, int step0, int nsteps,
+                           int flags)
 {
     if (threadIdx.x == 0) {
         ctl->base = base;
         ctl->in = in;
         ctl->out = out;
+        desc->step0 = step0;
+        desc->nsteps = nsteps;
+        desc->flags = flags;
     }
 }
 
@@ -482,9 +486,10 @@ hipError_t launch_wide_finish(const SolveDesc *desc, const double *part, int nbl
     return hipGetLastError();
 }
 
-hipError_t launch_wide_ctl(WideCtl *ctl, int base, const char *in, char *out, hipStream_t s)
+hipError_t launch_wide_ctl(WideCtl *ctl, SolveDesc *desc, int base, const char *in, char *out, int step0, int nsteps,
+                           int flags, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_wide_ctl, dim3(1), dim3(64), 0, s, ctl, base, in, out);
+    hipLaunchKernelGGL(k_wide_ctl, dim3(1), dim3(64), 0, s, ctl, desc, base, in, out, step0, nsteps, flags);
     return hipGetLastError();
 }
 

@@ -445,6 +445,38 @@ def test_wide_lane_matches_one_workgroup_march_and_oracle(name):
     plan.close()
 
 
+def test_server_marches_long_staged_solves_in_the_wide_lane():
+    """A long staged-size request (estimated one-workgroup march > 0.5 s) runs in
+    the server's wide lane in chunks of 2*chunk_steps z-steps (graph blocks and
+    remainders, natural order between chunks): its envelopes equal the
+    single-solve march's bitwise; the regular requests beside it still match the
+    oracle."""
+    B = bpm()
+    long_p, long_psi = synth.flat_bragg_scan(n_angles=1, nx=65536, nz=4000, precision="f32")[0]
+    small = [synth.flat_bragg_scan(n_angles=1, nx=2048, nz=300, precision="f32")[0],
+             synth.bent_laue(radii_m=(1.0,), nx=8192, nz=200, thickness=1.0, precision="f64")[0]]
+    plan = B.Plan(long_p)
+    rp, rm, rR, rT = plan.propagate(long_psi)
+    plan.close()
+    srv = B.Server(hbm_budget_bytes=4 << 30, max_slots=8, chunk_steps=300)
+    t_long = srv.submit(long_p, long_psi)
+    t_small = [srv.submit(p, psi) for p, psi in small]
+    assert srv.drain(120.0)
+    st = srv.stats()
+    say("server wide solves", st["wide"], "launches", st["launches"])
+    assert st["wide"] == 1 and st["completed"] == 3
+    r = srv.poll(t_long)
+    assert r["status"] == 0
+    assert np.array_equal(r["psi_p"], rp) and np.array_equal(r["psi_m"], rm)
+    assert abs(r["R"] - rR) <= SUM_ORDER_RTOL * abs(rR) and abs(r["T"] - rT) <= SUM_ORDER_RTOL * abs(rT)
+    for t, (p, psi) in zip(t_small, small):
+        x = srv.poll(t)
+        assert x["status"] == 0
+        op, om, _, _ = oracle.propagate(p, psi)
+        assert rel_pair(x["psi_p"], x["psi_m"], op, om) <= TOL[p["precision"]][0]
+    srv.close()
+
+
 @pytest.mark.parametrize("name", ["f32-32768-bent", "3d-f64-16-o2"])
 def test_one_workgroup_staged_and_3d_march_matches_oracle(name):
     """The one-workgroup staged / 3D march (what batches and the server run)
