@@ -207,23 +207,24 @@ bpm_status bpm_td_assemble(bpm_batch *batch, void *stream, const void *d_state, 
  * thread advances all admitted solves together in rounds: per precision one
  * stream and one launch that takes every size and strain class side by side
  * (sizes below 1024 launch separately).  A solve of size nx advances
- * chunk_steps*16384/nx z-steps per round (at least 1), so every class takes
- * about the same time per round.  While a round runs, the worker builds the
+ * chunk_steps*16384/nx z-steps per round in FP32, half that in FP64 (at least
+ * 1), so every class takes about the same time per round.  While a round runs, the worker builds the
  * plans and entrance states of requests admitted in arrival order whose state
  * and tables fit the budget; after it, finished solves are retired and the new
  * ones join the next round.  Per-solve arithmetic does not depend on what else
  * is in the launch, so a result is the same alone and in the mix.
- * Long solves of a staged size or 3D envelopes (an estimated one-workgroup march
- * of more than 0.5 s; at most 4 at a time, and only while at most 64 other
- * solves are in the rounds: under load the one-workgroup march does more work
- * per second) are marched in the wide lane of
+ * Solves of a staged size or 3D envelopes with a long march ahead (an estimated
+ * one-workgroup time of more than 0.5 s for their remaining steps; at most 4 at
+ * a time, and only while at most 64 other solves are in the rounds: under load
+ * the one-workgroup march does more work per second) move, at a round boundary,
+ * to the wide lane of
  * bpm_propagate_device instead, 2*chunk_steps z-steps per round spread over the
  * device on a stream of their own; their envelopes are the same bitwise, R and
  * T the same sums grouped per workgroup. */
 typedef struct bpm_server_desc {
     size_t hbm_budget_bytes;   /* device bytes the server may hold for admitted solves */
     int32_t max_slots;         /* max solves in flight */
-    int32_t chunk_steps;       /* z-steps per round at nx = 16384 (>= 1); scaled by 16384/nx */
+    int32_t chunk_steps;       /* z-steps per round at nx = 16384 FP32 (>= 1); scaled by 16384/nx, halved in FP64 */
 } bpm_server_desc;
 
 typedef struct bpm_request {

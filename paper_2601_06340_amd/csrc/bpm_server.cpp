@@ -12,10 +12,10 @@
 // schedule whatever else runs, and its state crosses round boundaries through
 // HBM unchanged, so results do not depend on what else is running.
 //
-// Long solves of a staged size or 3D envelopes (estimated one-workgroup march
-// time above kWideMinSeconds; at most kMaxWide at a time, and only while at
-// most kWideMaxRegular other solves march in the rounds) run in the wide lane
-// instead: each round advances them kWideChunkFactor * chunk_steps z-steps
+// Staged-size or 3D solves with a long march ahead (estimated one-workgroup
+// time of their remaining steps above kWideMinSeconds; at most kMaxWide at a
+// time, and only while at most kWideMaxRegular other solves march in the
+// rounds) move to the wide lane, from the start or part way through: each round advances them kWideChunkFactor * chunk_steps z-steps
 // spread over the device on a stream of their own, alongside the round's
 // launches, and the round waits for them too.  Their envelopes are the
 // one-workgroup march's bitwise.
@@ -156,14 +156,17 @@ void bpm_server::finish(const std::shared_ptr<Request> &r, int status)
     cv_done.notify_all();
 }
 
-// z-steps a solve advances per round: chunk_steps at nx = 16384, scaled by
-// 16384/nx so every size class takes about the same time per round.
+// z-steps a solve advances per round: chunk_steps at nx = 16384 in FP32,
+// scaled by 16384/nx and halved in FP64 (a workgroup marches about half the
+// FP64 cell-steps per second) so every class takes about the same time per
+// round and no round waits long for one class.
 int bpm_server::steps_for(const Request &r) const
 {
     // a z-step of a splitting runs one FFT pair per propagation sub-step
     const int fft_pairs = r.desc.split_order == 4 ? 3 : 1;
+    const int prec_cost = r.desc.precision == BPM_F64 ? 2 : 1;
     const long long cells = (long long)r.desc.nx * (r.desc.ny > 1 ? r.desc.ny : 1);
-    const long long s = (long long)cfg.chunk_steps * 16384 / cells / fft_pairs;
+    const long long s = (long long)cfg.chunk_steps * 16384 / cells / fft_pairs / prec_cost;
     return (int)std::max(1LL, std::min<long long>(s, r.desc.nz - r.step));
 }
 
@@ -295,13 +298,14 @@ void bpm_server::run()
             }
         }
 
-        // ---- long staged / 3D solves that have not started take a free wide
-        // lane while the device has room
+        // ---- staged / 3D solves with a long march ahead take a free wide lane
+        // while the device has room (at a round boundary the state is in
+        // natural order, so a solve can move there part way through)
         int regular = 0;
         for (auto &r : active) regular += r->wide_lane < 0;
         for (auto &r : active) {
-            if (r->wide_lane >= 0 || r->step != 0 || !r->plan->d_wide_ctl ||
-                one_workgroup_seconds(r->desc) <= kWideMinSeconds || regular - 1 > kWideMaxRegular)
+            if (r->wide_lane >= 0 || !r->plan->d_wide_ctl || regular - 1 > kWideMaxRegular ||
+                one_workgroup_seconds(r->desc) * (r->desc.nz - r->step) / r->desc.nz <= kWideMinSeconds)
                 continue;
             for (int k = 0; k < kMaxWide && r->wide_lane < 0; ++k) {
                 if (wide_busy[k]) continue;

@@ -477,6 +477,34 @@ def test_server_marches_long_staged_solves_in_the_wide_lane():
     srv.close()
 
 
+def test_server_moves_a_running_solve_to_the_wide_lane():
+    """With more than 64 other solves in the first round the long request starts
+    in the rounds (one workgroup, any-size kernel); once they have finished it
+    moves to the wide lane part way through.  Its envelopes still equal the
+    single-solve march's bitwise."""
+    B = bpm()
+    long_p, long_psi = synth.flat_bragg_scan(n_angles=1, nx=65536, nz=8000, precision="f32")[0]
+    plan = B.Plan(long_p)
+    rp, rm, rR, rT = plan.propagate(long_psi)
+    plan.close()
+    srv = B.Server(hbm_budget_bytes=4 << 30, max_slots=128, chunk_steps=300)
+    # about 8 rounds each; admitted in arrival order, so all of them are in the
+    # rounds when the long request's plan is ready
+    shorts = [synth.flat_bragg_scan(n_angles=1, nx=1024, nz=40000, precision="f32")[0] for _ in range(70)]
+    ts = [srv.submit(p, psi, want_fields=False) for p, psi in shorts]
+    t_long = srv.submit(long_p, long_psi)
+    assert srv.drain(120.0)
+    st = srv.stats()
+    say("server wide solves", st["wide"], "launches", st["launches"])
+    assert st["wide"] == 1 and st["completed"] == 71
+    assert all(srv.poll(t)["status"] == 0 for t in ts)
+    r = srv.poll(t_long)
+    assert r["status"] == 0
+    assert np.array_equal(r["psi_p"], rp) and np.array_equal(r["psi_m"], rm)
+    assert abs(r["R"] - rR) <= SUM_ORDER_RTOL * abs(rR) and abs(r["T"] - rT) <= SUM_ORDER_RTOL * abs(rT)
+    srv.close()
+
+
 @pytest.mark.parametrize("name", ["f32-32768-bent", "3d-f64-16-o2"])
 def test_one_workgroup_staged_and_3d_march_matches_oracle(name):
     """The one-workgroup staged / 3D march (what batches and the server run)
