@@ -119,6 +119,22 @@ __device__ __forceinline__ Cx<double> tload_cx(const BufView &t, Cx<double> *, i
     const u4v v = __builtin_amdgcn_raw_buffer_load_b128(t.r, lane_off, t.base + uni_off, 0);
     return {d_of(v.x, v.y), d_of(v.z, v.w)};
 }
+// real entry at byte offset lane_off (per lane) + uni_off (wave-uniform)
+__device__ __forceinline__ float tload_r(const BufView &t, float *, int lane_off, int uni_off)
+{
+    return f_of(__builtin_amdgcn_raw_buffer_load_b32(t.r, lane_off, t.base + uni_off, 0));
+}
+__device__ __forceinline__ double tload_r(const BufView &t, double *, int lane_off, int uni_off)
+{
+    const u2v v = __builtin_amdgcn_raw_buffer_load_b64(t.r, lane_off, t.base + uni_off, 0);
+    return d_of(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ T tload_r(const BufView &t, int lane_i, int uni_i)
+{
+    return tload_r(t, (T *)nullptr, lane_i * (int)sizeof(T), uni_i * (int)sizeof(T));
+}
+
 // complex entry i of a table of Cx<T>, split as lane index + uniform index
 template <typename T>
 __device__ __forceinline__ Cx<T> tload_cx(const BufView &t, int lane_i, int uni_i)
@@ -491,15 +507,13 @@ __device__ __forceinline__ double edge_phase_rev(double X, double Z, double k, d
 }
 
 // exp(i m atan2(Z, X)) for a whole winding number m (|m| <= 8) without the
-// arctangent: ((X + i Z)/r)^m, by squaring; 1 at the core itself.
+// arctangent: ((X + i Z)/r)^m, by squaring, from ir = 1/r; 1 at the core itself
+// (ir = 0).
 template <typename T>
-__device__ __forceinline__ Cx<T> winding_phasor(T X, T Z, T r2, int m)
+__device__ __forceinline__ Cx<T> winding_phasor(T X, T Z, T ir, int m)
 {
     Cx<T> w = {(T)1, (T)0};
-    if (r2 > (T)0) {
-        const T ir = (T)1 / sqrt(r2);
-        w = {X * ir, Z * ir};
-    }
+    if (ir > (T)0) w = {X * ir, Z * ir};
     if (m < 0) w.y = -w.y;
     int k = m < 0 ? -m : m;
     Cx<T> p = {(T)1, (T)0};
@@ -654,7 +668,8 @@ struct Coupler {
             // revolution when the plan was built)
             const bool edge = d.strain_kind == STRAIN_EDGE;
             const T dk = (T)d.disl_k, dq = (T)d.disl_q;
-            const gptr<T> urow = utab + (size_t)n * nx;
+            // table [nz][nx]: row n, sample j0 + JS e
+            const BufView utv = buf_view(d.utab, edge ? 0u : (uint32_t)d.nz * nx * (uint32_t)sizeof(T));
             const int m = d.disl_m;
             if (edge && m != 0) {
                 // whole winding number: exp(i h u) = ((X + i Z)/r)^m exp(2 pi i k q X Z / r^2)
@@ -663,7 +678,8 @@ struct Coupler {
                     const bool in = inside_at_e(e);
                     const T X = (T)__builtin_fma((double)j, d.dx, X0), Zt = (T)Z;
                     const T r2 = fmaT(X, X, Zt * Zt);
-                    const Cx<T> W = winding_phasor<T>(X, Zt, r2, m);
+                    const T ir = r2 > (T)0 ? (T)1 / sqrt(r2) : (T)0;
+                    const Cx<T> W = winding_phasor<T>(X, Zt, ir, m);
                     const Cx<T> S = phasor<T>(r2 > (T)0 ? dk * (X * Zt * dq / r2) : (T)0);
                     const Cx<T> P = {fmaT(W.x, S.x, -W.y * S.y), fmaT(W.x, S.y, W.y * S.x)};
                     const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
@@ -676,7 +692,7 @@ struct Coupler {
                 const int j = j0 + e * JS;
                 const bool in = inside_at_e(e);
                 const T rev = edge ? edge_phase_rev((T)__builtin_fma((double)j, d.dx, X0), (T)Z, dk, dq)
-                                   : urow[j];
+                                   : tload_r<T>(utv, j0, n * nx + CV(e) * JS);
                 const Cx<T> P = phasor<T>(rev);
                 const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
                 const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
@@ -707,7 +723,8 @@ struct Coupler {
                 const T X = (T)Xd, Zt = (T)Z, dk = (T)d.disl_k, dq = (T)d.disl_q;
                 if (d.disl_m != 0) {
                     const T r2 = fmaT(X, X, Zt * Zt);
-                    const Cx<T> W = winding_phasor<T>(X, Zt, r2, d.disl_m);
+                    const T ir = r2 > (T)0 ? (T)1 / sqrt(r2) : (T)0;
+                    const Cx<T> W = winding_phasor<T>(X, Zt, ir, d.disl_m);
                     const Cx<T> S = phasor<T>(r2 > (T)0 ? dk * (X * Zt * dq / r2) : (T)0);
                     P = {fmaT(W.x, S.x, -W.y * S.y), fmaT(W.x, S.y, W.y * S.x)};
                 } else {
@@ -716,14 +733,21 @@ struct Coupler {
             }
         }
         const bool table = SC == SC_GENERAL && d.strain_kind == STRAIN_TABLE;
+        // strain table [nz][NY][nx]: row n*NY + y0 + YS*e, column x
+        const BufView utv = buf_view(d.utab, table ? (uint32_t)d.nz * NY * nx * (uint32_t)sizeof(T) : 0u);
+        // mask rows [nz][NY][nseg] of (lo, hi) pairs: row n*NY + y0 + YS*e
+        const BufView sgv = buf_view(d.seg, (uint32_t)d.nz * NY * nseg * 8u);
+        const int lane_off = y0 * nseg * 8;
         static_for<0, E>([&](auto e) {
-            const int row = n * NY + y0 + YS * CV(e);
-            const gptr<int> sg = seg + (size_t)row * nseg * 2;
+            const int uni_off = (n * NY + YS * CV(e)) * nseg * 8;
             bool in = false;
             static_for<0, kMaxSeg>([&](auto k) {
-                if (CV(k) < nseg) in |= (x >= sg[2 * CV(k)]) & (x < sg[2 * CV(k) + 1]);
+                if (CV(k) < nseg) {
+                    const u2v iv = __builtin_amdgcn_raw_buffer_load_b64(sgv.r, lane_off, sgv.base + uni_off + 8 * CV(k), 0);
+                    in |= (x >= (int)iv.x) & (x < (int)iv.y);
+                }
             });
-            const Cx<T> Pe = table ? phasor<T>(utab[(size_t)row * nx + x]) : P;
+            const Cx<T> Pe = table ? phasor<T>(tload_r<T>(utv, y0 * nx + x, (n * NY + YS * CV(e)) * nx)) : P;
             const Cx<T> bp = {fmaT(ap.x, Pe.x, -ap.y * Pe.y), fmaT(ap.x, Pe.y, ap.y * Pe.x)};
             const Cx<T> bm = {fmaT(am.x, Pe.x, am.y * Pe.y), fmaT(am.y, Pe.x, -am.x * Pe.y)};
             couple_sel(vp[e], vm[e], in, d0, bp, bm);

@@ -101,11 +101,11 @@ hipError_t launch_staged(const SolveDesc *d_descs, int n, const char *in_base, c
 // 3D envelopes [ny][nx = 512]: one solve per workgroup, the staged lane's two
 // phases as the 2D transform (Staged<> with D3).
 template <typename T, int LOG2NY, int SC>
-using Stage3D = Staged<T, k3DLog2Nx + LOG2NY, SC, staged_log2th(staged_prec<T>()), true>;
+using Stage3D = Staged<T, k3DLog2Nx + LOG2NY, SC, staged3d_log2th(staged_prec<T>(), SC), true>;
 
 template <typename T, int LOG2NY, int SC>
-__global__ __launch_bounds__(1 << staged_log2th(staged_prec<T>()))
-__attribute__((amdgpu_waves_per_eu(1, (1 << staged_log2th(staged_prec<T>())) / 256)))
+__global__ __launch_bounds__(1 << staged3d_log2th(staged_prec<T>(), SC))
+__attribute__((amdgpu_waves_per_eu(1, (1 << staged3d_log2th(staged_prec<T>(), SC)) / 256)))
 void k_march_3d(const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
 {
     extern __shared__ __align__(16) unsigned char smem[];
