@@ -445,6 +445,59 @@ def test_wide_lane_matches_one_workgroup_march_and_oracle(name):
     plan.close()
 
 
+@pytest.mark.parametrize("nz", [0, 1])
+@pytest.mark.parametrize("name", ["f32-32768-bent", "3d-f64-16-o2"])
+def test_wide_lane_degenerate_marches(name, nz):
+    """nz = 0 (entry and detector sums only: the output is the input, R and T
+    its powers) and nz = 1 (one step, no graph) in the wide lane, against the
+    oracle and the one-workgroup march."""
+    B = bpm()
+    import torch
+    p, a, b = _wide_case(name)
+    p = dict(p, nz=nz)
+    p["seg"] = np.asarray(p["seg"])[:nz]
+    plan = B.Plan(p)
+    one = B.Batch([plan])
+    buf = one.pack([(a, b)])
+    dst = torch.empty_like(buf)
+    rt = torch.zeros(2, dtype=torch.float64, device="cuda")
+    plan.propagate_device(buf.data_ptr(), dst.data_ptr(), rt.data_ptr())
+    rt1 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    one.run(buf.data_ptr(), buf.data_ptr(), rt1.data_ptr())
+    torch.cuda.synchronize()
+    got, ref = one.unpack(dst)[0], one.unpack(buf)[0]
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    rt, rt1 = rt.cpu().numpy(), rt1.cpu().numpy()
+    op, om, oR, oT = oracle.propagate(p, a, b)
+    err = rel_pair(got[0], got[1], op, om)
+    say("wide nz", nz, name, "rel L2 %.3e R %.6g oracle %.6g" % (err, rt[0], oR))
+    assert err <= TOL[p["precision"]][0]
+    assert abs(rt[0] - oR) <= TOL[p["precision"]][1] and abs(rt[1] - oT) <= TOL[p["precision"]][1]
+    assert abs(rt[0] - rt1[0]) <= SUM_ORDER_RTOL * abs(rt1[0]) and abs(rt[1] - rt1[1]) <= SUM_ORDER_RTOL * abs(rt1[1])
+    one.close()
+    plan.close()
+
+
+def test_server_marches_long_3d_request_in_the_wide_lane():
+    """A long 3D request (estimated one-workgroup march > 0.5 s) runs wide in the
+    server and equals the single-solve march bitwise."""
+    B = bpm()
+    p, a, b = _problem3d(256, 2000, "f32", seed=3)   # estimated one-workgroup march 0.52 s
+    plan = B.Plan(p)
+    rp, rm, rR, rT = plan.propagate(a, b)
+    plan.close()
+    srv = B.Server(hbm_budget_bytes=4 << 30, max_slots=4, chunk_steps=100)
+    t = srv.submit(p, a, b)
+    assert srv.drain(120.0)
+    st = srv.stats()
+    assert st["wide"] == 1
+    r = srv.poll(t)
+    assert r["status"] == 0
+    assert np.array_equal(r["psi_p"], rp) and np.array_equal(r["psi_m"], rm)
+    assert abs(r["R"] - rR) <= SUM_ORDER_RTOL * abs(rR) and abs(r["T"] - rT) <= SUM_ORDER_RTOL * abs(rT)
+    srv.close()
+
+
 def test_server_marches_long_staged_solves_in_the_wide_lane():
     """A long staged-size request (estimated one-workgroup march > 0.5 s) runs in
     the server's wide lane in chunks of 2*chunk_steps z-steps (graph blocks and
