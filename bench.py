@@ -239,6 +239,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-chunk", type=int, default=256)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the schedule autotuner for the headline size (64 synthetic solves, 100 steps)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -269,6 +271,16 @@ def main():
         print("copy calibration: torch.neg, %d bytes read + %d bytes written per launch" % (nb, nb),
               file=sys.stderr)
     cases, cfg = workload(args.workload, args.beams_per_radius, args.nz)
+    nx = cases[0][0]["nx"]
+    uniform = all(p["nx"] == nx for p, _ in cases)
+    prec = cases[0][0]["precision"]
+    tuned = None
+    if uniform and not args.no_autotune:
+        # the batch below takes the kernel family the autotuner measures fastest
+        kind = bpm.STRAIN[(cases[0][0].get("strain") or {}).get("kind", "none")]
+        if all(bpm.STRAIN[(p.get("strain") or {}).get("kind", "none")] == kind for p, _ in cases):
+            print("autotune %s nx %d" % (prec, nx), file=sys.stderr, flush=True)
+            tuned = bpm.autotune(prec, nx, kind, nsolves=64, nsteps=100)
     print("workload %s: %d solves" % (cfg["workload"], len(cases)), file=sys.stderr, flush=True)
     launch_cs = sum(cell_steps(p) for p, _ in cases)
     per, total_ms, wall, Rs = time_batch(bpm, torch, cases, args.steps, args.warmup)
@@ -280,11 +292,14 @@ def main():
         k = min(len(per_sorted) - 1, max(0, int(math.ceil(q * len(per_sorted))) - 1))
         return per_sorted[k]
 
-    nx = cases[0][0]["nx"]
-    uniform = all(p["nx"] == nx for p, _ in cases)
-    prec = cases[0][0]["precision"]
-    kernel = ("k_march_uniform<%s,%d>" % ("float" if prec == "f32" else "double", int(math.log2(nx)))
-              if uniform else "k_march_mixed<%s>" % ("float" if prec == "f32" else "double"))
+    tname = "float" if prec == "f32" else "double"
+    sched = tuned["schedule"] if tuned else "uniform"
+    if not uniform or sched == "mixed":
+        kernel = "k_march_mixed<%s>" % tname
+    elif sched == "any":
+        kernel = "k_march_any<%s>" % tname
+    else:
+        kernel = "k_march_uniform<%s,%d>" % (tname, int(math.log2(nx)))
     flop_cs = (sum((10 * math.log2(p["nx"]) + 26) * cell_steps(p) for p, _ in cases) / launch_cs)
     achieved = flop_cs * launch_cs / (sum(per) / len(per) / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -296,6 +311,9 @@ def main():
            "vs_baseline": None, "dtype": prec, "data": "synthetic", "config": cfg,
            "latency_ms": {"p50": pct(0.5), "p99": pct(0.99), "what": "batch completion per step"},
            "roofline": roof, "wall_s": wall}
+    if tuned:
+        out["autotune"] = dict(tuned, what="kernel family of the headline batch, timed on 64 synthetic "
+                                           "solves of its size and strain kind (ms per 100-step batch march)")
     if not args.no_fp64_plain:
         out["fp64_plain"] = fp64_plain(bpm, torch, synth)
         out["fp32_batched_over_fp64_plain"] = value / out["fp64_plain"]["value"]

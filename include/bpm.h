@@ -266,6 +266,54 @@ bpm_status bpm_server_stats_get(bpm_server *server, bpm_server_stats *out);
 bpm_status bpm_server_drain(bpm_server *server, double timeout_s);
 void bpm_server_destroy(bpm_server *server);
 
+/* --- schedules and autotuning ----------------------------------------------------
+ * A batch marches each group of solves that share (precision, nx, strain class;
+ * strain classes: none, POLY2, dislocation/table) with one kernel family:
+ *   BPM_SCHED_UNIFORM  the per-size kernel: nx/16 threads per solve for nx up to
+ *                      16384 FP32 / 8192 FP64, the staged kernel above;
+ *   BPM_SCHED_MIXED    the mixed-size kernel: 512 (or 256) threads, nx/512
+ *                      samples per thread (nx 1024..16384 FP32, ..8192 FP64);
+ *   BPM_SCHED_ANY      the any-size kernel of the server: 512 threads, register-
+ *                      resident sizes as MIXED, staged sizes with 512 threads
+ *                      (nx >= 1024).
+ * BPM_SCHED_DEFAULT is UNIFORM (and MIXED for a group of several sizes that the
+ * mixed kernel takes).  The process-wide schedule table, consulted when a batch
+ * is created, overrides the default per (precision, nx, strain class); 3D
+ * envelopes and bpm_propagate keep their own kernels.  Schedules change the
+ * samples per thread, so results change within rounding, not in value. */
+typedef enum bpm_schedule {
+    BPM_SCHED_DEFAULT = 0,
+    BPM_SCHED_UNIFORM = 1,
+    BPM_SCHED_MIXED = 2,
+    BPM_SCHED_ANY = 3
+} bpm_schedule;
+
+typedef struct bpm_tune_result {
+    int32_t schedule;   /* the fastest candidate, now in the table */
+    int32_t nsolves, nsteps;
+    double ms[4];       /* time of one batch march per candidate (index = schedule); 0 = not a candidate */
+} bpm_tune_result;
+
+/* Times every schedule that can march nx at `precision` on a synthetic batch of
+ * nsolves solves (a crystal filling the window, strain of strain_kind: none, a
+ * 1 m bend, a dislocation, or a zero table) over nsteps z-steps (one untimed run,
+ * then the median of three), enters the fastest into the schedule table and
+ * reports all.  Blocks; needs 1 <= nsolves <= 4096, 1 <= nsteps <= 100000.
+ * BPM_E_INVALID for bad arguments, BPM_E_NOMEM / BPM_E_DEVICE on failure. */
+bpm_status bpm_autotune(int32_t precision, int32_t nx, int32_t strain_kind, int32_t nsolves, int32_t nsteps,
+                        bpm_tune_result *out);
+/* Table entry for (precision, nx, strain kind): BPM_SCHED_DEFAULT removes it.
+ * BPM_E_INVALID for a bad key or a schedule that cannot march nx. */
+bpm_status bpm_schedule_set(int32_t precision, int32_t nx, int32_t strain_kind, int32_t schedule);
+/* The table entry (BPM_SCHED_DEFAULT when none), or -1 for a bad key. */
+int32_t bpm_schedule_get(int32_t precision, int32_t nx, int32_t strain_kind);
+/* Write the table to a text file (one entry per line: precision log2(nx) strain
+ * class schedule) / merge such a file into the table.  Loading checks every
+ * line first and changes nothing on error (BPM_E_INVALID, message in
+ * bpm_last_error). */
+bpm_status bpm_schedule_save(const char *path);
+bpm_status bpm_schedule_load(const char *path);
+
 /* --- misc -------------------------------------------------------------------- */
 const char *bpm_status_str(bpm_status s);
 const char *bpm_last_error(void);

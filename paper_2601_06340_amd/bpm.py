@@ -81,8 +81,21 @@ class ServerStats(C.Structure):
                 ("peak_bytes", C.c_size_t), ("wide", C.c_int64)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("schedule", C.c_int32), ("nsolves", C.c_int32), ("nsteps", C.c_int32),
+                ("ms", C.c_double * 4)]
+
+
+SCHEDULES = {"default": 0, "uniform": 1, "mixed": 2, "any": 3}
+
+
 # name -> (restype, argtypes); every entry point declared in include/bpm.h
 SIGNATURES = {
+    "bpm_autotune": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(TuneResult)]),
+    "bpm_schedule_set": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "bpm_schedule_get": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32]),
+    "bpm_schedule_save": (C.c_int, [C.c_char_p]),
+    "bpm_schedule_load": (C.c_int, [C.c_char_p]),
     "bpm_plan_create": (C.c_int, [C.POINTER(PlanDesc), C.POINTER(C.c_void_p)]),
     "bpm_plan_destroy": (None, [C.c_void_p]),
     "bpm_plan_info_get": (C.c_int, [C.c_void_p, C.POINTER(PlanInfo)]),
@@ -361,6 +374,36 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def autotune(precision: str, nx: int, strain_kind: int = 0, nsolves: int = 256, nsteps: int = 200) -> dict:
+    """Time every kernel family that can march nx on a synthetic batch, enter the
+    fastest into the schedule table (bpm_autotune); returns the choice and times."""
+    r = TuneResult()
+    _check(lib().bpm_autotune(PRECISION[precision], int(nx), int(strain_kind), int(nsolves), int(nsteps),
+                              C.byref(r)))
+    names = {v: k for k, v in SCHEDULES.items()}
+    return {"schedule": names[r.schedule], "nsolves": r.nsolves, "nsteps": r.nsteps,
+            "ms": {names[i]: r.ms[i] for i in range(1, 4) if r.ms[i] > 0}}
+
+
+def schedule_set(precision: str, nx: int, strain_kind: int, schedule: str):
+    _check(lib().bpm_schedule_set(PRECISION[precision], int(nx), int(strain_kind), SCHEDULES[schedule]))
+
+
+def schedule_get(precision: str, nx: int, strain_kind: int) -> str:
+    v = lib().bpm_schedule_get(PRECISION[precision], int(nx), int(strain_kind))
+    if v < 0:
+        raise BpmError(E_INVALID, "bad schedule key")
+    return {v2: k for k, v2 in SCHEDULES.items()}[v]
+
+
+def schedule_save(path: str):
+    _check(lib().bpm_schedule_save(str(path).encode()))
+
+
+def schedule_load(path: str):
+    _check(lib().bpm_schedule_load(str(path).encode()))
 
 
 def max_nx(precision: str) -> int:

@@ -98,7 +98,8 @@ def _compile(src: str) -> str:
 def build(jobs: int | None = None, verbose: bool = True) -> str:
     t0 = time.time()
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [os.path.join(CSRC, f) for f in ("bpm_setup.hip", "bpm_td.hip", "bpm_api.cpp", "bpm_server.cpp")]
+    srcs = [os.path.join(CSRC, f) for f in ("bpm_setup.hip", "bpm_td.hip", "bpm_api.cpp", "bpm_server.cpp",
+                                            "bpm_tune.cpp")]
     srcs += _gen_units()
     # largest units first
     srcs.sort(key=lambda s: ("_any_" not in s, "mixed" not in s,

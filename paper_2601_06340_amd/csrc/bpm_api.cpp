@@ -690,9 +690,18 @@ extern "C" bpm_status bpm_propagate(bpm_plan *p, const bpm_complex *psi_p0, cons
 bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<int> &rt_index,
                                const std::vector<uint64_t> &in_off, const std::vector<uint64_t> &out_off,
                                const std::vector<int> &step0, const std::vector<int> &nsteps,
-                               const std::vector<int> &flags, std::vector<Launch> &launches, bool any_size)
+                               const std::vector<int> &flags, std::vector<Launch> &launches, bool any_size,
+                               int force_schedule)
 {
     launches.clear();
+    // launch kind of a group of one size: the schedule table's (or the forced)
+    // kernel family when it can march the size, else the per-size kernel
+    auto kind_of = [&](int prec, int sc, int log2n) {
+        const int f = force_schedule ? force_schedule : tuned_schedule(prec, log2n, sc);
+        if (f == BPM_SCHED_MIXED && schedule_fits(prec, log2n, f)) return (int)kLaunchMixed;
+        if (f == BPM_SCHED_ANY && schedule_fits(prec, log2n, f)) return (int)kLaunchAny;
+        return log2n;
+    };
     // longest first: the hardware dispatcher then balances uneven solves
     auto cost = [&](int i) {
         const int pairs = plans[i]->desc.split_order == 4 ? 3 : 1;
@@ -780,7 +789,7 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
             }
         } else if (lo == hi) {
             groups.push_back(idx);
-            group_log2n.push_back(lo);
+            group_log2n.push_back(kind_of(prec, sc, lo));
         } else if (lo >= mixed_min_log2n(prec) && hi <= mixed_max_log2n(prec)) {
             groups.push_back(idx);
             group_log2n.push_back(kLaunchMixed);
@@ -791,7 +800,7 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
                     if (plans[i]->log2n == l) g.push_back(i);
                 if (!g.empty()) {
                     groups.push_back(g);
-                    group_log2n.push_back(l);
+                    group_log2n.push_back(kind_of(prec, sc, l));
                 }
             }
         }

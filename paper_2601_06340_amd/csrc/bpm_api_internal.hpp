@@ -55,6 +55,12 @@ bpm_status ensure_device();
 bpm_status validate_desc(const bpm_plan_desc *d);
 bpm_status check_input(const bpm_plan_desc &d, const bpm_complex *a, const bpm_complex *b);
 bpm_status twiddle_table(int prec, int log2n, int log2e, const void **out);
+// Schedule table (bpm_tune.cpp): the bpm_schedule a batch group of one
+// (precision, log2 nx, strain class) runs with; BPM_SCHED_DEFAULT when none.
+int tuned_schedule(int prec, int log2n, int sc);
+// can `schedule` march 2^log2n at prec (2D)
+bool schedule_fits(int prec, int log2n, int schedule);
+
 // Library-owned non-blocking stream of the current device for plan setup.
 hipStream_t setup_stream();
 // z-steps [step0, step0 + nsteps) of a plan that has a wide form (p->d_wide_ctl
@@ -75,16 +81,18 @@ struct Launch {
     size_t d_cap = 0;
 };
 
-// Group solves into launches: per (precision, strain class), one uniform launch
-// when all share nx, one mixed launch when all sizes fit the mixed kernel, and
-// otherwise per size.  With any_size, every solve of a size the any-size kernel
+// Group solves into launches: per (precision, strain class), one launch when
+// all share nx (the schedule table's kernel family for that size, or
+// force_schedule when nonzero; by default the per-size kernel), one mixed launch
+// when all sizes fit the mixed kernel, and otherwise per size.  With any_size, every solve of a size the any-size kernel
 // takes, of any strain class, goes into one launch of it per precision (whatever
 // the mix, so a solve's arithmetic never depends on what else is launched) and
 // smaller sizes per size.  Longest solves first.
 bpm_status build_launches(bpm_plan *const *plans, int n, const std::vector<int> &rt_index,
                           const std::vector<uint64_t> &in_off, const std::vector<uint64_t> &out_off,
                           const std::vector<int> &step0, const std::vector<int> &nsteps,
-                          const std::vector<int> &flags, std::vector<Launch> &launches, bool any_size = false);
+                          const std::vector<int> &flags, std::vector<Launch> &launches, bool any_size = false,
+                          int force_schedule = 0);
 // Descriptor upload: blocking when s is NULL, else ordered on stream s.
 bpm_status upload_launches(std::vector<Launch> &launches, hipStream_t s = nullptr);
 bpm_status run_launches(const std::vector<Launch> &launches, hipStream_t s, const char *in, char *out,

@@ -582,14 +582,13 @@ __device__ __forceinline__ void wave_lds_sync()
 }
 
 // Real-space coupling of one z-step or sub-step (Eq. (9)-(13)) for the E samples
-// a thread holds at j0 + JS*e.  Outside the crystal the step is pure propagation: the
-// coefficients become (0, 0, 0), which leaves both envelopes untouched.
+// a thread holds at j0 + JS*e.  Outside the crystal the step is pure propagation:
+// those samples keep their propagated values.
 template <typename T, int SC>
 struct Coupler {
     double X0;       // x0 - x_ref
     int nseg, nx;
     gptr<int> seg;
-    gptr<T> utab;
     Cx<T> rr;        // polynomial strain: phasor of the phase's second difference along a thread's samples
 
     // JS: sample stride between a thread's elements
@@ -600,7 +599,6 @@ struct Coupler {
         nseg = d.nseg;
         nx = nx_;
         seg = to_global<int>(d.seg);
-        utab = to_global<T>(d.utab);
         if constexpr (SC == SC_POLY2) {
             // the second difference 2 pc D^2 (D = JS dx) does not depend on z
             const double D = (double)JS * d.dx;
@@ -637,7 +635,8 @@ struct Coupler {
         });
         auto inside_at_e = [&](auto e) { return ((inside >> CV(e)) & 1u) != 0u; };
         const double Z = (n + ss.zoff) * d.dz - d.z_ref;
-        // (one straight-line copy: a separate all-inside copy costs registers)
+        // (one straight-line copy: a wave-uniform branch to a copy without the
+        // selects for all-inside waves keeps both copies' values live and spills)
         if constexpr (SC == SC_NONE) {
             static_for<0, E>([&](auto e) { couple_sel(vp[e], vm[e], inside_at_e(e), d0, ap, am); });
         } else if constexpr (SC == SC_POLY2) {

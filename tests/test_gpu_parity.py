@@ -558,6 +558,52 @@ def test_server_moves_a_running_solve_to_the_wide_lane():
     srv.close()
 
 
+def test_autotune_and_every_schedule_match_the_oracle():
+    """The autotuner times the three kernel families on a synthetic batch and
+    enters the fastest; a batch marched with each schedule matches the oracle,
+    and at a staged size the any-size kernel (512 threads) gives the staged
+    kernel's envelopes bitwise."""
+    B = bpm()
+    import torch
+    r = B.autotune("f32", 4096, 0, nsolves=32, nsteps=64)
+    say("autotune f32 4096:", r)
+    assert r["schedule"] in ("uniform", "mixed", "any") and set(r["ms"]) == {"uniform", "mixed", "any"}
+    assert B.schedule_get("f32", 4096, 0) == r["schedule"]
+    try:
+        p, psi = synth.flat_bragg_scan(n_angles=1, nx=4096, nz=300, precision="f32")[0]
+        op, om, oR, _ = oracle.propagate(p, psi)
+        for sched in ("uniform", "mixed", "any"):
+            B.schedule_set("f32", 4096, 0, sched)
+            plan = B.Plan(p)
+            batch = B.Batch([plan])
+            buf = batch.pack([(psi, None)])
+            rt = torch.zeros(2, dtype=torch.float64, device="cuda")
+            batch.run(buf.data_ptr(), buf.data_ptr(), rt.data_ptr())
+            torch.cuda.synchronize()
+            gp, gm = batch.unpack(buf)[0]
+            err = rel_pair(gp, gm, op, om)
+            say("   schedule", sched, "rel L2 %.3e" % err)
+            assert err <= TOL["f32"][0] and abs(rt.cpu().numpy()[0] - oR) <= TOL["f32"][1]
+            batch.close()
+            plan.close()
+        p, psi = synth.bent_laue(radii_m=(0.7,), nx=32768, nz=60, thickness=4.0, precision="f32")[0]
+        outs = {}
+        for sched in ("uniform", "any"):
+            B.schedule_set("f32", 32768, 1, sched)
+            plan = B.Plan(p)
+            batch = B.Batch([plan])
+            buf = batch.pack([(psi, None)])
+            batch.run(buf.data_ptr(), buf.data_ptr(), None)
+            torch.cuda.synchronize()
+            outs[sched] = batch.unpack(buf)[0]
+            batch.close()
+            plan.close()
+        assert np.array_equal(outs["uniform"][0], outs["any"][0]) and np.array_equal(outs["uniform"][1], outs["any"][1])
+    finally:
+        B.schedule_set("f32", 4096, 0, "default")
+        B.schedule_set("f32", 32768, 1, "default")
+
+
 @pytest.mark.parametrize("name", ["f32-32768-bent", "3d-f64-16-o2"])
 def test_one_workgroup_staged_and_3d_march_matches_oracle(name):
     """The one-workgroup staged / 3D march (what batches and the server run)
