@@ -206,9 +206,11 @@ bpm_status bpm_td_assemble(bpm_batch *batch, void *stream, const void *d_state, 
  * A server owns a device-memory budget and a pool of solve slots.  A worker
  * thread advances all admitted solves together in rounds: per precision one
  * stream and one launch that takes every size and strain class side by side
- * (sizes below 1024 launch separately).  A solve of size nx advances
- * chunk_steps*16384/nx z-steps per round in FP32, half that in FP64 (at least
- * 1), so every class takes about the same time per round.  While a round runs, the worker builds the
+ * (sizes below 1024 launch separately).  An FP32 nx = 16384 solve with a
+ * polynomial strain advances chunk_steps z-steps per round; every other
+ * (precision, size, strain class) the steps that take the same time at its
+ * measured per-workgroup rate (at least 1), so no round waits long for one
+ * class.  While a round runs, the worker builds the
  * plans and entrance states of requests admitted in arrival order whose state
  * and tables fit the budget; after it, finished solves are retired and the new
  * ones join the next round.  Per-solve arithmetic does not depend on what else
@@ -224,7 +226,8 @@ bpm_status bpm_td_assemble(bpm_batch *batch, void *stream, const void *d_state, 
 typedef struct bpm_server_desc {
     size_t hbm_budget_bytes;   /* device bytes the server may hold for admitted solves */
     int32_t max_slots;         /* max solves in flight */
-    int32_t chunk_steps;       /* z-steps per round at nx = 16384 FP32 (>= 1); scaled by 16384/nx, halved in FP64 */
+    int32_t chunk_steps;       /* z-steps per round of an FP32 nx = 16384 bent solve (>= 1); other classes
+                                  advance the steps that take the same time at their measured rate */
 } bpm_server_desc;
 
 typedef struct bpm_request {

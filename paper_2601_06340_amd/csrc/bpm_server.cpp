@@ -62,6 +62,30 @@ struct Request {
     bpm_result res{};
 };
 
+// Per-workgroup march rate of the any-size kernel in cell-steps/s, by
+// precision (FP64, FP32), log2 nx (10..16; 3D by its cell count) and strain
+// class (none, polynomial, dislocation/table): measured on MI355X with 64
+// solves of each class marching side by side (one per compute unit).  The
+// server sizes every solve's chunk so that chunks take about the same time.
+constexpr float kAnyRate[2][7][3] = {
+    {{4.14e8f, 3.81e8f, 2.97e8f}, {4.42e8f, 5.25e8f, 3.80e8f}, {7.96e8f, 7.27e8f, 5.30e8f},
+     {7.47e8f, 6.97e8f, 4.12e8f}, {3.62e8f, 3.29e8f, 2.99e8f}, {3.75e8f, 3.31e8f, 2.97e8f},
+     {3.56e8f, 3.13e8f, 2.78e8f}},
+    {{5.15e8f, 4.64e8f, 3.59e8f}, {7.00e8f, 6.48e8f, 4.57e8f}, {1.13e9f, 1.06e9f, 7.28e8f},
+     {1.27e9f, 1.14e9f, 7.52e8f}, {1.20e9f, 1.17e9f, 6.49e8f}, {4.22e8f, 4.08e8f, 3.49e8f},
+     {3.94e8f, 3.82e8f, 3.30e8f}}};
+// the reference class: FP32, nx = 16384, polynomial strain
+constexpr double kRefRate = 1.17e9;
+
+double any_rate(const bpm_plan_desc &d)
+{
+    const long long cells = (long long)d.nx * (d.ny > 1 ? d.ny : 1);
+    int l = 0;
+    while ((1LL << l) < cells) ++l;
+    l = std::min(16, std::max(10, l));
+    return kAnyRate[d.precision == BPM_F32 ? 1 : 0][l - 10][strain_class(d.strain.kind)];
+}
+
 constexpr int kMaxWide = 4;              // wide-lane solves at once
 constexpr double kWideMinSeconds = 0.5;  // one-workgroup march time above which a solve goes wide
 constexpr int kWideChunkFactor = 2;      // wide-lane z-steps per round = factor * chunk_steps
@@ -70,13 +94,12 @@ constexpr int kWideChunkFactor = 2;      // wide-lane z-steps per round = factor
 // done.  A solve goes wide only while at most this many others march in the rounds.
 constexpr int kWideMaxRegular = 64;
 
-// Rough one-workgroup march time of a request: staged-lane rate of one
-// workgroup, about 1e9 cell-steps/s in FP32 and 5e8 in FP64.
+// One-workgroup march time of a request at the measured rate of its class.
 double one_workgroup_seconds(const bpm_plan_desc &d)
 {
     const double cells = (double)d.nx * (d.ny > 1 ? d.ny : 1);
     const double pairs = d.split_order == 4 ? 3.0 : 1.0;
-    return 2.0 * cells * d.nz * pairs / (d.precision == BPM_F32 ? 1.0e9 : 5.0e8);
+    return 2.0 * cells * d.nz * pairs / any_rate(d);
 }
 
 size_t estimate_bytes(const bpm_plan_desc &d)
@@ -156,18 +179,17 @@ void bpm_server::finish(const std::shared_ptr<Request> &r, int status)
     cv_done.notify_all();
 }
 
-// z-steps a solve advances per round: chunk_steps at nx = 16384 in FP32,
-// scaled by 16384/nx and halved in FP64 (a workgroup marches about half the
-// FP64 cell-steps per second) so every class takes about the same time per
-// round and no round waits long for one class.
+// z-steps a solve advances per round: chunk_steps for an FP32 nx = 16384
+// solve with polynomial strain, and for every other class the steps that take
+// the same time at its measured rate (kAnyRate), so no round waits long for
+// one class.
 int bpm_server::steps_for(const Request &r) const
 {
     // a z-step of a splitting runs one FFT pair per propagation sub-step
-    const int fft_pairs = r.desc.split_order == 4 ? 3 : 1;
-    const int prec_cost = r.desc.precision == BPM_F64 ? 2 : 1;
-    const long long cells = (long long)r.desc.nx * (r.desc.ny > 1 ? r.desc.ny : 1);
-    const long long s = (long long)cfg.chunk_steps * 16384 / cells / fft_pairs / prec_cost;
-    return (int)std::max(1LL, std::min<long long>(s, r.desc.nz - r.step));
+    const double fft_pairs = r.desc.split_order == 4 ? 3.0 : 1.0;
+    const double cells = (double)r.desc.nx * (r.desc.ny > 1 ? r.desc.ny : 1);
+    const double s = cfg.chunk_steps * (16384.0 / cells) * (any_rate(r.desc) / kRefRate) / fft_pairs;
+    return (int)std::max(1.0, std::min<double>(std::floor(s), r.desc.nz - r.step));
 }
 
 // Device setup of one admitted request (plan tables and entrance state).  Runs
