@@ -33,12 +33,16 @@ METRIC = "BPM cell-steps/s (Nx·Nz·2 beams), FP32 batched vs FP64 plain; p50/p9
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
+# the sources the march kernels are compiled from (device code and the
+# descriptors it reads); host-side changes do not invalidate a profile
+KERNEL_SOURCES = ("bpm_internal.hpp", "bpm_march.hpp", "bpm_march_kernels.hpp")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2601_06340_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
