@@ -793,6 +793,30 @@ def test_server_budget_and_cancel():
     srv.close()
 
 
+def test_server_cancels_a_wide_lane_solve_between_rounds():
+    """A long request marching in the wide lane stops at the next round
+    boundary when cancelled; the server keeps serving the others."""
+    B = bpm()
+    import time
+    long_p, long_psi = synth.flat_bragg_scan(n_angles=1, nx=65536, nz=20000, precision="f32")[0]
+    short_p, short_psi = synth.flat_bragg_scan(n_angles=1, nx=2048, nz=300, precision="f32")[0]
+    srv = B.Server(hbm_budget_bytes=4 << 30, max_slots=8, chunk_steps=256)
+    t_long = srv.submit(long_p, long_psi, want_fields=False)
+    time.sleep(0.3)   # a few rounds in (the whole march takes about 0.3 s wide, 7 s on one workgroup)
+    srv.cancel(t_long)
+    t_short = srv.submit(short_p, short_psi)
+    assert srv.drain(60.0)
+    r = srv.poll(t_long)
+    st = srv.stats()
+    say("cancelled wide solve: status", r["status"], "wide", st["wide"], "cell-steps done %.3g" % st["cell_steps_done"])
+    assert r["status"] in (0, B.E_CANCELLED) and st["wide"] == 1
+    x = srv.poll(t_short)
+    assert x["status"] == 0
+    op, om, _, _ = oracle.propagate(short_p, short_psi)
+    assert rel_pair(x["psi_p"], x["psi_m"], op, om) <= TOL["f32"][0]
+    srv.close()
+
+
 def test_invalid_descriptors_rejected_before_any_launch():
     B = bpm()
     p, psi = synth.flat_bragg_scan(n_angles=1, nx=1024, nz=10)[0]
