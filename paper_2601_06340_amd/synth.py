@@ -128,6 +128,18 @@ def _index_at_or_above(x: float, x0: float, dx: float) -> int:
     return int(math.ceil((x - x0) / dx - 1e-9))
 
 
+def mask_tilted_face(nz: int, nx: int, dx: float, dz: float, xa: float, xb: float, alpha_rad: float,
+                     x0: float = 0.0) -> np.ndarray:
+    """Bragg-type crystal whose entrance face is tilted by alpha from the z axis:
+    crystal where xa + z tan(alpha) <= x < xb at z = n dz (sample j at x0 + j dx)."""
+    seg = np.zeros((nz, 1, 2), np.int32)
+    for n in range(nz):
+        xf = xa + n * dz * math.tan(alpha_rad)
+        seg[n, 0] = (max(0, min(nx, int(math.ceil((xf - x0) / dx - 1e-9)))),
+                     max(0, min(nx, int(round((xb - x0) / dx)))))
+    return seg
+
+
 def mask_x_slab(nz: int, nx: int, dx: float, xa: float, xb: float, x0: float = 0.0,
                 za: float = -math.inf, zb: float = math.inf, dz: float = 1.0) -> np.ndarray:
     """Bragg-type slab: crystal where xa <= x < xb and za <= z < zb."""

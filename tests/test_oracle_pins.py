@@ -259,14 +259,21 @@ def test_laue_pendellosung_period():
 
 
 # ------------------------------------------------------------------ P7 Darwin-Prins
-def darwin_pin(delta_urad, w, q0, k, s):
-    """Beam-averaged plane-wave Darwin-Prins reflectivity of a thick symmetric
-    Bragg crystal (textbook two-beam dynamical theory)."""
+def darwin_pin(delta_urad, w, q0, k, s, b=-1.0):
+    """Beam-averaged plane-wave reflectivity of a thick Bragg crystal (textbook
+    two-beam dynamical theory).  b = gamma0/gammah is the asymmetry factor (the
+    ratio of the direction cosines of the incident and reflected waves on the
+    inward surface normal; -1 for the symmetric Darwin-Prins case): the
+    deviation parameter is (b dev sin 2thetaB - (1 - b) chi0 / 2) /
+    (sqrt|b| sqrt(chih chihbar)) in this build's susceptibility sign convention,
+    and R = |G -+ sqrt(G^2 - 1)|^2 on the branch below 1 (the flux ratio through
+    the surface, which a beam's total power ratio equals)."""
     th_b = math.asin(s)
     q = q0 + np.linspace(-8, 8, 40001) / w
     W = np.exp(-((q - q0) ** 2) * w * w / 2)
     dev = np.arcsin(s + q / k) - th_b
-    G = -(dev * math.sin(2 * th_b) + synth.CHI0) / np.sqrt(synth.CHIH * synth.CHIH)
+    G = (b * dev * math.sin(2 * th_b) - 0.5 * (1 - b) * synth.CHI0) / (
+        math.sqrt(abs(b)) * np.sqrt(synth.CHIH * synth.CHIH))
     r = np.sqrt(G * G - 1)
     R = np.minimum(np.abs(G + r) ** 2, np.abs(G - r) ** 2)
     return float(np.sum(W * R) / np.sum(W))
@@ -296,6 +303,44 @@ def test_thick_bragg_matches_darwin_prins_after_richardson():
         assert abs(rich - ref) <= 1e-3, (dl, r1, r2, rich, ref)
         # first order in dz: halving the step halves the bias
         assert 1.6 <= (r1 - ref) / (r2 - ref) <= 2.4
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("alpha_deg,deltas", [(10.0, (1.5, 3.0, 4.5, 6.0)), (-10.0, (0.8, 1.6, 2.4, 3.2))])
+def test_asymmetric_bragg_matches_dynamical_theory_after_richardson(alpha_deg, deltas):
+    """Thick Bragg crystal whose entrance face is tilted by alpha from the
+    Bragg planes (the asymmetric geometry of the dislocation workload): the
+    inward normal is (cos a, -sin a) in (x, z), so gamma0 = sin(thetaB - a),
+    gammah = -sin(thetaB + a) and b = -0.532 (a = +10 deg, grazing incidence:
+    wider curve, shifted to 3.3 urad) or -1.88 (a = -10 deg, grazing exit).
+    The march, extrapolated to dz -> 0, follows that curve, not the symmetric
+    one, and converges at first order."""
+    nx, dx, Lz, w, xc, xa, xb = 8192, 0.1, 600.0, 20.0, 300.0, 360.0, 800.0
+    alpha = math.radians(alpha_deg)
+    th_b = math.asin(0.5)
+    b = -math.sin(th_b - alpha) / math.sin(th_b + alpha)
+    probs, psis = [], []
+    for dz in (0.2, 0.1):
+        nz = int(round(Lz / dz))
+        seg = synth.mask_tilted_face(nz, nx, dx, dz, xa, xb, alpha)
+        det = (0, int(math.floor((xa + Lz * math.tan(alpha)) / dx)))   # the vacuum side at the last plane
+        for dl in deltas:
+            p = synth.base_problem(nx, nz, dx, dz, seg, det=det)
+            tilt = synth.envelope_tilt(synth.LAMBDA_UM, synth.D_UM, dl * 1e-6)
+            probs.append(p)
+            psis.append((synth.gaussian_beam(nx, dx, xc, w, tilt), None))
+    _, R, _ = oracle.propagate_batch(probs, psis, nthreads=min(8, os.cpu_count() or 1))
+    k = 2 * math.pi / synth.LAMBDA_UM
+    off_sym = 0.0
+    for i, dl in enumerate(deltas):
+        r1, r2 = R[i], R[len(deltas) + i]
+        tilt = synth.envelope_tilt(synth.LAMBDA_UM, synth.D_UM, dl * 1e-6)
+        ref = darwin_pin(dl, w, tilt, k, 0.5, b)
+        rich = 2 * r2 - r1
+        assert abs(rich - ref) <= 1e-3, (alpha_deg, dl, r1, r2, rich, ref)
+        assert 1.6 <= (r1 - ref) / (r2 - ref) <= 2.4
+        off_sym = max(off_sym, abs(rich - darwin_pin(dl, w, tilt, k, 0.5)))
+    assert off_sym > 0.1   # the symmetric curve is far off somewhere in the band
 
 
 # ------------------------------------------------------------------ P8/P9 strain, linearity
