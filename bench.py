@@ -235,8 +235,9 @@ def main():
     ap.add_argument("--nz", type=int, default=None, help="shorter march (profiling runs only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
-    ap.add_argument("--legs", default="cfg2,cfg3,3d,cfg4",
-                    help="extra workloads after the headline: cfg2 (dislocation, Nx 32768), cfg3 (pulse "
+    ap.add_argument("--legs", default="cfg0,cfg2,cfg3,3d,cfg4",
+                    help="extra workloads after the headline: cfg0 (64-angle FP64 scan, and its FP32 "
+                         "twin), cfg2 (dislocation, Nx 32768), cfg3 (pulse "
                          "components, one mixed launch), 3d (the paper's 3D case), cfg4 (serving mix); "
                          "'none' for the headline only")
     ap.add_argument("--serve-requests", type=int, default=1000)
@@ -324,6 +325,22 @@ def main():
     out["R_mean"] = float(np.mean(Rs[0::2]))
     legs = {}
     want = set() if args.legs == "none" else set(args.legs.split(","))
+    if "cfg0" in want:
+        # the batch takes the kernel family the autotuner measures fastest for 64 solves of this size
+        t64 = None if args.no_autotune else bpm.autotune("f64", 4096, 0, nsolves=64, nsteps=200)
+        t32 = None if args.no_autotune else bpm.autotune("f32", 4096, 0, nsolves=64, nsteps=200)
+        r64 = leg_batch(bpm, torch, synth.flat_bragg_scan(n_angles=64, precision="f64"), "cfg0 FP64", steps=3,
+                        warmup=1)
+        r32 = leg_batch(bpm, torch, synth.flat_bragg_scan(n_angles=64, precision="f32"), "cfg0 FP32", steps=3,
+                        warmup=1)
+        legs["cfg0_angle_scan"] = {
+            "workload": "64-angle scan across the Darwin width, flat symmetric Bragg slab, Nx 4096, Nz 2000, "
+                        "one batch launch",
+            "f64_value": r64["value"], "f64_ms": r64["ms_per_step"],
+            "f32_value": r32["value"], "f32_ms": r32["ms_per_step"], "unit": "cell-steps/s",
+            "autotune": {"f64": t64, "f32": t32}}
+        for prec in ("f64", "f32"):
+            bpm.schedule_set(prec, 4096, 0, "default")
     if "cfg2" in want:
         legs["cfg2_dislocation"] = dict(
             leg_batch(bpm, torch, synth.disl_bragg_cores(256), "cfg2"),
