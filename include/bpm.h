@@ -66,7 +66,8 @@ typedef enum bpm_strain_kind {
     /* straight edge dislocation, line along y, Burgers vector b along h (Eq. (15)):
      * u = b/(2 pi) * (atan2(Z, X) + X Z / (2 (1 - nu) (X^2 + Z^2))), core at (x_ref, z_ref) */
     BPM_STRAIN_EDGE_DISLOCATION = 2,
-    /* u given at every grid point: u_table[n*nx + j] (um), copied at plan creation */
+    /* u given at every grid point: u_table[n*nx + j] (um), copied at plan creation;
+     * at most 2 GiB on the device (nz*nx*4 B FP32, *8 B FP64), else BPM_E_UNSUPPORTED */
     BPM_STRAIN_TABLE = 3
 } bpm_strain_kind;
 

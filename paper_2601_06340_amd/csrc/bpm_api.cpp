@@ -212,6 +212,10 @@ static void prop_release(void *p)
 static bool is_finite(double v) { return std::isfinite(v); }
 static bool is_finite(bpm_complex c) { return std::isfinite(c.re) && std::isfinite(c.im); }
 
+// largest table (mask, strain table) one solve may hold: the kernels index
+// them with 32-bit byte offsets
+constexpr long long kMaxTableBytes = 0x7fffffffLL;
+
 bpm_status bpm::validate_desc(const bpm_plan_desc *d)
 {
     if (!d) return fail(BPM_E_INVALID, "NULL descriptor");
@@ -240,6 +244,8 @@ bpm_status bpm::validate_desc(const bpm_plan_desc *d)
     if (d->nseg < 1) return fail(BPM_E_INVALID, "nseg = %d < 1", d->nseg);
     if (d->nseg > 4) return fail(BPM_E_UNSUPPORTED, "nseg = %d: at most 4 mask intervals per step", d->nseg);
     if (d->nz > 0 && !d->seg) return fail(BPM_E_INVALID, "seg is NULL");
+    if (rows * d->nseg * 8 > kMaxTableBytes)
+        return fail(BPM_E_UNSUPPORTED, "mask of %lld rows x %d intervals: at most 2 GiB per solve", rows, d->nseg);
     for (long long i = 0; i < rows * d->nseg; ++i) {
         const int lo = d->seg[2 * i], hi = d->seg[2 * i + 1];
         if (lo < 0 || hi < 0 || lo > d->nx || hi > d->nx)
@@ -259,6 +265,9 @@ bpm_status bpm::validate_desc(const bpm_plan_desc *d)
         break;
     case BPM_STRAIN_TABLE:
         if (d->nz > 0 && !st.u_table) return fail(BPM_E_INVALID, "u_table is NULL");
+        // the kernels read tables through 32-bit byte offsets
+        if (rows * d->nx * (d->precision == BPM_F32 ? 4LL : 8LL) > kMaxTableBytes)
+            return fail(BPM_E_UNSUPPORTED, "strain table of %lld x %d samples: at most 2 GiB per solve", rows, d->nx);
         for (long long i = 0; i < rows * d->nx; ++i)
             if (!is_finite(st.u_table[i])) return fail(BPM_E_INVALID, "u_table[%lld] not finite", i);
         break;

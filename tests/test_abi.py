@@ -90,3 +90,20 @@ def test_every_synthetic_workload_passes_descriptor_validation():
         with pytest.raises(bpm.BpmError) as e:
             bpm.Plan(p)
         assert e.value.status == bpm.E_DEVICE, (p["nx"], p["nz"], p.get("kind"), str(e.value))
+
+
+def test_tables_beyond_32_bit_offsets_are_refused_before_the_device():
+    """A strain table or mask too large for the kernels' 32-bit byte offsets is
+    BPM_E_UNSUPPORTED at validation (the table itself is not read)."""
+    import numpy as np
+    from paper_2601_06340_amd import bpm, synth
+    if not os.path.exists(bpm.LIB_PATH):
+        pytest.skip("library not built")
+    nx, nz = 65536, 9000                       # FP32 table: 2.36e9 bytes
+    seg = np.zeros((nz, 1, 2), np.int32)
+    seg[:, 0, 1] = nx
+    p = synth.base_problem(nx, nz, 0.1, 0.05, seg, precision="f32",
+                           strain={"kind": "table", "u_table": np.zeros((1, nx))})
+    with pytest.raises(bpm.BpmError) as e:
+        bpm.Plan(p)
+    assert e.value.status == bpm.E_UNSUPPORTED, str(e.value)
