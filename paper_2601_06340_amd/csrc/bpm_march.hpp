@@ -539,15 +539,29 @@ __device__ __forceinline__ Cx<T> phasor(V v)
     return {cs, sn};
 }
 
+// a/N + k a for a propagator table entry k = (P - 1)/N.  The two terms of
+// k a are summed first and a/N (exact: N is a power of two) is added last, so
+// the one rounding against the large value sees the whole increment.  Added
+// one at a time, a second-order term below half an ulp (the -theta^2/2 that
+// keeps |P| = 1 for a small phase theta per step) would be dropped at every
+// step and the power of slowly turning bins would grow by theta^2 per step.
+template <typename T>
+__device__ __forceinline__ Cx<T> prop_mul(Cx<T> a, Cx<T> k, T invN)
+{
+    return {fmaT(a.x, invN, fmaT(k.x, a.x, -k.y * a.y)), fmaT(a.y, invN, fmaT(k.x, a.y, k.y * a.x))};
+}
+
 // psi+ <- psi+ + d0 psi+ + bp psi-,  psi- <- psi- + d0 psi- + bm psi+   (Eq. (12))
+// The increments are summed before the envelope itself is added, for the same
+// reason as in prop_mul.
 template <typename T>
 __device__ __forceinline__ void couple(Cx<T> &vp, Cx<T> &vm, Cx<T> d0, Cx<T> bp, Cx<T> bm)
 {
     const Cx<T> a = vp, b = vm;
-    vp = {fmaT(bp.x, b.x, fmaT(-bp.y, b.y, fmaT(d0.x, a.x, fmaT(-d0.y, a.y, a.x)))),
-          fmaT(bp.x, b.y, fmaT(bp.y, b.x, fmaT(d0.x, a.y, fmaT(d0.y, a.x, a.y))))};
-    vm = {fmaT(bm.x, a.x, fmaT(-bm.y, a.y, fmaT(d0.x, b.x, fmaT(-d0.y, b.y, b.x)))),
-          fmaT(bm.x, a.y, fmaT(bm.y, a.x, fmaT(d0.x, b.y, fmaT(d0.y, b.x, b.y))))};
+    vp = {a.x + fmaT(bp.x, b.x, fmaT(-bp.y, b.y, fmaT(d0.x, a.x, -d0.y * a.y))),
+          a.y + fmaT(bp.x, b.y, fmaT(bp.y, b.x, fmaT(d0.x, a.y, d0.y * a.x)))};
+    vm = {b.x + fmaT(bm.x, a.x, fmaT(-bm.y, a.y, fmaT(d0.x, b.x, -d0.y * b.y))),
+          b.y + fmaT(bm.x, a.y, fmaT(bm.y, a.x, fmaT(d0.x, b.y, d0.y * b.x)))};
 }
 
 // couple() where the sample is inside the crystal; outside, both envelopes
@@ -1108,10 +1122,8 @@ struct March {
                     static_for<0, E>([&](auto e) {
                         const Cx<T> kp = tload_cx<T>(propn, t, e * TH), km = tload_cx<T>(propn, t, N + e * TH);
                         const Cx<T> a = vp[e], b = vm[e];
-                        vp[e] = {fmaT(kp.x, a.x, fmaT(-kp.y, a.y, a.x * invN)),
-                                 fmaT(kp.x, a.y, fmaT(kp.y, a.x, a.y * invN))};
-                        vm[e] = {fmaT(km.x, b.x, fmaT(-km.y, b.y, b.x * invN)),
-                                 fmaT(km.x, b.y, fmaT(km.y, b.x, b.y * invN))};
+                        vp[e] = prop_mul(a, kp, invN);
+                        vm[e] = prop_mul(b, km, invN);
                     });
                     if constexpr (W > 1) pass_inv<G::LOG2G, G::LOG2M, TH>(vp, vm, twi, G::TWFINAL, t);
                 }
@@ -1346,8 +1358,8 @@ struct Staged {
             const int f = k1 * C + x.lane;
             const Cx<T> kp = tload_cx<T>(pr, f, e * 64), km = tload_cx<T>(pr, f, N + e * 64);
             const Cx<T> a = vp[e], b = vm[e];
-            vp[e] = {fmaT(kp.x, a.x, fmaT(-kp.y, a.y, a.x * invN)), fmaT(kp.x, a.y, fmaT(kp.y, a.x, a.y * invN))};
-            vm[e] = {fmaT(km.x, b.x, fmaT(-km.y, b.y, b.x * invN)), fmaT(km.x, b.y, fmaT(km.y, b.x, b.y * invN))};
+            vp[e] = prop_mul(a, kp, invN);
+            vm[e] = prop_mul(b, km, invN);
         });
         RowM::inv_local(vp, vm, x.tw + oi * TWB, x.RRp, x.RRm, x.lane, true);
         const int rbi = k1 * C + x.lane + oi;

@@ -1,0 +1,189 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times: every solve of each batch is checked for the bounds the physics fixes at
+any size (R, T in [0, 1], R + T <= 1 and exit power <= incident power in an
+absorbing crystal), and sampled solves against the FP64 oracle one by one
+(the oracle marches the same full-size solve)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import oracle  # noqa: E402
+from paper_2601_06340_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TOL = {"f64": (1e-10, 1e-12), "f32": (1e-4, 1e-5)}
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def bpm():
+    from paper_2601_06340_amd import bpm as b
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return b
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_pair(gp, gm, op, om):
+    g = np.concatenate([np.ravel(gp), np.ravel(gm)])
+    o = np.concatenate([np.ravel(op), np.ravel(om)])
+    return float(np.linalg.norm(g - o) / np.linalg.norm(o))
+
+
+def march_batch(B, cases):
+    """One batch launch over all cases, as bench.py times it."""
+    import torch
+    plans = [B.Plan(p) for p, _ in cases]
+    batch = B.Batch(plans)
+    buf = batch.pack([(psi, None) for _, psi in cases])
+    rt = torch.zeros(2 * len(plans), dtype=torch.float64, device="cuda")
+    batch.run(buf.data_ptr(), buf.data_ptr(), rt.data_ptr())
+    torch.cuda.synchronize()
+    outs = batch.unpack(buf)
+    batch.close()
+    for p in plans:
+        p.close()
+    rt = rt.cpu().numpy()
+    return outs, rt[0::2], rt[1::2]
+
+
+def check_bounds(cases, outs, R, T, label):
+    """Passive, absorbing crystals: reflected and transmitted powers within the
+    incident power, the whole exit power too.  Where a beam never meets the
+    crystal (pulse components far off the Bragg energy) T is exactly 1, so the
+    slack is what the parity bar allows R and T each: 2 x the bar on R + T."""
+    assert np.all(np.isfinite(R)) and np.all(np.isfinite(T))
+    assert np.all(R >= 0) and np.all(T >= 0)
+    slack = 2 * max(TOL[p["precision"]][1] for p, _ in cases)
+    assert np.all(R + T <= 1 + slack), (label, float(np.max(R + T)))
+    for (p, psi), (gp, gm) in zip(cases, outs):
+        pin = float(np.sum(np.abs(psi) ** 2))
+        pout = float(np.sum(np.abs(gp) ** 2) + np.sum(np.abs(gm) ** 2))
+        assert pout <= pin * (1 + slack), (label, pout / pin)
+    say(label, "bounds hold for %d solves; R in [%.3g, %.3g]" % (len(cases), float(R.min()), float(R.max())))
+
+
+def check_samples(cases, outs, R, T, idx, label):
+    probs = [cases[i][0] for i in idx]
+    psis = [(cases[i][1], None) for i in idx]
+    ofs, oR, oT = oracle.propagate_batch(probs, psis, nthreads=min(THREADS, len(idx)))
+    for k, i in enumerate(idx):
+        prec = cases[i][0]["precision"]
+        err = rel_pair(outs[i][0], outs[i][1], ofs[k][0], ofs[k][1])
+        say(label, "solve", i, "nx", cases[i][0]["nx"], "nz", cases[i][0]["nz"],
+            "rel L2 %.3e  dR %.2e  dT %.2e" % (err, abs(R[i] - oR[k]), abs(T[i] - oT[k])))
+        assert err <= TOL[prec][0], (label, i, err)
+        assert abs(R[i] - oR[k]) <= TOL[prec][1] and abs(T[i] - oT[k]) <= TOL[prec][1], (label, i)
+
+
+def test_headline_bent_laue_batch_full_size():
+    """255 FP32 bent-Laue solves, Nx 16384 x Nz 8000 (R = 1, 0.1, 10 m), one
+    launch; one sampled solve per radius against the oracle."""
+    B = bpm()
+    cases = synth.bent_laue(radii_m=(1.0, 0.1, 10.0), beams_per_radius=85, precision="f32")
+    outs, R, T = march_batch(B, cases)
+    check_bounds(cases, outs, R, T, "bent-laue 255")
+    check_samples(cases, outs, R, T, [0, 85 + 41, 170 + 84], "bent-laue 255")
+
+
+def test_config0_angle_scan_full_size_every_solve():
+    """The 64-angle FP64 scan (Nx 4096 x Nz 2000) in one launch: every solve
+    against the oracle."""
+    B = bpm()
+    cases = synth.flat_bragg_scan(n_angles=64, precision="f64")
+    outs, R, T = march_batch(B, cases)
+    check_bounds(cases, outs, R, T, "scan 64")
+    check_samples(cases, outs, R, T, list(range(64)), "scan 64")
+
+
+def test_dislocation_batch_full_size():
+    """256 FP32 dislocation solves, Nx 32768 x Nz 16000 (asymmetric trapezoid),
+    one launch of the staged lane; one sampled solve against the oracle."""
+    B = bpm()
+    cases = synth.disl_bragg_cores(256)
+    outs, R, T = march_batch(B, cases)
+    check_bounds(cases, outs, R, T, "dislocation 256")
+    check_samples(cases, outs, R, T, [137], "dislocation 256")
+
+
+def test_pulse_component_batch_full_size():
+    """1024 pulse components (Nx 2048..16384, Nz 1000..8000) in one mixed-size
+    launch; the longest and the shortest component and one between against the
+    oracle."""
+    B = bpm()
+    cases = synth.td_batch()
+    outs, R, T = march_batch(B, cases)
+    check_bounds(cases, outs, R, T, "pulse 1024")
+    cost = [p["nx"] * p["nz"] for p, _ in cases]
+    order = np.argsort(cost)
+    check_samples(cases, outs, R, T, [int(order[0]), int(order[len(order) // 2]), int(order[-1])], "pulse 1024")
+
+
+def test_paper_3d_case_full_size():
+    """The paper's 3D case (512 x 256 x 300, FP32, dislocation in a 10 um cube):
+    alone through the wide lane and in a 4-solve batch, against the oracle."""
+    B = bpm()
+    import torch
+    cases = [synth.cube_3d(seed=synth.SEED_BASE + 5 + k) for k in range(4)]
+    outs, R, T = march_batch(B, cases)
+    check_bounds(cases, outs, R, T, "3d batch")
+    p, psi = cases[0]
+    op, om, oR, oT = oracle.propagate(p, psi)
+    err = rel_pair(outs[0][0], outs[0][1], op, om)
+    plan = B.Plan(p)
+    wp, wm, wR, wT = plan.propagate(psi)
+    plan.close()
+    errw = rel_pair(wp, wm, op, om)
+    say("3d full size: batch rel L2 %.3e, wide lane %.3e, dR %.2e" % (err, errw, abs(wR - oR)))
+    assert err <= TOL["f32"][0] and errw <= TOL["f32"][0]
+    assert abs(R[0] - oR) <= TOL["f32"][1] and abs(wR - oR) <= TOL["f32"][1] and abs(wT - oT) <= TOL["f32"][1]
+    del torch
+
+
+def test_serving_stream_full_configuration():
+    """A stretch of the serving stream (200 requests of the mix at 200/s) through
+    a server configured as bench.py's (64 GB budget, 1024 slots, chunk 256):
+    every request completes within the bounds; three requests of different
+    sizes and precisions against the oracle."""
+    B = bpm()
+    import time
+    reqs = synth.serve_mix(n_req=200, rate_hz=200.0)
+    cost = np.array([r["nx"] * r["nz"] for r in reqs], float)
+    picks = []
+    for want in ("f32", "f64"):
+        cand = [i for i, r in enumerate(reqs) if r["problem"]["precision"] == want and cost[i] <= 4e7]
+        if cand:
+            picks.append(max(cand, key=lambda i: cost[i]))
+    small = [i for i, r in enumerate(reqs) if i not in picks and cost[i] <= 4e7]
+    if small:
+        picks.append(small[0])
+    srv = B.Server(hbm_budget_bytes=64 << 30, max_slots=1024, chunk_steps=256)
+    t0 = time.perf_counter()
+    tickets = []
+    for i, r in enumerate(reqs):
+        dt = t0 + r["t_arrival"] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(r["problem"], r["psi_p0"], want_fields=i in picks))
+    assert srv.drain(300.0)
+    res = [srv.poll(t) for t in tickets]
+    srv.close()
+    assert all(x is not None and x["status"] == 0 for x in res)
+    R = np.array([x["R"] for x in res])
+    T = np.array([x["T"] for x in res])
+    slack = 2 * TOL["f32"][1]      # the mix holds FP32 requests: R and T each within the FP32 bar
+    assert np.all(np.isfinite(R)) and np.all(R >= 0) and np.all(T >= 0) and np.all(R + T <= 1 + slack)
+    probs = [reqs[i]["problem"] for i in picks]
+    ofs, oR, oT = oracle.propagate_batch(probs, [(reqs[i]["psi_p0"], None) for i in picks],
+                                         nthreads=min(THREADS, len(picks)))
+    for k, i in enumerate(picks):
+        prec = probs[k]["precision"]
+        err = rel_pair(res[i]["psi_p"], res[i]["psi_m"], ofs[k][0], ofs[k][1])
+        say("serving request", i, prec, "nx", reqs[i]["nx"], "nz", reqs[i]["nz"], "rel L2 %.3e" % err)
+        assert err <= TOL[prec][0] and abs(R[i] - oR[k]) <= TOL[prec][1]
