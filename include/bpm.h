@@ -302,7 +302,9 @@ typedef struct bpm_tune_result {
  * nsolves solves (a crystal filling the window, strain of strain_kind: none, a
  * 1 m bend, a dislocation, or a zero table) over nsteps z-steps (one untimed run,
  * then the median of three), enters the fastest into the schedule table and
- * reports all.  Blocks; needs 1 <= nsolves <= 4096, 1 <= nsteps <= 100000.
+ * reports all.  A more general family (uniform, then mixed, then any) is
+ * entered only when it is more than 1 % faster than the more specialised pick,
+ * so timings within noise keep the specialised kernel.  Blocks; needs 1 <= nsolves <= 4096, 1 <= nsteps <= 100000.
  * BPM_E_INVALID for bad arguments, BPM_E_NOMEM / BPM_E_DEVICE on failure. */
 bpm_status bpm_autotune(int32_t precision, int32_t nx, int32_t strain_kind, int32_t nsolves, int32_t nsteps,
                         bpm_tune_result *out);
