@@ -3,6 +3,7 @@ times: every solve of each batch is checked for the bounds the physics fixes at
 any size (R, T in [0, 1], R + T <= 1 and exit power <= incident power in an
 absorbing crystal), and sampled solves against the FP64 oracle one by one
 (the oracle marches the same full-size solve)."""
+import math
 import os
 import sys
 
@@ -16,6 +17,18 @@ from paper_2601_06340_amd import synth  # noqa: E402
 pytestmark = pytest.mark.gpu
 TOL = {"f64": (1e-10, 1e-12), "f32": (1e-4, 1e-5)}
 THREADS = min(16, os.cpu_count() or 1)
+
+
+def t_bar(prec, t_oracle):
+    """Bar on |T - T_oracle|.  The stated FP32 tolerances are 1e-4 on the
+    envelopes and 1e-5 absolute on the reflectivity R; for T they imply, with
+    psi+ = psi+_o + d and |d| <= tol |psi_o| over the pair,
+    |dT| <= (2 |psi+_o|_D |d| + |d|^2) / P_in <= 2 tol sqrt(T) + tol^2.
+    FP64 keeps the R bar for T."""
+    tol, rbar = TOL[prec]
+    if prec == "f64":
+        return rbar
+    return 2 * tol * math.sqrt(max(float(t_oracle), 0.0)) + tol * tol
 
 
 def bpm():
@@ -57,10 +70,10 @@ def check_bounds(cases, outs, R, T, label):
     """Passive, absorbing crystals: reflected and transmitted powers within the
     incident power, the whole exit power too.  Where a beam never meets the
     crystal (pulse components far off the Bragg energy) T is exactly 1, so the
-    slack is what the parity bar allows R and T each: 2 x the bar on R + T."""
+    slack is what the parity bars allow R and T at T = 1."""
     assert np.all(np.isfinite(R)) and np.all(np.isfinite(T))
     assert np.all(R >= 0) and np.all(T >= 0)
-    slack = 2 * max(TOL[p["precision"]][1] for p, _ in cases)
+    slack = max(TOL[p["precision"]][1] + t_bar(p["precision"], 1.0) for p, _ in cases)
     assert np.all(R + T <= 1 + slack), (label, float(np.max(R + T)))
     for (p, psi), (gp, gm) in zip(cases, outs):
         pin = float(np.sum(np.abs(psi) ** 2))
@@ -79,7 +92,7 @@ def check_samples(cases, outs, R, T, idx, label):
         say(label, "solve", i, "nx", cases[i][0]["nx"], "nz", cases[i][0]["nz"],
             "rel L2 %.3e  dR %.2e  dT %.2e" % (err, abs(R[i] - oR[k]), abs(T[i] - oT[k])))
         assert err <= TOL[prec][0], (label, i, err)
-        assert abs(R[i] - oR[k]) <= TOL[prec][1] and abs(T[i] - oT[k]) <= TOL[prec][1], (label, i)
+        assert abs(R[i] - oR[k]) <= TOL[prec][1] and abs(T[i] - oT[k]) <= t_bar(prec, oT[k]), (label, i)
 
 
 def test_headline_bent_laue_batch_full_size():
@@ -142,7 +155,7 @@ def test_paper_3d_case_full_size():
     errw = rel_pair(wp, wm, op, om)
     say("3d full size: batch rel L2 %.3e, wide lane %.3e, dR %.2e" % (err, errw, abs(wR - oR)))
     assert err <= TOL["f32"][0] and errw <= TOL["f32"][0]
-    assert abs(R[0] - oR) <= TOL["f32"][1] and abs(wR - oR) <= TOL["f32"][1] and abs(wT - oT) <= TOL["f32"][1]
+    assert abs(R[0] - oR) <= TOL["f32"][1] and abs(wR - oR) <= TOL["f32"][1] and abs(wT - oT) <= t_bar("f32", oT)
     del torch
 
 
@@ -177,7 +190,7 @@ def test_serving_stream_full_configuration():
     assert all(x is not None and x["status"] == 0 for x in res)
     R = np.array([x["R"] for x in res])
     T = np.array([x["T"] for x in res])
-    slack = 2 * TOL["f32"][1]      # the mix holds FP32 requests: R and T each within the FP32 bar
+    slack = TOL["f32"][1] + t_bar("f32", 1.0)    # the mix holds FP32 requests: the FP32 R and T bars
     assert np.all(np.isfinite(R)) and np.all(R >= 0) and np.all(T >= 0) and np.all(R + T <= 1 + slack)
     probs = [reqs[i]["problem"] for i in picks]
     ofs, oR, oT = oracle.propagate_batch(probs, [(reqs[i]["psi_p0"], None) for i in picks],

@@ -22,6 +22,18 @@ TOL = {"f64": (1e-10, 1e-12), "f32": (1e-4, 1e-5)}
 SUM_ORDER_RTOL = 1e-13
 
 
+def t_bar(prec, t_oracle):
+    """Bar on |T - T_oracle|.  The stated FP32 tolerances are 1e-4 on the
+    envelopes and 1e-5 absolute on the reflectivity R; for T they imply, with
+    psi+ = psi+_o + d and |d| <= tol |psi_o| over the pair,
+    |dT| <= (2 |psi+_o|_D |d| + |d|^2) / P_in <= 2 tol sqrt(T) + tol^2.
+    FP64 keeps the R bar for T."""
+    tol, rbar = TOL[prec]
+    if prec == "f64":
+        return rbar
+    return 2 * tol * math.sqrt(max(float(t_oracle), 0.0)) + tol * tol
+
+
 def bpm():
     from paper_2601_06340_amd import bpm as b
     import torch
@@ -52,7 +64,7 @@ def check(p, psi_p0, psi_m0=None, label=""):
     tol, rtol = TOL[prec]
     say("   rel L2 %.3e  dR %.2e  dT %.2e" % (err, abs(gR - oR), abs(gT - oT)))
     assert err <= tol, (label, err)
-    assert abs(gR - oR) <= rtol and abs(gT - oT) <= rtol, (label, gR, oR, gT, oT)
+    assert abs(gR - oR) <= rtol and abs(gT - oT) <= t_bar(prec, oT), (label, gR, oR, gT, oT)
     plan.close()
     return err
 
@@ -305,6 +317,45 @@ def test_fp32_vacuum_march_keeps_power(nx, tilt):
     check(p, psi, label="vacuum nx %d tilt %g" % (nx, tilt))
 
 
+@pytest.mark.parametrize("nz", [2000, 8000, 16000])
+def test_fp32_gate_lengths_every_kernel_family(nz):
+    """The FP32 bars at Nz = 2000, 8000 and 16000 (config 0's crystal, Nx 4096,
+    three angles across the Darwin width), through the per-size kernel (single
+    plans) and through batches on the mixed-size and any-size kernels."""
+    B = bpm()
+    import torch
+    cases = synth.flat_bragg_scan(n_angles=3, nx=4096, nz=nz, precision="f32")
+    ores, oR, oT = oracle.propagate_batch([p for p, _ in cases], [(psi, None) for _, psi in cases])
+    tol, rtol = TOL["f32"]
+    for i, (p, psi) in enumerate(cases):
+        pl = B.Plan(p)
+        gp, gm, gR, gT = pl.propagate(psi)
+        pl.close()
+        err = rel_pair(gp, gm, ores[i][0], ores[i][1])
+        say("gate nz %d single %d rel L2 %.3e dR %.2e dT %.2e" % (nz, i, err, abs(gR - oR[i]), abs(gT - oT[i])))
+        assert err <= tol and abs(gR - oR[i]) <= rtol and abs(gT - oT[i]) <= t_bar("f32", oT[i])
+    for sched in ("mixed", "any"):
+        B.schedule_set("f32", 4096, 0, sched)
+        try:
+            plans = [B.Plan(p) for p, _ in cases]
+            batch = B.Batch(plans)
+            buf = batch.pack([(psi, None) for _, psi in cases])
+            rt = torch.zeros(2 * len(plans), dtype=torch.float64, device="cuda")
+            batch.run(buf.data_ptr(), buf.data_ptr(), rt.data_ptr())
+            torch.cuda.synchronize()
+            outs = batch.unpack(buf)
+            batch.close()
+            for pl in plans:
+                pl.close()
+        finally:
+            B.schedule_set("f32", 4096, 0, "default")
+        rt = rt.cpu().numpy()
+        for i in range(len(cases)):
+            err = rel_pair(outs[i][0], outs[i][1], ores[i][0], ores[i][1])
+            say("gate nz %d %s %d rel L2 %.3e dR %.2e" % (nz, sched, i, err, abs(rt[2 * i] - oR[i])))
+            assert err <= tol and abs(rt[2 * i] - oR[i]) <= rtol and abs(rt[2 * i + 1] - oT[i]) <= t_bar("f32", oT[i])
+
+
 # ------------------------------------------------------------------ batches
 def test_uniform_batch_bitwise_equals_single_solves():
     B = bpm()
@@ -344,7 +395,7 @@ def test_mixed_size_batch_one_launch_matches_oracle(prec):
         err = rel_pair(outs[i][0], outs[i][1], ores[i][0], ores[i][1])
         say("mixed", i, cases[i][0]["nx"], cases[i][0]["nz"], "%.3e" % err)
         assert err <= tol
-        assert abs(rt[2 * i] - oR[i]) <= rtol and abs(rt[2 * i + 1] - oT[i]) <= rtol
+        assert abs(rt[2 * i] - oR[i]) <= rtol and abs(rt[2 * i + 1] - oT[i]) <= t_bar(prec, oT[i])
 
 
 def test_staged_sizes_in_batch_and_chunked_server_equal_single_solves():
@@ -456,7 +507,7 @@ def test_wide_lane_matches_one_workgroup_march_and_oracle(name):
     err = rel_pair(got[0], got[1], op, om)
     tol, rtol = TOL[p["precision"]]
     say("   oracle rel L2 %.3e  dR %.2e" % (err, abs(rt[0] - oR)))
-    assert err <= tol and abs(rt[0] - oR) <= rtol and abs(rt[1] - oT) <= rtol
+    assert err <= tol and abs(rt[0] - oR) <= rtol and abs(rt[1] - oT) <= t_bar(p["precision"], oT)
     one.close()
     plan.close()
 
@@ -488,7 +539,7 @@ def test_wide_lane_degenerate_marches(name, nz):
     err = rel_pair(got[0], got[1], op, om)
     say("wide nz", nz, name, "rel L2 %.3e R %.6g oracle %.6g" % (err, rt[0], oR))
     assert err <= TOL[p["precision"]][0]
-    assert abs(rt[0] - oR) <= TOL[p["precision"]][1] and abs(rt[1] - oT) <= TOL[p["precision"]][1]
+    assert abs(rt[0] - oR) <= TOL[p["precision"]][1] and abs(rt[1] - oT) <= t_bar(p["precision"], oT)
     assert abs(rt[0] - rt1[0]) <= SUM_ORDER_RTOL * abs(rt1[0]) and abs(rt[1] - rt1[1]) <= SUM_ORDER_RTOL * abs(rt1[1])
     one.close()
     plan.close()
