@@ -69,7 +69,9 @@ def workload(name: str, beams_per_radius: int, nz_override: int | None):
     return cases, cfg
 
 
-def time_batch(bpm, torch, cases, steps, warmup):
+def time_batch(bpm, torch, cases, steps, warmup, keep=()):
+    """Times `steps` batch launches; also returns the exit envelopes of the
+    solves listed in `keep` (read back after the timed region)."""
     plans = [bpm.Plan(p) for p, _ in cases]
     batch = bpm.Batch(plans)
     d_in = batch.pack([(psi, None) for _, psi in cases])
@@ -91,10 +93,33 @@ def time_batch(bpm, torch, cases, steps, warmup):
     per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
     total_ms = ev[0].elapsed_time(ev[steps])
     Rs = rt.cpu().numpy()
+    kept = {}
+    if keep:
+        outs = batch.unpack(d_out)
+        kept = {i: outs[i] for i in keep}
     batch.close()
     for p in plans:
         p.close()
-    return per, total_ms, wall, Rs
+    return per, total_ms, wall, Rs, kept
+
+
+def fp32_error_vs_fp64(bpm, cases, Rs, kept):
+    """The FP32 batch's error against FP64 marches of the same solves on the
+    GPU (relative L2 over both envelopes, |dR|, |dT|)."""
+    import numpy as np
+    rows = []
+    for i, (gp, gm) in sorted(kept.items()):
+        p, psi = cases[i]
+        plan = bpm.Plan(dict(p, precision="f64"))
+        fp, fm, fR, fT = plan.propagate(psi)
+        plan.close()
+        d = np.concatenate([np.ravel(gp) - np.ravel(fp), np.ravel(gm) - np.ravel(fm)])
+        ref = np.concatenate([np.ravel(fp), np.ravel(fm)])
+        rows.append({"solve": i, "rel_l2": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+                     "dR": float(abs(Rs[2 * i] - fR)), "dT": float(abs(Rs[2 * i + 1] - fT))})
+    return {"solves": rows, "rel_l2_max": max(r["rel_l2"] for r in rows),
+            "dR_max": max(r["dR"] for r in rows), "dT_max": max(r["dT"] for r in rows),
+            "what": "FP32 batch results against FP64 marches of the same solves on the GPU"}
 
 
 def time_single(bpm, torch, case, steps, warmup):
@@ -127,7 +152,7 @@ def time_single(bpm, torch, case, steps, warmup):
 def fp64_plain(bpm, torch, synth):
     """One FP64 solve alone on the GPU (the flat Bragg case: Nx 4096, Nz 2000)."""
     p, psi = synth.flat_bragg_scan(n_angles=1, precision="f64")[0]
-    per, total, _, _ = time_batch(bpm, torch, [(p, psi)], 3, 1)
+    per, total, _, _, _ = time_batch(bpm, torch, [(p, psi)], 3, 1)
     cs = cell_steps(p)
     return {"value": cs / (sum(per) / len(per) / 1e3), "unit": "cell-steps/s",
             "workload": "flat_bragg Nx 4096 Nz 2000, one FP64 solve", "ms": sum(per) / len(per)}
@@ -138,14 +163,18 @@ def cell_steps(p) -> float:
     return 2.0 * p["nx"] * max(1, int(p.get("ny", 1))) * p["nz"]
 
 
-def leg_batch(bpm, torch, cases, label, steps=1, warmup=1):
-    """Throughput of one workload batch in one launch per step."""
+def leg_batch(bpm, torch, cases, label, steps=1, warmup=1, keep=()):
+    """Throughput of one workload batch in one launch per step; the solves in
+    `keep` (FP32) are also compared with FP64 marches of the same solves."""
     print("leg %s: %d solves" % (label, len(cases)), file=sys.stderr, flush=True)
-    per, total, _, _ = time_batch(bpm, torch, cases, steps, warmup)
+    per, total, _, Rs, kept = time_batch(bpm, torch, cases, steps, warmup, keep)
     cs = sum(cell_steps(p) for p, _ in cases)
     ms = total / steps
-    return {"value": cs / (ms / 1e3), "unit": "cell-steps/s", "ms_per_step": ms, "solves": len(cases),
-            "cell_steps": cs}
+    out = {"value": cs / (ms / 1e3), "unit": "cell-steps/s", "ms_per_step": ms, "solves": len(cases),
+           "cell_steps": cs}
+    if kept:
+        out["fp32_error_vs_fp64"] = fp32_error_vs_fp64(bpm, cases, Rs, kept)
+    return out
 
 
 def leg_serve(bpm, synth, n_req, rate_hz, budget_gb, chunk_steps):
@@ -288,7 +317,8 @@ def main():
             tuned = bpm.autotune(prec, nx, kind, nsolves=64, nsteps=100)
     print("workload %s: %d solves" % (cfg["workload"], len(cases)), file=sys.stderr, flush=True)
     launch_cs = sum(cell_steps(p) for p, _ in cases)
-    per, total_ms, wall, Rs = time_batch(bpm, torch, cases, args.steps, args.warmup)
+    keep = sorted({0, len(cases) // 2, len(cases) - 1}) if prec == "f32" else []
+    per, total_ms, wall, Rs, kept = time_batch(bpm, torch, cases, args.steps, args.warmup, keep)
     ms = total_ms / args.steps
     value = launch_cs / (ms / 1e3)
     per_sorted = sorted(per)
@@ -323,6 +353,8 @@ def main():
         out["fp64_plain"] = fp64_plain(bpm, torch, synth)
         out["fp32_batched_over_fp64_plain"] = value / out["fp64_plain"]["value"]
     out["R_mean"] = float(np.mean(Rs[0::2]))
+    if kept:
+        out["fp32_error_vs_fp64"] = fp32_error_vs_fp64(bpm, cases, Rs, kept)
     legs = {}
     want = set() if args.legs == "none" else set(args.legs.split(","))
     if "cfg0" in want:
@@ -332,23 +364,24 @@ def main():
         r64 = leg_batch(bpm, torch, synth.flat_bragg_scan(n_angles=64, precision="f64"), "cfg0 FP64", steps=3,
                         warmup=1)
         r32 = leg_batch(bpm, torch, synth.flat_bragg_scan(n_angles=64, precision="f32"), "cfg0 FP32", steps=3,
-                        warmup=1)
+                        warmup=1, keep=(0, 31, 63))
         legs["cfg0_angle_scan"] = {
             "workload": "64-angle scan across the Darwin width, flat symmetric Bragg slab, Nx 4096, Nz 2000, "
                         "one batch launch",
             "f64_value": r64["value"], "f64_ms": r64["ms_per_step"],
             "f32_value": r32["value"], "f32_ms": r32["ms_per_step"], "unit": "cell-steps/s",
+            "f32_error_vs_fp64": r32["fp32_error_vs_fp64"],
             "autotune": {"f64": t64, "f32": t32}}
         for prec in ("f64", "f32"):
             bpm.schedule_set(prec, 4096, 0, "default")
     if "cfg2" in want:
         legs["cfg2_dislocation"] = dict(
-            leg_batch(bpm, torch, synth.disl_bragg_cores(256), "cfg2"),
+            leg_batch(bpm, torch, synth.disl_bragg_cores(256), "cfg2", keep=(137,)),
             workload="asymmetric Bragg trapezoid + edge dislocation, Nx 32768, Nz 16000, FP32, "
                      "256 seeded core positions")
     if "cfg3" in want:
         legs["cfg3_td_batch"] = dict(
-            leg_batch(bpm, torch, synth.td_batch(), "cfg3"),
+            leg_batch(bpm, torch, synth.td_batch(), "cfg3", keep=(0, 511, 1023)),
             workload="1024 spectral components of a 20 fs pulse, Nx 2048-16384, Nz 1000-8000, FP32, "
                      "one mixed-size launch")
     if "3d" in want:
@@ -356,13 +389,14 @@ def main():
         print("leg 3d single (wide lane)", file=sys.stderr, flush=True)
         wide = time_single(bpm, torch, cube[0], steps=3, warmup=1)
         one = leg_batch(bpm, torch, cube[:1], "3d single, one workgroup", steps=1, warmup=1)
-        many = leg_batch(bpm, torch, cube, "3d batch", steps=1, warmup=1)
+        many = leg_batch(bpm, torch, cube, "3d batch", steps=1, warmup=1, keep=(0,))
         legs["paper_3d"] = {
             "workload": "3D envelopes 512 x 256 x 300 steps (the paper's 300 x 200 x 300 3D case padded to "
                         "powers of two), 10 um cube with an edge dislocation, FP32",
             "single_solve_ms": wide["ms"], "single_value": wide["value"],
             "single_one_workgroup_ms": one["ms_per_step"],
             "batch_solves": many["solves"], "value": many["value"], "unit": "cell-steps/s",
+            "fp32_error_vs_fp64": many["fp32_error_vs_fp64"],
             "paper_context": "about 13 s per realization on a Perlmutter node (Python package; CPU or GPU not stated)"}
         print("leg single large solves (wide lane)", file=sys.stderr, flush=True)
         big = {}
