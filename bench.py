@@ -177,6 +177,67 @@ def leg_batch(bpm, torch, cases, label, steps=1, warmup=1, keep=()):
     return out
 
 
+def leg_next(bpm, torch, synth):
+    """The rows after the first-order march: splitting orders 2 and 4
+    (Eq. (13)) against order 1 on the 64-angle FP32 scan; the time-domain
+    assembly of a 1024-component pulse on one grid; far-field propagation."""
+    import numpy as np
+    out = {}
+    base = synth.flat_bragg_scan(n_angles=64, precision="f32")
+    orders = {}
+    for order in (1, 2, 4):
+        cases = [(dict(p, split_order=order), psi) for p, psi in base]
+        r = leg_batch(bpm, torch, cases, "split order %d" % order, steps=3, warmup=1)
+        orders[str(order)] = {"ms": r["ms_per_step"], "value": r["value"]}
+    out["split_orders"] = dict(orders, unit="cell-steps/s (z-steps of the scan, both beams)",
+                               workload="64-angle FP32 scan, Nx 4096, Nz 2000, one batch launch per order")
+    cases = synth.td_batch(n_comp=1024, nx_choices=(4096,), nz_range=(1000, 8000))
+    print("leg td assembly: %d components" % len(cases), file=sys.stderr, flush=True)
+    plans = [bpm.Plan(p) for p, _ in cases]
+    batch = bpm.Batch(plans)
+    buf = batch.pack([(psi, None) for _, psi in cases])
+    stream = torch.cuda.current_stream()
+    sid = stream.cuda_stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    batch.run(buf.data_ptr(), buf.data_ptr(), None, sid)        # warm-up march (plans, tables, code)
+    batch.td_assemble(buf.data_ptr(), sid)
+    buf = batch.pack([(psi, None) for _, psi in cases])
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    batch.run(buf.data_ptr(), buf.data_ptr(), None, sid)
+    ev[1].record(stream)
+    batch.td_assemble(buf.data_ptr(), sid)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    cs = sum(cell_steps(p) for p, _ in cases)
+    out["td_pulse"] = {"workload": "1024 components of a 20 fs pulse on one grid, Nx 4096, Nz 1000-8000, FP32: "
+                                   "one batch march, then bpm_td_assemble to a [2][4096][1024] time trace",
+                       "march_ms": ev[0].elapsed_time(ev[1]), "march_value": cs / (ev[0].elapsed_time(ev[1]) / 1e3),
+                       "assemble_ms": ev[1].elapsed_time(ev[2]), "unit": "cell-steps/s"}
+    batch.close()
+    for pl in plans:
+        pl.close()
+    ff = {}
+    for nx in (16384, 65536):
+        p, psi = synth.flat_bragg_scan(n_angles=1, nx=nx, nz=10, precision="f32")[0]
+        plan = bpm.Plan(p)
+        st = torch.zeros(2 * nx, dtype=torch.complex64, device="cuda")
+        st[:nx] = torch.from_numpy(psi.astype(np.complex64)).cuda()
+        dst = torch.empty_like(st)
+        plan.far_field_device(2.0e6, st.data_ptr(), dst.data_ptr(), sid)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(100):
+            plan.far_field_device(2.0e6, st.data_ptr(), dst.data_ptr(), sid)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ff[str(nx)] = e0.elapsed_time(e1) / 100
+        plan.close()
+    out["far_field_ms"] = dict(ff, what="one bpm_far_field call (2 m of vacuum, both beams), FP32, by nx")
+    return out
+
+
 def leg_serve(bpm, synth, n_req, rate_hz, budget_gb, chunk_steps):
     """Serving mix: a seeded Poisson stream submitted in real time to the
     continuous-batching server; latency = submit -> done on the server clock."""
@@ -264,7 +325,7 @@ def main():
     ap.add_argument("--nz", type=int, default=None, help="shorter march (profiling runs only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
-    ap.add_argument("--legs", default="cfg0,cfg2,cfg3,3d,cfg4",
+    ap.add_argument("--legs", default="cfg0,cfg2,cfg3,3d,next,cfg4",
                     help="extra workloads after the headline: cfg0 (64-angle FP64 scan, and its FP32 "
                          "twin), cfg2 (dislocation, Nx 32768), cfg3 (pulse "
                          "components, one mixed launch), 3d (the paper's 3D case), cfg4 (serving mix); "
@@ -384,6 +445,8 @@ def main():
             leg_batch(bpm, torch, synth.td_batch(), "cfg3", keep=(0, 511, 1023)),
             workload="1024 spectral components of a 20 fs pulse, Nx 2048-16384, Nz 1000-8000, FP32, "
                      "one mixed-size launch")
+    if "next" in want:
+        legs["next_rows"] = leg_next(bpm, torch, synth)
     if "3d" in want:
         cube = [synth.cube_3d(seed=synth.SEED_BASE + 5 + k) for k in range(256)]
         print("leg 3d single (wide lane)", file=sys.stderr, flush=True)
