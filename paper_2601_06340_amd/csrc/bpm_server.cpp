@@ -182,14 +182,17 @@ void bpm_server::finish(const std::shared_ptr<Request> &r, int status)
 // z-steps a solve advances per round: chunk_steps for an FP32 nx = 16384
 // solve with polynomial strain, and for every other class the steps that take
 // the same time at its measured rate (kAnyRate), so no round waits long for
-// one class.
+// one class.  A request with no z-step (nz = 0) gets one launch of 0 steps,
+// which reports R and T of its entrance state.
 int bpm_server::steps_for(const Request &r) const
 {
+    const int left = r.desc.nz - r.step;
+    if (left <= 0) return 0;
     // a z-step of a splitting runs one FFT pair per propagation sub-step
     const double fft_pairs = r.desc.split_order == 4 ? 3.0 : 1.0;
     const double cells = (double)r.desc.nx * (r.desc.ny > 1 ? r.desc.ny : 1);
     const double s = cfg.chunk_steps * (16384.0 / cells) * (any_rate(r.desc) / kRefRate) / fft_pairs;
-    return (int)std::max(1.0, std::min<double>(std::floor(s), r.desc.nz - r.step));
+    return (int)std::max(1.0, std::min<double>(std::floor(s), left));
 }
 
 // Device setup of one admitted request (plan tables and entrance state).  Runs

@@ -842,6 +842,25 @@ def test_server_alone_equals_in_mix_and_matches_oracle():
     srv.close()
 
 
+@pytest.mark.parametrize("order", [1, 2])
+def test_server_zero_step_request_returns_entrance_state(order):
+    """A request with nz = 0 through the server: the exit state is the entrance
+    state and R, T are its detector powers (the server once ran one step)."""
+    B = bpm()
+    p = synth.base_problem(256, 0, 0.1, 0.05, synth.mask_empty(0), det=(40, 200), precision="f32")
+    p["split_order"] = order
+    a, b = synth.random_envelopes(256, 21)
+    op, om, oR, oT = oracle.propagate(p, a, b)
+    srv = B.Server(hbm_budget_bytes=1 << 30, max_slots=8, chunk_steps=16)
+    t = srv.submit(p, a, b)
+    assert srv.drain(60.0)
+    r = srv.poll(t)
+    srv.close()
+    assert r is not None and r["status"] == 0
+    assert rel_pair(r["psi_p"], r["psi_m"], op, om) <= TOL["f32"][0]
+    assert abs(r["R"] - oR) <= TOL["f32"][1] and abs(r["T"] - oT) <= t_bar("f32", oT)
+
+
 def test_server_budget_and_cancel():
     B = bpm()
     p, psi = synth.flat_bragg_scan(n_angles=1, nx=1024, nz=200, precision="f32")[0]

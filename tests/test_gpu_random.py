@@ -1,0 +1,163 @@
+"""Seeded random problems through every public march entry point against the
+oracle: sizes 64..65536 in both precisions, 0..200 z-steps, splitting orders
+1, 2 and 4, every strain kind (none, polynomial, edge dislocation with whole and
+fractional winding, table), ragged masks of 1..4 intervals per step (empty rows
+included), random detector windows and entrance fields with and without a
+reflected beam.  Each problem runs alone (bpm_propagate), all of them together
+in one mixed batch (bpm_batch_run) and through the chunked server."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import oracle  # noqa: E402
+from paper_2601_06340_amd import synth  # noqa: E402
+from paper_2601_06340_amd.synth import SplitMix64  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TOL = {"f64": (1e-10, 1e-12), "f32": (1e-4, 1e-5)}
+
+
+def bpm():
+    from paper_2601_06340_amd import bpm as b
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return b
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def t_bar(prec, t_oracle):
+    """|T - T_oracle| bar: FP64 the R bar; FP32 what the envelope bar implies,
+    2 tol sqrt(T) + tol^2 (|psi+ - psi+_o| <= tol |psi_o| over the pair)."""
+    tol, rbar = TOL[prec]
+    return rbar if prec == "f64" else 2 * tol * math.sqrt(max(float(t_oracle), 0.0)) + tol * tol
+
+
+def rel_pair(gp, gm, op, om):
+    g = np.concatenate([np.ravel(gp), np.ravel(gm)])
+    o = np.concatenate([np.ravel(op), np.ravel(om)])
+    n = np.linalg.norm(o)
+    return float(np.linalg.norm(g - o) / n) if n > 0 else float(np.linalg.norm(g))
+
+
+def ragged_mask(rng, nz, nx):
+    """Per step 1..4 disjoint intervals at random cut points (some rows empty)."""
+    nseg = rng.randint(1, 4)
+    seg = np.zeros((nz, nseg, 2), np.int32)
+    for n in range(nz):
+        if rng.uniform() < 0.1:
+            continue                                   # empty row: pure propagation
+        cuts = sorted(rng.randint(0, nx) for _ in range(2 * nseg))
+        for k in range(nseg):
+            seg[n, k] = (cuts[2 * k], cuts[2 * k + 1])
+    return seg
+
+
+def random_problem(rng, idx):
+    prec = rng.choice(["f32", "f64"])
+    big = rng.uniform() < 0.2
+    log2n = rng.randint(14, 16) if big else rng.randint(6, 13)
+    nx = 1 << log2n
+    nz = 0 if rng.uniform() < 0.05 else rng.randint(1, 40 if big else 200)
+    dx, dz = rng.uniform(0.05, 0.2), rng.uniform(0.02, 0.1)
+    Lx, Lz = nx * dx, max(nz, 1) * dz
+    seg = ragged_mask(rng, nz, nx)
+    kind = rng.choice(["none", "poly2", "edge", "edge_frac", "table"])
+    if kind == "table" and nz == 0:
+        kind = "none"
+    if kind == "poly2":
+        strain = {"kind": "poly2", "x_ref_um": rng.uniform(0, Lx), "z_ref_um": rng.uniform(0, Lz),
+                  "c": [rng.uniform(-1e-4, 1e-4), rng.uniform(-1e-6, 1e-6), rng.uniform(-1e-6, 1e-6),
+                        rng.uniform(-1e-9, 1e-9), rng.uniform(-1e-6, 1e-6), rng.uniform(-1e-9, 1e-9)]}
+    elif kind in ("edge", "edge_frac"):
+        # b = 0.38 nm winds the phase by 4 turns (whole); 0.1 nm by a fraction
+        b = rng.choice([0.38e-3, 0.19e-3]) if kind == "edge" else 0.1e-3
+        strain = {"kind": "edge_dislocation", "x_ref_um": (math.floor(rng.uniform(0, Lx) / dx) + 0.5) * dx,
+                  "z_ref_um": (math.floor(rng.uniform(0, Lz) / dz) + 0.5) * dz, "b_um": b, "nu": 0.22}
+    elif kind == "table":
+        t = SplitMix64(synth.SEED_BASE + 900 + idx)
+        strain = {"kind": "table", "u_table": (t.complex_normal(nz * nx).real.reshape(nz, nx) * 2e-5)}
+    else:
+        strain = {"kind": "none"}
+    lo = rng.randint(0, nx - 1)
+    hi = rng.randint(lo, nx)
+    p = synth.base_problem(nx, nz, dx, dz, seg, det=(lo, hi), precision=prec, strain=strain)
+    p["split_order"] = rng.choice([1, 2, 4])
+    if rng.uniform() < 0.5:
+        a, b = synth.random_envelopes(nx, synth.SEED_BASE + 700 + idx)
+    else:
+        a = synth.gaussian_beam(nx, dx, rng.uniform(0.2, 0.8) * Lx, rng.uniform(2.0, 40.0), rng.uniform(-0.5, 0.5))
+        b = None
+    return p, a, b
+
+
+def problems(seed, count):
+    rng = SplitMix64(seed)
+    return [random_problem(rng, seed * 1000 + i) for i in range(count)]
+
+
+def describe(p):
+    st = p["strain"]["kind"]
+    return "nx %d nz %d %s order %d strain %s nseg %d" % (p["nx"], p["nz"], p["precision"], p["split_order"],
+                                                          st, p["seg"].shape[1] if p["nz"] else 0)
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13, 14])
+def test_random_problems_single_batch_and_server(seed):
+    B = bpm()
+    import torch
+    cases = problems(synth.SEED_BASE + seed, 24)
+    ores, oR, oT = oracle.propagate_batch([p for p, _, _ in cases], [(a, b) for _, a, b in cases],
+                                          nthreads=min(16, os.cpu_count() or 1))
+
+    def check(label, i, gp, gm, gR, gT):
+        p = cases[i][0]
+        tol, rbar = TOL[p["precision"]]
+        err = rel_pair(gp, gm, ores[i][0], ores[i][1])
+        ok = err <= tol and abs(gR - oR[i]) <= rbar and abs(gT - oT[i]) <= t_bar(p["precision"], oT[i])
+        if not ok:
+            say(label, i, describe(p), "rel L2 %.3e dR %.2e dT %.2e" % (err, abs(gR - oR[i]), abs(gT - oT[i])))
+        assert ok, (label, i, describe(p))
+        return err
+
+    worst = {}
+    for i, (p, a, b) in enumerate(cases):
+        say("single", i, describe(p))
+        plan = B.Plan(p)
+        gp, gm, gR, gT = plan.propagate(a, b)
+        plan.close()
+        e = check("single", i, gp, gm, gR, gT)
+        worst[p["precision"]] = max(worst.get(p["precision"], 0.0), e)
+
+    say("batch of %d" % len(cases))
+    plans = [B.Plan(p) for p, _, _ in cases]
+    batch = B.Batch(plans)
+    buf = batch.pack([(a, b) for _, a, b in cases])
+    rt = torch.zeros(2 * len(plans), dtype=torch.float64, device="cuda")
+    batch.run(buf.data_ptr(), buf.data_ptr(), rt.data_ptr())
+    torch.cuda.synchronize()
+    outs = batch.unpack(buf)
+    batch.close()
+    for pl in plans:
+        pl.close()
+    rt = rt.cpu().numpy()
+    for i in range(len(cases)):
+        check("batch", i, outs[i][0], outs[i][1], rt[2 * i], rt[2 * i + 1])
+
+    say("server")
+    srv = B.Server(hbm_budget_bytes=8 << 30, max_slots=64, chunk_steps=16)
+    tickets = [srv.submit(p, a, b) for p, a, b in cases]
+    assert srv.drain(120.0)
+    res = [srv.poll(t) for t in tickets]
+    srv.close()
+    for i, r in enumerate(res):
+        assert r is not None and r["status"] == 0, (i, describe(cases[i][0]))
+        check("server", i, r["psi_p"], r["psi_m"], r["R"], r["T"])
+    say("seed", seed, "worst single rel L2", {k: "%.2e" % v for k, v in worst.items()})
