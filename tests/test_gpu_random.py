@@ -1,5 +1,6 @@
 """Seeded random problems through every public march entry point against the
-oracle: sizes 64..65536 in both precisions, 0..200 z-steps, splitting orders
+oracle: sizes 64..65536 in both precisions and 3D envelopes [16..256][512],
+0..200 z-steps, splitting orders
 1, 2 and 4, every strain kind (none, polynomial, edge dislocation with whole and
 fractional winding, table), ragged masks of 1..4 intervals per step (empty rows
 included), random detector windows and entrance fields with and without a
@@ -98,15 +99,72 @@ def random_problem(rng, idx):
     return p, a, b
 
 
+def random_problem_3d(rng, idx):
+    """3D envelopes [ny][512]: ragged masks per (step, row), every strain kind."""
+    prec = rng.choice(["f32", "f64"])
+    nx, ny = 512, 1 << rng.randint(4, 8)
+    nz = 0 if rng.uniform() < 0.05 else rng.randint(1, 30)
+    dx, dy, dz = rng.uniform(0.05, 0.2), rng.uniform(0.05, 0.3), rng.uniform(0.02, 0.1)
+    Lx, Lz = nx * dx, max(nz, 1) * dz
+    nseg = rng.randint(1, 4)
+    seg = np.zeros((nz, ny, nseg, 2), np.int32)
+    for n in range(nz):
+        for i in range(ny):
+            if rng.uniform() < 0.1:
+                continue
+            cuts = sorted(rng.randint(0, nx) for _ in range(2 * nseg))
+            for k in range(nseg):
+                seg[n, i, k] = (cuts[2 * k], cuts[2 * k + 1])
+    kind = rng.choice(["none", "poly2", "edge", "table"])
+    if kind == "table" and nz == 0:
+        kind = "none"
+    if kind == "poly2":
+        strain = {"kind": "poly2", "x_ref_um": rng.uniform(0, Lx), "z_ref_um": rng.uniform(0, Lz),
+                  "c": [0.0, rng.uniform(-1e-5, 1e-5), 0.0, 0.0, rng.uniform(-1e-4, 1e-4), 0.0]}
+    elif kind == "edge":
+        strain = {"kind": "edge_dislocation", "x_ref_um": (math.floor(rng.uniform(0, Lx) / dx) + 0.5) * dx,
+                  "z_ref_um": (math.floor(rng.uniform(0, Lz) / dz) + 0.5) * dz,
+                  "b_um": rng.choice([0.38e-3, 0.1e-3]), "nu": 0.22}
+    elif kind == "table":
+        t = SplitMix64(synth.SEED_BASE + 950 + idx)
+        strain = {"kind": "table", "u_table": t.complex_normal(nz * ny * nx).real.reshape(nz, ny, nx) * 2e-5}
+    else:
+        strain = {"kind": "none"}
+    lo = rng.randint(0, nx - 1)
+    p = synth.base_problem(nx, nz, dx, dz, seg, det=(lo, rng.randint(lo, nx)), precision=prec, strain=strain)
+    p["ny"], p["dy_um"] = ny, dy
+    p["split_order"] = rng.choice([1, 2, 4])
+    t = SplitMix64(synth.SEED_BASE + 800 + idx)
+    a = t.complex_normal(ny * nx).reshape(ny, nx)
+    b = t.complex_normal(ny * nx).reshape(ny, nx) * 0.3 if rng.uniform() < 0.5 else None
+    return p, a, b
+
+
 def problems(seed, count):
     rng = SplitMix64(seed)
-    return [random_problem(rng, seed * 1000 + i) for i in range(count)]
+    return [random_problem_3d(rng, seed * 1000 + i) if rng.uniform() < 0.15 else random_problem(rng, seed * 1000 + i)
+            for i in range(count)]
 
 
 def describe(p):
     st = p["strain"]["kind"]
-    return "nx %d nz %d %s order %d strain %s nseg %d" % (p["nx"], p["nz"], p["precision"], p["split_order"],
-                                                          st, p["seg"].shape[1] if p["nz"] else 0)
+    return "nx %d ny %d nz %d %s order %d strain %s nseg %d" % (
+        p["nx"], p.get("ny", 1), p["nz"], p["precision"], p["split_order"], st, p["seg"].shape[-2] if p["nz"] else 0)
+
+
+def oracle_results(cases):
+    """Oracle marches: the 2D problems in one thread pool, the 3D ones alone."""
+    flat = [i for i, (p, _, _) in enumerate(cases) if p.get("ny", 1) <= 1]
+    ores, oR, oT = [None] * len(cases), [0.0] * len(cases), [0.0] * len(cases)
+    fo, fR, fT = oracle.propagate_batch([cases[i][0] for i in flat], [(cases[i][1], cases[i][2]) for i in flat],
+                                        nthreads=min(16, os.cpu_count() or 1))
+    for k, i in enumerate(flat):
+        ores[i], oR[i], oT[i] = fo[k], fR[k], fT[k]
+    for i, (p, a, b) in enumerate(cases):
+        if p.get("ny", 1) > 1:
+            op, om, oR[i], oT[i] = oracle.propagate(p, a, b)
+            ores[i] = (op, om)
+    return ores, oR, oT
 
 
 @pytest.mark.parametrize("seed", [11, 12, 13, 14])
@@ -114,8 +172,7 @@ def test_random_problems_single_batch_and_server(seed):
     B = bpm()
     import torch
     cases = problems(synth.SEED_BASE + seed, 24)
-    ores, oR, oT = oracle.propagate_batch([p for p, _, _ in cases], [(a, b) for _, a, b in cases],
-                                          nthreads=min(16, os.cpu_count() or 1))
+    ores, oR, oT = oracle_results(cases)
 
     def check(label, i, gp, gm, gR, gT):
         p = cases[i][0]
