@@ -218,3 +218,44 @@ def test_random_problems_single_batch_and_server(seed):
         assert r is not None and r["status"] == 0, (i, describe(cases[i][0]))
         check("server", i, r["psi_p"], r["psi_m"], r["R"], r["T"])
     say("seed", seed, "worst single rel L2", {k: "%.2e" % v for k, v in worst.items()})
+
+
+def test_server_random_submits_and_cancels():
+    """40 random 2D/3D requests submitted in four waves while earlier ones march
+    (chunks of 8 steps, so requests span many rounds), a quarter of them
+    cancelled at random moments: every ticket ends completed (and equal to the
+    oracle) or cancelled, and the server's counters agree."""
+    B = bpm()
+    import time
+    cases = problems(synth.SEED_BASE + 21, 40)
+    ores, oR, oT = oracle_results(cases)
+    rng = SplitMix64(synth.SEED_BASE + 22)
+    srv = B.Server(hbm_budget_bytes=2 << 30, max_slots=16, chunk_steps=8)
+    tickets, cancelled = [], set()
+    for wave in range(4):
+        for p, a, b in cases[10 * wave: 10 * wave + 10]:
+            tickets.append(srv.submit(p, a, b))
+        time.sleep(rng.uniform(0.0, 0.05))
+        for _ in range(3):
+            k = rng.randint(0, len(tickets) - 1)
+            srv.cancel(tickets[k])
+            cancelled.add(k)
+    assert srv.drain(120.0)
+    res = [srv.poll(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    n_ok = n_cancel = 0
+    for i, r in enumerate(res):
+        assert r is not None, i
+        if r["status"] == 0:
+            n_ok += 1
+            p = cases[i][0]
+            err = rel_pair(r["psi_p"], r["psi_m"], ores[i][0], ores[i][1])
+            assert err <= TOL[p["precision"]][0] and abs(r["R"] - oR[i]) <= TOL[p["precision"]][1], (i, describe(p))
+        else:
+            assert i in cancelled and r["status"] == B.E_CANCELLED, (i, r["status"])
+            n_cancel += 1
+    say("random server: %d completed, %d cancelled of %d (cancel requests on %d)"
+        % (n_ok, n_cancel, len(tickets), len(cancelled)))
+    assert st["submitted"] == len(tickets) and st["failed"] == 0
+    assert st["completed"] == n_ok and st["cancelled"] == n_cancel
