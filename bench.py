@@ -330,7 +330,7 @@ def main():
                          "twin), cfg2 (dislocation, Nx 32768), cfg3 (pulse "
                          "components, one mixed launch), 3d (the paper's 3D case), cfg4 (serving mix); "
                          "'none' for the headline only")
-    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-chunk", type=int, default=256)
