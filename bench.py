@@ -340,8 +340,9 @@ def main():
                     help="first run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; every solve is independent, so N GPUs would "
-              "each march their own share of the batch (see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only. Every solve is independent, so N GPUs would each march "
+              "their own share of the batch (split by cell-step cost) and gather R/T at the end; "
+              "no multi-GPU figure is taken here.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
