@@ -44,7 +44,7 @@ typedef enum bpm_status {
     BPM_E_PENDING = 5,     /* ticket not finished yet */
     BPM_E_CANCELLED = 6,   /* ticket was cancelled before it finished */
     BPM_E_NOTFOUND = 7,    /* unknown ticket */
-    BPM_E_UNSUPPORTED = 8, /* valid request outside what this build runs */
+    BPM_E_UNSUPPORTED = 8, /* valid request outside what the library runs */
     BPM_E_NUMERIC = 9      /* non-finite input or result */
 } bpm_status;
 
@@ -135,7 +135,7 @@ typedef struct bpm_plan_info {
  * setup kernels on the current device (plan setup of Eq. (12)'s p+-, Eq. (9)-(10)).
  * Errors: BPM_E_INVALID (nx not a power of two in [64, 65536], nz < 0, a spacing
  * or wavelength <= 0, lambda >= 2d, non-finite values, bad intervals, unknown
- * kinds), BPM_E_UNSUPPORTED (nx too large for this build at this precision),
+ * kinds), BPM_E_UNSUPPORTED (nx too large for the library at this precision),
  * BPM_E_NOMEM, BPM_E_DEVICE.  *out is NULL on failure. */
 bpm_status bpm_plan_create(const bpm_plan_desc *desc, bpm_plan **out);
 void bpm_plan_destroy(bpm_plan *plan);
@@ -323,7 +323,7 @@ bpm_status bpm_schedule_load(const char *path);
 /* --- misc -------------------------------------------------------------------- */
 const char *bpm_status_str(bpm_status s);
 const char *bpm_last_error(void);
-/* Largest nx this build marches at a precision (LDS/register-resident lane). */
+/* Largest nx the library marches at a precision (LDS/register-resident lane). */
 int32_t bpm_max_nx(int32_t precision);
 
 #ifdef __cplusplus

@@ -282,7 +282,7 @@ bpm_status bpm::validate_desc(const bpm_plan_desc *d)
     int log2n = 0;
     while ((1 << log2n) < d->nx) ++log2n;
     if (log2n > max_log2n(d->precision))
-        return fail(BPM_E_UNSUPPORTED, "nx = %d above the largest size this build marches at %s (%d)", d->nx,
+        return fail(BPM_E_UNSUPPORTED, "nx = %d above the largest size the library marches at %s (%d)", d->nx,
                     d->precision == BPM_F32 ? "FP32" : "FP64", 1 << max_log2n(d->precision));
     return BPM_OK;
 }

@@ -265,7 +265,7 @@ def darwin_pin(delta_urad, w, q0, k, s, b=-1.0):
     ratio of the direction cosines of the incident and reflected waves on the
     inward surface normal; -1 for the symmetric Darwin-Prins case): the
     deviation parameter is (b dev sin 2thetaB - (1 - b) chi0 / 2) /
-    (sqrt|b| sqrt(chih chihbar)) in this build's susceptibility sign convention,
+    (sqrt|b| sqrt(chih chihbar)) in the susceptibility sign convention used here,
     and R = |G -+ sqrt(G^2 - 1)|^2 on the branch below 1 (the flux ratio through
     the surface, which a beam's total power ratio equals)."""
     th_b = math.asin(s)
