@@ -220,16 +220,17 @@ def test_random_problems_single_batch_and_server(seed):
     say("seed", seed, "worst single rel L2", {k: "%.2e" % v for k, v in worst.items()})
 
 
-def test_server_random_submits_and_cancels():
+@pytest.mark.parametrize("seed", [21, 31])
+def test_server_random_submits_and_cancels(seed):
     """40 random 2D/3D requests submitted in four waves while earlier ones march
     (chunks of 8 steps, so requests span many rounds), a quarter of them
     cancelled at random moments: every ticket ends completed (and equal to the
     oracle) or cancelled, and the server's counters agree."""
     B = bpm()
     import time
-    cases = problems(synth.SEED_BASE + 21, 40)
+    cases = problems(synth.SEED_BASE + seed, 40)
     ores, oR, oT = oracle_results(cases)
-    rng = SplitMix64(synth.SEED_BASE + 22)
+    rng = SplitMix64(synth.SEED_BASE + seed + 1)
     srv = B.Server(hbm_budget_bytes=2 << 30, max_slots=16, chunk_steps=8)
     tickets, cancelled = [], set()
     for wave in range(4):
