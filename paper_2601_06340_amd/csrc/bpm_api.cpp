@@ -173,7 +173,7 @@ static bpm_status prop_acquire(const bpm_plan_desc &d, const PlanParams *d_param
     int tab[kMaxSub];
     double afrac[kMaxSub];
     const int ntab = split_tables(order, tab, afrac);
-    const size_t one = 2 * (size_t)d.nx * ny * (d.precision == BPM_F32 ? 8 : 16);
+    const size_t one = 2 * (size_t)d.nx * ny * kPropEntryBytes;
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, one * ntab);
     if (e != hipSuccess) return hip_fail(e, "propagator table");

@@ -92,6 +92,9 @@ struct PlanParams {
 
 // 3D envelopes: nx = 2^k3DLog2Nx (one wave per x row), ny = 2^k3DLog2NyMin..2^k3DLog2NyMax.
 constexpr int k3DLog2Nx = 9, k3DLog2NyMin = 4, k3DLog2NyMax = 8;
+// bytes of one propagator table entry (P - 1)/N, both precisions: FP32 keeps
+// it as hi + lo pairs of floats, FP64 as (re, im)
+constexpr size_t kPropEntryBytes = 16;
 // launch kind of a 3D group: kLaunch3D + log2(ny)
 constexpr int kLaunch3D = 100;
 

@@ -120,6 +120,37 @@ __device__ __forceinline__ Cx<double> tload_cx(const BufView &t, Cx<double> *, i
     return {d_of(v.x, v.y), d_of(v.z, v.w)};
 }
 // real entry at byte offset lane_off (per lane) + uni_off (wave-uniform)
+// Propagator table entry k = (P - 1)/N.  The same k multiplies a bin at every
+// z-step, so in FP32 the rounding of k would add up linearly in Nz wherever a
+// field has energy at |P - 1| ~ 1; FP32 entries therefore carry k as hi + lo
+// (hi the nearest float, lo the nearest float to the remainder).
+template <typename T>
+struct PropE;
+template <>
+struct alignas(16) PropE<float> {
+    float hx, hy, lx, ly;
+};
+template <>
+struct alignas(16) PropE<double> {
+    double x, y;
+};
+static_assert(sizeof(PropE<float>) == kPropEntryBytes && sizeof(PropE<double>) == kPropEntryBytes, "table entry");
+__device__ __forceinline__ PropE<float> tload_prop(const BufView &t, PropE<float> *, int lane_i, int uni_i)
+{
+    const u4v v = __builtin_amdgcn_raw_buffer_load_b128(t.r, lane_i * 16, t.base + uni_i * 16, 0);
+    return {f_of(v.x), f_of(v.y), f_of(v.z), f_of(v.w)};
+}
+__device__ __forceinline__ PropE<double> tload_prop(const BufView &t, PropE<double> *, int lane_i, int uni_i)
+{
+    const u4v v = __builtin_amdgcn_raw_buffer_load_b128(t.r, lane_i * 16, t.base + uni_i * 16, 0);
+    return {d_of(v.x, v.y), d_of(v.z, v.w)};
+}
+template <typename T>
+__device__ __forceinline__ PropE<T> tload_prop(const BufView &t, int lane_i, int uni_i)
+{
+    return tload_prop(t, (PropE<T> *)nullptr, lane_i, uni_i);
+}
+
 __device__ __forceinline__ float tload_r(const BufView &t, float *, int lane_off, int uni_off)
 {
     return f_of(__builtin_amdgcn_raw_buffer_load_b32(t.r, lane_off, t.base + uni_off, 0));
@@ -545,8 +576,13 @@ __device__ __forceinline__ Cx<T> phasor(V v)
 // one at a time, a second-order term below half an ulp (the -theta^2/2 that
 // keeps |P| = 1 for a small phase theta per step) would be dropped at every
 // step and the power of slowly turning bins would grow by theta^2 per step.
-template <typename T>
-__device__ __forceinline__ Cx<T> prop_mul(Cx<T> a, Cx<T> k, T invN)
+// FP32: the lo products innermost, so every rounding sees k to about 2^-48.
+__device__ __forceinline__ Cx<float> prop_mul(Cx<float> a, const PropE<float> &k, float invN)
+{
+    return {fmaT(a.x, invN, fmaT(k.hx, a.x, fmaT(-k.hy, a.y, fmaT(k.lx, a.x, -k.ly * a.y)))),
+            fmaT(a.y, invN, fmaT(k.hx, a.y, fmaT(k.hy, a.x, fmaT(k.lx, a.y, k.ly * a.x))))};
+}
+__device__ __forceinline__ Cx<double> prop_mul(Cx<double> a, const PropE<double> &k, double invN)
 {
     return {fmaT(a.x, invN, fmaT(k.x, a.x, -k.y * a.y)), fmaT(a.y, invN, fmaT(k.x, a.y, k.y * a.x))};
 }
@@ -1043,7 +1079,7 @@ struct March {
         const Cx<T> *in = reinterpret_cast<const Cx<T> *>(in_base + d.in_off);
         Cx<T> *out = reinterpret_cast<Cx<T> *>(out_base + d.out_off);
         const BufView tw = buf_view(d.tw, TW_ENTRIES * (uint32_t)sizeof(Tw<T>));
-        const Cx<T> *prop = reinterpret_cast<const Cx<T> *>(d.prop);
+        const PropE<T> *prop = reinterpret_cast<const PropE<T> *>(d.prop);
         // sample index of element e of this thread: j0 + TH*e
         const int w0 = t0 >> G::LOG2LANES, l0 = t0 & (LANES - 1);
         const int j00 = w0 + W * l0;
@@ -1090,7 +1126,8 @@ struct March {
             const int oz = (n + i) & d.opaque_zero;
             const BufView twf = tw + oz * (int)sizeof(Tw<T>);
             const BufView twi = tw + ((n + i + 1) & d.opaque_zero) * (int)sizeof(Tw<T>);
-            const BufView propn = buf_view(prop + ss.table * 2 * N, 2 * N * (uint32_t)sizeof(Cx<T>), oz * (int)sizeof(Cx<T>));
+            const BufView propn = buf_view(prop + ss.table * 2 * N, 2 * N * (uint32_t)sizeof(PropE<T>),
+                                           oz * (int)sizeof(PropE<T>));
             const int t = t0 + oz;
             const int w = t >> G::LOG2LANES, l = t & (LANES - 1);
             Cx<T> *Rp = bufp + w * BUFM;
@@ -1120,7 +1157,7 @@ struct March {
                     if constexpr (W > 1) pass_fwd<G::LOG2G, G::LOG2M, TH>(vp, vm, twf, G::TWFINAL, t);
                     // ---- propagator: sample f = t + TH*e holds frequency bin f
                     static_for<0, E>([&](auto e) {
-                        const Cx<T> kp = tload_cx<T>(propn, t, e * TH), km = tload_cx<T>(propn, t, N + e * TH);
+                        const PropE<T> kp = tload_prop<T>(propn, t, e * TH), km = tload_prop<T>(propn, t, N + e * TH);
                         const Cx<T> a = vp[e], b = vm[e];
                         vp[e] = prop_mul(a, kp, invN);
                         vm[e] = prop_mul(b, km, invN);
@@ -1281,7 +1318,7 @@ struct Staged {
     // (gi) and lane within the column (lc), and the coupling context.
     struct Ctx {
         BufView in, st, tw;
-        const Cx<T> *prop;
+        const PropE<T> *prop;
         Cx<T> *CRp, *CRm, *RRp, *RRm;
         Coupler<T, SC> cpl;
         int lane, gi, lc;
@@ -1296,7 +1333,7 @@ struct Staged {
             in = buf_view(in_base + d.in_off, SB);
             st = buf_view(out_base + d.out_off, SB);   // the solve's state [2][N]
             tw = buf_view(d.tw, TW_TOTAL * (uint32_t)sizeof(Tw<T>));
-            prop = reinterpret_cast<const Cx<T> *>(d.prop);
+            prop = reinterpret_cast<const PropE<T> *>(d.prop);
             lane = lane_;
             gi = lane / LC;
             lc = lane % LC;
@@ -1351,12 +1388,12 @@ struct Staged {
         }
         RowM::fwd_local(vp, vm, x.tw + oz * TWB, x.RRp, x.RRm, x.lane, true);
         // bin k2 = lane + 64 e of row k1 is frequency k1 + R k2
-        const BufView pr = buf_view(x.prop + ss.table * 2 * N, 2 * N * (uint32_t)sizeof(Cx<T>),
-                                    oz * (int)sizeof(Cx<T>));
+        const BufView pr = buf_view(x.prop + ss.table * 2 * N, 2 * N * (uint32_t)sizeof(PropE<T>),
+                                    oz * (int)sizeof(PropE<T>));
         const T invN = x.invN;
         static_for<0, E>([&](auto e) {
             const int f = k1 * C + x.lane;
-            const Cx<T> kp = tload_cx<T>(pr, f, e * 64), km = tload_cx<T>(pr, f, N + e * 64);
+            const PropE<T> kp = tload_prop<T>(pr, f, e * 64), km = tload_prop<T>(pr, f, N + e * 64);
             const Cx<T> a = vp[e], b = vm[e];
             vp[e] = prop_mul(a, kp, invN);
             vm[e] = prop_mul(b, km, invN);

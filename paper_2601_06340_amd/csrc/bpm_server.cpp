@@ -109,7 +109,7 @@ size_t estimate_bytes(const bpm_plan_desc &d)
     double afrac[kMaxSub];
     const int ntab = split_tables(d.split_order <= 1 ? 1 : d.split_order, tab, afrac);
     const size_t ny = d.ny > 1 ? d.ny : 1;
-    size_t b = 2 * (size_t)d.nx * ny * eb * (1 + ntab);                  // state + propagator tables
+    size_t b = 2 * (size_t)d.nx * ny * (eb + kPropEntryBytes * ntab);    // state + propagator tables
     b += (size_t)std::max(d.nz, 1) * ny * d.nseg * 2 * sizeof(int32_t);  // mask
     if (d.strain.kind == BPM_STRAIN_TABLE) b += (size_t)d.nz * ny * d.nx * (d.precision == BPM_F32 ? 4 : 8);
     b += 4096;                                                       // scalars, descriptors

@@ -50,7 +50,7 @@ __device__ void coupling_substep(const PlanParams &P, double A, int form, SubSte
 // afrac*dz.  The table of a staged size is stored in [k1][k2] order (frequency
 // f = k1 + R k2 at k1*(nx/R) + k2, R = 2^log2r); log2r = 0 keeps natural order.
 template <typename T>
-__global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, Cx<T> *prop, int log2r, double afrac)
+__global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, PropE<T> *prop, int log2r, double afrac)
 {
     const PlanParams P = *pp;
     const double k = 2.0 * M_PI / P.lambda;
@@ -105,7 +105,13 @@ __global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, Cx<T> *prop,
                 ky = -mag * sin(afrac * dzh * c);
             }
             const int pos = log2r ? (f & ((1 << log2r) - 1)) * (nx >> log2r) + (f >> log2r) : f;
-            prop[beam * cells + pos] = {(T)(kx * invn), (T)(ky * invn)};
+            const double ex = kx * invn, ey = ky * invn;
+            if constexpr (std::is_same<T, float>::value) {
+                const float hx = (float)ex, hy = (float)ey;
+                prop[beam * cells + pos] = {hx, hy, (float)(ex - (double)hx), (float)(ey - (double)hy)};
+            } else {
+                prop[beam * cells + pos] = {ex, ey};
+            }
         }
     }
 }
@@ -234,10 +240,10 @@ hipError_t launch_plan_setup(const PlanParams *d_params, PlanScalars *d_sc, void
 {
     const int bs = 256, gs = d_prop ? (cells + bs - 1) / bs : 1;
     if (prec == PREC_F32)
-        hipLaunchKernelGGL(k_plan_setup<float>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (Cx<float> *)d_prop, log2r,
+        hipLaunchKernelGGL(k_plan_setup<float>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (PropE<float> *)d_prop, log2r,
                            afrac);
     else
-        hipLaunchKernelGGL(k_plan_setup<double>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (Cx<double> *)d_prop,
+        hipLaunchKernelGGL(k_plan_setup<double>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (PropE<double> *)d_prop,
                            log2r, afrac);
     return hipGetLastError();
 }

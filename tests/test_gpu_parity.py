@@ -23,14 +23,12 @@ SUM_ORDER_RTOL = 1e-13
 
 
 def t_bar(prec, t_oracle):
-    """Bar on |T - T_oracle|.  The stated FP32 tolerances are 1e-4 on the
-    envelopes and 1e-5 absolute on the reflectivity R; for T they imply, with
-    psi+ = psi+_o + d and |d| <= tol |psi_o| over the pair,
-    |dT| <= (2 |psi+_o|_D |d| + |d|^2) / P_in <= 2 tol sqrt(T) + tol^2.
-    FP64 keeps the R bar for T."""
-    tol, rbar = TOL[prec]
-    if prec == "f64":
-        return rbar
+    """Bar on |T - T_oracle|.  The stated tolerances bound the envelopes
+    (relative L2: FP64 1e-10, FP32 1e-4) and, in FP32, the reflectivity R
+    (1e-5 absolute); for T they imply, with psi+ = psi+_o + d and
+    |d| <= tol |psi_o| over the pair,
+    |dT| <= (2 |psi+_o|_D |d| + |d|^2) / P_in <= 2 tol sqrt(T) + tol^2."""
+    tol = TOL[prec][0]
     return 2 * tol * math.sqrt(max(float(t_oracle), 0.0)) + tol * tol
 
 

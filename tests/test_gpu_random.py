@@ -35,10 +35,13 @@ def say(*a):
 
 
 def t_bar(prec, t_oracle):
-    """|T - T_oracle| bar: FP64 the R bar; FP32 what the envelope bar implies,
-    2 tol sqrt(T) + tol^2 (|psi+ - psi+_o| <= tol |psi_o| over the pair)."""
-    tol, rbar = TOL[prec]
-    return rbar if prec == "f64" else 2 * tol * math.sqrt(max(float(t_oracle), 0.0)) + tol * tol
+    """Bar on |T - T_oracle|.  The stated tolerances bound the envelopes
+    (relative L2: FP64 1e-10, FP32 1e-4) and, in FP32, the reflectivity R
+    (1e-5 absolute); for T they imply, with psi+ = psi+_o + d and
+    |d| <= tol |psi_o| over the pair,
+    |dT| <= (2 |psi+_o|_D |d| + |d|^2) / P_in <= 2 tol sqrt(T) + tol^2."""
+    tol = TOL[prec][0]
+    return 2 * tol * math.sqrt(max(float(t_oracle), 0.0)) + tol * tol
 
 
 def rel_pair(gp, gm, op, om):
