@@ -15,7 +15,9 @@ import oracle  # noqa: E402
 from paper_2601_06340_amd import synth  # noqa: E402
 
 pytestmark = pytest.mark.gpu
-TOL = {"f64": (1e-10, 1e-12), "f32": (1e-4, 1e-5)}
+# (envelope relative L2, |dR|): FP32 as stated; FP64 states only the envelope
+# bar, which bounds |dR| by 2 tol sqrt(R) + tol^2 <= 2e-10 (R <= 1)
+TOL = {"f64": (1e-10, 2e-10), "f32": (1e-4, 1e-5)}
 THREADS = min(16, os.cpu_count() or 1)
 
 

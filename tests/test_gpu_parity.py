@@ -1,8 +1,9 @@
 """Parity of the HIP march (through the C ABI) with the FP64 oracle.
 
 Bars: FP64 path relative L2 <= 1e-10 on the exit envelopes, FP32 path <= 1e-4,
-|dR|, |dT| <= 1e-5 for FP32 (1e-12 for FP64).  Relative L2 is taken over the
-pair (psi+, psi-) of a solve.  Inputs are seeded and identical on both sides.
+|dR| <= 1e-5 for FP32 (2e-10 for FP64), |dT| within the bound the envelope bar
+implies.  Relative L2 is taken over the pair (psi+, psi-) of a solve.  Inputs
+are seeded and identical on both sides.
 """
 import math
 import sys
@@ -15,7 +16,9 @@ from paper_2601_06340_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": (1e-10, 1e-12), "f32": (1e-4, 1e-5)}
+# (envelope relative L2, |dR|): FP32 as stated; FP64 states only the envelope
+# bar, which bounds |dR| by 2 tol sqrt(R) + tol^2 <= 2e-10 (R <= 1)
+TOL = {"f64": (1e-10, 2e-10), "f32": (1e-4, 1e-5)}
 # R and T of the same envelopes summed in two groupings (per thread vs per
 # workgroup): FP64 sums of n <= 2^18 non-negative terms, whose rounding-order
 # differences are of order sqrt(n) 2^-53 ~ 6e-14
