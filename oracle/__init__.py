@@ -10,6 +10,7 @@ identical inputs without sharing code.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -61,35 +62,69 @@ class _Scalars(C.Structure):
 _lib = None
 
 
+def _open(path: str):
+    L = C.CDLL(path)
+    cd = C.POINTER(C.c_double)
+    L.oracle_fft.argtypes = [cd, C.c_int, C.c_int]
+    L.oracle_dft.argtypes = [cd, cd, C.c_int, C.c_int]
+    L.oracle_dft.restype = None
+    L.oracle_bessel_series.argtypes = [C.c_double, C.c_double, cd, cd]
+    L.oracle_bessel_series.restype = None
+    L.oracle_exp_series.argtypes = [C.c_double, C.c_double, cd, cd]
+    L.oracle_exp_series.restype = None
+    L.oracle_coupling.argtypes = [C.POINTER(_Desc), C.c_double, C.c_int, cd, cd, cd]
+    L.oracle_propagator_frac.argtypes = [C.POINTER(_Desc), C.c_double, cd, cd]
+    L.oracle_split_sequence.argtypes = [C.c_int, cd, cd]
+    L.oracle_strain_phase_z.argtypes = [C.POINTER(_Desc), C.c_int, C.c_int, C.c_double]
+    L.oracle_strain_phase_z.restype = C.c_double
+    L.oracle_td_assemble.argtypes = [C.POINTER(_Desc), C.c_int, cd, cd]
+    L.oracle_scalars_get.argtypes = [C.POINTER(_Desc), C.POINTER(_Scalars)]
+    L.oracle_propagator.argtypes = [C.POINTER(_Desc), cd, cd]
+    L.oracle_strain_phase.argtypes = [C.POINTER(_Desc), C.c_int, C.c_int]
+    L.oracle_strain_phase.restype = C.c_double
+    L.oracle_propagate.argtypes = [C.POINTER(_Desc), cd, cd, cd, cd]
+    L.oracle_propagate_batch.argtypes = [C.POINTER(_Desc), C.c_int, C.POINTER(cd),
+                                         cd, cd, C.c_int]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        L = C.CDLL(_LIB)
-        cd = C.POINTER(C.c_double)
-        L.oracle_fft.argtypes = [cd, C.c_int, C.c_int]
-        L.oracle_dft.argtypes = [cd, cd, C.c_int, C.c_int]
-        L.oracle_dft.restype = None
-        L.oracle_bessel_series.argtypes = [C.c_double, C.c_double, cd, cd]
-        L.oracle_bessel_series.restype = None
-        L.oracle_exp_series.argtypes = [C.c_double, C.c_double, cd, cd]
-        L.oracle_exp_series.restype = None
-        L.oracle_coupling.argtypes = [C.POINTER(_Desc), C.c_double, C.c_int, cd, cd, cd]
-        L.oracle_propagator_frac.argtypes = [C.POINTER(_Desc), C.c_double, cd, cd]
-        L.oracle_split_sequence.argtypes = [C.c_int, cd, cd]
-        L.oracle_strain_phase_z.argtypes = [C.POINTER(_Desc), C.c_int, C.c_int, C.c_double]
-        L.oracle_strain_phase_z.restype = C.c_double
-        L.oracle_td_assemble.argtypes = [C.POINTER(_Desc), C.c_int, cd, cd]
-        L.oracle_scalars_get.argtypes = [C.POINTER(_Desc), C.POINTER(_Scalars)]
-        L.oracle_propagator.argtypes = [C.POINTER(_Desc), cd, cd]
-        L.oracle_strain_phase.argtypes = [C.POINTER(_Desc), C.c_int, C.c_int]
-        L.oracle_strain_phase.restype = C.c_double
-        L.oracle_propagate.argtypes = [C.POINTER(_Desc), cd, cd, cd, cd]
-        L.oracle_propagate_batch.argtypes = [C.POINTER(_Desc), C.c_int, C.POINTER(cd),
-                                             cd, cd, C.c_int]
-        _lib = L
+        _lib = _open(_LIB)
     return _lib
+
+
+def build_variant(src_text: str, out_path: str) -> str:
+    """Compile another C text of the oracle (same flags) to ``out_path``.  The
+    mutation tests use it to build copies with one deliberate mistake each."""
+    c_path = out_path[:-3] + ".c" if out_path.endswith(".so") else out_path + ".c"
+    with open(c_path, "w") as f:
+        f.write(src_text)
+    cmd = ["gcc", "-std=gnu99", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+           "-I", _HERE, "-o", out_path, c_path, "-lm", "-lpthread"]
+    subprocess.run(cmd, check=True)
+    return out_path
+
+
+def source_text() -> str:
+    with open(_SRC) as f:
+        return f.read()
+
+
+@contextlib.contextmanager
+def using(path: str):
+    """Route every call of this module to another build of the oracle for the
+    duration of the block."""
+    global _lib
+    saved = _lib
+    _lib = _open(path)
+    try:
+        yield
+    finally:
+        _lib = saved
 
 
 def _dptr(a: np.ndarray):

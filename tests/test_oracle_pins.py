@@ -374,9 +374,9 @@ def test_dislocation_phase_winds_by_h_dot_b():
 
     hb = 2 * math.pi * 0.38e-3 / synth.D_UM
     assert hb == pytest.approx(8 * math.pi, rel=1e-12)
-    # unwrapped winding (small steps, no jump exceeds pi) around the core
-    assert loop(480, 520, 80, 120) == pytest.approx(hb, abs=1e-6) or \
-        abs(loop(480, 520, 80, 120) - hb) % (2 * math.pi) < 1e-6
+    # unwrapped winding (small steps, no jump exceeds pi) counter-clockwise in
+    # (x, z) around the core: +h.b exactly (a reversed or missing winding fails)
+    assert loop(480, 520, 80, 120) == pytest.approx(hb, abs=1e-6)
     assert abs(loop(600, 640, 80, 120)) <= 1e-9
 
 

@@ -1,0 +1,454 @@
+"""Value pins of the oracle's strain branches and of its evanescent propagator.
+
+Each pin compares the oracle with a result fixed by something other than the
+oracle's own formulas:
+
+* Shift identities (Eq. (11)-(12), with the strain phase h u of Eq. (11)).
+  If the per-step phase factor exp(i h u(x_j, z_n)) is a short sum of grid
+  harmonics sum_k alpha_k exp(2 pi i m_k j / N), the real-space coupling is a
+  sum of whole-bin shifts of the spectra:
+      F[psi+]' = a0 F[psi+] + a+ sum_k alpha_k      roll(F[psi-], +m_k)
+      F[psi-]' = a0 F[psi-] + a- sum_k conj(alpha_k) roll(F[psi+], -m_k)
+  so a full-window crystal evolves exactly (up to rounding) in Fourier space,
+  with no real-space step at all.  The strain coefficients are chosen to make
+  the phase such a sum: a linear term with h c1 dx = 2 pi m / N (a tilt by m
+  bins), a bend c4 X Z with h c4 dx dz = 2 pi kappa / N (a shift that grows by
+  kappa bins per step from the reference plane, z_ref on the grid), c2 Z and
+  c5 Z^2 (a phase per step), c3 X^2 with h c3 dx^2 = pi / 2 (i^((j+mu)^2), a mix
+  of the shifts 0 and N/2).  The coupling scalars come from the Fourier
+  harmonics of exp(i A delta_eps) by the trapezoid rule (Eq. (9)-(10)) or from
+  scipy's expm of the two-beam generator (the splittings of Eq. (13)), the
+  propagator from the plain square-root formula of Eq. (12).
+* Eq. (15) evaluated in its general vector form, in the dislocation's own
+  frame, for a line along y and b along h; and elastic equilibrium: the
+  oracle's u_x together with Eq. (15)'s u_z must satisfy Navier's equation of
+  plane strain, (1 - 2 nu) lap u + grad div u = 0, away from the core, which
+  fixes the 2 (1 - nu) of the X Z / r^2 term.
+* The evanescent branch of the propagator: the analytic continuation of
+  exp(i dzh (S - c)) with the principal complex square root, S = i sqrt(p^2 - 1),
+  which decays.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sl
+
+import oracle
+from paper_2601_06340_amd import synth
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def consts(p):
+    k = 2 * math.pi / p["lambda_um"]
+    h = 2 * math.pi / p["d_um"]
+    s = h / (2 * k)
+    return k, h, s, math.sqrt(1 - s * s)
+
+
+def harmonics(p, b=1.0):
+    """n = 0, +1, -1 Fourier coefficients in theta of
+    exp(i A (chi0 + chih e^{i theta} + chihb e^{-i theta})), A = b k dz / (2c):
+    Eq. (9)-(10) (Jacobi-Anger), by the trapezoid rule (spectrally exact here)."""
+    k, _, _, c = consts(p)
+    A = b * k * p["dz_um"] / (2 * c)
+    M = 64
+    th = 2 * np.pi * np.arange(M) / M
+    f = np.exp(1j * A * (p["chi0"] + p["chih"] * np.exp(1j * th) + p["chihb"] * np.exp(-1j * th)))
+    cn = lambda n: complex(np.mean(f * np.exp(-1j * n * th)))
+    return cn(0), cn(1), cn(-1)
+
+
+def expm_coupling(p, b):
+    """Coupling sub-step of the splittings: expm of i A [[chi0, chih], [chihb, chi0]]."""
+    k, _, _, c = consts(p)
+    A = b * k * p["dz_um"] / (2 * c)
+    M = sl.expm(1j * A * np.array([[p["chi0"], p["chih"]], [p["chihb"], p["chi0"]]]))
+    return complex(M[0, 0]), complex(M[0, 1]), complex(M[1, 0])
+
+
+def plain_propagator(p, a=1.0):
+    """exp(i a k dz (sqrt(1 - (q +/- s)^2) - c)) on numpy's frequency grid, the
+    principal complex root beyond |q +/- s| = 1 (no 1/N: numpy's ifft has it)."""
+    k, _, s, c = consts(p)
+    q = 2 * np.pi * np.fft.fftfreq(p["nx"], p["dx_um"]) / k
+    dzh = a * k * p["dz_um"]
+    S = lambda v: np.sqrt(1 - v * v + 0j)
+    return np.exp(1j * dzh * (S(q + s) - c)), np.exp(1j * dzh * (S(q - s) - c))
+
+
+def spectral_march(p, psi_p, psi_m, terms, order=1):
+    """Full-window crystal marched in Fourier space.  terms(n, zoff) lists the
+    (alpha, m) of exp(i h u(x_j, (n + zoff) dz)) = sum alpha exp(2 pi i m j / N)."""
+    Fp, Fm = np.fft.fft(psi_p), np.fft.fft(psi_m)
+    if order == 1:
+        seq = [(1.0, 1.0, 0.0, harmonics(p))]
+    elif order == 2:
+        half = expm_coupling(p, 0.5)
+        seq = [(0.0, 0.5, 0.0, half), (1.0, 0.5, 1.0, half)]
+    else:
+        raise ValueError(order)
+    props = {a: plain_propagator(p, a) for a, _, _, _ in seq if a != 0.0}
+    for n in range(p["nz"]):
+        for a, _, zoff, (a0, ap, am) in seq:
+            if a != 0.0:
+                Pp, Pm = props[a]
+                Fp, Fm = Fp * Pp, Fm * Pm
+            sp = np.zeros_like(Fp)
+            sm = np.zeros_like(Fm)
+            for alpha, m in terms(n, zoff):
+                sp += alpha * np.roll(Fm, m)
+                sm += np.conj(alpha) * np.roll(Fp, -m)
+            Fp, Fm = a0 * Fp + ap * sp, a0 * Fm + am * sm
+    return np.fft.ifft(Fp), np.fft.ifft(Fm)
+
+
+NX, NZ, DX, DZ = 256, 160, 0.1, 0.025
+X0, XREF = 3.3, 11.7          # grid origin and strain reference (x0 - x_ref not a multiple of dx)
+NREF = 57                     # z_ref = NREF dz, on the grid
+CHIH2, CHIHB2 = complex(-1.5e-6, 8e-9), complex(-1.1e-6, -3e-9)   # chih != chihb
+
+
+def problem(strain, nz=NZ, order=1, x0=X0, chihb=CHIHB2):
+    p = synth.base_problem(NX, nz, DX, DZ, synth.mask_full(nz, NX), chih=CHIH2, chihb=chihb,
+                           x0=x0, strain=strain)
+    p["split_order"] = order
+    return p
+
+
+def fields(seed):
+    a, b = synth.random_envelopes(NX, seed)
+    return a, 0.5 * b
+
+
+def check_march(p, terms, order=1, tol=2e-10, seed=5):
+    a, b = fields(seed)
+    op, om, _, _ = oracle.propagate(p, a, b)
+    cp, cm = spectral_march(p, a, b, terms, order)
+    err = rel_l2(np.concatenate([op, om]), np.concatenate([cp, cm]))
+    assert err <= tol, err
+    return err
+
+
+# ------------------------------------------------------------------ POLY2, coefficient by coefficient
+def pin_poly2_linear_x():
+    """u = c1 X with h c1 dx = 2 pi m / N: a tilt of psi- by m bins relative to
+    psi+, with the constant phase h c1 (x0 - x_ref)."""
+    _, h, _, _ = consts(problem(None))
+    m = 3
+    c1 = 2 * math.pi * m / (NX * h * DX)
+    p = problem({"kind": "poly2", "x_ref_um": XREF, "z_ref_um": 0.0, "c": [0, c1, 0, 0, 0, 0]})
+    alpha = np.exp(1j * h * c1 * (X0 - XREF))
+    check_march(p, lambda n, zo: [(alpha, m)])
+
+
+def pin_poly2_z_terms():
+    """u = c0 + c2 Z + c5 Z^2 (no x dependence): a phase per step, taken at
+    z_n = n dz (Eq. (12) couples after the propagation of step n)."""
+    _, h, _, _ = consts(problem(None))
+    zref = 1.37
+    c0, c2, c5 = 2.1e-5, 0.3 / (h * DZ), 0.05 / (h * DZ * DZ * NZ)
+    p = problem({"kind": "poly2", "x_ref_um": XREF, "z_ref_um": zref, "c": [c0, 0, c2, 0, 0, c5]})
+
+    def terms(n, zo):
+        Z = (n + zo) * DZ - zref
+        return [(np.exp(1j * h * (c0 + c2 * Z + c5 * Z * Z)), 0)]
+    check_march(p, terms)
+
+
+def bend_c4(kappa=1):
+    _, h, _, _ = consts(problem(None))
+    return 2 * math.pi * kappa / (NX * h * DX * DZ)
+
+
+def bend_terms(c4, kappa, h, x0=X0):
+    """u = c4 X Z, h c4 dx dz = 2 pi kappa / N, z_ref = NREF dz: at height
+    (n + zoff) dz the factor is exp(2 pi i kappa (n + zoff - NREF) j / N) times
+    exp(i h c4 (x0 - x_ref) Z)."""
+    def terms(n, zo):
+        Z = (n + zo - NREF) * DZ
+        return [(np.exp(1j * h * c4 * (x0 - XREF) * Z), int(round(kappa * (n + zo - NREF))))]
+    return terms
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_poly2_bend_xz_is_a_growing_shift(order):
+    pin_poly2_bend(order)
+
+
+def pin_poly2_bend(order=1):
+    """The bend of the headline workload, u = c4 X Z: the shift between the
+    beams' spectra changes by kappa bins per step, zero at z_ref.  Orders 2
+    (coupling sub-steps at z_n and z_n + dz, Eq. (13)) ride the same identity."""
+    kappa = 1
+    c4 = bend_c4(kappa)
+    _, h, _, _ = consts(problem(None))
+    p = problem({"kind": "poly2", "x_ref_um": XREF, "z_ref_um": NREF * DZ, "c": [0, 0, 0, 0, c4, 0]},
+                order=order)
+    check_march(p, bend_terms(c4, kappa, h), order=order)
+
+
+def pin_poly2_quadratic_x():
+    """u = c3 X^2 with h c3 dx^2 = pi / 2 and x0 - x_ref = mu dx:
+    exp(i h u) = i^((j + mu)^2) = (1 + i)/2 + (1 - i)/2 (-1)^(j + mu)."""
+    _, h, _, _ = consts(problem(None))
+    mu = 7
+    c3 = math.pi / (2 * h * DX * DX)
+    p = problem({"kind": "poly2", "x_ref_um": X0 - mu * DX, "z_ref_um": 0.0, "c": [0, 0, 0, c3, 0, 0]})
+    check_march(p, lambda n, zo: [((1 + 1j) / 2, 0), ((1 - 1j) / 2 * (-1) ** mu, NX // 2)])
+
+
+def test_poly2_linear_x_is_a_tilt():
+    pin_poly2_linear_x()
+
+
+def test_poly2_z_terms_are_a_phase_per_step():
+    pin_poly2_z_terms()
+
+
+def test_poly2_quadratic_x_is_two_shifts():
+    pin_poly2_quadratic_x()
+
+
+def test_shift_identity_fails_for_a_wrong_phase():
+    """The closed form is sensitive: the bend's shift taken one step late (the
+    strain sampled at z_{n+1}) misses the oracle by far more than rounding."""
+    kappa = 1
+    c4 = bend_c4(kappa)
+    _, h, _, _ = consts(problem(None))
+    p = problem({"kind": "poly2", "x_ref_um": XREF, "z_ref_um": NREF * DZ, "c": [0, 0, 0, 0, c4, 0]})
+    late = bend_terms(c4, kappa, h)
+    with pytest.raises(AssertionError):
+        check_march(p, lambda n, zo: late(n + 1, zo))
+
+
+# ------------------------------------------------------------------ TABLE
+def pin_table_bend():
+    """A TABLE holding the bend's displacement at every (x_j, z_n) gives the
+    bend's closed form (row n of the [nz][nx] table at step n)."""
+    kappa = 1
+    c4 = bend_c4(kappa)
+    _, h, _, _ = consts(problem(None))
+    X = X0 + DX * np.arange(NX) - XREF
+    Z = (np.arange(NZ) - NREF) * DZ
+    table = c4 * Z[:, None] * X[None, :]
+    p = problem({"kind": "table", "u_table": table})
+    check_march(p, bend_terms(c4, kappa, h))
+
+
+def pin_table_orientation():
+    """Tables that vary only along z (a phase per step) and only along x (a
+    tilt by m bins), with nz != nx: a transposed index fails both."""
+    _, h, _, _ = consts(problem(None))
+    nz = 96
+    theta = 0.37 * np.arange(nz) + 0.002 * np.arange(nz) ** 2
+    pz = problem({"kind": "table", "u_table": np.repeat((theta / h)[:, None], NX, axis=1)}, nz=nz)
+    check_march(pz, lambda n, zo: [(np.exp(1j * theta[n]), 0)])
+    m = 5
+    phx = 2 * math.pi * m * np.arange(NX) / NX + 0.4
+    px = problem({"kind": "table", "u_table": np.repeat((phx / h)[None, :], nz, axis=0)}, nz=nz)
+    check_march(px, lambda n, zo: [(np.exp(0.4j), m)])
+
+
+def test_table_holds_the_bend():
+    pin_table_bend()
+
+
+def test_table_index_is_row_n_column_j():
+    pin_table_orientation()
+
+
+# ------------------------------------------------------------------ EDGE_DISLOCATION, Eq. (15)
+NU, BLEN = 0.22, 0.38e-3
+
+
+def eq15(rx, rz, tau, bvec, nu=NU):
+    """Eq. (15) in the dislocation's own frame: x0 along the line tau, z0 along
+    tau x b, y0 = z0 x x0; returns the lab-frame displacement (ux, uy, uz) at
+    r - r_d = (rx, 0, rz) (arrays)."""
+    tau = np.asarray(tau, float) / np.linalg.norm(tau)
+    bvec = np.asarray(bvec, float)
+    ez0 = np.cross(tau, bvec)
+    ez0 /= np.linalg.norm(ez0)
+    ey0 = np.cross(ez0, tau)
+    rx, rz = np.asarray(rx, float), np.asarray(rz, float)
+    y0 = rx * ey0[0] + rz * ey0[2]
+    z0 = rx * ez0[0] + rz * ez0[2]
+    r2 = y0 * y0 + z0 * z0
+    edge = bvec - tau * np.dot(bvec, tau)
+    txb = np.cross(tau, bvec)
+    t1 = np.arctan2(z0, y0) / (2 * np.pi)
+    t2 = y0 * z0 / (2 * (1 - nu) * r2) / (2 * np.pi)
+    t3 = ((1 - 2 * nu) / (4 * (1 - nu)) * np.log(r2) + (y0 * y0 - z0 * z0) / (4 * (1 - nu) * r2)) / (2 * np.pi)
+    return [bvec[i] * t1 + edge[i] * t2 - txb[i] * t3 for i in range(3)]
+
+
+# The oracle's edge dislocation (line along y, b along h = +x) is Eq. (15) with
+# tau = -y: then y0 = X and z0 = Z.  (tau = +y flips u, i.e. b -> -b.)
+TAU = (0.0, -1.0, 0.0)
+BVEC = (BLEN, 0.0, 0.0)
+
+
+def disl_problem(xd, zd, x0=0.0, dx=DX):
+    return synth.base_problem(64, 8, dx, DZ, synth.mask_full(8, 64), x0=x0,
+                              strain={"kind": "edge_dislocation", "x_ref_um": xd, "z_ref_um": zd,
+                                      "b_um": BLEN, "nu": NU})
+
+
+def pin_dislocation_vector_form():
+    """exp(i h u_x) of the oracle equals Eq. (15)'s general form at points all
+    around the core (atan2 branches differ by multiples of h b / 2 = 4 pi)."""
+    xd, zd = 3.05, 0.4125
+    p = disl_problem(xd, zd)
+    _, h, _, _ = consts(p)
+    worst = 0.0
+    for j in range(0, 64, 3):
+        for z in np.linspace(0.0, 0.9, 13):
+            got = oracle.strain_phase_z(p, j, 0, float(z))
+            ux = eq15(j * DX - xd, z - zd, TAU, BVEC)[0]
+            worst = max(worst, abs(np.exp(1j * got) - np.exp(1j * h * ux)))
+    assert worst <= 1e-12, worst
+
+
+def pin_dislocation_equilibrium():
+    """Navier's equation of plane strain, (1 - 2 nu) lap u + grad div u = 0,
+    with u_x from the oracle and u_z from Eq. (15), by central differences on
+    rings of radius 0.5 and 2 um around the core."""
+    xd, zd = 0.0, 0.0
+    _, h, _, _ = consts(disl_problem(xd, zd))
+    hb = h * BLEN
+
+    def ux(x, z):
+        # unwrapped displacement from the phase: the branch of atan2 is kept away
+        # from the stencil by rotating the evaluation points off the cut
+        ph = oracle.strain_phase_z(disl_problem(xd, zd, x0=x), 0, 0, z)
+        return ph / h
+
+    def uz(x, z):
+        return eq15(x, z, TAU, BVEC)[2]
+
+    worst = 0.0
+    for r in (0.5, 2.0):
+        for ang in np.linspace(-2.6, 2.6, 9):          # stays off the atan2 cut at +-pi
+            x, z = r * math.cos(ang), r * math.sin(ang)
+            e = 2e-3 * r
+
+            def d2(f, ax, az):
+                return (f(x + ax * e, z + az * e) - 2 * f(x, z) + f(x - ax * e, z - az * e)) / (e * e)
+
+            def dxz(f):
+                return (f(x + e, z + e) - f(x + e, z - e) - f(x - e, z + e) + f(x - e, z - e)) / (4 * e * e)
+
+            lap_ux, lap_uz = d2(ux, 1, 0) + d2(ux, 0, 1), d2(uz, 1, 0) + d2(uz, 0, 1)
+            gdx = d2(ux, 1, 0) + dxz(uz)          # d/dx (du_x/dx + du_z/dz)
+            gdz = dxz(ux) + d2(uz, 0, 1)          # d/dz (...)
+            scale = BLEN / (2 * math.pi * r * r)
+            res = max(abs((1 - 2 * NU) * lap_ux + gdx), abs((1 - 2 * NU) * lap_uz + gdz)) / scale
+            worst = max(worst, res)
+    assert worst <= 1e-3, worst
+    assert hb == pytest.approx(8 * math.pi, rel=1e-12)
+
+
+def test_dislocation_phase_is_eq15_vector_form():
+    pin_dislocation_vector_form()
+
+
+def test_dislocation_displacement_is_in_elastic_equilibrium():
+    pin_dislocation_equilibrium()
+
+
+def test_eq15_reduction_and_equilibrium_reject_the_other_prefactor():
+    """Eq. (15)'s X Z term with 4 (1 - nu) (the form printed for the mixed
+    dislocation) is not in equilibrium with the same u_z: the check above has
+    the power to tell the two apart."""
+    r, ang = 1.0, 0.7
+    x, z, e = r * math.cos(ang), r * math.sin(ang), 2e-3
+
+    def ux4(x, z):
+        return BLEN / (2 * math.pi) * (math.atan2(z, x) + x * z / (4 * (1 - NU) * (x * x + z * z)))
+
+    def uz(x, z):
+        return eq15(x, z, TAU, BVEC)[2]
+
+    d2 = lambda f, ax, az: (f(x + ax * e, z + az * e) - 2 * f(x, z) + f(x - ax * e, z - az * e)) / (e * e)
+    dxz = lambda f: (f(x + e, z + e) - f(x + e, z - e) - f(x - e, z + e) + f(x - e, z - e)) / (4 * e * e)
+    res = abs((1 - 2 * NU) * (d2(ux4, 1, 0) + d2(ux4, 0, 1)) + d2(ux4, 1, 0) + dxz(uz))
+    assert res / (BLEN / (2 * math.pi)) > 0.05
+
+
+# ------------------------------------------------------------------ evanescent propagator
+def evanescent_problem(nz=5, full=False):
+    """dx = 5e-5 um: |q| reaches 0.95, so bins with |q +/- s| > 1 are evanescent
+    for both carriers (s = 0.5)."""
+    nx, dx, dz = 64, 5e-5, 2e-5
+    seg = synth.mask_full(nz, nx) if full else synth.mask_empty(nz)
+    return synth.base_problem(nx, nz, dx, dz, seg, chih=CHIH2, chihb=CHIHB2)
+
+
+def pin_evanescent():
+    """Vacuum: every bin is multiplied by the analytically continued propagator
+    per step; the evanescent ones decay and their phase turns by -dzh c."""
+    p = evanescent_problem()
+    k, _, s, c = consts(p)
+    Pp, Pm = plain_propagator(p)
+    q = 2 * np.pi * np.fft.fftfreq(p["nx"], p["dx_um"]) / k
+    ev = np.abs(q + s) > 1
+    assert ev.sum() >= 10 and (np.abs(q - s) > 1).sum() >= 10
+    assert np.all(np.abs(Pp[ev]) < 0.9)
+    a, b = synth.random_envelopes(p["nx"], 41)
+    op, om, _, _ = oracle.propagate(p, a, b)
+    n = p["nz"]
+    cp = np.fft.ifft(np.fft.fft(a) * Pp ** n)
+    cm = np.fft.ifft(np.fft.fft(b) * Pm ** n)
+    assert rel_l2(np.concatenate([op, om]), np.concatenate([cp, cm])) <= 1e-12
+    # the oracle's own table, bin by bin (1/N folded in)
+    tp, tm = oracle.propagator(p)
+    assert np.max(np.abs(tp * p["nx"] - Pp)) <= 1e-13 and np.max(np.abs(tm * p["nx"] - Pm)) <= 1e-13
+    # and inside a full crystal (x-uniform closed form with the coupling)
+    pf = evanescent_problem(full=True)
+    cf = lambda n_, zo: [(1.0, 0)]
+    a2, b2 = synth.random_envelopes(pf["nx"], 42)
+    op, om, _, _ = oracle.propagate(pf, a2, b2)
+    cp, cm = spectral_march(pf, a2, b2, cf)
+    assert rel_l2(np.concatenate([op, om]), np.concatenate([cp, cm])) <= 1e-12
+
+
+def test_evanescent_bins_decay_as_the_continued_propagator():
+    pin_evanescent()
+
+
+# ------------------------------------------------------------------ coupling sign (R5) and chih != chihb
+def pin_coupling_sign():
+    """psi+ takes a+ e^{+i h u} psi- and psi- takes a- e^{-i h u} psi+ (Eq. (11)):
+    with a tilt m the shifted copies must land at +m in psi+'s spectrum; with
+    chih != chihb, a+ pairs with chih."""
+    _, h, _, _ = consts(problem(None))
+    m = 9
+    c1 = 2 * math.pi * m / (NX * h * DX)
+    p = problem({"kind": "poly2", "x_ref_um": X0, "z_ref_um": 0.0, "c": [0, c1, 0, 0, 0, 0]}, nz=40)
+    check_march(p, lambda n, zo: [(1.0, m)])
+    a0, ap, am = harmonics(p)
+    assert abs(ap / am - CHIH2 / CHIHB2) <= 1e-12
+
+
+def test_coupling_sign_and_harmonic_pairing():
+    pin_coupling_sign()
+
+
+# every pin, for the mutation test
+PINS = {
+    "poly2_linear_x": pin_poly2_linear_x,
+    "poly2_z_terms": pin_poly2_z_terms,
+    "poly2_bend": pin_poly2_bend,
+    "poly2_bend_order2": lambda: pin_poly2_bend(2),
+    "poly2_quadratic_x": pin_poly2_quadratic_x,
+    "table_bend": pin_table_bend,
+    "table_orientation": pin_table_orientation,
+    "disl_vector_form": pin_dislocation_vector_form,
+    "disl_equilibrium": pin_dislocation_equilibrium,
+    "evanescent": pin_evanescent,
+    "coupling_sign": pin_coupling_sign,
+}
