@@ -8,8 +8,10 @@ case, Nx = 16384, Nz = 8000, dz = 0.025 um, bend radii R = 1, 0.1, 10 m, FP32,
 85 seeded Gaussian beams per radius (255 solves, one per compute unit).
 
 After the headline it reports, as side legs, one FP64 flat-Bragg solve alone,
-the dislocation batch (Nx 32768), the pulse-component batch (mixed sizes, one
-launch) and the serving mix (p50/p99 latency), and the FP64 oracle on the host.
+the 64-angle scan (and the scan replicated to 256 solves), the headline batch
+in FP64, the dislocation batch (Nx 32768), the pulse-component batch (mixed
+sizes, one launch), the paper's 3D case, the rows after the first-order march
+and the serving mix (p50/p99 latency), and the FP64 oracle on the host.
 
 Prints one JSON line (metric, value, roofline, cpu_baseline, legs, ...).
 """
@@ -27,10 +29,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "BPM cell-steps/s (Nx·Nz·2 beams), FP32 batched vs FP64 plain; p50/p99 solve ms"
-# MI355X: 256 CUs x 4 SIMD x 16 lanes, one FMA (2 flop) per lane per clock at 2.4 GHz.
-# The library is built without packed-FP32 instructions, so FP32 and FP64 share
-# this vector peak (the 157.3 TFLOP/s FP32 figure needs packed FP32).
-ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# MI355X published vector peaks (TFLOP/s): FP32 157.3 (packed FP32 issue), FP64 78.6.
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+# The library is built without packed-FP32 instructions: one wave64 FP32 FMA
+# per SIMD per 4 clocks, 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz.  This
+# issue ceiling is reported beside the published peak, never in its place.
+NONPACKED_F32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
 # the sources the march kernels are compiled from (device code and the
@@ -158,6 +162,28 @@ def fp64_plain(bpm, torch, synth):
             "workload": "flat_bragg Nx 4096 Nz 2000, one FP64 solve", "ms": sum(per) / len(per)}
 
 
+def flops(p) -> float:
+    """Algorithmic flops of one solve: 10 log2(Nx) + 26 per cell-step (two
+    complex FFTs of 5 N log2 N, the propagator 6, the coupling 14, a+-e^{+-i phi} 6)."""
+    n = p["nx"] * max(1, int(p.get("ny", 1)))
+    return (10 * math.log2(n) + 26) * cell_steps(p)
+
+
+def alu_roofline(cases, ms, prec):
+    """ALU roofline of one batch launch of `ms` milliseconds: achieved
+    algorithmic TFLOP/s against the published vector peak of its precision,
+    and (FP32) against the non-packed issue ceiling of this build."""
+    fl = sum(flops(p) for p, _ in cases)
+    achieved = fl / (ms / 1e3) / 1e12
+    out = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+           "frac": achieved / PEAK_TFLOPS[prec], "flop_per_cell_step": fl / sum(cell_steps(p) for p, _ in cases)}
+    if prec == "f32":
+        out["issue_ceiling"] = {"peak": NONPACKED_F32_TFLOPS, "frac": achieved / NONPACKED_F32_TFLOPS,
+                                "what": "non-packed FP32 VALU issue rate (this build has no packed FP32 "
+                                        "instructions): the ceiling the kernel can reach"}
+    return out
+
+
 def cell_steps(p) -> float:
     """Cells times z-steps of one solve, both beams (nx ny nz, ny = 1 in 2D)."""
     return 2.0 * p["nx"] * max(1, int(p.get("ny", 1))) * p["nz"]
@@ -272,11 +298,32 @@ def leg_serve(bpm, synth, n_req, rate_hz, budget_gb, chunk_steps):
             "budget_gb": budget_gb}
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores() -> dict:
+    """Cores this process may run on, and the share it uses: a one-GPU share of
+    the host is 16 cores, whatever the machine's total."""
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count() or 1
+    return {"machine": os.cpu_count() or 1, "allowed": allowed, "used": max(1, min(16, allowed))}
+
+
 def cpu_baseline(cases, target_s=12.0):
     """The FP64 oracle on the host cores over a bounded sample of the workload."""
     import oracle
-    cores = min(16, os.cpu_count() or 1)
-    nsolve = min(cores, len(cases))
+    hc = host_cores()
+    cores = hc["used"]
+    nsolve = min(cores, len(cases))   # one solve per thread
     # size the sample: time one short solve first
     p0, psi0 = cases[0]
     probe = dict(p0, nz=20, seg=p0["seg"][:20])
@@ -295,8 +342,9 @@ def cpu_baseline(cases, target_s=12.0):
     wall = time.perf_counter() - t
     cs = sum(cell_steps(q) for q, _ in sample)
     return {"value": cs / wall, "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
-            "sample": "%d of the %d solves, first %d of %d z-steps each, one solve per thread (%.1f s wall)"
-                      % (nsolve, len(cases), nz, p0["nz"], wall)}
+            "cpu_model": cpu_model(), "host_cores": hc,
+            "sample": "%d of the %d solves, first %d of %d z-steps each, one solve per thread on %d threads "
+                      "(%.1f s wall)" % (nsolve, len(cases), nz, p0["nz"], cores, wall)}
 
 
 def traffic_entry(kernel: str, launch_cell_steps: float):
@@ -325,9 +373,10 @@ def main():
     ap.add_argument("--nz", type=int, default=None, help="shorter march (profiling runs only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
-    ap.add_argument("--legs", default="cfg0,cfg2,cfg3,3d,next,cfg4",
+    ap.add_argument("--legs", default="cfg0,cfg0x4,cfg1f64,cfg2,cfg3,3d,next,cfg4",
                     help="extra workloads after the headline: cfg0 (64-angle FP64 scan, and its FP32 "
-                         "twin), cfg2 (dislocation, Nx 32768), cfg3 (pulse "
+                         "twin), cfg0x4 (the scan replicated to 256 solves), cfg1f64 (the headline batch "
+                         "in FP64), cfg2 (dislocation, Nx 32768), cfg3 (pulse "
                          "components, one mixed launch), 3d (the paper's 3D case), cfg4 (serving mix); "
                          "'none' for the headline only")
     ap.add_argument("--serve-requests", type=int, default=10000)
@@ -397,11 +446,8 @@ def main():
         kernel = "k_march_any<%s>" % tname
     else:
         kernel = "k_march_uniform<%s,%d>" % (tname, int(math.log2(nx)))
-    flop_cs = (sum((10 * math.log2(p["nx"]) + 26) * cell_steps(p) for p, _ in cases) / launch_cs)
-    achieved = flop_cs * launch_cs / (sum(per) / len(per) / 1e3) / 1e12
-    roof = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / ALU_PEAK_TFLOPS, "traffic": traffic_entry(kernel, launch_cs),
-            "kernel": kernel, "flop_per_cell_step": flop_cs}
+    roof = alu_roofline(cases, sum(per) / len(per), prec)
+    roof.update(traffic=traffic_entry(kernel, launch_cs), kernel=kernel)
 
     out = {"metric": METRIC, "value": value, "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -414,6 +460,9 @@ def main():
     if not args.no_fp64_plain:
         out["fp64_plain"] = fp64_plain(bpm, torch, synth)
         out["fp32_batched_over_fp64_plain"] = value / out["fp64_plain"]["value"]
+        out["fp32_batched_over_fp64_plain_what"] = (
+            "headline FP32 batch (255 solves on 255 CUs) over one FP64 solve alone on one CU: a batching "
+            "ratio; legs.cfg1_fp64_batch gives FP32 over FP64 at equal batching")
     out["R_mean"] = float(np.mean(Rs[0::2]))
     if kept:
         out["fp32_error_vs_fp64"] = fp32_error_vs_fp64(bpm, cases, Rs, kept)
@@ -436,6 +485,28 @@ def main():
             "autotune": {"f64": t64, "f32": t32}}
         for prec in ("f64", "f32"):
             bpm.schedule_set(prec, 4096, 0, "default")
+    if "cfg0x4" in want:
+        # config 0's scan replicated four times (256 solves, one per compute unit):
+        # the GPU-filling run for config 0's roofline
+        rep = {}
+        for pr in ("f64", "f32"):
+            scan = synth.flat_bragg_scan(n_angles=64, precision=pr)
+            cases4 = [(dict(p), psi) for _ in range(4) for p, psi in scan]
+            r = leg_batch(bpm, torch, cases4, "cfg0 x4 %s" % pr, steps=3, warmup=1)
+            rep[pr] = {"value": r["value"], "ms": r["ms_per_step"], "roofline": alu_roofline(cases4, r["ms_per_step"], pr)}
+        legs["cfg0_replicated_x4"] = dict(
+            rep, unit="cell-steps/s",
+            workload="config 0's 64-angle scan replicated 4 times: 256 solves of Nx 4096 x Nz 2000 in one batch "
+                     "launch (per-size kernel), labelled as a replica so the batch fills the 256 compute units")
+    if "cfg1f64" in want and cfg["workload"] == "bent_laue" and prec == "f32":
+        # the headline workload marched in FP64: FP32 against FP64 at equal batching
+        c64 = [(dict(p, precision="f64"), psi) for p, psi in cases]
+        r = leg_batch(bpm, torch, c64, "cfg1 FP64", steps=2, warmup=1)
+        legs["cfg1_fp64_batch"] = {
+            "workload": "the headline batch (255 bent-Laue solves, Nx 16384 x Nz 8000) in FP64, one launch",
+            "value": r["value"], "ms_per_step": r["ms_per_step"], "unit": "cell-steps/s",
+            "roofline": alu_roofline(c64, r["ms_per_step"], "f64"),
+            "fp32_over_fp64_equal_batching": value / r["value"]}
     if "cfg2" in want:
         legs["cfg2_dislocation"] = dict(
             leg_batch(bpm, torch, synth.disl_bragg_cores(256), "cfg2", keep=(137,)),

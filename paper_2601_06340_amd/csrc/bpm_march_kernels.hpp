@@ -57,13 +57,11 @@ hipError_t launch_uniform(const SolveDesc *d_descs, int n, const char *in_base, 
     if (n <= 0) return hipSuccess;
     constexpr int th = 1 << (LOG2N - uniform_log2e(LOG2N));
     const size_t lds = LdsPlan<T, LOG2N, uniform_log2e(LOG2N)>::bytes;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_uniform<T, LOG2N, SC>),
+    // raised once per process (a function-local static is initialised exactly
+    // once, also when several threads launch at the same time)
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_uniform<T, LOG2N, SC>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL((k_march_uniform<T, LOG2N, SC>), dim3(n), dim3(th), lds, s, d_descs, n, in_base, out_base, rt);
     return hipGetLastError();
 }
@@ -86,13 +84,11 @@ hipError_t launch_staged(const SolveDesc *d_descs, int n, const char *in_base, c
 {
     if (n <= 0) return hipSuccess;
     const size_t lds = Staged<T, LOG2N, SC>::lds_bytes;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_staged<T, LOG2N, SC>),
+    // raised once per process (a function-local static is initialised exactly
+    // once, also when several threads launch at the same time)
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_staged<T, LOG2N, SC>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL((k_march_staged<T, LOG2N, SC>), dim3(n), dim3(Staged<T, LOG2N, SC>::TH), lds, s, d_descs, n, in_base,
                        out_base, rt);
     return hipGetLastError();
@@ -118,13 +114,11 @@ hipError_t launch_3d(const SolveDesc *d_descs, int n, const char *in_base, char 
 {
     if (n <= 0) return hipSuccess;
     const size_t lds = Stage3D<T, LOG2NY, SC>::lds_bytes;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_3d<T, LOG2NY, SC>),
+    // raised once per process (a function-local static is initialised exactly
+    // once, also when several threads launch at the same time)
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_3d<T, LOG2NY, SC>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL((k_march_3d<T, LOG2NY, SC>), dim3(n), dim3(Stage3D<T, LOG2NY, SC>::TH), lds, s, d_descs, n,
                        in_base, out_base, rt);
     return hipGetLastError();
@@ -244,13 +238,11 @@ hipError_t launch_mixed(const SolveDesc *d_descs, int n, const char *in_base, ch
 {
     if (n <= 0) return hipSuccess;
     const size_t lds = mixed_lds_bytes<T>();
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_mixed<T, SC>),
+    // raised once per process (a function-local static is initialised exactly
+    // once, also when several threads launch at the same time)
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_mixed<T, SC>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL((k_march_mixed<T, SC>), dim3(n), dim3(1 << kMixedLog2Th), lds, s, d_descs, n, in_base, out_base,
                        rt);
     return hipGetLastError();
@@ -306,13 +298,11 @@ hipError_t launch_any(const SolveDesc *d_descs, int n, const char *in_base, char
 {
     if (n <= 0) return hipSuccess;
     const size_t lds = any_lds_bytes<T>();
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_any<T>),
+    // raised once per process (a function-local static is initialised exactly
+    // once, also when several threads launch at the same time)
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_any<T>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL((k_march_any<T>), dim3(n), dim3(1 << kMixedLog2Th), lds, s, d_descs, n, in_base, out_base, rt);
     return hipGetLastError();
 }

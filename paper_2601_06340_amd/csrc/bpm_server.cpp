@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <chrono>
 #include <condition_variable>
@@ -50,7 +51,7 @@ struct Request {
     std::vector<bpm_complex> psi_p0, psi_m0;
     bpm_complex *out_p = nullptr, *out_m = nullptr;
     size_t need = 0;          // budgeted device bytes
-    bool cancel = false;
+    std::atomic<bool> cancel{false};   // set by bpm_cancel, read by both server threads
     // running state
     bpm_plan *plan = nullptr;
     void *d_state = nullptr;

@@ -67,13 +67,10 @@ static hipError_t launch_td_T(const char *state, const uint64_t *offs, const dou
     using MF = March<T, LOG2M, LOG2M - 6, SC_NONE, 64 * kTdWaves, 1>;
     hipLaunchKernelGGL(k_td_phasors<T>, dim3((M + 255) / 256), dim3(256), 0, s, par, (Cx<T> *)ph, M);
     const size_t lds = (size_t)kTdWaves * MF::BUFM * sizeof(Cx<T>);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_td_assemble<T, LOG2M>),
+    // raised once per process (a function-local static is initialised exactly once)
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_td_assemble<T, LOG2M>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL((k_td_assemble<T, LOG2M>), dim3(nx / kTdWaves), dim3(64 * kTdWaves), lds, s, state, offs,
                        (const Cx<T> *)ph, (const Tw<T> *)tw, nx, (Cx<T> *)out);
     return hipGetLastError();

@@ -12,23 +12,11 @@ import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 import oracle  # noqa: E402
+from bars import TOL, r_bar, t_bar  # noqa: E402
 from paper_2601_06340_amd import synth  # noqa: E402
 
 pytestmark = pytest.mark.gpu
-# (envelope relative L2, |dR|): FP32 as stated; FP64 states only the envelope
-# bar, which bounds |dR| by 2 tol sqrt(R) + tol^2 <= 2e-10 (R <= 1)
-TOL = {"f64": (1e-10, 2e-10), "f32": (1e-4, 1e-5)}
 THREADS = min(16, os.cpu_count() or 1)
-
-
-def t_bar(prec, t_oracle):
-    """Bar on |T - T_oracle|.  The stated tolerances bound the envelopes
-    (relative L2: FP64 1e-10, FP32 1e-4) and, in FP32, the reflectivity R
-    (1e-5 absolute); for T they imply, with psi+ = psi+_o + d and
-    |d| <= tol |psi_o| over the pair,
-    |dT| <= (2 |psi+_o|_D |d| + |d|^2) / P_in <= 2 tol sqrt(T) + tol^2."""
-    tol = TOL[prec][0]
-    return 2 * tol * math.sqrt(max(float(t_oracle), 0.0)) + tol * tol
 
 
 def bpm():
@@ -73,7 +61,7 @@ def check_bounds(cases, outs, R, T, label):
     slack is what the parity bars allow R and T at T = 1."""
     assert np.all(np.isfinite(R)) and np.all(np.isfinite(T))
     assert np.all(R >= 0) and np.all(T >= 0)
-    slack = max(TOL[p["precision"]][1] + t_bar(p["precision"], 1.0) for p, _ in cases)
+    slack = max(r_bar(p["precision"], 1.0) + t_bar(p["precision"], 1.0) for p, _ in cases)
     assert np.all(R + T <= 1 + slack), (label, float(np.max(R + T)))
     for (p, psi), (gp, gm) in zip(cases, outs):
         pin = float(np.sum(np.abs(psi) ** 2))
@@ -92,7 +80,7 @@ def check_samples(cases, outs, R, T, idx, label):
         say(label, "solve", i, "nx", cases[i][0]["nx"], "nz", cases[i][0]["nz"],
             "rel L2 %.3e  dR %.2e  dT %.2e" % (err, abs(R[i] - oR[k]), abs(T[i] - oT[k])))
         assert err <= TOL[prec][0], (label, i, err)
-        assert abs(R[i] - oR[k]) <= TOL[prec][1] and abs(T[i] - oT[k]) <= t_bar(prec, oT[k]), (label, i)
+        assert abs(R[i] - oR[k]) <= r_bar(prec, oR[k]) and abs(T[i] - oT[k]) <= t_bar(prec, oT[k]), (label, i)
 
 
 def test_headline_bent_laue_batch_full_size():
@@ -155,7 +143,7 @@ def test_paper_3d_case_full_size():
     errw = rel_pair(wp, wm, op, om)
     say("3d full size: batch rel L2 %.3e, wide lane %.3e, dR %.2e" % (err, errw, abs(wR - oR)))
     assert err <= TOL["f32"][0] and errw <= TOL["f32"][0]
-    assert abs(R[0] - oR) <= TOL["f32"][1] and abs(wR - oR) <= TOL["f32"][1] and abs(wT - oT) <= t_bar("f32", oT)
+    assert abs(R[0] - oR) <= r_bar("f32", oR) and abs(wR - oR) <= r_bar("f32", oR) and abs(wT - oT) <= t_bar("f32", oT)
     del torch
 
 
@@ -190,7 +178,7 @@ def test_serving_stream_full_configuration():
     assert all(x is not None and x["status"] == 0 for x in res)
     R = np.array([x["R"] for x in res])
     T = np.array([x["T"] for x in res])
-    slack = TOL["f32"][1] + t_bar("f32", 1.0)    # the mix holds FP32 requests: the FP32 R and T bars
+    slack = r_bar("f32", 1.0) + t_bar("f32", 1.0)    # the mix holds FP32 requests: the FP32 R and T bars
     assert np.all(np.isfinite(R)) and np.all(R >= 0) and np.all(T >= 0) and np.all(R + T <= 1 + slack)
     probs = [reqs[i]["problem"] for i in picks]
     ofs, oR, oT = oracle.propagate_batch(probs, [(reqs[i]["psi_p0"], None) for i in picks],
@@ -199,4 +187,4 @@ def test_serving_stream_full_configuration():
         prec = probs[k]["precision"]
         err = rel_pair(res[i]["psi_p"], res[i]["psi_m"], ofs[k][0], ofs[k][1])
         say("serving request", i, prec, "nx", reqs[i]["nx"], "nz", reqs[i]["nz"], "rel L2 %.3e" % err)
-        assert err <= TOL[prec][0] and abs(R[i] - oR[k]) <= TOL[prec][1]
+        assert err <= TOL[prec][0] and abs(R[i] - oR[k]) <= r_bar(prec, oR[k])
