@@ -5,7 +5,7 @@ Every (precision, nx) march kernel is instantiated in its own translation unit
 library (C ABI, server) and the setup kernels are separate units.  The link
 produces ``paper_2601_06340_amd/libbpm_hip.so``.
 
-Usage: python -m paper_2601_06340_amd.build [-j N]
+Usage: python -m paper_2601_06340_amd.build [-j N] [--incremental]
 """
 from __future__ import annotations
 
@@ -85,9 +85,22 @@ def _gen_units() -> list[str]:
     return units
 
 
-def _compile(src: str) -> str:
+def _up_to_date(obj: str) -> bool:
+    """The object exists and is newer than every file its dependency list names."""
+    dep = obj + ".d"
+    if not (os.path.exists(obj) and os.path.exists(dep)):
+        return False
+    t = os.path.getmtime(obj)
+    text = open(dep).read().replace("\\\n", " ")
+    files = text.split(":", 1)[1].split() if ":" in text else []
+    return bool(files) and all(os.path.exists(f) and os.path.getmtime(f) <= t for f in files)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = ["hipcc"] + HIPFLAGS + ["-c", src, "-o", obj]
+    if incremental and _up_to_date(obj):
+        return obj
+    cmd = ["hipcc"] + HIPFLAGS + ["-MMD", "-MF", obj + ".d", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     errs = [l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip()]
     if r.returncode != 0:
@@ -95,7 +108,9 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = True) -> str:
+def build(jobs: int | None = None, verbose: bool = True, incremental: bool = False) -> str:
+    """Compile every unit and link the library (incremental: only the units
+    whose object is older than a file it depends on)."""
     t0 = time.time()
     os.makedirs(BUILD, exist_ok=True)
     srcs = [os.path.join(CSRC, f) for f in ("bpm_setup.hip", "bpm_td.hip", "bpm_api.cpp", "bpm_server.cpp",
@@ -106,7 +121,7 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
                             not any(("_%d_" % k) in s for k in (12, 13, 14, 15, 16))))
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda src: _compile(src, incremental), srcs))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     subprocess.run(cmd, check=True, capture_output=True)
@@ -119,9 +134,10 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true", help="rebuild only out-of-date units")
     a = ap.parse_args()
     try:
-        build(a.j)
+        build(a.j, incremental=a.incremental)
     except RuntimeError as e:
         print(e, file=sys.stderr)
         sys.exit(1)
