@@ -163,6 +163,21 @@ bpm_status bpm_propagate(bpm_plan *plan, const bpm_complex *psi_p0, const bpm_co
 bpm_status bpm_propagate_device(bpm_plan *plan, void *stream, const void *d_in, void *d_out,
                                 double *d_RT);
 
+/* bpm_propagate_device for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same march and arguments, bitwise the same results, but the
+ * call allocates nothing and records no graph.  A wide-lane plan (staged size
+ * or 3D envelopes) keeps its control block and per-workgroup partial sums in
+ * a static device array of the library (16 KiB per device, held until the
+ * process ends) instead of plan memory, and launches every z-step directly.
+ * Every call on a device shares that array: calls that overlap on one device
+ * race (as calls on one plan do).  BPM_E_INVALID for a NULL pointer,
+ * BPM_E_UNSUPPORTED if a plan would need more scratch than the array holds,
+ * BPM_E_DEVICE if its device address cannot be taken.  The plan itself is
+ * created (and allocated) beforehand with bpm_plan_create. */
+bpm_status bpm_propagate_device_noalloc(bpm_plan *plan, void *stream, const void *d_in, void *d_out,
+                                        double *d_RT);
+
 /* Far field (the far-field images of the paper's Sec. 7): the exit envelopes of
  * `plan` propagated through vacuum over distance_um along z in one FFT-based
  * step, each envelope about its own carrier (its own propagator, no coupling):

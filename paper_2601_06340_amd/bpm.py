@@ -102,6 +102,7 @@ SIGNATURES = {
     "bpm_propagate": (C.c_int, [C.c_void_p, C.POINTER(Complex), C.POINTER(Complex), C.POINTER(Complex),
                                 C.POINTER(Complex), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "bpm_propagate_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bpm_propagate_device_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bpm_far_field": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bpm_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
     "bpm_batch_layout": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
@@ -222,6 +223,10 @@ class Plan:
     def propagate_device(self, d_in: int, d_out: int, d_rt: int | None = None, stream: int | None = None):
         """Asynchronous march on device buffers (raw pointers, plan precision)."""
         _check(lib().bpm_propagate_device(self.handle, stream, d_in, d_out, d_rt))
+
+    def propagate_device_noalloc(self, d_in: int, d_out: int, d_rt: int | None = None, stream: int | None = None):
+        """bpm_propagate_device without any device allocation (the library's static scratch)."""
+        _check(lib().bpm_propagate_device_noalloc(self.handle, stream, d_in, d_out, d_rt))
 
     def far_field_device(self, distance_um: float, d_in: int, d_out: int, stream: int | None = None):
         """Vacuum propagation of a device state over distance_um (bpm_far_field)."""

@@ -114,7 +114,7 @@ def build(jobs: int | None = None, verbose: bool = True, incremental: bool = Fal
     t0 = time.time()
     os.makedirs(BUILD, exist_ok=True)
     srcs = [os.path.join(CSRC, f) for f in ("bpm_setup.hip", "bpm_td.hip", "bpm_api.cpp", "bpm_server.cpp",
-                                            "bpm_tune.cpp")]
+                                            "bpm_tune.cpp", "bpm_noalloc.hip")]
     srcs += _gen_units()
     # largest units first
     srcs.sort(key=lambda s: ("_any_" not in s, "mixed" not in s,

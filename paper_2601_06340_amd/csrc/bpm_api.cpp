@@ -513,8 +513,9 @@ extern "C" int32_t bpm_max_nx(int32_t precision)
 // ---- wide lane: one staged-size or 3D solve over the whole device
 constexpr int kWideGraphSteps = 32;   // z-steps per recorded graph
 
-// the launches of z-step base + k (every sub-step: row phase, column phase)
-static hipError_t wide_step(const bpm_plan *p, int k, hipStream_t s)
+// the launches of z-step base + k (every sub-step: row phase, column phase),
+// with the control block ctl and the partial sums part
+static hipError_t wide_step(const bpm_plan *p, int k, hipStream_t s, const WideCtl *ctl, double *part)
 {
     double a[kMaxSub], b[kMaxSub];
     const int nsub = split_sequence(p->desc.split_order <= 1 ? 1 : p->desc.split_order, a, b);
@@ -522,7 +523,7 @@ static hipError_t wide_step(const bpm_plan *p, int k, hipStream_t s)
     const int prec = p->desc.precision, sc = strain_class(p->desc.strain.kind);
     hipError_t e = hipSuccess;
     for (int i = lead ? 1 : 0; i < nsub && e == hipSuccess; ++i) {
-        const WideArgs w{p->d_desc1, p->d_wide_ctl, k, i, p->d_wide_part};
+        const WideArgs w{p->d_desc1, ctl, k, i, part};
         e = launch_wide(prec, p->launch_kind, sc, WIDE_ROWS, w, s, nullptr);
         if (e == hipSuccess) e = launch_wide(prec, p->launch_kind, sc, WIDE_COLS, w, s, nullptr);
     }
@@ -539,7 +540,7 @@ static void wide_record(bpm_plan *p)
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        for (int k = 0; k < kWideGraphSteps && e == hipSuccess; ++k) e = wide_step(p, k, cs);
+        for (int k = 0; k < kWideGraphSteps && e == hipSuccess; ++k) e = wide_step(p, k, cs, p->d_wide_ctl, p->d_wide_part);
         const hipError_t e2 = hipStreamEndCapture(cs, &g);
         if (e == hipSuccess) e = e2;
     }
@@ -556,23 +557,30 @@ static void wide_record(bpm_plan *p)
 }
 
 bpm_status bpm::propagate_wide(bpm_plan *p, hipStream_t s, const char *in, char *out, double *rt, int step0,
-                               int nsteps, int flags)
+                               int nsteps, int flags, WideCtl *ctl, double *part)
 {
     const int prec = p->desc.precision, sc = strain_class(p->desc.strain.kind), end = step0 + nsteps;
-    if (!p->wide_tried && nsteps >= kWideGraphSteps) wide_record(p);
-    const WideArgs w{p->d_desc1, p->d_wide_ctl, 0, 0, p->d_wide_part};
-    hipError_t e = launch_wide_ctl(p->d_wide_ctl, p->d_desc1, step0, in, out, step0, nsteps, flags, s);
+    // the plan's own control block and partial sums replay a recorded graph;
+    // the caller's (ctl, part) are launched step by step
+    const bool own = ctl == nullptr;
+    if (own) {
+        ctl = p->d_wide_ctl;
+        part = p->d_wide_part;
+        if (!p->wide_tried && nsteps >= kWideGraphSteps) wide_record(p);
+    }
+    const WideArgs w{p->d_desc1, ctl, 0, 0, part};
+    hipError_t e = launch_wide_ctl(ctl, p->d_desc1, step0, in, out, step0, nsteps, flags, s);
     if (e == hipSuccess) e = launch_wide(prec, p->launch_kind, sc, WIDE_ENTRY, w, s, nullptr);
     int n = step0;
-    for (; e == hipSuccess && p->wide_exec && n + kWideGraphSteps <= end; n += kWideGraphSteps) {
-        if (n > step0) e = launch_wide_ctl(p->d_wide_ctl, p->d_desc1, n, in, out, step0, nsteps, flags, s);
+    for (; e == hipSuccess && own && p->wide_exec && n + kWideGraphSteps <= end; n += kWideGraphSteps) {
+        if (n > step0) e = launch_wide_ctl(ctl, p->d_desc1, n, in, out, step0, nsteps, flags, s);
         if (e == hipSuccess) e = hipGraphLaunch(p->wide_exec, s);
     }
     for (; e == hipSuccess && n < end; ++n) {
-        e = launch_wide_ctl(p->d_wide_ctl, p->d_desc1, n, in, out, step0, nsteps, flags, s);
-        if (e == hipSuccess) e = wide_step(p, 0, s);
+        e = launch_wide_ctl(ctl, p->d_desc1, n, in, out, step0, nsteps, flags, s);
+        if (e == hipSuccess) e = wide_step(p, 0, s, ctl, part);
     }
-    if (e == hipSuccess) e = launch_wide_finish(p->d_desc1, p->d_wide_part, p->wide_blocks, rt, s);
+    if (e == hipSuccess) e = launch_wide_finish(p->d_desc1, part, p->wide_blocks, rt, s);
     if (e != hipSuccess) return hip_fail(e, "wide march launch");
     return BPM_OK;
 }

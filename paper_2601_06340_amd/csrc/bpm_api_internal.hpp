@@ -66,9 +66,13 @@ hipStream_t setup_stream();
 // z-steps [step0, step0 + nsteps) of a plan that has a wide form (p->d_wide_ctl
 // set) over the device, enqueued on s: natural-order state in `in`, out to
 // `out`; flags SF_FIRST (store the incident power) and SF_LAST (R, T to rt,
-// 2 doubles) as for the march kernels.
+// 2 doubles) as for the march kernels.  With ctl and part NULL the plan's own
+// control block and partial sums are used and 32-step blocks replay a graph
+// recorded on the first long call; otherwise the caller's ctl (one WideCtl)
+// and part (3 * p->wide_blocks doubles) are used and every step is launched
+// directly (no graph, no allocation).
 bpm_status propagate_wide(bpm_plan *p, hipStream_t s, const char *in, char *out, double *rt, int step0, int nsteps,
-                          int flags);
+                          int flags, WideCtl *ctl = nullptr, double *part = nullptr);
 
 // One kernel launch over a group of solves.
 struct Launch {
