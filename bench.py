@@ -272,11 +272,21 @@ def leg_serve(bpm, synth, n_req, rate_hz, budget_gb, chunk_steps):
     srv = bpm.Server(hbm_budget_bytes=int(budget_gb * (1 << 30)), max_slots=1024, chunk_steps=chunk_steps)
     t0 = time.perf_counter()
     tickets = []
+    trace = []   # (seconds since the first arrival, cell-steps done, solves in flight), about once a second
+
+    def sample():
+        st = srv.stats()
+        trace.append((time.perf_counter() - t0, st["cell_steps_done"],
+                      st["admitted"] - st["completed"] - st["cancelled"] - st["failed"]))
+
     for r in reqs:
         dt = t0 + r["t_arrival"] - time.perf_counter()
         if dt > 0:
             time.sleep(dt)
         tickets.append(srv.submit(r["problem"], r["psi_p0"], want_fields=False))
+        if not trace or time.perf_counter() - t0 - trace[-1][0] >= 1.0:
+            sample()
+    sample()
     drained = srv.drain(900.0)
     res = [srv.poll(t) for t in tickets]
     stats = srv.stats()
@@ -289,11 +299,28 @@ def leg_serve(bpm, synth, n_req, rate_hz, budget_gb, chunk_steps):
 
     span = max(x["t_done"] for _, x in good) - min(x["t_submit"] for _, x in good) if good else 0.0
     cs = sum(cell_steps(r) for r, _ in good)
+    # steady state: the rate at which the server completed cell-steps while
+    # requests kept arriving, after a ramp of 10 s (least-squares slope)
+    win = [(t, c, a) for t, c, a in trace if 10.0 <= t <= reqs[-1]["t_arrival"]]
+    steady = None
+    if len(win) >= 5:
+        ts = [w[0] for w in win]
+        cs_t = [w[1] for w in win]
+        tm, cm = sum(ts) / len(ts), sum(cs_t) / len(cs_t)
+        steady = (sum((a - tm) * (b - cm) for a, b in zip(ts, cs_t)) / sum((a - tm) ** 2 for a in ts))
     return {"requests": n_req, "completed": len(good), "drained": bool(drained), "rate_hz": rate_hz,
             "p50_ms": q(lat, 0.5), "p99_ms": q(lat, 0.99), "max_ms": lat[-1] if lat else None,
             "value": cs / span if span > 0 else None, "unit": "cell-steps/s",
+            "steady_state_value": steady,
+            "in_flight_during_arrivals": [round(a) for _, _, a in trace[::5]],
+            "value_what": "all completed cell-steps over first submit to last completion (includes the drain "
+                          "of the last large requests after arrivals end); steady_state_value: the completion "
+                          "rate while requests arrive, from 10 s to the last arrival",
             "offered": sum(cell_steps(r) for r in reqs) / reqs[-1]["t_arrival"],
             "launches": stats["launches"], "wide_lane_solves": stats["wide"], "peak_bytes": stats["peak_bytes"],
+            "rounds": stats.get("rounds"),
+            "active_max": stats.get("active_max"), "worker_device_wait_s": stats.get("t_device_wait_s"),
+            "worker_host_s": stats.get("t_host_s"),
             "chunk_steps": chunk_steps,
             "budget_gb": budget_gb}
 

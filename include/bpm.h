@@ -219,6 +219,9 @@ void bpm_batch_destroy(bpm_batch *batch);
 bpm_status bpm_td_assemble(bpm_batch *batch, void *stream, const void *d_state, void *d_out);
 
 /* --- serving (continuous batching) ------------------------------------------
+ * The paper evaluates independent realisations of the march (incidence angles,
+ * photon energies, configurations) in parallel (Sec. 3); a server does so for a
+ * stream of requests on one device.
  * A server owns a device-memory budget and a pool of solve slots.  A worker
  * thread advances all admitted solves together in rounds: per precision one
  * stream and one launch that takes every size and strain class side by side
@@ -226,9 +229,10 @@ bpm_status bpm_td_assemble(bpm_batch *batch, void *stream, const void *d_state, 
  * polynomial strain advances chunk_steps z-steps per round; every other
  * (precision, size, strain class) the steps that take the same time at its
  * measured per-workgroup rate (at least 1), so no round waits long for one
- * class.  While a round runs, the worker builds the
- * plans and entrance states of requests admitted in arrival order whose state
- * and tables fit the budget; after it, finished solves are retired and the new
+ * class.  While a round runs, an admission thread builds the plans and
+ * entrance states of requests admitted in arrival order whose state and tables
+ * fit the budget; after it, finished solves are retired (their device blocks
+ * return to the library's block cache rather than to the runtime) and the new
  * ones join the next round.  Per-solve arithmetic does not depend on what else
  * is in the launch, so a result is the same alone and in the mix.
  * Solves of a staged size or 3D envelopes with a long march ahead (an estimated
@@ -266,6 +270,10 @@ typedef struct bpm_server_stats {
     double cell_steps_done;
     size_t bytes_in_use, peak_bytes;
     int64_t wide;   /* solves marched in the wide lane (long staged-size / 3D solves, see bpm_server_create) */
+    int64_t rounds;          /* rounds the march worker ran */
+    int64_t active_max;      /* most solves marching in one round, waiting ones included */
+    double t_device_wait_s;  /* worker time spent waiting for rounds to finish */
+    double t_host_s;         /* worker time between rounds: retiring, freeing, building and launching */
 } bpm_server_stats;
 
 bpm_status bpm_server_create(const bpm_server_desc *desc, bpm_server **out);

@@ -78,7 +78,9 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
                 ("cancelled", C.c_int64), ("failed", C.c_int64), ("launches", C.c_int64),
                 ("cell_steps_done", C.c_double), ("bytes_in_use", C.c_size_t),
-                ("peak_bytes", C.c_size_t), ("wide", C.c_int64)]
+                ("peak_bytes", C.c_size_t), ("wide", C.c_int64), ("rounds", C.c_int64),
+                ("active_max", C.c_int64), ("t_device_wait_s", C.c_double),
+                ("t_host_s", C.c_double)]
 
 
 class TuneResult(C.Structure):

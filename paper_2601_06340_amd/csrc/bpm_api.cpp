@@ -296,19 +296,19 @@ void bpm_plan::release()
         delete far;
         far = nullptr;
     }
-    (void)hipFree(d_sc);
-    (void)hipFree(d_params);
+    dev_free(d_sc);
+    dev_free(d_params);
     prop_release(d_prop);
-    (void)hipFree(d_seg);
-    (void)hipFree(d_utab);
-    (void)hipFree(d_pin);
-    (void)hipFree(d_desc1);
-    (void)hipFree(d_state);
-    (void)hipFree(d_rt);
+    dev_free(d_seg);
+    dev_free(d_utab);
+    dev_free(d_pin);
+    dev_free(d_desc1);
+    dev_free(d_state);
+    dev_free(d_rt);
     if (wide_exec) (void)hipGraphExecDestroy(wide_exec);
     if (wide_graph) (void)hipGraphDestroy(wide_graph);
-    (void)hipFree(d_wide_ctl);
-    (void)hipFree(d_wide_part);
+    dev_free(d_wide_ctl);
+    dev_free(d_wide_part);
     wide_exec = nullptr;
     wide_graph = nullptr;
     d_wide_ctl = nullptr;
@@ -363,10 +363,72 @@ void bpm_plan::fill(SolveDesc &s, int log2e, const void *tw, int flags, int step
     (void)log2e;
 }
 
+// ------------------------------------------------------------------ device block cache
+// Plan tables, masks, descriptors and solve states come from size classes of
+// powers of two (256 B to 64 MiB).  A released block goes back to its class's
+// free list instead of hipFree, which waits for the whole device: a server
+// creating and destroying plans at hundreds per second then allocates and frees
+// no device memory in its steady state.  Larger blocks, and releases that would
+// take the cached total beyond kCacheCap, go to hipFree.  The caller makes sure
+// no kernel still uses a block it releases (plans wait for the device first).
+namespace {
+constexpr int kMinClassLog2 = 8, kMaxClassLog2 = 26;
+constexpr size_t kCacheCap = size_t(4) << 30;
+std::mutex g_blk_mu;
+std::map<void *, int> g_blk_class;   // block -> log2 of its class (-1: allocated directly)
+std::vector<void *> g_blk_free[kMaxClassLog2 + 1];
+size_t g_blk_cached = 0;
+}  // namespace
+
+hipError_t bpm::dev_malloc(void **p, size_t bytes)
+{
+    int l = kMinClassLog2;
+    while (l <= kMaxClassLog2 && (size_t(1) << l) < bytes) ++l;
+    if (l > kMaxClassLog2) {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e == hipSuccess) {
+            std::lock_guard<std::mutex> lk(g_blk_mu);
+            g_blk_class[*p] = -1;
+        }
+        return e;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_blk_mu);
+        if (!g_blk_free[l].empty()) {
+            *p = g_blk_free[l].back();
+            g_blk_free[l].pop_back();
+            g_blk_cached -= size_t(1) << l;
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipMalloc(p, size_t(1) << l);
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_blk_mu);
+        g_blk_class[*p] = l;
+    }
+    return e;
+}
+
+void bpm::dev_free(void *p)
+{
+    if (!p) return;
+    {
+        std::lock_guard<std::mutex> lk(g_blk_mu);
+        auto it = g_blk_class.find(p);
+        if (it != g_blk_class.end() && it->second >= 0 && g_blk_cached + (size_t(1) << it->second) <= kCacheCap) {
+            g_blk_free[it->second].push_back(p);
+            g_blk_cached += size_t(1) << it->second;
+            return;
+        }
+        if (it != g_blk_class.end()) g_blk_class.erase(it);
+    }
+    (void)hipFree(p);
+}
+
 template <typename F>
 static bpm_status dev_alloc(F **p, size_t bytes, const char *what)
 {
-    hipError_t e = hipMalloc((void **)p, std::max<size_t>(bytes, 16));
+    hipError_t e = dev_malloc((void **)p, std::max<size_t>(bytes, 16));
     if (e != hipSuccess) return hip_fail(e, what);
     return BPM_OK;
 }
@@ -440,13 +502,13 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
         double *d_u = nullptr;
         if ((st = dev_alloc(&d_u, nz * nx * sizeof(double), "strain staging")) != BPM_OK) return bail(st);
         if ((st = dev_alloc(&p->d_utab, nz * nx * (prec == BPM_F32 ? 4 : 8), "strain table")) != BPM_OK) {
-            (void)hipFree(d_u);
+            dev_free(d_u);
             return bail(st);
         }
         e = hipMemcpyAsync(d_u, d->strain.u_table, nz * nx * sizeof(double), hipMemcpyHostToDevice, ss);
         if (e == hipSuccess) e = launch_utab(d_u, p->d_utab, prec, nz * nx, 1.0 / d->d_um, ss);
         if (e == hipSuccess) e = hipStreamSynchronize(ss);
-        (void)hipFree(d_u);
+        dev_free(d_u);
         if (e != hipSuccess) return bail(hip_fail(e, "strain table"));
         p->device_bytes += nz * nx * (prec == BPM_F32 ? 4 : 8);
     }

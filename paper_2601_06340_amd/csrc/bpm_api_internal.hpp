@@ -55,6 +55,11 @@ bpm_status ensure_device();
 bpm_status validate_desc(const bpm_plan_desc *d);
 bpm_status check_input(const bpm_plan_desc &d, const bpm_complex *a, const bpm_complex *b);
 bpm_status twiddle_table(int prec, int log2n, int log2e, const void **out);
+// Device blocks of plans and solve states through the library's size-class
+// cache: dev_free returns a block to its class (no hipFree, which waits for the
+// device) unless the cache is full.  Blocks from dev_malloc go to dev_free only.
+hipError_t dev_malloc(void **p, size_t bytes);
+void dev_free(void *p);
 // Schedule table (bpm_tune.cpp): the bpm_schedule a batch group of one
 // (precision, log2 nx, strain class) runs with; BPM_SCHED_DEFAULT when none.
 int tuned_schedule(int prec, int log2n, int sc);

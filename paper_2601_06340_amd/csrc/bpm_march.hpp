@@ -556,6 +556,29 @@ __device__ __forceinline__ Cx<T> winding_phasor(T X, T Z, T ir, int m)
     return p;
 }
 
+// 1/x to about one ulp: the hardware reciprocal in FP32, a division in FP64
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_fast(double x) { return 1.0 / x; }
+
+// v^k for k >= 1, the same k across the wave: factors of two by squaring
+// first, so small powers cost only their squarings
+template <typename T>
+__device__ __forceinline__ Cx<T> cpow_pos(Cx<T> v, int k)
+{
+    while (!(k & 1)) {
+        v = {fmaT(v.x, v.x, -v.y * v.y), (T)2 * v.x * v.y};
+        k >>= 1;
+    }
+    Cx<T> p = v;
+    k >>= 1;
+    while (k) {
+        v = {fmaT(v.x, v.x, -v.y * v.y), (T)2 * v.x * v.y};
+        if (k & 1) p = {fmaT(p.x, v.x, -p.y * v.y), fmaT(p.x, v.y, p.y * v.x)};
+        k >>= 1;
+    }
+    return p;
+}
+
 __device__ __forceinline__ void sincospi_T(float x, float *s, float *c) { sincospif(x, s, c); }
 __device__ __forceinline__ void sincospi_T(double x, double *s, double *c) { sincospi(x, s, c); }
 
@@ -720,6 +743,35 @@ struct Coupler {
             // table [nz][nx]: row n, sample j0 + JS e
             const BufView utv = buf_view(d.utab, edge ? 0u : (uint32_t)d.nz * nx * (uint32_t)sizeof(T));
             const int m = d.disl_m;
+            if constexpr (std::is_same<T, float>::value) {
+                if (edge && m != 0 && (m & 1) == 0) {
+                    // even whole winding (b = m d with m even; 0.38 nm at d = 0.95 A
+                    // is m = 4): with v = (X + iZ)^2 / r^2 = (cos 2t, sin 2t),
+                    // t = atan2(Z, X), exp(i h u) = v^(m/2) exp(2 pi i k q Im(v) / 2),
+                    // because X Z / r^2 = sin(2t) / 2.  One reciprocal per sample,
+                    // no square root, division or arctangent.
+                    const int half = m < 0 ? -m / 2 : m / 2;
+                    const float Zt = (float)Z, Z2 = Zt * Zt, Zx2 = Zt + Zt;
+                    const float kqh = (float)(0.5 * d.disl_k * d.disl_q);
+                    static_for<0, E>([&](auto e) {
+                        const int j = j0 + e * JS;
+                        const bool in = inside_at_e(e);
+                        const float X = (float)__builtin_fma((double)j, d.dx, X0);
+                        const float r2 = fmaT(X, X, Z2);
+                        const bool core = !(r2 > 0.0f);   // the core itself: phase 0
+                        const float ir2 = core ? 0.0f : rcp_fast(r2);
+                        const Cx<float> v = {core ? 1.0f : fmaT(X, X, -Z2) * ir2, (X * Zx2) * ir2};
+                        Cx<float> W = cpow_pos(v, half);
+                        if (m < 0) W.y = -W.y;
+                        const Cx<float> S = phasor<float>(kqh * v.y);
+                        const Cx<float> P = {fmaT(W.x, S.x, -W.y * S.y), fmaT(W.x, S.y, W.y * S.x)};
+                        const Cx<float> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
+                        const Cx<float> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
+                        couple_sel(vp[e], vm[e], in, d0, bp, bm);
+                    });
+                    return;
+                }
+            }
             if (edge && m != 0) {
                 // whole winding number: exp(i h u) = ((X + i Z)/r)^m exp(2 pi i k q X Z / r^2)
                 static_for<0, E>([&](auto e) {

@@ -1,24 +1,31 @@
 // bpm_server.cpp — continuous-batching server over the march kernels.
 //
-// Two threads share the work.  The admission thread takes waiting requests in
-// arrival order while the slot count and device-memory budget allow and builds
-// their plans and entrance states; plan setup waits only for the library's
-// setup stream, so this overlaps the marches.  The march worker runs rounds:
-// every active solve advances a work-balanced number of z-steps (chunk_steps at
-// nx = 16384, scaled by 16384/nx) in one any-size launch per precision, so
-// solves of every size and strain class run side by side on the device; after the
-// round it retires the solves that reached nz, and the requests set up in the
-// meantime join the next round.  A solve's arithmetic is the same kernel and
-// schedule whatever else runs, and its state crosses round boundaries through
-// HBM unchanged, so results do not depend on what else is running.
+// The paper evaluates independent realisations (incidence angles, photon
+// energies) in parallel (Sec. 3); this server does the same for a stream of
+// requests on one device.  Two threads share the work.  The admission thread
+// takes waiting requests in arrival order while the slot count and the
+// device-memory budget allow and builds their plans and entrance states; plan
+// setup waits only for the library's setup stream, so this overlaps the
+// marches.  The march worker runs rounds: every active solve advances the
+// z-steps that take as long as chunk_steps steps of an FP32 nx = 16384 bent
+// solve at the measured per-workgroup rate of its (precision, size, strain
+// class), in one any-size launch per precision, so solves of every size and
+// strain class run side by side.  After the round it
+// retires the solves that reached nz (their plans and states go back to the
+// library's device block cache, not to hipFree, which would wait for the
+// device), and the requests set up in the meantime join the next round.  A
+// solve's arithmetic is the same kernel and schedule whatever else runs, and
+// its state crosses round boundaries through HBM unchanged, so results do not
+// depend on what else is running.
 //
 // Staged-size or 3D solves with a long march ahead (estimated one-workgroup
 // time of their remaining steps above kWideMinSeconds; at most kMaxWide at a
 // time, and only while at most kWideMaxRegular other solves march in the
-// rounds) move to the wide lane, from the start or part way through: each round advances them kWideChunkFactor * chunk_steps z-steps
-// spread over the device on a stream of their own, alongside the round's
-// launches, and the round waits for them too.  Their envelopes are the
-// one-workgroup march's bitwise.
+// rounds) move to the wide lane, from the start or part way through: each
+// round advances them kWideChunkFactor * chunk_steps z-steps spread over the
+// device on a stream of their own, alongside the round's launches, and the
+// round waits for them too.  Their envelopes are the one-workgroup march's
+// bitwise.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -65,18 +72,19 @@ struct Request {
 
 // Per-workgroup march rate of the any-size kernel in cell-steps/s, by
 // precision (FP64, FP32), log2 nx (10..16; 3D by its cell count) and strain
-// class (none, polynomial, dislocation/table): measured on MI355X with 64
-// solves of each class marching side by side (one per compute unit).  The
+// class (none, polynomial, dislocation/table; the dislocation with b = 4 d):
+// measured on MI355X with 64 solves of each class marching side by side (one per
+// compute unit), on the kernels of this source.  The
 // server sizes every solve's chunk so that chunks take about the same time.
 constexpr float kAnyRate[2][7][3] = {
-    {{4.14e8f, 3.81e8f, 2.97e8f}, {4.42e8f, 5.25e8f, 3.80e8f}, {7.96e8f, 7.27e8f, 5.30e8f},
-     {7.47e8f, 6.97e8f, 4.12e8f}, {3.62e8f, 3.29e8f, 2.99e8f}, {3.75e8f, 3.31e8f, 2.97e8f},
-     {3.56e8f, 3.13e8f, 2.78e8f}},
-    {{5.15e8f, 4.64e8f, 3.59e8f}, {7.00e8f, 6.48e8f, 4.57e8f}, {1.13e9f, 1.06e9f, 7.28e8f},
-     {1.27e9f, 1.14e9f, 7.52e8f}, {1.20e9f, 1.17e9f, 6.49e8f}, {4.22e8f, 4.08e8f, 3.49e8f},
-     {3.94e8f, 3.82e8f, 3.30e8f}}};
+    {{4.09e8f, 3.81e8f, 2.97e8f}, {4.43e8f, 5.26e8f, 3.81e8f}, {7.74e8f, 7.29e8f, 5.32e8f},
+     {7.56e8f, 6.98e8f, 4.18e8f}, {3.59e8f, 3.25e8f, 2.96e8f}, {3.75e8f, 3.31e8f, 2.98e8f},
+     {3.44e8f, 3.12e8f, 2.72e8f}},
+    {{4.88e8f, 4.44e8f, 3.97e8f}, {6.92e8f, 6.34e8f, 5.44e8f}, {1.11e9f, 1.04e9f, 8.40e8f},
+     {1.24e9f, 1.13e9f, 9.21e8f}, {1.18e9f, 1.16e9f, 7.48e8f}, {4.11e8f, 3.98e8f, 3.62e8f},
+     {3.86e8f, 3.77e8f, 3.43e8f}}};
 // the reference class: FP32, nx = 16384, polynomial strain
-constexpr double kRefRate = 1.17e9;
+constexpr double kRefRate = 1.16e9;
 
 double any_rate(const bpm_plan_desc &d)
 {
@@ -136,13 +144,20 @@ struct bpm_server {
     // worker-owned device resources
     std::map<int, hipStream_t> streams;  // one per precision
     double *d_rt = nullptr;
-    std::vector<Launch> launches;
+    // per precision: a device descriptor buffer reused from round to round and
+    // its pinned host staging copy (grown when a round needs more)
+    struct DescBuf {
+        SolveDesc *dev = nullptr, *host = nullptr;
+        size_t cap = 0;
+    };
+    std::map<int, DescBuf> descbuf;
     hipStream_t wide_streams[kMaxWide] = {};
     bool wide_busy[kMaxWide] = {};
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
     void run();
     void run_setup();
+    bpm_status upload(int prec, std::vector<Launch> &ls, hipStream_t st);
     int steps_for(const Request &r) const;
     bpm_status setup(Request &r, std::vector<char> &host);
     void finish(const std::shared_ptr<Request> &r, int status);
@@ -206,7 +221,7 @@ bpm_status bpm_server::setup(Request &r, std::vector<char> &host)
     bpm_status st = bpm_plan_create(&r.desc, &r.plan);
     if (st != BPM_OK) return st;
     const size_t sb = r.plan->state_bytes(), nx = r.plan->cells();   // samples per beam
-    hipError_t e = hipMalloc(&r.d_state, sb);
+    hipError_t e = dev_malloc(&r.d_state, sb);
     if (e != hipSuccess) return hip_fail(e, "server state");
     host.resize(sb);
     for (size_t j = 0; j < nx; ++j) {
@@ -266,7 +281,7 @@ void bpm_server::run_setup()
         if (st != BPM_OK) {
             if (r->plan) bpm_plan_destroy(r->plan);
             r->plan = nullptr;
-            (void)hipFree(r->d_state);
+            dev_free(r->d_state);
             r->d_state = nullptr;
             stats.bytes_in_use -= r->need;
             admitted_slots--;
@@ -312,6 +327,7 @@ int bpm_server::retire(Request &r, int status, const double *rt)
 // admission thread join at the start of the next round.
 void bpm_server::run()
 {
+    double t_host_prev = 0.0;   // host time after the previous round's wait (its retiring)
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(mu);
@@ -323,6 +339,7 @@ void bpm_server::run()
                 cv_work.wait(lk);
             }
         }
+        const double t_round = now();
 
         // ---- staged / 3D solves with a long march ahead take a free wide lane
         // while the device has room (at a round boundary the state is in
@@ -350,7 +367,9 @@ void bpm_server::run()
         // ---- one round: every active solve advances steps_for() z-steps (wide
         // solves kWideChunkFactor * chunk_steps); per precision one stream and
         // one any-size launch, so solves of every size and strain class run
-        // side by side, and each wide solve on its own stream
+        // side by side, and each wide solve on its own stream.  With more
+        // solves than compute units the launch runs in layers of workgroups
+        // (one per unit), and the hardware dispatcher packs the uneven chunks.
         std::vector<int> adv(active.size(), 0);
         bool ok = true;
         std::vector<size_t> reg;   // solves of the any-size launches
@@ -367,7 +386,6 @@ void bpm_server::run()
                                r->plan->d_rt, r->step, adv[i], fl) != BPM_OK)
                 ok = false;
         }
-        free_launches(launches);
         std::map<int, std::vector<size_t>> cls;
         for (size_t i : reg) cls[active[i]->desc.precision].push_back(i);
         for (auto &kv : cls) {
@@ -388,19 +406,21 @@ void bpm_server::run()
             hipStream_t cs = stream_for(kv.first);
             std::vector<Launch> ls;
             bpm_status st = build_launches(plans.data(), n, rt, off, off, s0, ns, fl, ls, true);
-            if (st == BPM_OK) st = upload_launches(ls, cs);
+            if (st == BPM_OK) st = upload(kv.first, ls, cs);
             if (st == BPM_OK) st = run_launches(ls, cs, nullptr, nullptr, d_rt);
-            for (auto &L : ls) launches.push_back(std::move(L));
+            for (auto &L : ls) L.d_descs = nullptr;   // they point into descbuf
             if (st != BPM_OK) ok = false;
             std::lock_guard<std::mutex> lk(mu);
             stats.launches++;
         }
 
         // ---- wait for the round, then retire the solves that reached nz
+        const double t_launched = now();
         for (auto &kv : streams)
             if (hipStreamSynchronize(kv.second) != hipSuccess) ok = false;
         for (auto &ws : wide_streams)
             if (ws && hipStreamSynchronize(ws) != hipSuccess) ok = false;
+        const double t_waited = now();
         std::vector<double> rt(2 * reg.size());
         if (!reg.empty() && ok &&
             hipMemcpy(rt.data(), d_rt, rt.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
@@ -426,9 +446,9 @@ void bpm_server::run()
                 status = retire(*r, status, prt);
             }
             if (fin) {
-                bpm_plan_destroy(r->plan);
+                bpm_plan_destroy(r->plan);   // its blocks return to the device block cache
                 r->plan = nullptr;
-                (void)hipFree(r->d_state);
+                dev_free(r->d_state);
                 r->d_state = nullptr;
                 if (r->wide_lane >= 0) wide_busy[r->wide_lane] = false;
             }
@@ -443,9 +463,50 @@ void bpm_server::run()
                 keep.push_back(r);
             }
         }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stats.rounds++;
+            stats.active_max = std::max<int64_t>(stats.active_max, (int64_t)active.size());
+            stats.t_device_wait_s += t_waited - t_launched;
+            stats.t_host_s += t_host_prev + (t_launched - t_round);
+        }
+        t_host_prev = 0.0;
         active.swap(keep);
         if (freed) cv_admit.notify_all();
+        t_host_prev = now() - t_waited;
     }
+}
+
+// Descriptors of a round's launches on stream st: one device buffer per
+// precision reused from round to round (the worker has waited for the previous
+// round, so nothing still reads it), filled from pinned host memory.
+bpm_status bpm_server::upload(int prec, std::vector<Launch> &ls, hipStream_t st)
+{
+    size_t total = 0;
+    for (auto &L : ls) total += L.host.size();
+    DescBuf &b = descbuf[prec];
+    if (total > b.cap) {
+        (void)hipFree(b.dev);
+        (void)hipHostFree(b.host);
+        b.dev = b.host = nullptr;
+        b.cap = 0;
+        const size_t cap = std::max<size_t>(2 * total, 512);
+        hipError_t e = hipMalloc((void **)&b.dev, cap * sizeof(SolveDesc));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b.host, cap * sizeof(SolveDesc), 0);
+        if (e != hipSuccess) return hip_fail(e, "server descriptor buffers");
+        b.cap = cap;
+    }
+    size_t off = 0;
+    for (auto &L : ls) {
+        std::memcpy(b.host + off, L.host.data(), L.host.size() * sizeof(SolveDesc));
+        L.d_descs = b.dev + off;
+        L.d_cap = L.host.size();
+        off += L.host.size();
+    }
+    if (total == 0) return BPM_OK;
+    hipError_t e = hipMemcpyAsync(b.dev, b.host, total * sizeof(SolveDesc), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    return BPM_OK;
 }
 
 extern "C" bpm_status bpm_server_create(const bpm_server_desc *d, bpm_server **out)
@@ -583,11 +644,14 @@ extern "C" void bpm_server_destroy(bpm_server *s)
     for (auto &r : s->ready) s->active.push_back(r);
     for (auto &r : s->active) {
         if (r->plan) bpm_plan_destroy(r->plan);
-        (void)hipFree(r->d_state);
+        dev_free(r->d_state);
     }
     for (auto &ws : s->wide_streams)
         if (ws) (void)hipStreamDestroy(ws);
-    free_launches(s->launches);
+    for (auto &kv : s->descbuf) {
+        (void)hipFree(kv.second.dev);
+        (void)hipHostFree(kv.second.host);
+    }
     for (auto &kv : s->streams)
         if (kv.second) (void)hipStreamDestroy(kv.second);
     (void)hipFree(s->d_rt);

@@ -876,6 +876,42 @@ def test_server_alone_equals_in_mix_and_matches_oracle():
     srv.close()
 
 
+def test_server_more_solves_than_compute_units():
+    """400 long requests at once, more than there are compute units (the
+    any-size launch then runs in layers of workgroups): every request
+    completes, copies of one request give bitwise the same result wherever
+    they sat in the launches, and a sample matches the oracle."""
+    B = bpm()
+    # long marches in short rounds (about 50 rounds each), so all of them are
+    # active together once admitted
+    target_p, target_psi = synth.flat_bragg_scan(n_angles=1, nx=2048, nz=3000, precision="f32")[0]
+    others = synth.flat_bragg_scan(n_angles=390, nx=1024, nz=3000, precision="f32")
+    srv = B.Server(hbm_budget_bytes=4 << 30, max_slots=1024, chunk_steps=8)
+    tick, copies = [], []
+    for k, (p, psi) in enumerate(others):
+        tick.append(srv.submit(p, psi))
+        if k % 39 == 0:
+            copies.append(srv.submit(target_p, target_psi))
+    assert srv.drain(120.0)
+    st = srv.stats()
+    say("400 requests: completed", st["completed"], "launches", st["launches"])
+    assert st["completed"] == len(tick) + len(copies) and st["failed"] == 0
+    res = [srv.poll(t) for t in copies]
+    for r in res:
+        assert r["status"] == 0
+        assert np.array_equal(r["psi_p"], res[0]["psi_p"]) and np.array_equal(r["psi_m"], res[0]["psi_m"])
+        assert r["R"] == res[0]["R"] and r["T"] == res[0]["T"]
+    op, om, oR, oT = oracle.propagate(target_p, target_psi)
+    assert rel_pair(res[0]["psi_p"], res[0]["psi_m"], op, om) <= TOL["f32"][0]
+    assert abs(res[0]["R"] - oR) <= r_bar("f32", oR) and abs(res[0]["T"] - oT) <= t_bar("f32", oT)
+    for k in (0, 199, 389):
+        p, psi = others[k]
+        r = srv.poll(tick[k])
+        op, om, oR, _ = oracle.propagate(p, psi)
+        assert r["status"] == 0 and rel_pair(r["psi_p"], r["psi_m"], op, om) <= TOL["f32"][0]
+    srv.close()
+
+
 @pytest.mark.parametrize("order", [1, 2])
 def test_server_zero_step_request_returns_entrance_state(order):
     """A request with nz = 0 through the server: the exit state is the entrance
