@@ -794,6 +794,21 @@ def test_evanescent_bins_decay(prec, nx):
     check(p, a, 0.5 * b, "evanescent-%d" % nx)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_evanescent_3d_rows_decay(prec):
+    """3D envelopes with dy = 2e-5 um: 2D bins beyond (qx +/- s)^2 + qy^2 = 1
+    take the decaying branch of the 2D propagator in the plan setup."""
+    nx, ny, nz, dy = 512, 32, 6, 2e-5
+    seg3 = np.zeros((nz, ny, 1, 2), np.int32)
+    seg3[:, :, 0, 1] = nx
+    p = synth.base_problem(nx, nz, 0.1, 2e-5, seg3, precision=prec, chih=CHIH_U, chihb=CHIHB_U)
+    p["ny"], p["dy_um"] = ny, dy
+    rng = np.random.default_rng(31)
+    a = rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
+    b = 0.4 * (rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx)))
+    check(p, a, b, "evanescent-3d")
+
+
 # ------------------------------------------------------------------ time-domain assembly
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_td_assembly_matches_oracle(prec):

@@ -40,6 +40,10 @@ MUTANTS = [
     ("evanescent growth", "exp(-sc.dzh * sqrt(p * p - 1.0))", "exp(sc.dzh * sqrt(p * p - 1.0))", ["evanescent"]),
     ("evanescent phase sign", "cexp(-I * sc.dzh * sc.c);\n            }\n            P /= (double)n;",
      "cexp(I * sc.dzh * sc.c);\n            }\n            P /= (double)n;", ["evanescent"]),
+    ("3D evanescent growth", "P = exp(-dzh * sqrt(-r)) * cexp(-I * dzh * sc.c);",
+     "P = exp(dzh * sqrt(-r)) * cexp(-I * dzh * sc.c);", ["evanescent_3d"]),
+    ("3D evanescent threshold on qx only", "double r = 1.0 - px * px - qy * qy;", "double r = 1.0 - px * px;",
+     ["evanescent_3d"]),
     ("strain sign on psi+", "psi_p[j] = sc.a0 * p + sc.ap * e * m;", "psi_p[j] = sc.a0 * p + sc.ap * conj(e) * m;",
      ["coupling_sign", "poly2_linear_x"]),
     ("a+ paired with chihb", "*ap = I * A * chih * off * E;", "*ap = I * A * chihb * off * E;",

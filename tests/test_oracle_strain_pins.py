@@ -420,6 +420,36 @@ def test_evanescent_bins_decay_as_the_continued_propagator():
     pin_evanescent()
 
 
+def pin_evanescent_3d():
+    """3D envelopes with dy = 2e-5 um: rows with (qx +/- s)^2 + qy^2 > 1 are
+    evanescent; a vacuum march multiplies every 2D bin by the continued
+    propagator exp(i dzh (sqrt(1 - (qx +/- s)^2 - qy^2) - c)) per step."""
+    nx, ny, nz, dx, dy, dz = 16, 64, 4, 0.1, 2e-5, 2e-5
+    seg3 = np.zeros((nz, ny, 1, 2), np.int32)
+    p = synth.base_problem(nx, nz, dx, dz, seg3)
+    p["ny"], p["dy_um"] = ny, dy
+    k, _, s_, c = consts(p)
+    qx = 2 * np.pi * np.fft.fftfreq(nx, dx) / k
+    qy = 2 * np.pi * np.fft.fftfreq(ny, dy) / k
+    QY, QX = np.meshgrid(qy, qx, indexing="ij")
+    S = lambda px: np.sqrt(1 - px * px - QY * QY + 0j)
+    Pp = np.exp(1j * k * dz * (S(QX + s_) - c))
+    Pm = np.exp(1j * k * dz * (S(QX - s_) - c))
+    ev = (QX + s_) ** 2 + QY ** 2 > 1
+    assert ev.sum() >= nx * ny // 4 and np.all(np.abs(Pp[ev]) < 0.95)
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
+    Bm = rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
+    gp, gm, _, _ = oracle.propagate(p, A, Bm)
+    cp = np.fft.ifft2(np.fft.fft2(A) * Pp ** nz)
+    cm = np.fft.ifft2(np.fft.fft2(Bm) * Pm ** nz)
+    assert rel_l2(np.concatenate([gp.ravel(), gm.ravel()]), np.concatenate([cp.ravel(), cm.ravel()])) <= 1e-12
+
+
+def test_evanescent_3d_bins_decay_as_the_continued_propagator():
+    pin_evanescent_3d()
+
+
 # ------------------------------------------------------------------ coupling sign (R5) and chih != chihb
 def pin_coupling_sign():
     """psi+ takes a+ e^{+i h u} psi- and psi- takes a- e^{-i h u} psi+ (Eq. (11)):
@@ -450,5 +480,6 @@ PINS = {
     "disl_vector_form": pin_dislocation_vector_form,
     "disl_equilibrium": pin_dislocation_equilibrium,
     "evanescent": pin_evanescent,
+    "evanescent_3d": pin_evanescent_3d,
     "coupling_sign": pin_coupling_sign,
 }
