@@ -55,6 +55,23 @@ __device__ __forceinline__ gptr<X> to_global(const void *p)
 {
     return (gptr<X>)(p);
 }
+// Plan scalars are read-only for a whole launch: read through the constant
+// address space, every field is a scalar load the compiler may issue early.
+using CPlanScalars = const __attribute__((address_space(4))) PlanScalars;
+__device__ __forceinline__ SubStep load_sub(CPlanScalars *p, int i)
+{
+    SubStep s;
+    s.d0x = p->sub[i].d0x;
+    s.d0y = p->sub[i].d0y;
+    s.apx = p->sub[i].apx;
+    s.apy = p->sub[i].apy;
+    s.amx = p->sub[i].amx;
+    s.amy = p->sub[i].amy;
+    s.zoff = p->sub[i].zoff;
+    s.table = p->sub[i].table;
+    s.pad = 0;
+    return s;
+}
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d2v __attribute__((ext_vector_type(2)));
@@ -1163,14 +1180,16 @@ struct March {
         cpl.template init<TH>(d, N);
         const T invN = (T)(1.0 / (double)N);
 
-        const PlanScalars &scl = *d.sc;
-        const int nsub = scl.nsub;
+        // plan scalars through the constant address space: read-only for the
+        // whole launch, so every field is a scalar load
+        CPlanScalars *scl = (CPlanScalars *)(d.sc);
+        const int nsub = scl->nsub;
         const int nend = d.step0 + d.nsteps;
         for (int n = d.step0; n < nend; ++n)
         for (int i = 0; i < nsub; ++i) {
             // one sub-step of the splitting: the propagation of its table (none
             // for a leading coupling), then its coupling
-            const SubStep &ss = scl.sub[i];
+            const SubStep ss = load_sub(scl, i);
             // Opaque zeros (the compiler cannot see they are zero): the tables
             // and per-lane offsets are re-derived each sub-step instead of being
             // hoisted into registers for the whole march, and the inverse
@@ -1375,7 +1394,7 @@ struct Staged {
         Coupler<T, SC> cpl;
         int lane, gi, lc;
         T invN;
-        const PlanScalars *scl;
+        CPlanScalars *scl;   // read-only for the launch: scalar loads
         bool lead;   // sub-step 0 is a leading coupling (no propagation before it)
 
         __device__ __forceinline__ void init(const SolveDesc &d, const char *in_base, char *out_base, Cx<T> *slab,
@@ -1395,7 +1414,7 @@ struct Staged {
             RRm = slab + (RowM::BX == 2 ? RowM::BUFM : 0);
             cpl.template init<LC * C>(d, D3 ? C : N);
             invN = (T)(1.0 / (double)N);
-            scl = d.sc;
+            scl = (CPlanScalars *)(d.sc);
             lead = scl->sub[0].table < 0;
         }
     };
@@ -1416,7 +1435,7 @@ struct Staged {
             });
         }
         if (d.nsteps > 0) {
-            if (x.lead) couple_at(x.cpl, vp, vm, d, d.step0, x.lc, c, x.scl->sub[0]);
+            if (x.lead) couple_at(x.cpl, vp, vm, d, d.step0, x.lc, c, load_sub(x.scl, 0));
             ColM::fwd_local(vp, vm, x.tw + (TW_COL + oz) * TWB, x.CRp, x.CRm, x.lc, true);
         } else if (rt_out) {
             det_sums(vp, vm, d, x.lc * C + c, LC * C, sp, sm);
@@ -1474,9 +1493,9 @@ struct Staged {
         Cx<T> vp[E], vm[E];
         load(vp, vm, x.st, x.lc * C + c + oz, LC * C);
         ColM::inv_local(vp, vm, x.tw + (TW_COL + oz) * TWB, x.CRp, x.CRm, x.lc, true);
-        couple_at(x.cpl, vp, vm, d, n, x.lc, c, x.scl->sub[i]);
+        couple_at(x.cpl, vp, vm, d, n, x.lc, c, load_sub(x.scl, i));
         if (!last) {
-            if (step_end && x.lead) couple_at(x.cpl, vp, vm, d, n + 1, x.lc, c, x.scl->sub[0]);
+            if (step_end && x.lead) couple_at(x.cpl, vp, vm, d, n + 1, x.lc, c, load_sub(x.scl, 0));
             ColM::fwd_local(vp, vm, x.tw + (TW_COL + of) * TWB, x.CRp, x.CRm, x.lc, true);
         } else if (rt_out) {
             det_sums(vp, vm, d, x.lc * C + c, LC * C, sp, sm);
@@ -1509,7 +1528,7 @@ struct Staged {
         const int nsub = x.scl->nsub;
         for (int n = d.step0; n < nend; ++n)
         for (int i = x.lead ? 1 : 0; i < nsub; ++i) {
-            const SubStep &ss = x.scl->sub[i];
+            const SubStep ss = load_sub(x.scl, i);
             __syncthreads();
 #pragma unroll 1
             for (int rr = 0; rr < ROW_ROUNDS; ++rr)

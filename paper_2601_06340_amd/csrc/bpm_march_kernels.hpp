@@ -23,7 +23,7 @@ template <typename T, int LOG2N, int SC>
 __global__ __launch_bounds__(1 << (LOG2N - uniform_log2e(LOG2N)))
 __attribute__((amdgpu_waves_per_eu(1, lds_waves_per_simd<T, LOG2N, uniform_log2e(LOG2N)>())))
 void k_march_uniform(
-    const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
+    const SolveDesc *__restrict__ descs, int n, const char *in_base, char *out_base, double *rt)
 {
     constexpr int LOG2E = uniform_log2e(LOG2N);
     extern __shared__ __align__(16) unsigned char smem[];
@@ -34,7 +34,7 @@ void k_march_uniform(
 
 // Mixed sizes in one launch: 512 threads per workgroup, E = nx/512.
 template <typename T, int SC>
-__global__ __launch_bounds__(1 << kMixedLog2Th) void k_march_mixed(const SolveDesc *descs, int n,
+__global__ __launch_bounds__(1 << kMixedLog2Th) void k_march_mixed(const SolveDesc *__restrict__ descs, int n,
                                                                     const char *in_base, char *out_base,
                                                                     double *rt)
 {
@@ -71,7 +71,7 @@ hipError_t launch_uniform(const SolveDesc *d_descs, int n, const char *in_base, 
 template <typename T, int LOG2N, int SC>
 __global__ __launch_bounds__(1 << staged_log2th(staged_prec<T>()))
 __attribute__((amdgpu_waves_per_eu(1, (1 << staged_log2th(staged_prec<T>())) / 256)))
-void k_march_staged(const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
+void k_march_staged(const SolveDesc *__restrict__ descs, int n, const char *in_base, char *out_base, double *rt)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[16];
@@ -102,7 +102,7 @@ using Stage3D = Staged<T, k3DLog2Nx + LOG2NY, SC, staged3d_log2th(staged_prec<T>
 template <typename T, int LOG2NY, int SC>
 __global__ __launch_bounds__(1 << staged3d_log2th(staged_prec<T>(), SC))
 __attribute__((amdgpu_waves_per_eu(1, (1 << staged3d_log2th(staged_prec<T>(), SC)) / 256)))
-void k_march_3d(const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
+void k_march_3d(const SolveDesc *__restrict__ descs, int n, const char *in_base, char *out_base, double *rt)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[16];
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(64) void k_wide_rows(const SolveDesc *descs, const 
     const SolveDesc &d = descs[0];
     typename S::Ctx x;
     x.init(d, ctl->out, ctl->out, reinterpret_cast<Cx<T> *>(smem), threadIdx.x);
-    S::row(x, x.scl->sub[i], blockIdx.x, 0, 0);
+    S::row(x, load_sub(x.scl, i), blockIdx.x, 0, 0);
 }
 
 template <typename T, int LOG2N, int SC, bool D3>
@@ -268,7 +268,7 @@ __device__ __forceinline__ void march_any_sc(const SolveDesc &d, const char *in_
 
 template <typename T>
 __global__ __launch_bounds__(1 << kMixedLog2Th) __attribute__((amdgpu_waves_per_eu(1, 2)))
-void k_march_any(const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
+void k_march_any(const SolveDesc *__restrict__ descs, int n, const char *in_base, char *out_base, double *rt)
 {
     static_assert(kMixedLog2Th == kStagedAnyLog2Th, "one workgroup shape");
     extern __shared__ __align__(16) unsigned char smem[];
