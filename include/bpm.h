@@ -106,7 +106,8 @@ typedef struct bpm_plan_desc {
     int32_t split_order;
     /* 3D envelopes (the paper's 3D form, Eq. (4) with a 2D transverse transform):
      * ny = 0 or 1 is the x-z problem described above.  ny > 1 (a power of two,
-     * 16 <= ny <= 256, with nx = 512) marches envelopes psi[ny][nx] (row i at
+     * 16 <= ny <= 256, with nx a power of two, 256 <= nx <= 1024; other sizes
+     * return BPM_E_UNSUPPORTED) marches envelopes psi[ny][nx] (row i at
      * y_i = i*dy_um, periodic) through the 2D transform over (x, y) and the
      * propagator exp(i dzh (S(qx +/- s, qy) - c)), S(p, r) = sqrt(1 - p^2 - r^2).
      * Then seg is [nz][ny][nseg][2] (intervals along x per step and row), a

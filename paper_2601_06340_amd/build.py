@@ -33,7 +33,8 @@ HIPFLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
 # keep in sync with Limits<> in csrc/bpm_march.hpp
 UNIFORM = {"float": range(6, 15), "double": range(6, 14)}
 STAGED = {"float": range(15, 17), "double": range(14, 17)}
-THREE_D_LOG2NY = range(4, 9)   # 3D envelopes: ny = 16..256 rows of nx = 512
+THREE_D_LOG2NX = range(8, 11)  # 3D envelopes: rows of nx = 256..1024
+THREE_D_LOG2NY = range(4, 9)   # ny = 16..256 rows
 MIXED = ("float", "double")
 STRAIN_CLASSES = (0, 1, 2)   # none, polynomial, dislocation/table
 
@@ -63,16 +64,17 @@ def _gen_units() -> list[str]:
                       '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
                       "template hipError_t launch_staged<%s, %d, %d>(const SolveDesc *, int, const char *, "
                       "char *, double *, hipStream_t);\n"
-                      "template hipError_t launch_wide_T<%s, %d, %d, false>(int, const WideArgs &, hipStream_t, "
-                      "WideShape *);\n}\n" % (t, l2, sc, t, l2, sc))
+                      "template hipError_t launch_wide_T<%s, %d, %d, false, 9>(int, const WideArgs &, "
+                      "hipStream_t, WideShape *);\n}\n" % (t, l2, sc, t, l2, sc))
         for t in MIXED:
-            for l2y in THREE_D_LOG2NY:
-                write("march_3d_%s_%d_sc%d.hip" % (t, l2y, sc),
-                      '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
-                      "template hipError_t launch_3d<%s, %d, %d>(const SolveDesc *, int, const char *, char *, "
-                      "double *, hipStream_t);\n"
-                      "template hipError_t launch_wide_T<%s, %d, %d, true>(int, const WideArgs &, hipStream_t, "
-                      "WideShape *);\n}\n" % (t, l2y, sc, t, 9 + l2y, sc))
+            for l2x in THREE_D_LOG2NX:
+                for l2y in THREE_D_LOG2NY:
+                    write("march_3d_%s_%d_%d_sc%d.hip" % (t, l2x, l2y, sc),
+                          '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
+                          "template hipError_t launch_3d<%s, %d, %d, %d>(const SolveDesc *, int, const char *, "
+                          "char *, double *, hipStream_t);\n"
+                          "template hipError_t launch_wide_T<%s, %d, %d, true, %d>(int, const WideArgs &, "
+                          "hipStream_t, WideShape *);\n}\n" % (t, l2x, l2y, sc, t, l2x + l2y, sc, l2x))
             write("march_mixed_%s_sc%d.hip" % (t, sc),
                   '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
                   "template hipError_t launch_mixed<%s, %d>(const SolveDesc *, int, const char *, char *, "

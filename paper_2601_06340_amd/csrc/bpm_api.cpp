@@ -121,11 +121,11 @@ bpm_status bpm::twiddle_table(int prec, int log2n, int log2e, const void **out)
         *out = it->second;
         return BPM_OK;
     }
-    // log2e = 0 names the combined table of a staged size, -1 that of 3D
-    // envelopes with log2(ny) = log2n - 9
+    // log2e = 0 names the combined table of a staged size, -log2(nx) that of
+    // 3D envelopes with log2(ny) = log2n - log2(nx)
     const size_t bytes = std::max<size_t>(log2e > 0    ? twiddle_bytes(prec, log2n, log2e)
                                           : log2e == 0 ? staged_twiddle_bytes(prec, log2n)
-                                                       : twiddle3d_bytes(prec, log2n - k3DLog2Nx),
+                                                       : twiddle3d_bytes(prec, -log2e, log2n + log2e),
                                           16);
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
@@ -133,7 +133,7 @@ bpm_status bpm::twiddle_table(int prec, int log2n, int log2e, const void **out)
     hipStream_t ss = setup_stream();
     e = log2e > 0    ? launch_twiddles(p, prec, log2n, log2e, ss)
         : log2e == 0 ? launch_staged_twiddles(p, prec, log2n, ss)
-                     : launch_twiddles_3d(p, prec, log2n - k3DLog2Nx, ss);
+                     : launch_twiddles_3d(p, prec, -log2e, log2n + log2e, ss);
     if (e == hipSuccess) e = hipStreamSynchronize(ss);
     if (e != hipSuccess) {
         (void)hipFree(p);
@@ -236,8 +236,9 @@ bpm_status bpm::validate_desc(const bpm_plan_desc *d)
         if ((d->ny & (d->ny - 1)) || d->ny < (1 << k3DLog2NyMin) || d->ny > (1 << k3DLog2NyMax))
             return fail(BPM_E_UNSUPPORTED, "3D envelopes need ny a power of two in [%d, %d], got %d", 1 << k3DLog2NyMin,
                         1 << k3DLog2NyMax, d->ny);
-        if (d->nx != (1 << k3DLog2Nx))
-            return fail(BPM_E_UNSUPPORTED, "3D envelopes need nx = %d, got %d", 1 << k3DLog2Nx, d->nx);
+        if ((d->nx & (d->nx - 1)) || d->nx < (1 << k3DLog2NxMin) || d->nx > (1 << k3DLog2NxMax))
+            return fail(BPM_E_UNSUPPORTED, "3D envelopes need nx a power of two in [%d, %d], got %d",
+                        1 << k3DLog2NxMin, 1 << k3DLog2NxMax, d->nx);
         if (!is_finite(d->dy_um) || d->dy_um <= 0) return fail(BPM_E_INVALID, "dy must be finite and > 0");
     }
     const long long rows = (long long)d->nz * (d3 ? d->ny : 1);
@@ -452,7 +453,7 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
         while ((1 << p->log2ny) < d->ny) ++p->log2ny;
         p->log2n += p->log2ny;   // 3D: log2 of the samples per beam
     }
-    p->launch_kind = p->log2ny ? kLaunch3D + p->log2ny : p->log2n;
+    p->launch_kind = p->log2ny ? kind_3d(p->log2n - p->log2ny, p->log2ny) : p->log2n;
     const int prec = d->precision;
     const size_t nx = p->cells(), nz = d->nz, rows = std::max<size_t>(p->rows(), 1);   // nx: samples per beam
 
@@ -516,9 +517,11 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
     if (e != hipSuccess) return bail(hip_fail(e, "plan setup"));
 
     const int log2e = uniform_log2e(p->log2n);
-    const int tw_key = p->log2ny ? -1 : is_staged(prec, p->log2n) ? 0 : log2e;
+    const int tw_key = p->log2ny ? -(p->log2n - p->log2ny) : is_staged(prec, p->log2n) ? 0 : log2e;
     if ((st = twiddle_table(prec, p->log2n, tw_key, &p->tw_uniform)) != BPM_OK) return bail(st);
-    if (p->log2ny) march_shape_3d(prec, p->log2ny, &p->threads, &p->lds_bytes);
+    if (p->log2ny)
+        march_shape_3d(prec, strain_class(d->strain.kind), p->log2n - p->log2ny, p->log2ny, &p->threads,
+                       &p->lds_bytes);
     else march_shape(prec, p->log2n, &p->threads, &p->lds_bytes);
 
     // wide lane of a staged size or 3D solve marched alone
@@ -809,21 +812,22 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
         launches.push_back(std::move(L));
         return BPM_OK;
     };
-    // 3D envelopes: one launch per (precision, strain class, ny)
+    // 3D envelopes: one launch per (precision, strain class, nx, ny)
     for (int prec : {BPM_F32, BPM_F64})
         for (int sc : {0, 1, 2})
-            for (int l = k3DLog2NyMin; l <= k3DLog2NyMax; ++l) {
-                std::vector<int> g;
-                for (int i = 0; i < n; ++i)
-                    if (plans[i]->log2ny == l && plans[i]->desc.precision == prec &&
-                        strain_class(plans[i]->desc.strain.kind) == sc)
-                        g.push_back(i);
-                std::stable_sort(g.begin(), g.end(), [&](int a, int b) { return cost(a) > cost(b); });
-                if (!g.empty()) {
-                    bpm_status st = emit(prec, sc, kLaunch3D + l, g);
-                    if (st != BPM_OK) return st;
+            for (int lx = k3DLog2NxMin; lx <= k3DLog2NxMax; ++lx)
+                for (int l = k3DLog2NyMin; l <= k3DLog2NyMax; ++l) {
+                    std::vector<int> g;
+                    for (int i = 0; i < n; ++i)
+                        if (plans[i]->log2ny && plans[i]->launch_kind == kind_3d(lx, l) &&
+                            plans[i]->desc.precision == prec && strain_class(plans[i]->desc.strain.kind) == sc)
+                            g.push_back(i);
+                    std::stable_sort(g.begin(), g.end(), [&](int a, int b) { return cost(a) > cost(b); });
+                    if (!g.empty()) {
+                        bpm_status st = emit(prec, sc, kind_3d(lx, l), g);
+                        if (st != BPM_OK) return st;
+                    }
                 }
-            }
     if (any_size) {
         // every size the any-size kernel takes, of every strain class, in one
         // launch per precision (a size always meets the same kernel, whatever

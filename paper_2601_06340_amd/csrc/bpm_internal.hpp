@@ -90,13 +90,22 @@ struct PlanParams {
     double dy;
 };
 
-// 3D envelopes: nx = 2^k3DLog2Nx (one wave per x row), ny = 2^k3DLog2NyMin..2^k3DLog2NyMax.
-constexpr int k3DLog2Nx = 9, k3DLog2NyMin = 4, k3DLog2NyMax = 8;
+// 3D envelopes: nx = 2^k3DLog2NxMin..2^k3DLog2NxMax (one wave per x row, nx/64
+// samples per thread and beam), ny = 2^k3DLog2NyMin..2^k3DLog2NyMax.
+constexpr int k3DLog2NxMin = 8, k3DLog2NxMax = 10, k3DLog2NyMin = 4, k3DLog2NyMax = 8;
 // bytes of one propagator table entry (P - 1)/N, both precisions: FP32 keeps
 // it as hi + lo pairs of floats, FP64 as (re, im)
 constexpr size_t kPropEntryBytes = 16;
-// launch kind of a 3D group: kLaunch3D + log2(ny)
+// launch kind of a 3D group: kLaunch3D + 16 (log2 nx - k3DLog2NxMin) + log2 ny
 constexpr int kLaunch3D = 100;
+constexpr int kind_3d(int log2nx, int log2ny) { return kLaunch3D + 16 * (log2nx - k3DLog2NxMin) + log2ny; }
+constexpr int kind3d_log2nx(int kind) { return k3DLog2NxMin + (kind - kLaunch3D) / 16; }
+constexpr int kind3d_log2ny(int kind) { return (kind - kLaunch3D) % 16; }
+constexpr bool is_kind_3d(int kind)
+{
+    return kind >= kLaunch3D && kind3d_log2nx(kind) <= k3DLog2NxMax && kind3d_log2ny(kind) >= k3DLog2NyMin &&
+           kind3d_log2ny(kind) <= k3DLog2NyMax;
+}
 
 // Flags of one solve in one launch.
 enum SolveFlags : int32_t {
@@ -133,10 +142,18 @@ constexpr int kStagedAnyLog2Th = 9;
 constexpr int staged_log2e(int prec) { return 3; }
 constexpr int staged_log2c(int prec) { return 6 + staged_log2e(prec); }
 constexpr int staged_log2th(int prec) { return prec == PREC_F32 ? 10 : 9; }
-// 3D envelopes: the same, except 512 threads for FP32 with the dislocation /
-// table coupling (its per-row mask and strain reads spill in 1024-thread
-// workgroups' register budget; 512 marches the 3D batch 12 % faster)
-constexpr int staged3d_log2th(int prec, int sc) { return prec == PREC_F32 && sc != SC_GENERAL ? 10 : 9; }
+// 3D envelopes: rows of nx = 2^log2nx samples, nx/64 per thread and beam.
+// Threads per solve: FP32 1024 for rows of 512 or fewer samples without the
+// dislocation / table coupling, else 512 (that coupling's per-row mask and
+// strain reads spill in a 1024-thread workgroup's register budget, and so do
+// 16 samples per thread; 512 threads march the 3D batch 12 % faster); FP64
+// 512, and 256 for rows of 1024 (16 FP64 samples per beam need more than the
+// 256 registers a 512-thread workgroup leaves each lane).
+constexpr int staged3d_log2th(int prec, int sc, int log2nx)
+{
+    if (prec == PREC_F64) return log2nx >= 10 ? 8 : 9;
+    return sc != SC_GENERAL && log2nx <= 9 ? 10 : 9;
+}
 
 // Wide lane: one staged-size or 3D solve spread over the device, two launches
 // (row phase, column phase) per coupling sub-step.  The control block carries
@@ -158,7 +175,7 @@ struct WideShape {
     size_t lds_bytes;
 };
 // launch one phase of a wide march (kind: log2 nx of a staged size or
-// kLaunch3D + log2 ny); shape (may be NULL) receives the grid sizes
+// kind_3d(log2 nx, log2 ny)); shape (may be NULL) receives the grid sizes
 hipError_t launch_wide(int prec, int kind, int sc, int phase, const WideArgs &a, hipStream_t s, WideShape *shape);
 hipError_t launch_wide_finish(const SolveDesc *desc, const double *part, int nblk, double *rt, hipStream_t s);
 // the control block's step base and buffers, and the descriptor's step range and flags
@@ -183,9 +200,9 @@ size_t twiddle_bytes(int prec, int log2n, int log2e);
 // [row FFT | column FFT | four-step].
 bool is_staged(int prec, int log2n);
 // 3D envelopes: twiddle table [row FFT | column FFT] and launch shape.
-size_t twiddle3d_bytes(int prec, int log2ny);
-hipError_t launch_twiddles_3d(void *d_tw, int prec, int log2ny, hipStream_t s);
-void march_shape_3d(int prec, int log2ny, int *threads, size_t *lds_bytes);
+size_t twiddle3d_bytes(int prec, int log2nx, int log2ny);
+hipError_t launch_twiddles_3d(void *d_tw, int prec, int log2nx, int log2ny, hipStream_t s);
+void march_shape_3d(int prec, int sc, int log2nx, int log2ny, int *threads, size_t *lds_bytes);
 size_t staged_twiddle_bytes(int prec, int log2n);
 hipError_t launch_staged_twiddles(void *d_tw, int prec, int log2n, hipStream_t s);
 hipError_t launch_utab(const double *d_u, void *d_tab, int prec, size_t count, double inv_d,

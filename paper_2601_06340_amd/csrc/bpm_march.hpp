@@ -72,6 +72,12 @@ __device__ __forceinline__ SubStep load_sub(CPlanScalars *p, int i)
     s.pad = 0;
     return s;
 }
+// the same through a generic pointer: a reference, loaded where it is used
+// (per-lane loads the compiler may keep in vector registers)
+__device__ __forceinline__ const SubStep &load_sub(const PlanScalars *p, int i) { return p->sub[i]; }
+// CS: the plan scalars as scalar loads (constant address space) or generic
+template <bool CS>
+using PlanPtr = typename std::conditional<CS, CPlanScalars *, const PlanScalars *>::type;
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d2v __attribute__((ext_vector_type(2)));
@@ -1140,6 +1146,10 @@ struct March {
         return v;
     }
 
+    // CS: read the plan scalars as scalar loads (false: generic loads, which the
+    // any-size kernel marches faster with; its inlined sizes and strain
+    // classes leave no scalar registers to hold them)
+    template <bool CS = true>
     static __device__ void run(const SolveDesc &d, const char *in_base, char *out_base, double *rt,
                                Cx<T> *lds, double *red)
     {
@@ -1180,16 +1190,15 @@ struct March {
         cpl.template init<TH>(d, N);
         const T invN = (T)(1.0 / (double)N);
 
-        // plan scalars through the constant address space: read-only for the
-        // whole launch, so every field is a scalar load
-        CPlanScalars *scl = (CPlanScalars *)(d.sc);
+        // plan scalars, read-only for the whole launch
+        const PlanPtr<CS> scl = (PlanPtr<CS>)(d.sc);
         const int nsub = scl->nsub;
         const int nend = d.step0 + d.nsteps;
         for (int n = d.step0; n < nend; ++n)
         for (int i = 0; i < nsub; ++i) {
             // one sub-step of the splitting: the propagation of its table (none
             // for a leading coupling), then its coupling
-            const SubStep ss = load_sub(scl, i);
+            decltype(auto) ss = load_sub(scl, i);   // a value (CS) or a reference
             // Opaque zeros (the compiler cannot see they are zero): the tables
             // and per-lane offsets are re-derived each sub-step instead of being
             // hoisted into registers for the whole march, and the inverse
@@ -1318,11 +1327,14 @@ constexpr int staged_bx()
 
 // D3: 3D envelopes, ny = R rows of nx = C samples: the same two phases are the
 // 2D transform over (y, x) (no four-step twiddle), the propagator table is
-// [ky][kx], and the coupling reads the mask per row.
-template <typename T, int LOG2N, int SC, int LOG2TH = staged_log2th(staged_prec<T>()), bool D3 = false>
+// [ky][kx], and the coupling reads the mask per row.  Rows are always one wave
+// wide, so C = 2^LOG2C_ samples take C/64 per thread (in both phases).
+template <typename T, int LOG2N, int SC, int LOG2TH = staged_log2th(staged_prec<T>()), bool D3 = false,
+          int LOG2C_ = staged_log2c(staged_prec<T>())>
 struct Staged {
-    static constexpr int LOG2E = staged_log2e(staged_prec<T>()), E = 1 << LOG2E;
-    static constexpr int N = 1 << LOG2N, LOG2C = staged_log2c(staged_prec<T>()), C = 1 << LOG2C;
+    static constexpr int LOG2C = LOG2C_, C = 1 << LOG2C;
+    static constexpr int LOG2E = LOG2C - 6, E = 1 << LOG2E;
+    static constexpr int N = 1 << LOG2N;
     static constexpr int LOG2R = LOG2N - LOG2C, R = 1 << LOG2R;
     static constexpr int TH = 1 << LOG2TH, WAVES = TH / 64;
     static constexpr int BXS = staged_bx<T, LOG2C, LOG2E, LOG2TH>();

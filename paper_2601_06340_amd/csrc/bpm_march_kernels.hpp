@@ -94,33 +94,36 @@ hipError_t launch_staged(const SolveDesc *d_descs, int n, const char *in_base, c
     return hipGetLastError();
 }
 
-// 3D envelopes [ny][nx = 512]: one solve per workgroup, the staged lane's two
-// phases as the 2D transform (Staged<> with D3).
-template <typename T, int LOG2NY, int SC>
-using Stage3D = Staged<T, k3DLog2Nx + LOG2NY, SC, staged3d_log2th(staged_prec<T>(), SC), true>;
+// 3D envelopes [ny][nx], nx = 2^LOG2NX: one solve per workgroup, the staged
+// lane's two phases as the 2D transform (Staged<> with D3).
+template <typename T, int LOG2NX, int LOG2NY, int SC>
+using Stage3D = Staged<T, LOG2NX + LOG2NY, SC, staged3d_log2th(staged_prec<T>(), SC, LOG2NX), true, LOG2NX>;
 
-template <typename T, int LOG2NY, int SC>
-__global__ __launch_bounds__(1 << staged3d_log2th(staged_prec<T>(), SC))
-__attribute__((amdgpu_waves_per_eu(1, (1 << staged3d_log2th(staged_prec<T>(), SC)) / 256)))
+template <typename T, int LOG2NX, int LOG2NY, int SC>
+__global__ __launch_bounds__(1 << staged3d_log2th(staged_prec<T>(), SC, LOG2NX))
+__attribute__((amdgpu_waves_per_eu(1, (1 << staged3d_log2th(staged_prec<T>(), SC, LOG2NX)) / 256)))
 void k_march_3d(const SolveDesc *__restrict__ descs, int n, const char *in_base, char *out_base, double *rt)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[16];
-    Stage3D<T, LOG2NY, SC>::run(descs[blockIdx.x], in_base, out_base, rt, reinterpret_cast<Cx<T> *>(smem), red);
+    Stage3D<T, LOG2NX, LOG2NY, SC>::run(descs[blockIdx.x], in_base, out_base, rt, reinterpret_cast<Cx<T> *>(smem),
+                                        red);
 }
 
-template <typename T, int LOG2NY, int SC>
+template <typename T, int LOG2NX, int LOG2NY, int SC>
 hipError_t launch_3d(const SolveDesc *d_descs, int n, const char *in_base, char *out_base, double *rt, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    const size_t lds = Stage3D<T, LOG2NY, SC>::lds_bytes;
+    using S = Stage3D<T, LOG2NX, LOG2NY, SC>;
+    const size_t lds = S::lds_bytes;
     // raised once per process (a function-local static is initialised exactly
     // once, also when several threads launch at the same time)
-    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_3d<T, LOG2NY, SC>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&k_march_3d<T, LOG2NX, LOG2NY, SC>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_march_3d<T, LOG2NY, SC>), dim3(n), dim3(Stage3D<T, LOG2NY, SC>::TH), lds, s, d_descs, n,
-                       in_base, out_base, rt);
+    hipLaunchKernelGGL((k_march_3d<T, LOG2NX, LOG2NY, SC>), dim3(n), dim3(S::TH), lds, s, d_descs, n, in_base,
+                       out_base, rt);
     return hipGetLastError();
 }
 
@@ -133,13 +136,13 @@ hipError_t launch_3d(const SolveDesc *d_descs, int n, const char *in_base, char 
 // agree with it bitwise.  The kernels read the step base and the buffers from a
 // control block, so a recorded graph of steps k = 0..K-1 (z-step base + k)
 // replays for any step and any buffers.
-template <typename T, int LOG2N, int SC, bool D3>
-using Wide = Staged<T, LOG2N, SC, 6, D3>;
+template <typename T, int LOG2N, int SC, bool D3, int LOG2C>
+using Wide = Staged<T, LOG2N, SC, 6, D3, LOG2C>;
 
-template <typename T, int LOG2N, int SC, bool D3>
+template <typename T, int LOG2N, int SC, bool D3, int LOG2C>
 __global__ __launch_bounds__(64) void k_wide_entry(const SolveDesc *descs, const WideCtl *ctl, double *part)
 {
-    using S = Wide<T, LOG2N, SC, D3>;
+    using S = Wide<T, LOG2N, SC, D3, LOG2C>;
     extern __shared__ __align__(16) unsigned char smem[];
     const SolveDesc &d = descs[0];
     typename S::Ctx x;
@@ -157,10 +160,10 @@ __global__ __launch_bounds__(64) void k_wide_entry(const SolveDesc *descs, const
     }
 }
 
-template <typename T, int LOG2N, int SC, bool D3>
+template <typename T, int LOG2N, int SC, bool D3, int LOG2C>
 __global__ __launch_bounds__(64) void k_wide_rows(const SolveDesc *descs, const WideCtl *ctl, int i)
 {
-    using S = Wide<T, LOG2N, SC, D3>;
+    using S = Wide<T, LOG2N, SC, D3, LOG2C>;
     extern __shared__ __align__(16) unsigned char smem[];
     const SolveDesc &d = descs[0];
     typename S::Ctx x;
@@ -168,11 +171,11 @@ __global__ __launch_bounds__(64) void k_wide_rows(const SolveDesc *descs, const 
     S::row(x, load_sub(x.scl, i), blockIdx.x, 0, 0);
 }
 
-template <typename T, int LOG2N, int SC, bool D3>
+template <typename T, int LOG2N, int SC, bool D3, int LOG2C>
 __global__ __launch_bounds__(64) void k_wide_cols(const SolveDesc *descs, const WideCtl *ctl, int k, int i,
                                                   double *part)
 {
-    using S = Wide<T, LOG2N, SC, D3>;
+    using S = Wide<T, LOG2N, SC, D3, LOG2C>;
     extern __shared__ __align__(16) unsigned char smem[];
     const SolveDesc &d = descs[0];
     typename S::Ctx x;
@@ -191,10 +194,10 @@ __global__ __launch_bounds__(64) void k_wide_cols(const SolveDesc *descs, const 
     }
 }
 
-template <typename T, int LOG2N, int SC, bool D3>
+template <typename T, int LOG2N, int SC, bool D3, int LOG2C>
 hipError_t launch_wide_T(int phase, const WideArgs &a, hipStream_t s, WideShape *shape)
 {
-    using S = Wide<T, LOG2N, SC, D3>;
+    using S = Wide<T, LOG2N, SC, D3, LOG2C>;
     if (shape) {
         shape->row_blocks = S::ROW_ROUNDS;
         shape->col_blocks = S::COL_ROUNDS;
@@ -203,15 +206,16 @@ hipError_t launch_wide_T(int phase, const WideArgs &a, hipStream_t s, WideShape 
     const size_t lds = S::lds_bytes;
     switch (phase) {
     case WIDE_ENTRY:
-        hipLaunchKernelGGL((k_wide_entry<T, LOG2N, SC, D3>), dim3(S::COL_ROUNDS), dim3(64), lds, s, a.desc, a.ctl,
-                           a.part);
+        hipLaunchKernelGGL((k_wide_entry<T, LOG2N, SC, D3, LOG2C>), dim3(S::COL_ROUNDS), dim3(64), lds, s, a.desc,
+                           a.ctl, a.part);
         break;
     case WIDE_ROWS:
-        hipLaunchKernelGGL((k_wide_rows<T, LOG2N, SC, D3>), dim3(S::ROW_ROUNDS), dim3(64), lds, s, a.desc, a.ctl, a.i);
+        hipLaunchKernelGGL((k_wide_rows<T, LOG2N, SC, D3, LOG2C>), dim3(S::ROW_ROUNDS), dim3(64), lds, s, a.desc,
+                           a.ctl, a.i);
         break;
     case WIDE_COLS:
-        hipLaunchKernelGGL((k_wide_cols<T, LOG2N, SC, D3>), dim3(S::COL_ROUNDS), dim3(64), lds, s, a.desc, a.ctl, a.k,
-                           a.i, a.part);
+        hipLaunchKernelGGL((k_wide_cols<T, LOG2N, SC, D3, LOG2C>), dim3(S::COL_ROUNDS), dim3(64), lds, s, a.desc,
+                           a.ctl, a.k, a.i, a.part);
         break;
     default:
         return hipSuccess;
@@ -259,16 +263,21 @@ __device__ __forceinline__ void march_any_sc(const SolveDesc &d, const char *in_
     static_for<Limits<T>::mix_lo, Limits<T>::mix_hi + 1>([&](auto l) {
         constexpr int L2 = CV(l);
         if (d.log2n == L2)
-            March<T, L2, L2 - mixed_log2th(L2), SC, 1 << kMixedLog2Th>::run(d, in_base, out_base, rt, lds, red);
+            March<T, L2, L2 - mixed_log2th(L2), SC, 1 << kMixedLog2Th>::template run<false>(d, in_base, out_base, rt,
+                                                                                           lds, red);
     });
     static_for<Limits<T>::stg_lo, Limits<T>::stg_hi + 1>([&](auto l) {
         if (d.log2n == CV(l)) Staged<T, CV(l), SC, kStagedAnyLog2Th>::run(d, in_base, out_base, rt, lds, red);
     });
 }
 
+// The descriptors and the resident sizes' plan scalars are read with generic
+// loads here: with scalar loads (as in the other kernels) the resident sizes
+// of the polynomial and dislocation classes marched up to 27 % slower, the
+// kernel already spilling scalar registers.
 template <typename T>
 __global__ __launch_bounds__(1 << kMixedLog2Th) __attribute__((amdgpu_waves_per_eu(1, 2)))
-void k_march_any(const SolveDesc *__restrict__ descs, int n, const char *in_base, char *out_base, double *rt)
+void k_march_any(const SolveDesc *descs, int n, const char *in_base, char *out_base, double *rt)
 {
     static_assert(kMixedLog2Th == kStagedAnyLog2Th, "one workgroup shape");
     extern __shared__ __align__(16) unsigned char smem[];

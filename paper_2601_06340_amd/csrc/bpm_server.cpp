@@ -77,12 +77,12 @@ struct Request {
 // compute unit), on the kernels of this source.  The
 // server sizes every solve's chunk so that chunks take about the same time.
 constexpr float kAnyRate[2][7][3] = {
-    {{4.09e8f, 3.81e8f, 2.97e8f}, {4.43e8f, 5.26e8f, 3.81e8f}, {7.74e8f, 7.29e8f, 5.32e8f},
-     {7.56e8f, 6.98e8f, 4.18e8f}, {3.59e8f, 3.25e8f, 2.96e8f}, {3.75e8f, 3.31e8f, 2.98e8f},
-     {3.44e8f, 3.12e8f, 2.72e8f}},
-    {{4.88e8f, 4.44e8f, 3.97e8f}, {6.92e8f, 6.34e8f, 5.44e8f}, {1.11e9f, 1.04e9f, 8.40e8f},
-     {1.24e9f, 1.13e9f, 9.21e8f}, {1.18e9f, 1.16e9f, 7.48e8f}, {4.11e8f, 3.98e8f, 3.62e8f},
-     {3.86e8f, 3.77e8f, 3.43e8f}}};
+    {{4.09e8f, 3.81e8f, 3.01e8f}, {4.41e8f, 5.29e8f, 3.82e8f}, {7.72e8f, 7.28e8f, 5.30e8f},
+     {7.25e8f, 7.13e8f, 4.19e8f}, {3.47e8f, 3.28e8f, 2.85e8f}, {3.44e8f, 3.31e8f, 2.92e8f},
+     {3.14e8f, 3.10e8f, 2.63e8f}},
+    {{4.93e8f, 4.42e8f, 3.98e8f}, {6.99e8f, 6.34e8f, 5.40e8f}, {1.11e9f, 1.05e9f, 8.63e8f},
+     {1.24e9f, 1.17e9f, 8.99e8f}, {1.18e9f, 1.16e9f, 7.54e8f}, {4.17e8f, 3.89e8f, 3.64e8f},
+     {3.97e8f, 3.63e8f, 3.45e8f}}};
 // the reference class: FP32, nx = 16384, polynomial strain
 constexpr double kRefRate = 1.16e9;
 

@@ -265,60 +265,76 @@ static bool staged_layout_T(int log2n, int *tw_col, int *tw_4, int *total)
     return ok;
 }
 
-// 3D twiddle table [row FFT | column FFT], as Staged<..., D3> reads it.
-template <typename T>
-static bool layout_3d_T(int log2ny, int *tw_col, int *total)
+// 3D twiddle table [row FFT | column FFT], as Staged<..., D3> reads it; f(S)
+// is called with the Staged<> type of the (nx, ny) pair and the strain class
+template <typename T, int SC, typename F>
+static bool with_3d_T(int log2nx, int log2ny, F &&f)
 {
     bool ok = false;
-    static_for<k3DLog2NyMin, k3DLog2NyMax + 1>([&](auto l) {
-        using S = Staged<T, k3DLog2Nx + CV(l), SC_NONE, staged_log2th(staged_prec<T>()), true>;
-        if (log2ny == CV(l)) {
-            *tw_col = S::TW_COL;
-            *total = S::TW_TOTAL;
-            ok = true;
-        }
+    static_for<k3DLog2NxMin, k3DLog2NxMax + 1>([&](auto lx) {
+        static_for<k3DLog2NyMin, k3DLog2NyMax + 1>([&](auto ly) {
+            using S = Staged<T, CV(lx) + CV(ly), SC, staged3d_log2th(staged_prec<T>(), SC, CV(lx)), true, CV(lx)>;
+            if (log2nx == CV(lx) && log2ny == CV(ly)) {
+                f(S{});
+                ok = true;
+            }
+        });
     });
     return ok;
 }
 
-size_t twiddle3d_bytes(int prec, int log2ny)
+template <typename T>
+static bool layout_3d_T(int log2nx, int log2ny, int *tw_col, int *total)
+{
+    return with_3d_T<T, SC_NONE>(log2nx, log2ny, [&](auto s) {
+        using S = decltype(s);
+        *tw_col = S::TW_COL;
+        *total = S::TW_TOTAL;
+    });
+}
+
+size_t twiddle3d_bytes(int prec, int log2nx, int log2ny)
 {
     int a = 0, tot = 0;
-    const bool ok = prec == PREC_F32 ? layout_3d_T<float>(log2ny, &a, &tot) : layout_3d_T<double>(log2ny, &a, &tot);
+    const bool ok = prec == PREC_F32 ? layout_3d_T<float>(log2nx, log2ny, &a, &tot)
+                                     : layout_3d_T<double>(log2nx, log2ny, &a, &tot);
     return ok ? (size_t)tot * tw_bytes(prec) : 0;
 }
 
-hipError_t launch_twiddles_3d(void *d_tw, int prec, int log2ny, hipStream_t s)
+hipError_t launch_twiddles_3d(void *d_tw, int prec, int log2nx, int log2ny, hipStream_t s)
 {
     int tw_col = 0, tot = 0;
-    const bool ok = prec == PREC_F32 ? layout_3d_T<float>(log2ny, &tw_col, &tot)
-                                     : layout_3d_T<double>(log2ny, &tw_col, &tot);
-    const int le = staged_log2e(prec);
-    if (!ok || tw_count(k3DLog2Nx, le) != tw_col || tw_col + tw_count(log2ny, le) != tot) return hipErrorInvalidValue;
+    const bool ok = prec == PREC_F32 ? layout_3d_T<float>(log2nx, log2ny, &tw_col, &tot)
+                                     : layout_3d_T<double>(log2nx, log2ny, &tw_col, &tot);
+    const int le = log2nx - 6;   // one wave per row
+    if (!ok || tw_count(log2nx, le) != tw_col || tw_col + tw_count(log2ny, le) != tot) return hipErrorInvalidValue;
     char *base = static_cast<char *>(d_tw);
-    hipError_t e = launch_twiddles(base, prec, k3DLog2Nx, le, s);
+    hipError_t e = launch_twiddles(base, prec, log2nx, le, s);
     if (e == hipSuccess) e = launch_twiddles(base + (size_t)tw_col * tw_bytes(prec), prec, log2ny, le, s);
     return e;
 }
 
-template <typename T>
-static void shape_3d_T(int log2ny, int *threads, size_t *lds)
+template <typename T, int SC>
+static void shape_3d_T(int log2nx, int log2ny, int *threads, size_t *lds)
 {
     *threads = 0;
     *lds = 0;
-    static_for<k3DLog2NyMin, k3DLog2NyMax + 1>([&](auto l) {
-        using S = Staged<T, k3DLog2Nx + CV(l), SC_NONE, staged_log2th(staged_prec<T>()), true>;
-        if (log2ny == CV(l)) {
-            *threads = S::TH;
-            *lds = S::lds_bytes;
-        }
+    with_3d_T<T, SC>(log2nx, log2ny, [&](auto s) {
+        using S = decltype(s);
+        *threads = S::TH;
+        *lds = S::lds_bytes;
     });
 }
 
-void march_shape_3d(int prec, int log2ny, int *threads, size_t *lds_bytes)
+void march_shape_3d(int prec, int sc, int log2nx, int log2ny, int *threads, size_t *lds_bytes)
 {
-    if (prec == PREC_F32) shape_3d_T<float>(log2ny, threads, lds_bytes);
-    else shape_3d_T<double>(log2ny, threads, lds_bytes);
+    if (prec == PREC_F32) {
+        if (sc == SC_GENERAL) shape_3d_T<float, SC_GENERAL>(log2nx, log2ny, threads, lds_bytes);
+        else shape_3d_T<float, SC_NONE>(log2nx, log2ny, threads, lds_bytes);
+    } else {
+        if (sc == SC_GENERAL) shape_3d_T<double, SC_GENERAL>(log2nx, log2ny, threads, lds_bytes);
+        else shape_3d_T<double, SC_NONE>(log2nx, log2ny, threads, lds_bytes);
+    }
 }
 
 bool is_staged(int prec, int log2n)
@@ -382,7 +398,7 @@ template <typename T, int LOG2N, int SC>
 hipError_t launch_staged(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
 template <typename T>
 hipError_t launch_any(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
-template <typename T, int LOG2NY, int SC>
+template <typename T, int LOG2NX, int LOG2NY, int SC>
 hipError_t launch_3d(const SolveDesc *, int, const char *, char *, double *, hipStream_t);
 
 
@@ -393,8 +409,11 @@ static hipError_t dispatch(const SolveDesc *d_descs, int n, int uniform_log2n, c
     if (uniform_log2n == kLaunchAny) return launch_any<T>(d_descs, n, in_base, out_base, rt, s);
     if (uniform_log2n >= kLaunch3D) {
         hipError_t err = hipErrorInvalidValue;
-        static_for<k3DLog2NyMin, k3DLog2NyMax + 1>([&](auto l) {
-            if (uniform_log2n == kLaunch3D + CV(l)) err = launch_3d<T, CV(l), SC>(d_descs, n, in_base, out_base, rt, s);
+        static_for<k3DLog2NxMin, k3DLog2NxMax + 1>([&](auto lx) {
+            static_for<k3DLog2NyMin, k3DLog2NyMax + 1>([&](auto ly) {
+                if (uniform_log2n == kind_3d(CV(lx), CV(ly)))
+                    err = launch_3d<T, CV(lx), CV(ly), SC>(d_descs, n, in_base, out_base, rt, s);
+            });
         });
         return err;
     }
@@ -410,7 +429,7 @@ static hipError_t dispatch(const SolveDesc *d_descs, int n, int uniform_log2n, c
 }
 
 // ---- wide lane
-template <typename T, int LOG2N, int SC, bool D3>
+template <typename T, int LOG2N, int SC, bool D3, int LOG2C>
 hipError_t launch_wide_T(int, const WideArgs &, hipStream_t, WideShape *);
 
 template <typename T, int SC>
@@ -418,13 +437,17 @@ static hipError_t wide_dispatch(int kind, int phase, const WideArgs &a, hipStrea
 {
     hipError_t err = hipErrorInvalidValue;
     if (kind >= kLaunch3D) {
-        static_for<k3DLog2NyMin, k3DLog2NyMax + 1>([&](auto l) {
-            if (kind == kLaunch3D + CV(l)) err = launch_wide_T<T, k3DLog2Nx + CV(l), SC, true>(phase, a, s, shape);
+        static_for<k3DLog2NxMin, k3DLog2NxMax + 1>([&](auto lx) {
+            static_for<k3DLog2NyMin, k3DLog2NyMax + 1>([&](auto ly) {
+                if (kind == kind_3d(CV(lx), CV(ly)))
+                    err = launch_wide_T<T, CV(lx) + CV(ly), SC, true, CV(lx)>(phase, a, s, shape);
+            });
         });
         return err;
     }
     static_for<Limits<T>::stg_lo, Limits<T>::stg_hi + 1>([&](auto l) {
-        if (kind == CV(l)) err = launch_wide_T<T, CV(l), SC, false>(phase, a, s, shape);
+        if (kind == CV(l))
+            err = launch_wide_T<T, CV(l), SC, false, staged_log2c(staged_prec<T>())>(phase, a, s, shape);
     });
     return err;
 }
@@ -445,7 +468,7 @@ hipError_t launch_wide(int prec, int kind, int sc, int phase, const WideArgs &a,
 
 bool wide_kind(int prec, int kind)
 {
-    if (kind >= kLaunch3D) return kind - kLaunch3D >= k3DLog2NyMin && kind - kLaunch3D <= k3DLog2NyMax;
+    if (kind >= kLaunch3D) return is_kind_3d(kind);
     if (prec == PREC_F32) return kind >= Limits<float>::stg_lo && kind <= Limits<float>::stg_hi;
     return kind >= Limits<double>::stg_lo && kind <= Limits<double>::stg_hi;
 }

@@ -107,3 +107,22 @@ def test_tables_beyond_32_bit_offsets_are_refused_before_the_device():
     with pytest.raises(bpm.BpmError) as e:
         bpm.Plan(p)
     assert e.value.status == bpm.E_UNSUPPORTED, str(e.value)
+
+
+def test_3d_sizes_outside_the_built_kernels_are_refused_before_the_device():
+    """3D envelopes take nx and ny powers of two with 256 <= nx <= 1024 and
+    16 <= ny <= 256; other powers of two are BPM_E_UNSUPPORTED at validation
+    (an nx that is no power of two is BPM_E_INVALID for every plan)."""
+    import numpy as np
+    from paper_2601_06340_amd import bpm, synth
+    if not os.path.exists(bpm.LIB_PATH):
+        pytest.skip("library not built")
+    for nx, ny, want in ((128, 16, bpm.E_UNSUPPORTED), (2048, 16, bpm.E_UNSUPPORTED), (384, 16, bpm.E_INVALID),
+                         (512, 8, bpm.E_UNSUPPORTED), (512, 512, bpm.E_UNSUPPORTED), (256, 48, bpm.E_UNSUPPORTED)):
+        seg = np.zeros((4, ny, 1, 2), np.int32)
+        seg[:, :, 0, 1] = nx
+        p = synth.base_problem(nx, 4, 0.1, 0.05, seg, precision="f32")
+        p["ny"], p["dy_um"] = ny, 0.2
+        with pytest.raises(bpm.BpmError) as e:
+            bpm.Plan(p)
+        assert e.value.status == want, (nx, ny, str(e.value))

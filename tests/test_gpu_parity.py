@@ -452,11 +452,18 @@ def _wide_case(name):
     if name == "3d-f64-16-o2":
         p, a, b = _problem3d(16, 35, "f64", order=2)
         return p, a, b
+    if name == "3d-f64-1024x16-disl-o2":
+        d2 = dict(disl, x_ref_um=51.25)
+        p, a, b = _problem3d(16, 35, "f64", strain=d2, order=2, nx=1024)
+        return p, a, b
+    if name == "3d-f32-256x128":
+        p, a, b = _problem3d(128, 40, "f32", nx=256)
+        return p, a, b
     raise KeyError(name)
 
 
 WIDE_CASES = ["f32-32768-bent", "f64-16384-bragg-o2", "f32-65536-disl-o4", "f64-65536-bent-short",
-              "3d-f32-256-disl", "3d-f64-16-o2"]
+              "3d-f32-256-disl", "3d-f64-16-o2", "3d-f64-1024x16-disl-o2", "3d-f32-256x128"]
 
 
 @pytest.mark.parametrize("name", WIDE_CASES)
@@ -683,14 +690,15 @@ def test_one_workgroup_staged_and_3d_march_matches_oracle(name):
 
 
 # ------------------------------------------------------------------ 3D envelopes
-def _problem3d(ny, nz, prec, strain=None, order=1, seed=0):
-    nx, dx, dy, dz = 512, 0.1, 0.2, 0.05
+def _problem3d(ny, nz, prec, strain=None, order=1, seed=0, nx=512):
+    dx, dy, dz = 0.1, 0.2, 0.05
+    f = nx / 512   # the section and the detector scale with the row length
     seg = np.zeros((nz, ny, 2, 2), np.int32)
     for n in range(nz):
         for i in range(ny):   # a ragged crystal section that changes with y and z
-            seg[n, i, 0] = (40 + (7 * i + 3 * n) % 50, 200 + (5 * i) % 60)
-            seg[n, i, 1] = (300 - (2 * n) % 40, 470 - (3 * i + n) % 30)
-    p = synth.base_problem(nx, nz, dx, dz, seg, precision=prec, strain=strain, det=(30, 480))
+            seg[n, i, 0] = (int(f * (40 + (7 * i + 3 * n) % 50)), int(f * (200 + (5 * i) % 60)))
+            seg[n, i, 1] = (int(f * (300 - (2 * n) % 40)), int(f * (470 - (3 * i + n) % 30)))
+    p = synth.base_problem(nx, nz, dx, dz, seg, precision=prec, strain=strain, det=(int(30 * f), int(480 * f)))
     p["ny"], p["dy_um"] = ny, dy
     p["split_order"] = order
     rng = np.random.default_rng(seed)
@@ -721,6 +729,67 @@ def test_3d_strain_kinds_and_splitting(prec):
                    for i in range(16)] for n in range(20)])
     p, a, b = _problem3d(16, 20, prec, strain={"kind": "table", "u_table": u}, seed=4)
     check(p, a, b, "3d-table")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("nx", [256, 1024])
+@pytest.mark.parametrize("ny", [16, 64, 256])
+def test_3d_other_row_lengths_random_fields(prec, nx, ny):
+    """Rows of 256 and 1024 samples (4 and 16 per thread), every ny: ragged row
+    masks and random fields against the oracle."""
+    p, a, b = _problem3d(ny, 24, prec, seed=nx + ny, nx=nx)
+    check(p, a, b, "3d-%dx%d" % (nx, ny))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("nx", [256, 1024])
+def test_3d_other_row_lengths_strain_and_splitting(prec, nx):
+    """Polynomial strain with order-2 splitting, the dislocation with order 4
+    and a strain table, at rows of 256 and 1024 samples."""
+    Lx = nx * 0.1
+    poly = {"kind": "poly2", "x_ref_um": Lx / 2, "z_ref_um": 0.7, "c": [0, 1e-5, 0, 0, 4e-5, 0]}
+    p, a, b = _problem3d(32, 30, prec, strain=poly, order=2, seed=21, nx=nx)
+    check(p, a, b, "3d-%d-poly2-o2" % nx)
+    disl = {"kind": "edge_dislocation", "x_ref_um": Lx / 2 + 0.05, "z_ref_um": 0.825, "b_um": 0.38e-3, "nu": 0.22}
+    p, a, b = _problem3d(16, 30, prec, strain=disl, order=4, seed=22, nx=nx)
+    check(p, a, b, "3d-%d-disl-o4" % nx)
+    rng = synth.SplitMix64(12 + nx)
+    u = np.array([[[2e-5 * math.sin(0.01 * j + 0.3 * i + 0.1 * n) + 1e-6 * rng.uniform() for j in range(nx)]
+                   for i in range(16)] for n in range(12)])
+    p, a, b = _problem3d(16, 12, prec, strain={"kind": "table", "u_table": u}, seed=23, nx=nx)
+    check(p, a, b, "3d-%d-table" % nx)
+
+
+def test_3d_row_lengths_of_one_total_size_in_one_batch():
+    """256 x 64, 512 x 32 and 1024 x 16 have the same number of samples: in one
+    batch each keeps its own kernel and tables and reproduces its single solve
+    bitwise, and each matches the oracle."""
+    B = bpm()
+    import torch
+    cases = [_problem3d(64, 20, "f32", seed=31, nx=256), _problem3d(32, 20, "f32", seed=32, nx=512),
+             _problem3d(16, 20, "f32", seed=33, nx=1024), _problem3d(16, 20, "f64", seed=34, nx=1024)]
+    plans = [B.Plan(p) for p, _, _ in cases]
+    singles = [pl.propagate(a, b) for pl, (_, a, b) in zip(plans, cases)]
+    batch = B.Batch(plans)
+    buf = batch.pack([(a, b) for _, a, b in cases])
+    rt = torch.zeros(2 * len(cases), dtype=torch.float64, device="cuda")
+    batch.run(buf.data_ptr(), buf.data_ptr(), rt.data_ptr())
+    torch.cuda.synchronize()
+    outs = batch.unpack(buf)
+    rt = rt.cpu().numpy()
+    for k, ((p, a, b), s, o) in enumerate(zip(cases, singles, outs)):
+        say("   3d %d x %d %s in batch bitwise" % (p["nx"], p["ny"], p["precision"]),
+            np.array_equal(o[0], s[0]) and np.array_equal(o[1], s[1]))
+        assert np.array_equal(o[0], s[0]) and np.array_equal(o[1], s[1])
+        # a single 3D solve marches in the wide lane: same envelopes, FP64 power
+        # sums grouped per workgroup
+        assert abs(rt[2 * k] - s[2]) <= SUM_ORDER_RTOL * abs(s[2])
+        assert abs(rt[2 * k + 1] - s[3]) <= SUM_ORDER_RTOL * abs(s[3])
+        op, om, oR, oT = oracle.propagate(p, a, b)
+        assert rel_pair(o[0], o[1], op, om) <= TOL[p["precision"]][0]
+    batch.close()
+    for pl in plans:
+        pl.close()
 
 
 def test_3d_batch_with_2d_solves_and_far_field():

@@ -1,5 +1,5 @@
 """Seeded random problems through every public march entry point against the
-oracle: sizes 64..65536 in both precisions and 3D envelopes [16..256][512],
+oracle: sizes 64..65536 in both precisions and 3D envelopes [16..256][256..1024],
 0..200 z-steps, splitting orders
 1, 2 and 4, chi0, chih and chihbar drawn per problem (chihbar != chih in most),
 every strain kind (none, polynomial, edge dislocation with whole and
@@ -105,9 +105,9 @@ def random_problem(rng, idx):
 
 
 def random_problem_3d(rng, idx):
-    """3D envelopes [ny][512]: ragged masks per (step, row), every strain kind."""
+    """3D envelopes [ny][nx], nx 256..1024: ragged masks per (step, row), every strain kind."""
     prec = rng.choice(["f32", "f64"])
-    nx, ny = 512, 1 << rng.randint(4, 8)
+    nx, ny = rng.choice([256, 512, 1024]), 1 << rng.randint(4, 8)
     nz = 0 if rng.uniform() < 0.05 else rng.randint(1, 30)
     dx, dy, dz = rng.uniform(0.05, 0.2), rng.uniform(0.05, 0.3), rng.uniform(0.02, 0.1)
     Lx, Lz = nx * dx, max(nz, 1) * dz
