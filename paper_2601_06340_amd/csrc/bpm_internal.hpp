@@ -136,12 +136,15 @@ struct SolveDesc {
 
 // Staged (four-step) lane: 2^staged_log2e samples per thread and beam, rows of
 // one wave (2^(6 + log2e) points); its own kernel runs staged_log2th threads
-// per solve (FP32 1024: sixteen waves keep more state loads in flight), the
-// any-size kernel 2^kStagedAnyLog2Th.
+// per solve, the any-size kernel 2^kStagedAnyLog2Th.  staged_prefetch: the
+// kernels keep the next round's state loads in flight while a round computes
+// (FP32: with 512 threads the register budget holds the second set of samples;
+// 1024 threads without it waited for every round's loads, 4 % slower).
 constexpr int kStagedAnyLog2Th = 9;
 constexpr int staged_log2e(int prec) { return 3; }
 constexpr int staged_log2c(int prec) { return 6 + staged_log2e(prec); }
-constexpr int staged_log2th(int prec) { return prec == PREC_F32 ? 10 : 9; }
+constexpr int staged_log2th(int prec) { return 9; }
+constexpr bool staged_prefetch(int prec) { return prec == PREC_F32; }
 // 3D envelopes: rows of nx = 2^log2nx samples, nx/64 per thread and beam.
 // Threads per solve: FP32 1024 for rows of 512 or fewer samples without the
 // dislocation / table coupling, else 512 (that coupling's per-row mask and

@@ -1329,8 +1329,11 @@ constexpr int staged_bx()
 // 2D transform over (y, x) (no four-step twiddle), the propagator table is
 // [ky][kx], and the coupling reads the mask per row.  Rows are always one wave
 // wide, so C = 2^LOG2C_ samples take C/64 per thread (in both phases).
+// PF: each wave issues its next round's state loads before the current round's
+// arithmetic (one more set of E samples per beam in registers), so only the
+// first round of a phase waits for the state.
 template <typename T, int LOG2N, int SC, int LOG2TH = staged_log2th(staged_prec<T>()), bool D3 = false,
-          int LOG2C_ = staged_log2c(staged_prec<T>())>
+          int LOG2C_ = staged_log2c(staged_prec<T>()), bool PF = false>
 struct Staged {
     static constexpr int LOG2C = LOG2C_, C = 1 << LOG2C;
     static constexpr int LOG2E = LOG2C - 6, E = 1 << LOG2E;
@@ -1457,11 +1460,21 @@ struct Staged {
 
     // Row phase of row k1 (one wave): propagation in Fourier space of sub-step
     // ss (Eq. (12)-(13)); oz, oi are opaque zeros.
+    static __device__ __forceinline__ void row_load(const Ctx &x, int k1, int oz, Cx<T> *vp, Cx<T> *vm)
+    {
+        load(vp, vm, x.st, k1 * C + x.lane + oz, 64);
+    }
     static __device__ __forceinline__ void row(const Ctx &x, const SubStep &ss, int k1, int oz, int oi)
     {
-        const int rb = k1 * C + x.lane + oz;
         Cx<T> vp[E], vm[E];
-        load(vp, vm, x.st, rb, 64);
+        row_load(x, k1, oz, vp, vm);
+        row_run(x, ss, k1, oz, oi, vp, vm);
+    }
+    // the row phase of row k1 on its loaded samples
+    static __device__ __forceinline__ void row_run(const Ctx &x, const SubStep &ss, int k1, int oz, int oi, Cx<T> *vp,
+                                                   Cx<T> *vm)
+    {
+        const int rb = k1 * C + x.lane + oz;
         if constexpr (!D3) {
             static_for<0, E>([&](auto e) {
                 const Tw<T> w = tload_tw<T>(x.tw, rb, TW_4 + e * 64);
@@ -1496,14 +1509,25 @@ struct Staged {
     // Column phase of column c for sub-step i of z-step n: inverse column DFT,
     // coupling (Eq. (9)-(13)), then, unless the march ends here, the next step's
     // leading coupling and forward column DFT; at the end the detector sums.
+    static __device__ __forceinline__ void col_load(const Ctx &x, int c, int oz, Cx<T> *vp, Cx<T> *vm)
+    {
+        load(vp, vm, x.st, x.lc * C + c + oz, LC * C);
+    }
     static __device__ __forceinline__ void col(const Ctx &x, const SolveDesc &d, int n, int i, int c, int oz,
                                                int of, bool rt_out, double &sp, double &sm)
+    {
+        Cx<T> vp[E], vm[E];
+        col_load(x, c, oz, vp, vm);
+        col_run(x, d, n, i, c, oz, of, rt_out, sp, sm, vp, vm);
+    }
+    // the column phase of column c on its loaded samples
+    static __device__ __forceinline__ void col_run(const Ctx &x, const SolveDesc &d, int n, int i, int c, int oz,
+                                                   int of, bool rt_out, double &sp, double &sm, Cx<T> *vp,
+                                                   Cx<T> *vm)
     {
         const int nsub = x.scl->nsub;
         const bool step_end = i + 1 == nsub;
         const bool last = step_end && n + 1 == d.step0 + d.nsteps;
-        Cx<T> vp[E], vm[E];
-        load(vp, vm, x.st, x.lc * C + c + oz, LC * C);
         ColM::inv_local(vp, vm, x.tw + (TW_COL + oz) * TWB, x.CRp, x.CRm, x.lc, true);
         couple_at(x.cpl, vp, vm, d, n, x.lc, c, load_sub(x.scl, i));
         if (!last) {
@@ -1542,14 +1566,48 @@ struct Staged {
         for (int i = x.lead ? 1 : 0; i < nsub; ++i) {
             const SubStep ss = load_sub(x.scl, i);
             __syncthreads();
+            if constexpr (!PF) {
 #pragma unroll 1
-            for (int rr = 0; rr < ROW_ROUNDS; ++rr)
-                row(x, ss, rr * WAVES + wv, (n + i + rr) & d.opaque_zero, (n + i + rr + 1) & d.opaque_zero);
-            __syncthreads();
+                for (int rr = 0; rr < ROW_ROUNDS; ++rr)
+                    row(x, ss, rr * WAVES + wv, (n + i + rr) & d.opaque_zero, (n + i + rr + 1) & d.opaque_zero);
+                __syncthreads();
 #pragma unroll 1
-            for (int cr = 0; cr < COL_ROUNDS; ++cr)
-                col(x, d, n, i, cr * COLS_PER_ROUND + wv * GPW + x.gi, (n + i + cr) & d.opaque_zero,
-                    (n + i + cr + 1) & d.opaque_zero, rt_out, sp, sm);
+                for (int cr = 0; cr < COL_ROUNDS; ++cr)
+                    col(x, d, n, i, cr * COLS_PER_ROUND + wv * GPW + x.gi, (n + i + cr) & d.opaque_zero,
+                        (n + i + cr + 1) & d.opaque_zero, rt_out, sp, sm);
+            } else {
+                // each round's state loads are issued before the previous
+                // round's arithmetic, so only the first round of a phase waits
+                Cx<T> np[E], nm[E];
+                row_load(x, wv, (n + i) & d.opaque_zero, np, nm);
+#pragma unroll 1
+                for (int rr = 0; rr < ROW_ROUNDS; ++rr) {
+                    Cx<T> vp[E], vm[E];
+                    static_for<0, E>([&](auto e) {
+                        vp[e] = np[e];
+                        vm[e] = nm[e];
+                    });
+                    if (rr + 1 < ROW_ROUNDS)
+                        row_load(x, (rr + 1) * WAVES + wv, (n + i + rr + 1) & d.opaque_zero, np, nm);
+                    row_run(x, ss, rr * WAVES + wv, (n + i + rr) & d.opaque_zero, (n + i + rr + 1) & d.opaque_zero,
+                            vp, vm);
+                }
+                __syncthreads();
+                col_load(x, wv * GPW + x.gi, (n + i) & d.opaque_zero, np, nm);
+#pragma unroll 1
+                for (int cr = 0; cr < COL_ROUNDS; ++cr) {
+                    Cx<T> vp[E], vm[E];
+                    static_for<0, E>([&](auto e) {
+                        vp[e] = np[e];
+                        vm[e] = nm[e];
+                    });
+                    if (cr + 1 < COL_ROUNDS)
+                        col_load(x, (cr + 1) * COLS_PER_ROUND + wv * GPW + x.gi, (n + i + cr + 1) & d.opaque_zero,
+                                 np, nm);
+                    col_run(x, d, n, i, cr * COLS_PER_ROUND + wv * GPW + x.gi, (n + i + cr) & d.opaque_zero,
+                            (n + i + cr + 1) & d.opaque_zero, rt_out, sp, sm, vp, vm);
+                }
+            }
         }
 
         if (rt_out) {

@@ -69,13 +69,17 @@ hipError_t launch_uniform(const SolveDesc *d_descs, int n, const char *in_base, 
 // One solve per workgroup for the staged sizes (Staged<>): one workgroup per
 // compute unit (LDS), TH/256 waves per SIMD.
 template <typename T, int LOG2N, int SC>
+using StagedK = Staged<T, LOG2N, SC, staged_log2th(staged_prec<T>()), false, staged_log2c(staged_prec<T>()),
+                       staged_prefetch(staged_prec<T>())>;
+
+template <typename T, int LOG2N, int SC>
 __global__ __launch_bounds__(1 << staged_log2th(staged_prec<T>()))
 __attribute__((amdgpu_waves_per_eu(1, (1 << staged_log2th(staged_prec<T>())) / 256)))
 void k_march_staged(const SolveDesc *__restrict__ descs, int n, const char *in_base, char *out_base, double *rt)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[16];
-    Staged<T, LOG2N, SC>::run(descs[blockIdx.x], in_base, out_base, rt, reinterpret_cast<Cx<T> *>(smem), red);
+    StagedK<T, LOG2N, SC>::run(descs[blockIdx.x], in_base, out_base, rt, reinterpret_cast<Cx<T> *>(smem), red);
 }
 
 template <typename T, int LOG2N, int SC>
@@ -83,14 +87,14 @@ hipError_t launch_staged(const SolveDesc *d_descs, int n, const char *in_base, c
                          hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    const size_t lds = Staged<T, LOG2N, SC>::lds_bytes;
+    const size_t lds = StagedK<T, LOG2N, SC>::lds_bytes;
     // raised once per process (a function-local static is initialised exactly
     // once, also when several threads launch at the same time)
     static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march_staged<T, LOG2N, SC>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_march_staged<T, LOG2N, SC>), dim3(n), dim3(Staged<T, LOG2N, SC>::TH), lds, s, d_descs, n, in_base,
-                       out_base, rt);
+    hipLaunchKernelGGL((k_march_staged<T, LOG2N, SC>), dim3(n), dim3(StagedK<T, LOG2N, SC>::TH), lds, s, d_descs, n,
+                       in_base, out_base, rt);
     return hipGetLastError();
 }
 
@@ -266,8 +270,12 @@ __device__ __forceinline__ void march_any_sc(const SolveDesc &d, const char *in_
             March<T, L2, L2 - mixed_log2th(L2), SC, 1 << kMixedLog2Th>::template run<false>(d, in_base, out_base, rt,
                                                                                            lds, red);
     });
+    // staged sizes with the next round's loads in flight in FP32 (FP64 in this
+    // kernel's 256-register budget marched 3 % slower with them)
     static_for<Limits<T>::stg_lo, Limits<T>::stg_hi + 1>([&](auto l) {
-        if (d.log2n == CV(l)) Staged<T, CV(l), SC, kStagedAnyLog2Th>::run(d, in_base, out_base, rt, lds, red);
+        if (d.log2n == CV(l))
+            Staged<T, CV(l), SC, kStagedAnyLog2Th, false, staged_log2c(staged_prec<T>()),
+                   staged_prec<T>() == PREC_F32>::run(d, in_base, out_base, rt, lds, red);
     });
 }
 

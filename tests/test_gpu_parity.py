@@ -420,9 +420,9 @@ def test_staged_sizes_in_batch_and_chunked_server_equal_single_solves():
     r = srv.poll(t)
     assert r["status"] == 0
     assert np.array_equal(r["psi_p"], singles[0][0]) and np.array_equal(r["psi_m"], singles[0][1])
-    # the server marches staged sizes in the any-size kernel (512-thread
-    # workgroups), a single solve in the staged kernel (1024 threads in FP32):
-    # same envelopes, FP64 power sums grouped differently
+    # the server marches staged sizes in the any-size kernel, a single solve
+    # alone runs in the wide lane: same envelopes, FP64 power sums grouped
+    # differently
     assert abs(r["R"] - singles[0][2]) <= SUM_ORDER_RTOL * abs(singles[0][2])
     srv.close()
 
