@@ -81,8 +81,8 @@ constexpr float kAnyRate[2][7][3] = {
      {7.25e8f, 7.13e8f, 4.19e8f}, {3.47e8f, 3.28e8f, 2.85e8f}, {3.44e8f, 3.31e8f, 2.92e8f},
      {3.14e8f, 3.10e8f, 2.63e8f}},
     {{4.93e8f, 4.42e8f, 3.98e8f}, {6.99e8f, 6.34e8f, 5.40e8f}, {1.11e9f, 1.05e9f, 8.63e8f},
-     {1.24e9f, 1.17e9f, 8.99e8f}, {1.18e9f, 1.16e9f, 7.54e8f}, {4.17e8f, 3.89e8f, 3.64e8f},
-     {3.97e8f, 3.63e8f, 3.45e8f}}};
+     {1.24e9f, 1.17e9f, 8.99e8f}, {1.18e9f, 1.16e9f, 7.54e8f}, {4.33e8f, 4.19e8f, 3.76e8f},
+     {5.44e8f, 3.95e8f, 3.56e8f}}};
 // the reference class: FP32, nx = 16384, polynomial strain
 constexpr double kRefRate = 1.16e9;
 
