@@ -833,8 +833,8 @@ struct Coupler {
                 if constexpr (CV(e) + 1 < E) {
                     bp = {fmaT(bp.x, Q.x, -bp.y * Q.y), fmaT(bp.x, Q.y, bp.y * Q.x)};
                     bm = {fmaT(bm.x, Q.x, bm.y * Q.y), fmaT(bm.y, Q.x, -bm.x * Q.y)};
-                    Q = {fmaT(Q.x, rr.x, -Q.y * rr.y), fmaT(Q.x, rr.y, Q.y * rr.x)};
                 }
+                if constexpr (CV(e) + 2 < E) Q = {fmaT(Q.x, rr.x, -Q.y * rr.y), fmaT(Q.x, rr.y, Q.y * rr.x)};
             });
         } else {
             // dislocation field or tabulated phase (already reduced to one
@@ -981,6 +981,22 @@ struct March {
     template <int LR, int LL, int THR>
     static __device__ __forceinline__ void pass_fwd(Cx<T> *vp, Cx<T> *vm, const BufView &tw, int twb, int tid)
     {
+        constexpr int L = 1 << LL;
+        auto twf = [&](auto, auto m, int j) { return tload_tw<T>(tw, j, twb + (CV(m) - 1) * L); };
+        pass_fwd_f<LR, LL, THR>(vp, vm, twf, tid);
+    }
+    template <int LR, int LL, int THR>
+    static __device__ __forceinline__ void pass_inv(Cx<T> *vp, Cx<T> *vm, const BufView &tw, int twb, int tid)
+    {
+        constexpr int L = 1 << LL;
+        auto twf = [&](auto, auto m, int j) { return tload_tw<T>(tw, j, twb + (CV(m) - 1) * L); };
+        pass_inv_f<LR, LL, THR>(vp, vm, twf, tid);
+    }
+    // the same with the twiddle of element m of group i (at position j of the
+    // sub-length) from tw(i, m, j)
+    template <int LR, int LL, int THR, typename F>
+    static __device__ __forceinline__ void pass_fwd_f(Cx<T> *vp, Cx<T> *vm, const F &twf, int tid)
+    {
         constexpr int r = 1 << LR, EPR = E / r, L = 1 << LL;
         static_for<0, EPR>([&](auto i) {
             Cx<T> ap[r], am[r];
@@ -994,7 +1010,7 @@ struct March {
                 const int j = (tid + i * THR) & (L - 1);
                 sp[0] = sm[0] = 1.0f;
                 static_for<1, r>([&](auto m) {
-                    const Tw<T> w = tload_tw<T>(tw, j, twb + (m - 1) * L);
+                    const Tw<T> w = twf(i, m, j);
                     ap[m] = lift(ap[m], w.p, w.u);
                     am[m] = lift(am[m], w.p, w.u);
                     // angle 2 pi j m / (L r) < pi/2 for m <= r/4: no sign taken out
@@ -1010,7 +1026,7 @@ struct March {
                 if constexpr (L > 1) {
                     const int j = (tid + i * THR) & (L - 1);
                     static_for<1, r>([&](auto m) {
-                        const Tw<T> w = tload_tw<T>(tw, j, twb + (m - 1) * L);
+                        const Tw<T> w = twf(i, m, j);
                         // angle 2 pi j m / (L r) < pi/2 for m <= r/4: no sign taken out
                         if constexpr (4 * CV(m) <= r) {
                             ap[m] = mul_tw_nosign(ap[m], w);
@@ -1030,8 +1046,8 @@ struct March {
             });
         });
     }
-    template <int LR, int LL, int THR>
-    static __device__ __forceinline__ void pass_inv(Cx<T> *vp, Cx<T> *vm, const BufView &tw, int twb, int tid)
+    template <int LR, int LL, int THR, typename F>
+    static __device__ __forceinline__ void pass_inv_f(Cx<T> *vp, Cx<T> *vm, const F &twf, int tid)
     {
         constexpr int r = 1 << LR, EPR = E / r, L = 1 << LL;
         static_for<0, EPR>([&](auto i) {
@@ -1045,7 +1061,7 @@ struct March {
             if constexpr (L > 1) {
                 const int j = (tid + i * THR) & (L - 1);
                 static_for<1, r>([&](auto m) {
-                    const Tw<T> w = tload_tw<T>(tw, j, twb + (m - 1) * L);
+                    const Tw<T> w = twf(i, m, j);
                     if constexpr (4 * CV(m) <= r) {
                         ap[m] = mul_tw_inv_nosign(ap[m], w);
                         am[m] = mul_tw_inv_nosign(am[m], w);
@@ -1228,6 +1244,57 @@ struct March {
             constexpr int p = PW - 1 - CV(pp);
             if constexpr (p + 1 < PW) gx<p, true>(vp, vm, Rp, Rm, l, active);
             if (active) pass_inv<SW::log2r(p), SW::log2L(p), LANES>(vp, vm, tw, SW::twbase(p), l);
+        });
+    }
+
+    // ---- the group-local passes' twiddles of one lane, held in registers: they
+    // depend only on the lane's position (element m of group i of pass p at
+    // position j = (l + i LANES) mod L), so a kernel that runs many transforms
+    // per lane loads them once instead of after every LDS exchange
+    static constexpr int cache_off(int p)
+    {
+        int o = 0;
+        for (int q = 0; q < p; ++q)
+            if (SW::log2L(q) > 0) o += (E >> SW::log2r(q)) * ((1 << SW::log2r(q)) - 1);
+        return o;
+    }
+    static constexpr int CACHE_N = cache_off(PW) > 0 ? cache_off(PW) : 1;
+    struct TwCache {
+        Tw<T> v[CACHE_N];
+    };
+    static __device__ __forceinline__ void load_cache(TwCache &c, const BufView &tw, int l)
+    {
+        static_for<0, PW>([&](auto pc) {
+            constexpr int p = CV(pc), LR = SW::log2r(p), r = 1 << LR, L = 1 << SW::log2L(p), EPR = E / r;
+            if constexpr (L > 1) {
+                static_for<0, EPR>([&](auto i) {
+                    const int j = (l + CV(i) * LANES) & (L - 1);
+                    static_for<1, r>([&](auto m) {
+                        c.v[cache_off(p) + CV(i) * (r - 1) + CV(m) - 1] =
+                            tload_tw<T>(tw, j, SW::twbase(p) + (CV(m) - 1) * L);
+                    });
+                });
+            }
+        });
+    }
+    static __device__ __forceinline__ void fwd_local(Cx<T> *vp, Cx<T> *vm, const TwCache &c, Cx<T> *Rp, Cx<T> *Rm,
+                                                     int l, bool active)
+    {
+        static_for<0, PW>([&](auto pc) {
+            constexpr int p = CV(pc), r = 1 << SW::log2r(p);
+            auto twf = [&](auto i, auto m, int) { return c.v[cache_off(p) + CV(i) * (r - 1) + CV(m) - 1]; };
+            if (active) pass_fwd_f<SW::log2r(p), SW::log2L(p), LANES>(vp, vm, twf, l);
+            if constexpr (p + 1 < PW) gx<p, false>(vp, vm, Rp, Rm, l, active);
+        });
+    }
+    static __device__ __forceinline__ void inv_local(Cx<T> *vp, Cx<T> *vm, const TwCache &c, Cx<T> *Rp, Cx<T> *Rm,
+                                                     int l, bool active)
+    {
+        static_for<0, PW>([&](auto pp) {
+            constexpr int p = PW - 1 - CV(pp), r = 1 << SW::log2r(p);
+            auto twf = [&](auto i, auto m, int) { return c.v[cache_off(p) + CV(i) * (r - 1) + CV(m) - 1]; };
+            if constexpr (p + 1 < PW) gx<p, true>(vp, vm, Rp, Rm, l, active);
+            if (active) pass_inv_f<SW::log2r(p), SW::log2L(p), LANES>(vp, vm, twf, l);
         });
     }
 
@@ -1512,6 +1579,10 @@ struct Staged {
         T invN;
         CPlanScalars *scl;   // read-only for the launch: scalar loads
         bool lead;   // sub-step 0 is a leading coupling (no propagation before it)
+        // PF: the row and column passes' twiddles of this lane in registers
+        struct NoCache {};
+        typename std::conditional<PF, typename RowM::TwCache, NoCache>::type rc;
+        typename std::conditional<PF, typename ColM::TwCache, NoCache>::type cc;
 
         __device__ __forceinline__ void init(const SolveDesc &d, const char *in_base, char *out_base, Cx<T> *slab,
                                              int lane_)
@@ -1532,6 +1603,10 @@ struct Staged {
             invN = (T)(1.0 / (double)N);
             scl = (CPlanScalars *)(d.sc);
             lead = scl->sub[0].table < 0;
+            if constexpr (PF) {
+                RowM::load_cache(rc, tw, lane);
+                ColM::load_cache(cc, tw + TW_COL * (int)sizeof(Tw<T>), lc);
+            }
         }
     };
     static constexpr int TWB = (int)sizeof(Tw<T>);
@@ -1583,7 +1658,8 @@ struct Staged {
                 vm[e] = mul_tw(vm[e], w);
             });
         }
-        RowM::fwd_local(vp, vm, x.tw + oz * TWB, x.RRp, x.RRm, x.lane, true);
+        if constexpr (PF) RowM::fwd_local(vp, vm, x.rc, x.RRp, x.RRm, x.lane, true);
+        else RowM::fwd_local(vp, vm, x.tw + oz * TWB, x.RRp, x.RRm, x.lane, true);
         // bin k2 = lane + 64 e of row k1 is frequency k1 + R k2
         const BufView pr = buf_view(x.prop + ss.table * 2 * N, 2 * N * (uint32_t)sizeof(PropE<T>),
                                     oz * (int)sizeof(PropE<T>));
@@ -1595,7 +1671,8 @@ struct Staged {
             vp[e] = prop_mul(a, kp, invN);
             vm[e] = prop_mul(b, km, invN);
         });
-        RowM::inv_local(vp, vm, x.tw + oi * TWB, x.RRp, x.RRm, x.lane, true);
+        if constexpr (PF) RowM::inv_local(vp, vm, x.rc, x.RRp, x.RRm, x.lane, true);
+        else RowM::inv_local(vp, vm, x.tw + oi * TWB, x.RRp, x.RRm, x.lane, true);
         const int rbi = k1 * C + x.lane + oi;
         if constexpr (!D3) {
             static_for<0, E>([&](auto e) {
@@ -1629,11 +1706,13 @@ struct Staged {
         const int nsub = x.scl->nsub;
         const bool step_end = i + 1 == nsub;
         const bool last = step_end && n + 1 == d.step0 + d.nsteps;
-        ColM::inv_local(vp, vm, x.tw + (TW_COL + oz) * TWB, x.CRp, x.CRm, x.lc, true);
+        if constexpr (PF) ColM::inv_local(vp, vm, x.cc, x.CRp, x.CRm, x.lc, true);
+        else ColM::inv_local(vp, vm, x.tw + (TW_COL + oz) * TWB, x.CRp, x.CRm, x.lc, true);
         couple_at(x.cpl, vp, vm, d, n, x.lc, c, load_sub(x.scl, i));
         if (!last) {
             if (step_end && x.lead) couple_at(x.cpl, vp, vm, d, n + 1, x.lc, c, load_sub(x.scl, 0));
-            ColM::fwd_local(vp, vm, x.tw + (TW_COL + of) * TWB, x.CRp, x.CRm, x.lc, true);
+            if constexpr (PF) ColM::fwd_local(vp, vm, x.cc, x.CRp, x.CRm, x.lc, true);
+            else ColM::fwd_local(vp, vm, x.tw + (TW_COL + of) * TWB, x.CRp, x.CRm, x.lc, true);
         } else if (rt_out) {
             det_sums(vp, vm, d, x.lc * C + c, LC * C, sp, sm);
         }
