@@ -1499,9 +1499,10 @@ constexpr int staged_bx()
 // wide, so C = 2^LOG2C_ samples take C/64 per thread (in both phases).
 // PF: each wave issues its next round's state loads before the current round's
 // arithmetic (one more set of E samples per beam in registers), so only the
-// first round of a phase waits for the state.
+// first round of a phase waits for the state.  TC: the row and column passes'
+// twiddles of each lane are held in registers for the whole launch.
 template <typename T, int LOG2N, int SC, int LOG2TH = staged_log2th(staged_prec<T>()), bool D3 = false,
-          int LOG2C_ = staged_log2c(staged_prec<T>()), bool PF = false>
+          int LOG2C_ = staged_log2c(staged_prec<T>()), bool PF = false, bool TC = PF>
 struct Staged {
     static constexpr int LOG2C = LOG2C_, C = 1 << LOG2C;
     static constexpr int LOG2E = LOG2C - 6, E = 1 << LOG2E;
@@ -1579,10 +1580,10 @@ struct Staged {
         T invN;
         CPlanScalars *scl;   // read-only for the launch: scalar loads
         bool lead;   // sub-step 0 is a leading coupling (no propagation before it)
-        // PF: the row and column passes' twiddles of this lane in registers
+        // TC: the row and column passes' twiddles of this lane in registers
         struct NoCache {};
-        typename std::conditional<PF, typename RowM::TwCache, NoCache>::type rc;
-        typename std::conditional<PF, typename ColM::TwCache, NoCache>::type cc;
+        typename std::conditional<TC, typename RowM::TwCache, NoCache>::type rc;
+        typename std::conditional<TC, typename ColM::TwCache, NoCache>::type cc;
 
         __device__ __forceinline__ void init(const SolveDesc &d, const char *in_base, char *out_base, Cx<T> *slab,
                                              int lane_)
@@ -1603,7 +1604,7 @@ struct Staged {
             invN = (T)(1.0 / (double)N);
             scl = (CPlanScalars *)(d.sc);
             lead = scl->sub[0].table < 0;
-            if constexpr (PF) {
+            if constexpr (TC) {
                 RowM::load_cache(rc, tw, lane);
                 ColM::load_cache(cc, tw + TW_COL * (int)sizeof(Tw<T>), lc);
             }
@@ -1658,7 +1659,7 @@ struct Staged {
                 vm[e] = mul_tw(vm[e], w);
             });
         }
-        if constexpr (PF) RowM::fwd_local(vp, vm, x.rc, x.RRp, x.RRm, x.lane, true);
+        if constexpr (TC) RowM::fwd_local(vp, vm, x.rc, x.RRp, x.RRm, x.lane, true);
         else RowM::fwd_local(vp, vm, x.tw + oz * TWB, x.RRp, x.RRm, x.lane, true);
         // bin k2 = lane + 64 e of row k1 is frequency k1 + R k2
         const BufView pr = buf_view(x.prop + ss.table * 2 * N, 2 * N * (uint32_t)sizeof(PropE<T>),
@@ -1671,7 +1672,7 @@ struct Staged {
             vp[e] = prop_mul(a, kp, invN);
             vm[e] = prop_mul(b, km, invN);
         });
-        if constexpr (PF) RowM::inv_local(vp, vm, x.rc, x.RRp, x.RRm, x.lane, true);
+        if constexpr (TC) RowM::inv_local(vp, vm, x.rc, x.RRp, x.RRm, x.lane, true);
         else RowM::inv_local(vp, vm, x.tw + oi * TWB, x.RRp, x.RRm, x.lane, true);
         const int rbi = k1 * C + x.lane + oi;
         if constexpr (!D3) {
@@ -1706,12 +1707,12 @@ struct Staged {
         const int nsub = x.scl->nsub;
         const bool step_end = i + 1 == nsub;
         const bool last = step_end && n + 1 == d.step0 + d.nsteps;
-        if constexpr (PF) ColM::inv_local(vp, vm, x.cc, x.CRp, x.CRm, x.lc, true);
+        if constexpr (TC) ColM::inv_local(vp, vm, x.cc, x.CRp, x.CRm, x.lc, true);
         else ColM::inv_local(vp, vm, x.tw + (TW_COL + oz) * TWB, x.CRp, x.CRm, x.lc, true);
         couple_at(x.cpl, vp, vm, d, n, x.lc, c, load_sub(x.scl, i));
         if (!last) {
             if (step_end && x.lead) couple_at(x.cpl, vp, vm, d, n + 1, x.lc, c, load_sub(x.scl, 0));
-            if constexpr (PF) ColM::fwd_local(vp, vm, x.cc, x.CRp, x.CRm, x.lc, true);
+            if constexpr (TC) ColM::fwd_local(vp, vm, x.cc, x.CRp, x.CRm, x.lc, true);
             else ColM::fwd_local(vp, vm, x.tw + (TW_COL + of) * TWB, x.CRp, x.CRm, x.lc, true);
         } else if (rt_out) {
             det_sums(vp, vm, d, x.lc * C + c, LC * C, sp, sm);
