@@ -1316,8 +1316,9 @@ struct March {
 
     // CS: read the plan scalars as scalar loads (false: generic loads, which the
     // any-size kernel marches faster with; its inlined sizes and strain
-    // classes leave no scalar registers to hold them)
-    template <bool CS = true>
+    // classes leave no scalar registers to hold them).  TC: hold the
+    // group-local passes' twiddles of this thread in registers for the march.
+    template <bool CS = true, bool TC = false>
     static __device__ void run(const SolveDesc &d, const char *in_base, char *out_base, double *rt,
                                Cx<T> *lds, double *red)
     {
@@ -1333,6 +1334,9 @@ struct March {
         Cx<T> *bufp = lds;
         Cx<T> *bufm = lds + (BX == 2 ? W * BUFM : 0);
 
+        struct NoCache {};
+        typename std::conditional<TC, TwCache, NoCache>::type tcache;
+        if constexpr (TC) load_cache(tcache, tw, l0);
         Cx<T> vp[E], vm[E];
         if (active) {
             static_for<0, E>([&](auto e) {
@@ -1383,7 +1387,8 @@ struct March {
 
             if (ss.table >= 0) {
                 // ---- forward transforms (Eq. (12): F[psi+-]); group-local passes
-                fwd_local(vp, vm, twf, Rp, Rm, l, active);
+                if constexpr (TC) fwd_local(vp, vm, tcache, Rp, Rm, l, active);
+                else fwd_local(vp, vm, twf, Rp, Rm, l, active);
                 // ---- cross-group radix-W pass (wave groups only)
                 if constexpr (W > 1) {
                     if (active) {
@@ -1430,7 +1435,8 @@ struct March {
                         if (active) read_own(Rm, vm, l);
                     }
                 }
-                inv_local(vp, vm, twi, Rp, Rm, l, active);
+                if constexpr (TC) inv_local(vp, vm, tcache, Rp, Rm, l, active);
+                else inv_local(vp, vm, twi, Rp, Rm, l, active);
             }
 
             // ---- real-space coupling inside the crystal (Eq. (9)-(13))

@@ -29,7 +29,12 @@ void k_march_uniform(
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[16];
     const SolveDesc &d = descs[blockIdx.x];
-    March<T, LOG2N, LOG2E, SC>::run(d, in_base, out_base, rt, reinterpret_cast<Cx<T> *>(smem), red);
+    // FP32 with up to 256 threads (one wave per SIMD or fewer: a 512-register
+    // budget): the pass twiddles stay in registers (Nx 4096 +8 %; FP64 held
+    // part of them in the accumulation registers and lost 6 %)
+    constexpr bool TC = LOG2N - LOG2E <= 8 && staged_prec<T>() == PREC_F32;
+    March<T, LOG2N, LOG2E, SC>::template run<true, TC>(d, in_base, out_base, rt, reinterpret_cast<Cx<T> *>(smem),
+                                                       red);
 }
 
 // Mixed sizes in one launch: 512 threads per workgroup, E = nx/512.
