@@ -1658,9 +1658,12 @@ struct Staged {
                                                    Cx<T> *vm)
     {
         const int rb = k1 * C + x.lane + oz;
+        // TC: the round's four-step twiddles stay in registers for the inverse
+        Tw<T> w4[TC && !D3 ? E : 1];
         if constexpr (!D3) {
             static_for<0, E>([&](auto e) {
                 const Tw<T> w = tload_tw<T>(x.tw, rb, TW_4 + e * 64);
+                if constexpr (TC) w4[e] = w;
                 vp[e] = mul_tw(vp[e], w);
                 vm[e] = mul_tw(vm[e], w);
             });
@@ -1683,7 +1686,9 @@ struct Staged {
         const int rbi = k1 * C + x.lane + oi;
         if constexpr (!D3) {
             static_for<0, E>([&](auto e) {
-                const Tw<T> w = tload_tw<T>(x.tw, rbi, TW_4 + e * 64);
+                Tw<T> w;
+                if constexpr (TC) w = w4[e];
+                else w = tload_tw<T>(x.tw, rbi, TW_4 + e * 64);
                 vp[e] = mul_tw_inv(vp[e], w);
                 vm[e] = mul_tw_inv(vm[e], w);
             });
