@@ -37,6 +37,7 @@ THREE_D_LOG2NX = range(8, 11)  # 3D envelopes: rows of nx = 256..1024
 THREE_D_LOG2NY = range(4, 9)   # ny = 16..256 rows
 MIXED = ("float", "double")
 STRAIN_CLASSES = (0, 1, 2)   # none, polynomial, dislocation/table
+POLY1_CLASS = 3              # polynomial without the X^2 term: FP32 per-size kernels only
 
 
 def _gen_units() -> list[str]:
@@ -79,6 +80,11 @@ def _gen_units() -> list[str]:
                   '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
                   "template hipError_t launch_mixed<%s, %d>(const SolveDesc *, int, const char *, char *, "
                   "double *, hipStream_t);\n}\n" % (t, sc))
+    for l2 in UNIFORM["float"]:
+        write("march_float_%d_sc%d.hip" % (l2, POLY1_CLASS),
+              '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'
+              "template hipError_t launch_uniform<float, %d, %d>(const SolveDesc *, int, const char *, "
+              "char *, double *, hipStream_t);\n}\n" % (l2, POLY1_CLASS))
     for t in MIXED:
         write("march_any_%s.hip" % t,
               '#include "bpm_march_kernels.hpp"\nnamespace bpm {\n'

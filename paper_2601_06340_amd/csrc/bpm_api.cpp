@@ -181,9 +181,12 @@ static bpm_status prop_acquire(const bpm_plan_desc &d, const PlanParams *d_param
     int log2n = 0;
     while ((1 << log2n) < d.nx) ++log2n;
     const int log2r = ny == 1 && is_staged(d.precision, log2n) ? log2n - staged_log2c(d.precision) : 0;
+    // the staged 2D kernels read FP32 entries in the lifting form
+    const bool lift = d.precision == BPM_F32 && ny == 1 && is_staged(d.precision, log2n);
     hipStream_t ss = setup_stream();
     for (int k = 0; k < ntab && e == hipSuccess; ++k)
-        e = launch_plan_setup(d_params, nullptr, (char *)p + k * one, d.precision, d.nx * ny, log2r, afrac[k], ss);
+        e = launch_plan_setup(d_params, nullptr, (char *)p + k * one, d.precision, d.nx * ny, log2r, afrac[k], lift,
+                              ss);
     if (e == hipSuccess) e = hipStreamSynchronize(ss);
     if (e != hipSuccess) {
         (void)hipFree(p);
@@ -215,6 +218,8 @@ static bool is_finite(bpm_complex c) { return std::isfinite(c.re) && std::isfini
 // largest table (mask, strain table) one solve may hold: the kernels index
 // them with 32-bit byte offsets
 constexpr long long kMaxTableBytes = 0x7fffffffLL;
+// bounds on one coupling sub-step (see validate_desc)
+constexpr double kMaxCouplingY = 100.0, kMaxCouplingPhase = 700.0;
 
 bpm_status bpm::validate_desc(const bpm_plan_desc *d)
 {
@@ -230,6 +235,27 @@ bpm_status bpm::validate_desc(const bpm_plan_desc *d)
     if (!(d->lambda_um < 2.0 * d->d_um)) return fail(BPM_E_INVALID, "lambda >= 2d: no Bragg angle");
     if (!is_finite(d->chi0) || !is_finite(d->chih) || !is_finite(d->chihbar))
         return fail(BPM_E_INVALID, "susceptibilities must be finite");
+    if (d->split_order == 0 || d->split_order == 1 || d->split_order == 2 || d->split_order == 4) {
+        // The coupling coefficients of a sub-step (Eq. (9)-(12)) are series in
+        // y = -A^2 chih chihbar and carry exp(i A chi0), A = b k dz / 2 cos(theta_B).
+        // Bounding |y| keeps the 60-term series converged and free of ruinous
+        // cancellation (its largest term stays below 1e7), bounding |A chi0|
+        // keeps the exponential finite: every coefficient is finite, which the
+        // march relies on where it weights the coupling by 0 outside the crystal.
+        double a[kMaxSub], b[kMaxSub];
+        const int m = split_sequence(d->split_order, a, b);
+        double bmax = 0.0;
+        for (int i = 0; i < m; ++i) bmax = std::max(bmax, std::fabs(b[i]));
+        const double k = 2.0 * M_PI / d->lambda_um, s = M_PI / (d->d_um * k);
+        const double A = bmax * k * d->dz_um / (2.0 * std::sqrt(1.0 - s * s));
+        const double y = A * A * std::hypot(d->chih.re, d->chih.im) * std::hypot(d->chihbar.re, d->chihbar.im);
+        const double g = A * std::hypot(d->chi0.re, d->chi0.im);
+        if (!(y <= kMaxCouplingY) || !(g <= kMaxCouplingPhase))
+            return fail(BPM_E_INVALID,
+                        "coupling step too long: |A^2 chih chihbar| = %.3g (at most %g), |A chi0| = %.3g (at most %g); "
+                        "reduce dz",
+                        y, kMaxCouplingY, g, kMaxCouplingPhase);
+    }
     const bool d3 = d->ny > 1;
     if (d->ny < 0) return fail(BPM_E_INVALID, "ny = %d < 0", d->ny);
     if (d3) {
@@ -495,7 +521,7 @@ extern "C" bpm_status bpm_plan_create(const bpm_plan_desc *d, bpm_plan **out)
         e = hipMemcpyAsync(p->d_seg, d->seg, p->rows() * d->nseg * 2 * sizeof(int32_t), hipMemcpyHostToDevice, ss);
     if (e == hipSuccess) e = hipStreamSynchronize(ss);
     if (e != hipSuccess) return bail(hip_fail(e, "plan upload"));
-    e = launch_plan_setup(p->d_params, p->d_sc, nullptr, prec, d->nx, 0, 1.0, ss);
+    e = launch_plan_setup(p->d_params, p->d_sc, nullptr, prec, d->nx, 0, 1.0, false, ss);
     if (e != hipSuccess) return bail(hip_fail(e, "plan setup kernel"));
     if ((st = prop_acquire(*d, p->d_params, &p->d_prop)) != BPM_OK) return bail(st);
 
@@ -656,7 +682,8 @@ extern "C" bpm_status bpm_propagate_device(bpm_plan *p, void *stream, const void
     if (p->d_wide_ctl)
         return propagate_wide(p, (hipStream_t)stream, (const char *)d_in, (char *)d_out, d_RT ? d_RT : p->d_rt, 0,
                               p->desc.nz, SF_FIRST | SF_LAST);
-    hipError_t e = launch_march(p->d_desc1, 1, p->desc.precision, p->launch_kind, strain_class(p->desc.strain.kind),
+    hipError_t e = launch_march(p->d_desc1, 1, p->desc.precision, p->launch_kind,
+                                march_class(p->desc.strain.kind, p->desc.strain.c[3]),
                                 (const char *)d_in, (char *)d_out,
                                 d_RT ? d_RT : p->d_rt, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "march launch");
@@ -679,6 +706,9 @@ extern "C" bpm_status bpm_far_field(bpm_plan *p, double distance_um, void *strea
         const std::vector<int32_t> empty(2 * (size_t)std::max(1, p->desc.ny), 0);   // one empty interval per row
         v.nz = 1;
         v.dz_um = distance_um;
+        // no crystal anywhere: zero susceptibilities (the propagator does not
+        // depend on them, and the coupling of a metres-long step is not bounded)
+        v.chi0 = v.chih = v.chihbar = bpm_complex{0.0, 0.0};
         v.nseg = 1;
         v.seg = empty.data();
         std::memset(&v.strain, 0, sizeof v.strain);
@@ -793,6 +823,12 @@ bpm_status bpm::build_launches(bpm_plan *const *plans, int n, const std::vector<
         Launch L;
         L.prec = prec;
         L.sc = sc;
+        // a polynomial class whose every solve lacks the X^2 term runs as SC_POLY1
+        if (sc == SC_POLY2) {
+            bool lin = true;
+            for (int i : g) lin = lin && march_class(plans[i]->desc.strain.kind, plans[i]->desc.strain.c[3]) == SC_POLY1;
+            if (lin) L.sc = SC_POLY1;
+        }
         L.uniform_log2n = group_log2n;
         std::vector<SolveDesc> descs(g.size());
         for (size_t k = 0; k < g.size(); ++k) {

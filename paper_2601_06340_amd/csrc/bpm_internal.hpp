@@ -13,10 +13,18 @@ enum Prec : int32_t { PREC_F64 = 0, PREC_F32 = 1 };
 enum StrainKind : int32_t { STRAIN_NONE = 0, STRAIN_POLY2 = 1, STRAIN_EDGE = 2, STRAIN_TABLE = 3 };
 
 // Strain classes compiled as separate kernels (one straight-line coupling each).
-enum StrainClass : int { SC_NONE = 0, SC_POLY2 = 1, SC_GENERAL = 2 };
+// SC_POLY1 is a polynomial phase without its X^2 term (c3 = 0, as a bend
+// u = X Z / R): the FP32 per-size kernels have a copy for it, every other
+// kernel takes it as SC_POLY2 (same results: the X^2 factor it leaves out is
+// then exactly one).  strain_class() never returns it; march_class() does.
+enum StrainClass : int { SC_NONE = 0, SC_POLY2 = 1, SC_GENERAL = 2, SC_POLY1 = 3 };
 __host__ __device__ constexpr int strain_class(int kind)
 {
     return kind == STRAIN_NONE ? SC_NONE : kind == STRAIN_POLY2 ? SC_POLY2 : SC_GENERAL;
+}
+__host__ __device__ constexpr int march_class(int kind, double c3)
+{
+    return strain_class(kind) == SC_POLY2 && c3 == 0.0 ? SC_POLY1 : strain_class(kind);
 }
 
 // Splitting of one z-step (Eq. (13)): the product A(a_1 dz) B(b_1 dz) ...
@@ -195,8 +203,9 @@ constexpr int uniform_log2e(int log2n) { return log2n >= 8 ? 4 : (log2n >= 7 ? 3
 // sub-step of afrac*dz over `cells` = nx (or nx*ny for 3D, [ky][kx] order)
 // entries per beam; log2r > 0 stores the propagator of a staged size in
 // [k1][k2] order (R = 2^log2r).
+// lift: FP32 propagator entries in the lifting form of the staged 2D kernels
 hipError_t launch_plan_setup(const PlanParams *d_params, PlanScalars *d_sc, void *d_prop, int prec,
-                             int cells, int log2r, double afrac, hipStream_t s);
+                             int cells, int log2r, double afrac, bool lift, hipStream_t s);
 hipError_t launch_twiddles(void *d_tw, int prec, int log2n, int log2e, hipStream_t s);
 size_t twiddle_bytes(int prec, int log2n, int log2e);
 // Staged sizes (four-step lane): whether log2n is one, and its twiddle table

@@ -174,6 +174,32 @@ __device__ __forceinline__ PropE<T> tload_prop(const BufView &t, int lane_i, int
     return tload_prop(t, (PropE<T> *)nullptr, lane_i, uni_i);
 }
 
+// FP32 table entry of the staged 2D sizes: P/N = c exp(i phi) as a lifting
+// rotation by phi (folded into [-pi/2, pi/2]) and a scale c = +-|P|/N (the
+// sign takes the folded half turn; |P| = 1 outside the evanescent bins, so c
+// is then a signed power of two): p = -tan(phi/2) rounded to float and
+// u = (1 - cos phi)/(-p) as hi + lo.  With p u = 1 - cos phi to about 2^-48
+// the three shears turn the bin by exactly phi; the rounding of p only makes
+// the orbit an ellipse of axis ratio 1 + O(2^-24), an amplitude wobble that
+// does not grow with Nz (each shear has determinant one).  Three fewer
+// operations per sample than a/N + k a with k as hi + lo; the per-size,
+// mixed-size and 3D kernels, which wait on the table loads of this step, are
+// faster with the hi + lo entries, whose arithmetic covers more of that wait.
+// (Staged 2D batch of Nx 32768: +2 %; per-size Nx 16384: -5 %, mixed-size
+// pulse batch -20 %, 3D batch -2 % when they took the lifting form as well.)
+struct alignas(16) PropLift {
+    float p, uh, ul, c;
+};
+static_assert(sizeof(PropLift) == kPropEntryBytes, "table entry");
+__device__ __forceinline__ PropLift tload_prop(const BufView &t, PropLift *, int lane_i, int uni_i)
+{
+    const u4v v = __builtin_amdgcn_raw_buffer_load_b128(t.r, lane_i * 16, t.base + uni_i * 16, 0);
+    return {f_of(v.x), f_of(v.y), f_of(v.z), f_of(v.w)};
+}
+// the entry type of the staged tables (D3: the 3D envelopes' tables)
+template <typename T, bool D3>
+using StagedPropE = typename std::conditional<std::is_same<T, float>::value && !D3, PropLift, PropE<T>>::type;
+
 __device__ __forceinline__ float tload_r(const BufView &t, float *, int lane_off, int uni_off)
 {
     return f_of(__builtin_amdgcn_raw_buffer_load_b32(t.r, lane_off, t.base + uni_off, 0));
@@ -716,23 +742,38 @@ __device__ __forceinline__ Cx<double> prop_mul(Cx<double> a, const PropE<double>
 {
     return {fmaT(a.x, invN, fmaT(k.x, a.x, -k.y * a.y)), fmaT(a.y, invN, fmaT(k.x, a.y, k.y * a.x))};
 }
-
-// psi+ <- psi+ + d0 psi+ + bp psi-,  psi- <- psi- + d0 psi- + bm psi+   (Eq. (12))
-// where the sample is inside the crystal; outside, both envelopes keep their
-// propagated values (pure propagation).  The increments are summed before the
-// envelope itself is added, for the same reason as in prop_mul.
-template <typename T>
-__device__ __forceinline__ void couple_sel(Cx<T> &vp, Cx<T> &vm, bool in, Cx<T> d0, Cx<T> bp, Cx<T> bm)
+// P a / N from a lifting entry: three shears x += p y, y += u x, x += p y (the
+// middle increment summed from its hi and lo products before it meets y, so it
+// sees u to about 2^-48; each shear adds its whole increment in one rounding),
+// then the scale c (exact outside the evanescent bins)
+__device__ __forceinline__ Cx<float> prop_mul(Cx<float> a, const PropLift &k, float)
 {
-    // (selected, not weighted by 0 / 1: outside the crystal the coefficients
-    // need not be finite, e.g. those of a far-field plan's vacuum step)
+    const float x1 = fmaT(k.p, a.y, a.x);
+    const float y1 = a.y + fmaT(k.uh, x1, k.ul * x1);
+    const float x2 = fmaT(k.p, y1, x1);
+    return {k.c * x2, k.c * y1};
+}
+
+// psi+ <- psi+ + m (d0 psi+ + bp psi-),  psi- <- psi- + m (d0 psi- + bm psi+)
+// (Eq. (12)) with m = 1 where the sample is inside the crystal and m = 0
+// outside, where both envelopes keep their propagated values (pure
+// propagation).  The increments are summed before the envelope itself is
+// added, for the same reason as in prop_mul; m weights them in that last
+// fused operation, so for m = 1 the result is the sum rounded once and for
+// m = 0 the envelope itself.  The coefficients are finite by construction
+// (plan creation bounds the coupling step), so 0 x increment is 0.
+template <typename T>
+__device__ __forceinline__ void couple(Cx<T> &vp, Cx<T> &vm, T m, Cx<T> d0, Cx<T> bp, Cx<T> bm)
+{
     const Cx<T> a = vp, b = vm;
-    const Cx<T> np = {a.x + fmaT(bp.x, b.x, fmaT(-bp.y, b.y, fmaT(d0.x, a.x, -d0.y * a.y))),
-                      a.y + fmaT(bp.x, b.y, fmaT(bp.y, b.x, fmaT(d0.x, a.y, d0.y * a.x)))};
-    const Cx<T> nm = {b.x + fmaT(bm.x, a.x, fmaT(-bm.y, a.y, fmaT(d0.x, b.x, -d0.y * b.y))),
-                      b.y + fmaT(bm.x, a.y, fmaT(bm.y, a.x, fmaT(d0.x, b.y, d0.y * b.x)))};
-    vp = {in ? np.x : a.x, in ? np.y : a.y};
-    vm = {in ? nm.x : b.x, in ? nm.y : b.y};
+    const Cx<T> ip = {fmaT(bp.x, b.x, fmaT(-bp.y, b.y, fmaT(d0.x, a.x, -d0.y * a.y))),
+                      fmaT(bp.x, b.y, fmaT(bp.y, b.x, fmaT(d0.x, a.y, d0.y * a.x)))};
+    const Cx<T> im = {fmaT(bm.x, a.x, fmaT(-bm.y, a.y, fmaT(d0.x, b.x, -d0.y * b.y))),
+                      fmaT(bm.x, a.y, fmaT(bm.y, a.x, fmaT(d0.x, b.y, d0.y * b.x)))};
+    vp.x = fmaT(ip.x, m, vp.x);
+    vp.y = fmaT(ip.y, m, vp.y);
+    vm.x = fmaT(im.x, m, vm.x);
+    vm.y = fmaT(im.y, m, vm.y);
 }
 
 // a value the whole wave holds, moved to scalar registers
@@ -757,9 +798,12 @@ __device__ __forceinline__ void wave_lds_sync()
 
 // Real-space coupling of one z-step or sub-step (Eq. (9)-(13)) for the E samples
 // a thread holds at j0 + JS*e.  Outside the crystal the step is pure propagation:
-// those samples keep their propagated values.
+// those samples keep their propagated values.  SC_POLY1 (no X^2 term) has a
+// phase whose second difference along a thread's samples is zero: its phasor
+// steps leave out that factor, which is then exactly one.
 template <typename T, int SC>
 struct Coupler {
+    static constexpr bool POLY = SC == SC_POLY2 || SC == SC_POLY1, LIN = SC == SC_POLY1;
     double X0;       // x0 - x_ref
     int nseg, nx;
     gptr<int> seg;
@@ -773,7 +817,7 @@ struct Coupler {
         nseg = d.nseg;
         nx = nx_;
         seg = to_global<int>(d.seg);
-        if constexpr (SC == SC_POLY2) {
+        if constexpr (POLY) {
             // the second difference 2 pc D^2 (D = JS dx) does not depend on z
             const double D = (double)JS * d.dx;
             const Cx<T> r = phasor_hw<T>(2.0 * (d.c[3] * d.inv_d) * D * D);
@@ -807,13 +851,14 @@ struct Coupler {
                 inside |= below_hi & ~below_lo;
             }
         });
-        auto inside_at_e = [&](auto e) { return ((inside >> CV(e)) & 1u) != 0u; };
+        // the weight m of element e: 1 inside the crystal, 0 outside
+        auto inside_at_e = [&](auto e) { return (T)((inside >> CV(e)) & 1u); };
         const double Z = (n + ss.zoff) * d.dz - d.z_ref;
         // (one straight-line copy: a wave-uniform branch to a copy without the
         // selects for all-inside waves keeps both copies' values live and spills)
         if constexpr (SC == SC_NONE) {
-            static_for<0, E>([&](auto e) { couple_sel(vp[e], vm[e], inside_at_e(e), d0, ap, am); });
-        } else if constexpr (SC == SC_POLY2) {
+            static_for<0, E>([&](auto e) { couple(vp[e], vm[e], inside_at_e(e), d0, ap, am); });
+        } else if constexpr (POLY) {
             // phase (revolutions) u/d = pa + pb X + pc X^2 along this z; along a
             // thread's samples X_e = X_0 + e D it is quadratic in e: with
             // P_e = exp(2 pi i u_e/d), P_{e+1} = P_e Q_e and Q_{e+1} = Q_e R, so the
@@ -829,12 +874,13 @@ struct Coupler {
             Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
             Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
             static_for<0, E>([&](auto e) {
-                couple_sel(vp[e], vm[e], inside_at_e(e), d0, bp, bm);
+                couple(vp[e], vm[e], inside_at_e(e), d0, bp, bm);
                 if constexpr (CV(e) + 1 < E) {
                     bp = {fmaT(bp.x, Q.x, -bp.y * Q.y), fmaT(bp.x, Q.y, bp.y * Q.x)};
                     bm = {fmaT(bm.x, Q.x, bm.y * Q.y), fmaT(bm.y, Q.x, -bm.x * Q.y)};
                 }
-                if constexpr (CV(e) + 2 < E) Q = {fmaT(Q.x, rr.x, -Q.y * rr.y), fmaT(Q.x, rr.y, Q.y * rr.x)};
+                if constexpr (CV(e) + 2 < E && !LIN)
+                    Q = {fmaT(Q.x, rr.x, -Q.y * rr.y), fmaT(Q.x, rr.y, Q.y * rr.x)};
             });
         } else {
             // dislocation field or tabulated phase (already reduced to one
@@ -856,7 +902,7 @@ struct Coupler {
                     const float kqh = (float)(0.5 * d.disl_k * d.disl_q);
                     static_for<0, E>([&](auto e) {
                         const int j = j0 + e * JS;
-                        const bool in = inside_at_e(e);
+                        const T in = inside_at_e(e);
                         const float X = (float)__builtin_fma((double)j, d.dx, X0);
                         const float r2 = fmaT(X, X, Z2);
                         const bool core = !(r2 > 0.0f);   // the core itself: phase 0
@@ -871,7 +917,7 @@ struct Coupler {
                         const Cx<float> P = {fmaT(W.x, S.x, -W.y * S.y), fmaT(W.x, S.y, W.y * S.x)};
                         const Cx<float> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
                         const Cx<float> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
-                        couple_sel(vp[e], vm[e], in, d0, bp, bm);
+                        couple(vp[e], vm[e], in, d0, bp, bm);
                     });
                     return;
                 }
@@ -880,7 +926,7 @@ struct Coupler {
                 // whole winding number: exp(i h u) = ((X + i Z)/r)^m exp(2 pi i k q X Z / r^2)
                 static_for<0, E>([&](auto e) {
                     const int j = j0 + e * JS;
-                    const bool in = inside_at_e(e);
+                    const T in = inside_at_e(e);
                     const T X = (T)__builtin_fma((double)j, d.dx, X0), Zt = (T)Z;
                     const T r2 = fmaT(X, X, Zt * Zt);
                     const T ir = r2 > (T)0 ? (T)1 / sqrt(r2) : (T)0;
@@ -889,19 +935,19 @@ struct Coupler {
                     const Cx<T> P = {fmaT(W.x, S.x, -W.y * S.y), fmaT(W.x, S.y, W.y * S.x)};
                     const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
                     const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
-                    couple_sel(vp[e], vm[e], in, d0, bp, bm);
+                    couple(vp[e], vm[e], in, d0, bp, bm);
                 });
                 return;
             }
             static_for<0, E>([&](auto e) {
                 const int j = j0 + e * JS;
-                const bool in = inside_at_e(e);
+                const T in = inside_at_e(e);
                 const T rev = edge ? edge_phase_rev((T)__builtin_fma((double)j, d.dx, X0), (T)Z, dk, dq)
                                    : tload_r<T>(utv, j0, n * nx + CV(e) * JS);
                 const Cx<T> P = phasor<T>(rev);
                 const Cx<T> bp = {fmaT(ap.x, P.x, -ap.y * P.y), fmaT(ap.x, P.y, ap.y * P.x)};
                 const Cx<T> bm = {fmaT(am.x, P.x, am.y * P.y), fmaT(am.y, P.x, -am.x * P.y)};
-                couple_sel(vp[e], vm[e], in, d0, bp, bm);
+                couple(vp[e], vm[e], in, d0, bp, bm);
             });
         }
     }
@@ -918,7 +964,7 @@ struct Coupler {
         const double Z = (n + ss.zoff) * d.dz - d.z_ref;
         const double Xd = __builtin_fma((double)x, d.dx, X0);
         Cx<T> P = {(T)1, (T)0};
-        if constexpr (SC == SC_POLY2) {
+        if constexpr (POLY) {
             const double pa = (d.c[0] + Z * (d.c[2] + Z * d.c[5])) * d.inv_d;
             const double pb = (d.c[1] + Z * d.c[4]) * d.inv_d;
             const double pc = d.c[3] * d.inv_d;
@@ -955,7 +1001,7 @@ struct Coupler {
             const Cx<T> Pe = table ? phasor<T>(tload_r<T>(utv, y0 * nx + x, (n * NY + YS * CV(e)) * nx)) : P;
             const Cx<T> bp = {fmaT(ap.x, Pe.x, -ap.y * Pe.y), fmaT(ap.x, Pe.y, ap.y * Pe.x)};
             const Cx<T> bm = {fmaT(am.x, Pe.x, am.y * Pe.y), fmaT(am.y, Pe.x, -am.x * Pe.y)};
-            couple_sel(vp[e], vm[e], in, d0, bp, bm);
+            couple(vp[e], vm[e], in ? (T)1 : (T)0, d0, bp, bm);
         });
     }
 };
@@ -1579,7 +1625,7 @@ struct Staged {
     // (gi) and lane within the column (lc), and the coupling context.
     struct Ctx {
         BufView in, st, tw;
-        const PropE<T> *prop;
+        const StagedPropE<T, D3> *prop;
         Cx<T> *CRp, *CRm, *RRp, *RRm;
         Coupler<T, SC> cpl;
         int lane, gi, lc;
@@ -1598,7 +1644,7 @@ struct Staged {
             in = buf_view(in_base + d.in_off, SB);
             st = buf_view(out_base + d.out_off, SB);   // the solve's state [2][N]
             tw = buf_view(d.tw, TW_TOTAL * (uint32_t)sizeof(Tw<T>));
-            prop = reinterpret_cast<const PropE<T> *>(d.prop);
+            prop = reinterpret_cast<const StagedPropE<T, D3> *>(d.prop);
             lane = lane_;
             gi = lane / LC;
             lc = lane % LC;
@@ -1671,12 +1717,12 @@ struct Staged {
         if constexpr (TC) RowM::fwd_local(vp, vm, x.rc, x.RRp, x.RRm, x.lane, true);
         else RowM::fwd_local(vp, vm, x.tw + oz * TWB, x.RRp, x.RRm, x.lane, true);
         // bin k2 = lane + 64 e of row k1 is frequency k1 + R k2
-        const BufView pr = buf_view(x.prop + ss.table * 2 * N, 2 * N * (uint32_t)sizeof(PropE<T>),
-                                    oz * (int)sizeof(PropE<T>));
+        using PE = StagedPropE<T, D3>;
+        const BufView pr = buf_view(x.prop + ss.table * 2 * N, 2 * N * (uint32_t)sizeof(PE), oz * (int)sizeof(PE));
         const T invN = x.invN;
         static_for<0, E>([&](auto e) {
             const int f = k1 * C + x.lane;
-            const PropE<T> kp = tload_prop<T>(pr, f, e * 64), km = tload_prop<T>(pr, f, N + e * 64);
+            const PE kp = tload_prop(pr, (PE *)nullptr, f, e * 64), km = tload_prop(pr, (PE *)nullptr, f, N + e * 64);
             const Cx<T> a = vp[e], b = vm[e];
             vp[e] = prop_mul(a, kp, invN);
             vm[e] = prop_mul(b, km, invN);

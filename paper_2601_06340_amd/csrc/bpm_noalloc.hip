@@ -68,7 +68,8 @@ extern "C" bpm_status bpm_propagate_device_noalloc(bpm_plan *p, void *stream, co
     if (!p->d_wide_ctl) {
         // one workgroup marches the solve: no scratch, the plan's own descriptor
         hipError_t e = launch_march(p->d_desc1, 1, p->desc.precision, p->launch_kind,
-                                    strain_class(p->desc.strain.kind), (const char *)d_in, (char *)d_out, rt, s);
+                                    march_class(p->desc.strain.kind, p->desc.strain.c[3]), (const char *)d_in,
+                                    (char *)d_out, rt, s);
         if (e != hipSuccess) return hip_fail(e, "march launch");
         return BPM_OK;
     }

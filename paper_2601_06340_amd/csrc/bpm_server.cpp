@@ -77,12 +77,12 @@ struct Request {
 // compute unit), on the kernels of this source.  The
 // server sizes every solve's chunk so that chunks take about the same time.
 constexpr float kAnyRate[2][7][3] = {
-    {{4.07e8f, 3.80e8f, 2.99e8f}, {4.41e8f, 5.26e8f, 3.81e8f}, {7.74e8f, 7.25e8f, 5.28e8f},
-     {7.37e8f, 7.08e8f, 4.16e8f}, {3.47e8f, 3.29e8f, 2.86e8f}, {3.49e8f, 3.30e8f, 2.92e8f},
-     {3.14e8f, 3.10e8f, 2.63e8f}},
-    {{4.90e8f, 4.57e8f, 4.15e8f}, {6.92e8f, 6.37e8f, 5.76e8f}, {1.11e9f, 1.05e9f, 9.02e8f},
-     {1.23e9f, 1.12e9f, 9.65e8f}, {1.19e9f, 1.11e9f, 8.63e8f}, {5.83e8f, 5.57e8f, 5.36e8f},
-     {6.37e8f, 5.37e8f, 5.16e8f}}};
+    {{4.13e8f, 3.85e8f, 2.98e8f}, {4.49e8f, 5.33e8f, 3.85e8f}, {7.85e8f, 7.33e8f, 5.34e8f},
+     {7.51e8f, 7.22e8f, 4.12e8f}, {3.47e8f, 3.30e8f, 2.87e8f}, {3.50e8f, 3.29e8f, 2.92e8f},
+     {3.15e8f, 3.11e8f, 2.60e8f}},
+    {{4.98e8f, 4.60e8f, 4.22e8f}, {7.08e8f, 6.50e8f, 5.75e8f}, {1.13e9f, 1.06e9f, 9.09e8f},
+     {1.26e9f, 1.16e9f, 9.82e8f}, {1.21e9f, 1.11e9f, 9.02e8f}, {6.27e8f, 5.92e8f, 5.69e8f},
+     {5.93e8f, 5.75e8f, 5.47e8f}}};
 // the reference class: FP32, nx = 16384, polynomial strain
 constexpr double kRefRate = 1.11e9;
 

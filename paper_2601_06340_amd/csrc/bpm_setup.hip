@@ -49,8 +49,10 @@ __device__ void coupling_substep(const PlanParams &P, double A, int form, SubSte
 // splitting; prop != NULL: the propagator table (P - 1)/nx of a sub-step of
 // afrac*dz.  The table of a staged size is stored in [k1][k2] order (frequency
 // f = k1 + R k2 at k1*(nx/R) + k2, R = 2^log2r); log2r = 0 keeps natural order.
+// lift: FP32 entries in the lifting form the staged 2D kernels read.
 template <typename T>
-__global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, PropE<T> *prop, int log2r, double afrac)
+__global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, PropE<T> *prop, int log2r, double afrac,
+                             int lift)
 {
     const PlanParams P = *pp;
     const double k = 2.0 * M_PI / P.lambda;
@@ -91,21 +93,38 @@ __global__ void k_plan_setup(const PlanParams *pp, PlanScalars *sc, PropE<T> *pr
             const double sg = beam == 0 ? 1.0 : -1.0;
             const double pq = q + sg * s;
             const double r = 1.0 - pq * pq - qy * qy;
-            double kx, ky;  // P - 1
+            // P = mag exp(i th)
+            double th, mag;
             if (r >= 0.0) {
                 // S - c = -(q^2 +/- 2 s q + qy^2) / (S + c)
                 const double S = sqrt(r);
-                const double th = -afrac * dzh * (q * q + 2.0 * sg * s * q + qy * qy) / (S + c);
-                const double sh = sin(0.5 * th);
-                kx = -2.0 * sh * sh;
-                ky = sin(th);
+                th = -afrac * dzh * (q * q + 2.0 * sg * s * q + qy * qy) / (S + c);
+                mag = 1.0;
             } else {
-                const double mag = exp(-afrac * dzh * sqrt(-r));
-                kx = mag * cos(afrac * dzh * c) - 1.0;
-                ky = -mag * sin(afrac * dzh * c);
+                th = -afrac * dzh * c;
+                mag = exp(-afrac * dzh * sqrt(-r));
             }
             const int pos = log2r ? (f & ((1 << log2r) - 1)) * (nx >> log2r) + (f >> log2r) : f;
-            const double ex = kx * invn, ey = ky * invn;
+            const double sh = sin(0.5 * th);
+            if constexpr (std::is_same<T, float>::value) {
+                if (lift) {
+                    // lifting entry: th reduced to [-pi, pi], then folded into
+                    // [-pi/2, pi/2] with the half turn in the sign of the scale
+                    double phi = remainder(th, 2.0 * M_PI), sgn = 1.0;
+                    if (phi > 0.5 * M_PI) phi -= M_PI, sgn = -1.0;
+                    else if (phi < -0.5 * M_PI) phi += M_PI, sgn = -1.0;
+                    const float pf = (float)(-tan(0.5 * phi));
+                    const double hh = sin(0.5 * phi);
+                    // u = (1 - cos phi)/(-p) = 2 sin^2(phi/2)/(-p): p u = 1 - cos phi
+                    const double u = pf != 0.0f ? 2.0 * hh * hh / -(double)pf : 0.0;
+                    const float uh = (float)u;
+                    reinterpret_cast<PropLift *>(prop)[beam * cells + pos] = {pf, uh, (float)(u - (double)uh),
+                                                                               (float)(sgn * mag * invn)};
+                    continue;
+                }
+            }
+            // k = (P - 1)/N, FP32 as hi + lo
+            const double ex = (r >= 0.0 ? -2.0 * sh * sh : mag * cos(th) - 1.0) * invn, ey = mag * sin(th) * invn;
             if constexpr (std::is_same<T, float>::value) {
                 const float hx = (float)ex, hy = (float)ey;
                 prop[beam * cells + pos] = {hx, hy, (float)(ex - (double)hx), (float)(ey - (double)hy)};
@@ -236,15 +255,15 @@ hipError_t launch_twiddles(void *d_tw, int prec, int log2n, int log2e, hipStream
 }
 
 hipError_t launch_plan_setup(const PlanParams *d_params, PlanScalars *d_sc, void *d_prop, int prec, int cells,
-                             int log2r, double afrac, hipStream_t s)
+                             int log2r, double afrac, bool lift, hipStream_t s)
 {
     const int bs = 256, gs = d_prop ? (cells + bs - 1) / bs : 1;
     if (prec == PREC_F32)
         hipLaunchKernelGGL(k_plan_setup<float>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (PropE<float> *)d_prop, log2r,
-                           afrac);
+                           afrac, lift ? 1 : 0);
     else
         hipLaunchKernelGGL(k_plan_setup<double>, dim3(gs), dim3(bs), 0, s, d_params, d_sc, (PropE<double> *)d_prop,
-                           log2r, afrac);
+                           log2r, afrac, 0);
     return hipGetLastError();
 }
 
@@ -527,7 +546,17 @@ static hipError_t dispatch_sc(const SolveDesc *d_descs, int n, int uniform_log2n
                               char *out_base, double *rt, hipStream_t s)
 {
     if (sc == SC_NONE) return dispatch<T, SC_NONE>(d_descs, n, uniform_log2n, in_base, out_base, rt, s);
-    if (sc == SC_POLY2) return dispatch<T, SC_POLY2>(d_descs, n, uniform_log2n, in_base, out_base, rt, s);
+    if (sc == SC_POLY1 && std::is_same<T, float>::value && uniform_log2n >= Limits<T>::uni_lo &&
+        uniform_log2n <= Limits<T>::uni_hi) {
+        hipError_t err = hipErrorInvalidValue;
+        static_for<Limits<float>::uni_lo, Limits<float>::uni_hi + 1>([&](auto l) {
+            if (uniform_log2n == CV(l))
+                err = launch_uniform<float, CV(l), SC_POLY1>(d_descs, n, in_base, out_base, rt, s);
+        });
+        return err;
+    }
+    if (sc == SC_POLY2 || sc == SC_POLY1)
+        return dispatch<T, SC_POLY2>(d_descs, n, uniform_log2n, in_base, out_base, rt, s);
     return dispatch<T, SC_GENERAL>(d_descs, n, uniform_log2n, in_base, out_base, rt, s);
 }
 

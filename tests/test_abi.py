@@ -126,3 +126,44 @@ def test_3d_sizes_outside_the_built_kernels_are_refused_before_the_device():
         with pytest.raises(bpm.BpmError) as e:
             bpm.Plan(p)
         assert e.value.status == want, (nx, ny, str(e.value))
+
+
+def test_coupling_step_beyond_the_series_bound_is_refused_before_the_device():
+    """A plan whose coupling sub-step has |A^2 chih chihbar| above 100 or
+    |A chi0| above 700 (A = b k dz / 2 cos theta_B, Eq. (9)-(12)) is
+    BPM_E_INVALID at validation; just below the bound it passes validation.
+    The marches weight the coupling by 0 outside the crystal, which needs
+    finite coefficients: the bound guarantees them."""
+    import math
+    import numpy as np
+    from paper_2601_06340_amd import bpm, synth
+    if not os.path.exists(bpm.LIB_PATH):
+        pytest.skip("library not built")
+    nx = 256
+    k = 2 * math.pi / synth.LAMBDA_UM
+    c = math.sqrt(1 - (synth.LAMBDA_UM / (2 * synth.D_UM)) ** 2)
+
+    def dz_for(y):   # order 1: b = 1, |A|^2 |chih| |chihb| = y
+        return math.sqrt(y / (abs(synth.CHIH) ** 2)) * 2 * c / k
+
+    import torch
+    for y in (101.0, 1e4, 99.0):
+        seg = synth.mask_x_slab(2, nx, 0.1, 0.0, nx * 0.1)
+        p = synth.base_problem(nx, 2, 0.1, dz_for(y), seg, precision="f32")
+        if y < 100.0:
+            if torch.cuda.is_available():
+                bpm.Plan(p).close()
+                continue
+            want = bpm.E_DEVICE   # past validation, stopped at the device check
+        else:
+            want = bpm.E_INVALID
+        with pytest.raises(bpm.BpmError) as e:
+            bpm.Plan(p)
+        assert e.value.status == want and (want != bpm.E_INVALID or "coupling step" in str(e.value)), (y, str(e.value))
+    # |A chi0| > 700 with chih = chihbar = 0
+    seg = synth.mask_x_slab(2, nx, 0.1, 0.0, nx * 0.1)
+    p = synth.base_problem(nx, 2, 0.1, 701.0 * 2 * c / (k * abs(synth.CHI0)), seg, precision="f32",
+                           chih=0j, chihb=0j)
+    with pytest.raises(bpm.BpmError) as e:
+        bpm.Plan(p)
+    assert e.value.status == bpm.E_INVALID and "coupling step" in str(e.value)
