@@ -136,7 +136,9 @@ typedef struct bpm_plan_info {
  * setup kernels on the current device (plan setup of Eq. (12)'s p+-, Eq. (9)-(10)).
  * Errors: BPM_E_INVALID (nx not a power of two in [64, 65536], nz < 0, a spacing
  * or wavelength <= 0, lambda >= 2d, non-finite values, bad intervals, unknown
- * kinds), BPM_E_UNSUPPORTED (nx too large for the library at this precision),
+ * kinds, a coupling sub-step too long for its series: |A^2 chih chihbar| > 100
+ * or |A chi0| > 700 with A = b k dz / (2 cos theta_B) and b the largest
+ * splitting weight), BPM_E_UNSUPPORTED (nx too large for the library at this precision),
  * BPM_E_NOMEM, BPM_E_DEVICE.  *out is NULL on failure. */
 bpm_status bpm_plan_create(const bpm_plan_desc *desc, bpm_plan **out);
 void bpm_plan_destroy(bpm_plan *plan);
