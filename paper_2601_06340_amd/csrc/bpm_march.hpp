@@ -1006,6 +1006,9 @@ struct Coupler {
     }
 };
 
+// propagator-table samples in flight ahead of the one a resident march multiplies
+constexpr int kPropAhead = 5;
+
 // One solve marched by the first TH of BLOCK threads (the rest only take part
 // in the workgroup barriers).
 // BXO overrides the LDS plan's beams-per-buffer choice (0 = the plan's).
@@ -1454,9 +1457,23 @@ struct March {
                 }
                 if (active) {
                     if constexpr (W > 1) pass_fwd<G::LOG2G, G::LOG2M, TH>(vp, vm, twf, G::TWFINAL, t);
-                    // ---- propagator: sample f = t + TH*e holds frequency bin f
+                    // ---- propagator: sample f = t + TH*e holds frequency bin f.
+                    // The entries of PD samples are in flight ahead of the one
+                    // multiplied (a rolling set of registers): left to itself the
+                    // compiler kept one or two loads in flight and every sample
+                    // waited on the L2 (per-size Nx 16384: +3.5 % with PD = 5).
+                    constexpr int PD = E < kPropAhead ? E : kPropAhead;
+                    PropE<T> kq[PD][2];
+                    static_for<0, PD>([&](auto e) {
+                        kq[CV(e)][0] = tload_prop<T>(propn, t, CV(e) * TH);
+                        kq[CV(e)][1] = tload_prop<T>(propn, t, N + CV(e) * TH);
+                    });
                     static_for<0, E>([&](auto e) {
-                        const PropE<T> kp = tload_prop<T>(propn, t, e * TH), km = tload_prop<T>(propn, t, N + e * TH);
+                        const PropE<T> kp = kq[CV(e) % PD][0], km = kq[CV(e) % PD][1];
+                        if constexpr (CV(e) + PD < E) {
+                            kq[CV(e) % PD][0] = tload_prop<T>(propn, t, (CV(e) + PD) * TH);
+                            kq[CV(e) % PD][1] = tload_prop<T>(propn, t, N + (CV(e) + PD) * TH);
+                        }
                         const Cx<T> a = vp[e], b = vm[e];
                         vp[e] = prop_mul(a, kp, invN);
                         vm[e] = prop_mul(b, km, invN);
