@@ -1733,16 +1733,23 @@ struct Staged {
         }
         if constexpr (TC) RowM::fwd_local(vp, vm, x.rc, x.RRp, x.RRm, x.lane, true);
         else RowM::fwd_local(vp, vm, x.tw + oz * TWB, x.RRp, x.RRm, x.lane, true);
-        // bin k2 = lane + 64 e of row k1 is frequency k1 + R k2
+        // bin k2 = lane + 64 e of row k1 is frequency k1 + R k2.  Every entry
+        // of the row is requested before the first is used: taken one sample
+        // at a time, each waited on the L2 with two waves per SIMD to cover it
+        // (dislocation batch of Nx 32768: +11 %).
         using PE = StagedPropE<T, D3>;
         const BufView pr = buf_view(x.prop + ss.table * 2 * N, 2 * N * (uint32_t)sizeof(PE), oz * (int)sizeof(PE));
         const T invN = x.invN;
+        const int f = k1 * C + x.lane;
+        PE kp[E], km[E];
         static_for<0, E>([&](auto e) {
-            const int f = k1 * C + x.lane;
-            const PE kp = tload_prop(pr, (PE *)nullptr, f, e * 64), km = tload_prop(pr, (PE *)nullptr, f, N + e * 64);
+            kp[e] = tload_prop(pr, (PE *)nullptr, f, e * 64);
+            km[e] = tload_prop(pr, (PE *)nullptr, f, N + e * 64);
+        });
+        static_for<0, E>([&](auto e) {
             const Cx<T> a = vp[e], b = vm[e];
-            vp[e] = prop_mul(a, kp, invN);
-            vm[e] = prop_mul(b, km, invN);
+            vp[e] = prop_mul(a, kp[e], invN);
+            vm[e] = prop_mul(b, km[e], invN);
         });
         if constexpr (TC) RowM::inv_local(vp, vm, x.rc, x.RRp, x.RRm, x.lane, true);
         else RowM::inv_local(vp, vm, x.tw + oi * TWB, x.RRp, x.RRm, x.lane, true);
