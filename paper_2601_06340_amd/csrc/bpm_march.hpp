@@ -1717,47 +1717,83 @@ struct Staged {
         row_run(x, ss, k1, oz, oi, vp, vm);
     }
     // the row phase of row k1 on its loaded samples
-    static __device__ __forceinline__ void row_run(const Ctx &x, const SubStep &ss, int k1, int oz, int oi, Cx<T> *vp,
-                                                   Cx<T> *vm)
+    // A row round's tables, its four-step twiddles and its propagator entries
+    // (bin k2 = lane + 64 e of row k1 is frequency k1 + R k2), all requested
+    // before the first is used and, with state loads in flight (PF), before the
+    // next round's state loads: loads complete in issue order, so a wait for a
+    // table issued after those would wait for them as well.  Requested one
+    // sample at a time after the row transform, each entry waited on the L2
+    // with two waves per SIMD to cover it (dislocation batch of Nx 32768:
+    // 1.445e11 -> 1.634e11 cell-steps/s with the entries requested together
+    // after the transform, 1.73e11 with every table ahead of the state loads).
+    // Without state loads in flight (FP64) the entries are requested after the
+    // row transform: held across it they spilled.
+    using PE = StagedPropE<T, D3>;
+    struct RowTables {
+        Tw<T> w4[D3 ? 1 : E];
+        PE kp[PF ? E : 1], km[PF ? E : 1];
+    };
+    static __device__ __forceinline__ void row_tables(const Ctx &x, const SubStep &ss, int k1, int oz, RowTables &tb)
     {
         const int rb = k1 * C + x.lane + oz;
-        // TC: the round's four-step twiddles stay in registers for the inverse
-        Tw<T> w4[TC && !D3 ? E : 1];
         if constexpr (!D3) {
-            static_for<0, E>([&](auto e) {
-                const Tw<T> w = tload_tw<T>(x.tw, rb, TW_4 + e * 64);
-                if constexpr (TC) w4[e] = w;
-                vp[e] = mul_tw(vp[e], w);
-                vm[e] = mul_tw(vm[e], w);
-            });
+            static_for<0, E>([&](auto e) { tb.w4[e] = tload_tw<T>(x.tw, rb, TW_4 + e * 64); });
         }
-        if constexpr (TC) RowM::fwd_local(vp, vm, x.rc, x.RRp, x.RRm, x.lane, true);
-        else RowM::fwd_local(vp, vm, x.tw + oz * TWB, x.RRp, x.RRm, x.lane, true);
-        // bin k2 = lane + 64 e of row k1 is frequency k1 + R k2.  Every entry
-        // of the row is requested before the first is used: taken one sample
-        // at a time, each waited on the L2 with two waves per SIMD to cover it
-        // (dislocation batch of Nx 32768: +11 %).
-        using PE = StagedPropE<T, D3>;
+        if constexpr (PF) load_prop_row(x, ss, k1, oz, tb.kp, tb.km);
+    }
+    static __device__ __forceinline__ void load_prop_row(const Ctx &x, const SubStep &ss, int k1, int oz, PE *kp,
+                                                         PE *km)
+    {
         const BufView pr = buf_view(x.prop + ss.table * 2 * N, 2 * N * (uint32_t)sizeof(PE), oz * (int)sizeof(PE));
-        const T invN = x.invN;
         const int f = k1 * C + x.lane;
-        PE kp[E], km[E];
         static_for<0, E>([&](auto e) {
             kp[e] = tload_prop(pr, (PE *)nullptr, f, e * 64);
             km[e] = tload_prop(pr, (PE *)nullptr, f, N + e * 64);
         });
-        static_for<0, E>([&](auto e) {
-            const Cx<T> a = vp[e], b = vm[e];
-            vp[e] = prop_mul(a, kp[e], invN);
-            vm[e] = prop_mul(b, km[e], invN);
-        });
+    }
+    static __device__ __forceinline__ void row_run(const Ctx &x, const SubStep &ss, int k1, int oz, int oi, Cx<T> *vp,
+                                                   Cx<T> *vm)
+    {
+        RowTables tb;
+        row_tables(x, ss, k1, oz, tb);
+        row_run_t(x, ss, k1, oz, oi, vp, vm, tb);
+    }
+    static __device__ __forceinline__ void row_run_t(const Ctx &x, const SubStep &ss, int k1, int oz, int oi, Cx<T> *vp,
+                                                     Cx<T> *vm, const RowTables &tb)
+    {
+        const int rb = k1 * C + x.lane + oz;
+        if constexpr (!D3) {
+            static_for<0, E>([&](auto e) {
+                vp[e] = mul_tw(vp[e], tb.w4[e]);
+                vm[e] = mul_tw(vm[e], tb.w4[e]);
+            });
+        }
+        if constexpr (TC) RowM::fwd_local(vp, vm, x.rc, x.RRp, x.RRm, x.lane, true);
+        else RowM::fwd_local(vp, vm, x.tw + oz * TWB, x.RRp, x.RRm, x.lane, true);
+        const T invN = x.invN;
+        if constexpr (PF) {
+            static_for<0, E>([&](auto e) {
+                const Cx<T> a = vp[e], b = vm[e];
+                vp[e] = prop_mul(a, tb.kp[e], invN);
+                vm[e] = prop_mul(b, tb.km[e], invN);
+            });
+        } else {
+            PE kp[E], km[E];
+            load_prop_row(x, ss, k1, oz, kp, km);
+            static_for<0, E>([&](auto e) {
+                const Cx<T> a = vp[e], b = vm[e];
+                vp[e] = prop_mul(a, kp[e], invN);
+                vm[e] = prop_mul(b, km[e], invN);
+            });
+        }
         if constexpr (TC) RowM::inv_local(vp, vm, x.rc, x.RRp, x.RRm, x.lane, true);
         else RowM::inv_local(vp, vm, x.tw + oi * TWB, x.RRp, x.RRm, x.lane, true);
         const int rbi = k1 * C + x.lane + oi;
         if constexpr (!D3) {
+            // TC: the round's four-step twiddles stay in registers for the inverse
             static_for<0, E>([&](auto e) {
                 Tw<T> w;
-                if constexpr (TC) w = w4[e];
+                if constexpr (TC) w = tb.w4[e];
                 else w = tload_tw<T>(x.tw, rbi, TW_4 + e * 64);
                 vp[e] = mul_tw_inv(vp[e], w);
                 vm[e] = mul_tw_inv(vm[e], w);
@@ -1849,10 +1885,12 @@ struct Staged {
                         vp[e] = np[e];
                         vm[e] = nm[e];
                     });
+                    RowTables tb;
+                    row_tables(x, ss, rr * WAVES + wv, (n + i + rr) & d.opaque_zero, tb);
                     if (rr + 1 < ROW_ROUNDS)
                         row_load(x, (rr + 1) * WAVES + wv, (n + i + rr + 1) & d.opaque_zero, np, nm);
-                    row_run(x, ss, rr * WAVES + wv, (n + i + rr) & d.opaque_zero, (n + i + rr + 1) & d.opaque_zero,
-                            vp, vm);
+                    row_run_t(x, ss, rr * WAVES + wv, (n + i + rr) & d.opaque_zero, (n + i + rr + 1) & d.opaque_zero,
+                              vp, vm, tb);
                 }
                 __syncthreads();
                 col_load(x, wv * GPW + x.gi, (n + i) & d.opaque_zero, np, nm);

@@ -77,14 +77,14 @@ struct Request {
 // compute unit), on the kernels of this source.  The
 // server sizes every solve's chunk so that chunks take about the same time.
 constexpr float kAnyRate[2][7][3] = {
-    {{4.15e8f, 3.82e8f, 2.99e8f}, {5.39e8f, 5.40e8f, 3.86e8f}, {7.88e8f, 7.32e8f, 5.35e8f},
-     {7.35e8f, 7.07e8f, 4.19e8f}, {3.68e8f, 3.51e8f, 3.02e8f}, {3.76e8f, 3.51e8f, 3.01e8f},
-     {3.24e8f, 3.24e8f, 2.79e8f}},
-    {{4.99e8f, 4.63e8f, 4.24e8f}, {7.05e8f, 6.54e8f, 5.82e8f}, {1.12e9f, 1.08e9f, 9.05e8f},
-     {1.27e9f, 1.17e9f, 9.84e8f}, {1.20e9f, 1.15e9f, 9.10e8f}, {6.86e8f, 6.42e8f, 6.05e8f},
-     {6.10e8f, 5.87e8f, 5.38e8f}}};
+    {{4.11e8f, 3.85e8f, 3.00e8f}, {5.40e8f, 5.35e8f, 3.87e8f}, {7.86e8f, 7.38e8f, 5.35e8f},
+     {7.37e8f, 7.15e8f, 4.20e8f}, {3.89e8f, 3.65e8f, 3.13e8f}, {3.91e8f, 3.62e8f, 3.10e8f},
+     {3.34e8f, 3.28e8f, 2.88e8f}},
+    {{5.02e8f, 4.65e8f, 4.24e8f}, {7.06e8f, 6.65e8f, 5.75e8f}, {1.13e9f, 1.08e9f, 9.20e8f},
+     {1.27e9f, 1.16e9f, 9.72e8f}, {1.20e9f, 1.17e9f, 9.14e8f}, {7.03e8f, 6.65e8f, 6.23e8f},
+     {6.16e8f, 5.97e8f, 6.04e8f}}};
 // the reference class: FP32, nx = 16384, polynomial strain
-constexpr double kRefRate = 1.15e9;
+constexpr double kRefRate = 1.17e9;
 
 double any_rate(const bpm_plan_desc &d)
 {
