@@ -1273,6 +1273,23 @@ struct March {
         }
     }
 
+    // The cross-group pass's twiddles of thread t (element m of group i at
+    // index i*(W-1) + m-1).
+    static __device__ __forceinline__ void load_cross_tw(Tw<T> *w, const BufView &tw, int t)
+    {
+        constexpr int r = W, EPR = E / r, L = M;
+        static_for<0, EPR>([&](auto i) {
+            const int j = (t + CV(i) * TH) & (L - 1);
+            static_for<1, r>([&](auto m) {
+                w[CV(i) * (r - 1) + CV(m) - 1] = tload_tw<T>(tw, j, G::TWFINAL + (CV(m) - 1) * L);
+            });
+        });
+    }
+    static __device__ __forceinline__ auto cross_tw_f(const Tw<T> *w)
+    {
+        return [w](auto i, auto m, int) { return w[CV(i) * (W - 1) + CV(m) - 1]; };
+    }
+
     // Group-local forward FFT of M points (radix-E Stockham passes with the
     // group's exchanges through its LDS region Rp/Rm); natural-order samples
     // l + LANES*e in, bins l + LANES*e out.
@@ -1438,7 +1455,12 @@ struct March {
                 // ---- forward transforms (Eq. (12): F[psi+-]); group-local passes
                 if constexpr (TC) fwd_local(vp, vm, tcache, Rp, Rm, l, active);
                 else fwd_local(vp, vm, twf, Rp, Rm, l, active);
-                // ---- cross-group radix-W pass (wave groups only)
+                // ---- cross-group radix-W pass (wave groups only).  Its
+                // twiddles are requested before the exchange: after it, every
+                // wave of the workgroup leaves the same barrier and waited on
+                // the L2 at once (per-size Nx 16384: 3.27 -> 3.41e11).
+                Tw<T> xw[W > 1 ? E : 1];
+                if constexpr (W > 1) load_cross_tw(xw, twf, t);
                 if constexpr (W > 1) {
                     if (active) {
                         write_own(Rp, vp, l);
@@ -1456,7 +1478,7 @@ struct March {
                     }
                 }
                 if (active) {
-                    if constexpr (W > 1) pass_fwd<G::LOG2G, G::LOG2M, TH>(vp, vm, twf, G::TWFINAL, t);
+                    if constexpr (W > 1) pass_fwd_f<G::LOG2G, G::LOG2M, TH>(vp, vm, cross_tw_f(xw), t);
                     // ---- propagator: sample f = t + TH*e holds frequency bin f.
                     // The entries of PD samples are in flight ahead of the one
                     // multiplied (a rolling set of registers): left to itself the
