@@ -182,11 +182,11 @@ __device__ __forceinline__ PropE<T> tload_prop(const BufView &t, int lane_i, int
 // the three shears turn the bin by exactly phi; the rounding of p only makes
 // the orbit an ellipse of axis ratio 1 + O(2^-24), an amplitude wobble that
 // does not grow with Nz (each shear has determinant one).  Three fewer
-// operations per sample than a/N + k a with k as hi + lo; the per-size,
-// mixed-size and 3D kernels, which wait on the table loads of this step, are
-// faster with the hi + lo entries, whose arithmetic covers more of that wait.
-// (Staged 2D batch of Nx 32768: +2 %; per-size Nx 16384: -5 %, mixed-size
-// pulse batch -20 %, 3D batch -2 % when they took the lifting form as well.)
+// operations per sample than a/N + k a with k as hi + lo; the per-size and
+// mixed-size kernels, which wait on the table loads of this step, were faster
+// with the hi + lo entries, whose arithmetic covers more of that wait (staged
+// 2D batch of Nx 32768: +2 %; per-size Nx 16384: -5 %, mixed-size pulse batch
+// -20 % when they took the lifting form as well).  The 3D kernels keep hi + lo.
 struct alignas(16) PropLift {
     float p, uh, ul, c;
 };
