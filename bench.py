@@ -472,7 +472,18 @@ def main():
     elif sched == "any":
         kernel = "k_march_any<%s>" % tname
     else:
-        kernel = "k_march_uniform<%s,%d>" % (tname, int(math.log2(nx)))
+        # the per-size kernel's strain class (template argument): 0 none,
+        # 1 polynomial, 2 dislocation / table, 3 polynomial without X^2
+        def strain_cls(pr):
+            st = pr.get("strain") or {"kind": "none"}
+            if st.get("kind", "none") == "none":
+                return 0
+            if st["kind"] == "poly2":
+                return 3 if float(st["c"][3]) == 0.0 else 1
+            return 2
+        classes = {strain_cls(pr) for pr, _ in cases}
+        kernel = "k_march_uniform<%s,%d%s>" % (tname, int(math.log2(nx)),
+                                               ",%d" % classes.pop() if len(classes) == 1 else "")
     roof = alu_roofline(cases, sum(per) / len(per), prec)
     roof.update(traffic=traffic_entry(kernel, launch_cs), kernel=kernel)
 
