@@ -1106,3 +1106,46 @@ def test_invalid_descriptors_rejected_before_any_launch():
     with pytest.raises(B.BpmError) as e:
         plan.propagate(bad)
     assert e.value.status == B.E_NUMERIC
+
+
+# ------------------------------------------------------------------ staged FP32 lifting-form table, long march
+def test_staged_fp32_lifting_table_long_march_random_fields():
+    """The FP32 staged sizes hold P/N as an exact-angle lifting rotation; a
+    fixed rounding in a table entry would add up linearly in Nz wherever the
+    field has energy at large |P - 1|.  Random envelopes (energy in every bin)
+    over 2000 steps at Nx 32768, through the staged batch kernel and the wide
+    lane, against the oracle at the FP32 bars."""
+    import torch
+    B = bpm()
+    nx, nz, dx, dz = 32768, 2000, 0.05, 0.025
+    seg = np.zeros((nz, 1, 2), np.int32)
+    for n in range(nz):
+        seg[n, 0] = (nx // 16 + (n % 97), nx - nx // 9)
+    p = synth.base_problem(nx, nz, dx, dz, seg, precision="f32", chih=CHIH_U, chihb=CHIHB_U)
+    a, b = synth.random_envelopes(nx, 47)
+    b = 0.5 * b
+    op, om, oR, oT = oracle.propagate(p, a, b)
+    tol = TOL["f32"][0]
+    # wide lane (one solve alone)
+    plan = B.Plan(p)
+    gp, gm, gR, gT = plan.propagate(a, b)
+    err = rel_pair(gp, gm, op, om)
+    say("lifting long march, wide lane: rel L2 %.3e dR %.2e dT %.2e" % (err, abs(gR - oR), abs(gT - oT)))
+    assert err <= tol and abs(gR - oR) <= r_bar("f32", oR) and abs(gT - oT) <= t_bar("f32", oT)
+    # staged batch kernel (two copies of the solve in one launch)
+    plans = [plan, B.Plan(p)]
+    batch = B.Batch(plans)
+    buf = batch.pack([(a, b), (a, b)])
+    rt = torch.zeros(4, dtype=torch.float64, device="cuda")
+    batch.run(buf.data_ptr(), buf.data_ptr(), rt.data_ptr())
+    torch.cuda.synchronize()
+    outs = batch.unpack(buf)
+    rt = rt.cpu().numpy()
+    batch.close()
+    for q in plans:
+        q.close()
+    for i in range(2):
+        err = rel_pair(outs[i][0], outs[i][1], op, om)
+        say("lifting long march, batch %d: rel L2 %.3e dR %.2e dT %.2e" % (i, err, abs(rt[2 * i] - oR),
+                                                                         abs(rt[2 * i + 1] - oT)))
+        assert err <= tol and abs(rt[2 * i] - oR) <= r_bar("f32", oR) and abs(rt[2 * i + 1] - oT) <= t_bar("f32", oT)
