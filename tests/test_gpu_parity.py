@@ -1149,3 +1149,42 @@ def test_staged_fp32_lifting_table_long_march_random_fields():
         say("lifting long march, batch %d: rel L2 %.3e dR %.2e dT %.2e" % (i, err, abs(rt[2 * i] - oR),
                                                                          abs(rt[2 * i + 1] - oT)))
         assert err <= tol and abs(rt[2 * i] - oR) <= r_bar("f32", oR) and abs(rt[2 * i + 1] - oT) <= t_bar("f32", oT)
+
+
+# ------------------------------------------------------------------ POLY1: a polynomial phase without its X^2 term
+def test_linear_phase_class_equals_the_polynomial_kernels_bitwise():
+    """A bend (u = X Z / R, c3 = 0) runs the per-size FP32 kernels' POLY1 copy,
+    whose phasor steps leave out the second-difference factor (exactly one for
+    c3 = 0); the mixed-size and any-size kernels run the same solve as POLY2.
+    The results must agree bitwise and match the oracle; a phase with an X^2
+    term (c3 != 0) runs POLY2 everywhere."""
+    import torch
+    B = bpm()
+    cases = []
+    p, psi = synth.bent_laue(radii_m=(0.3,), nx=8192, nz=120, thickness=3.0, precision="f32")[0]
+    cases.append((p, psi))
+    q = dict(p, strain=dict(p["strain"], c=[0.0, 1e-5, 2e-7, -3e-9, p["strain"]["c"][4], 1e-9]))
+    cases.append((q, psi))
+    try:
+        for k, (pp, ps) in enumerate(cases):
+            op, om, oR, oT = oracle.propagate(pp, ps)
+            outs = {}
+            for sched in ("uniform", "mixed", "any"):
+                B.schedule_set("f32", 8192, 1, sched)
+                plan = B.Plan(pp)
+                batch = B.Batch([plan])
+                buf = batch.pack([(ps, None)])
+                rt = torch.zeros(2, dtype=torch.float64, device="cuda")
+                batch.run(buf.data_ptr(), buf.data_ptr(), rt.data_ptr())
+                torch.cuda.synchronize()
+                outs[sched] = batch.unpack(buf)[0]
+                err = rel_pair(outs[sched][0], outs[sched][1], op, om)
+                say("poly case %d schedule %s rel L2 %.3e" % (k, sched, err))
+                assert err <= TOL["f32"][0] and abs(rt.cpu().numpy()[0] - oR) <= r_bar("f32", oR)
+                batch.close()
+                plan.close()
+            for sched in ("mixed", "any"):
+                assert np.array_equal(outs["uniform"][0], outs[sched][0]), (k, sched)
+                assert np.array_equal(outs["uniform"][1], outs[sched][1]), (k, sched)
+    finally:
+        B.schedule_set("f32", 8192, 1, "default")
